@@ -1,0 +1,512 @@
+/*
+ * wave_oracle.c -- FP64 CPU oracle for the dimensionally unsplit
+ * wave-propagation step of 2D linear acoustics
+ * (Qin, LeVeque & Motley, arXiv 1808.02638).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow, obviously-correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark load it; the
+ * product path never links, imports or calls it, and it shares no code,
+ * header, table or constant with the GPU library.
+ *
+ * What it follows:
+ *   - the update formula, paper Sec. 2.1 eq. (2.3): first-order fluctuations
+ *     A+dQ, A-dQ, B+dQ, B-dQ plus the differences of the second-order
+ *     correction fluxes F~ and G~, which hold both the limited-wave
+ *     corrections and the transverse waves obtained by splitting the
+ *     fluctuations in the other direction (Sec. 2.1, last paragraph, and
+ *     Sec. 3.3, "normal and transverse Riemann solvers");
+ *   - the acoustics system q = (p,u,v), q_t + A q_x + B q_y = 0 with the
+ *     matrices of Sec. 4.1 eqs. (4.1)-(4.2);
+ *   - the Courant number of Sec. 2.4 eq. (2.10) and the time-step rule of
+ *     Sec. 2.5 eq. (2.11) (applied by the Python driver);
+ *   - physical boundaries through ghost cells, Sec. 2.2 item 1; the benchmark
+ *     uses non-reflecting outflow (Sec. 4.1), i.e. zero-order extrapolation.
+ * The paper defers the exact form of the correction terms to LeVeque's
+ * finite-volume book (its standard unsplit wave-propagation method with
+ * transverse Riemann solvers); the readings taken where the paper is silent
+ * are listed in the repository design notes:
+ *   * the transverse solver splits the first-order fluctuations;
+ *   * limiter ratio theta = (W_upwind . W) / (W . W) over all components,
+ *     W~ = W when W . W = 0; MC limiter phi = max(0, min((1+theta)/2, 2, 2 theta));
+ *   * CFL number of a 2D step = max over x-edges of |s| dt/dx and over
+ *     y-edges of |s| dt/dy.
+ *
+ * Everything is written edge by edge with explicit arrays for the
+ * fluctuations and for F~ and G~, with all three eigen-waves (speeds -c, 0,
+ * +c) taken from the full eigen-decomposition.  OpenMP parallelises rows /
+ * columns (each writes only its own entries) and independent patches.
+ *
+ * Storage of one patch: dense [3][my+4][mx+4] doubles (components p, u, v;
+ * two ghost layers on every side; x fastest).  Interior cells are
+ * i = 0..mx-1, j = 0..my-1; ghost cells are i = -2,-1,mx,mx+1 (and j alike).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NM 3 /* components of q = (p, u, v) */
+#define NW 3 /* waves: eigenvalues -c, 0, +c */
+
+enum { OR_LIM_MC = 0, OR_LIM_NONE = 1, OR_LIM_ZERO = 2, OR_LIM_VANLEER = 3 };
+enum { OR_BC_EXTRAP = 0, OR_BC_PERIODIC = 1 };
+
+/* ---------------------------------------------------------------------- */
+/* Eigen-decomposition of A (dir 0) and B (dir 1), Sec. 4.1 eq. (4.2).      */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+  double s[NW];     /* eigenvalues, ordered -c, 0, +c              */
+  double R[NM][NW]; /* right eigenvectors, one per column          */
+  double L[NW][NM]; /* left eigenvectors (rows of R^-1)            */
+} eig_t;
+
+static void acoustics_eig(double rho, double K, int dir, eig_t *e) {
+  const double c = sqrt(K / rho); /* sound speed c = sqrt(K0/rho0) */
+  const double Z = rho * c;       /* impedance                      */
+  const int n = (dir == 0) ? 1 : 2; /* normal velocity component     */
+  const int t = (dir == 0) ? 2 : 1; /* tangential velocity component */
+  memset(e, 0, sizeof *e);
+  e->s[0] = -c;
+  e->s[1] = 0.0;
+  e->s[2] = c;
+  /* r^(-c) = (-Z, e_n), r^(0) = e_t, r^(+c) = (Z, e_n) */
+  e->R[0][0] = -Z;
+  e->R[n][0] = 1.0;
+  e->R[t][1] = 1.0;
+  e->R[0][2] = Z;
+  e->R[n][2] = 1.0;
+  /* alpha^(-c) = (-dp + Z dn)/(2Z), alpha^(0) = dt, alpha^(+c) = (dp + Z dn)/(2Z) */
+  e->L[0][0] = -1.0 / (2.0 * Z);
+  e->L[0][n] = 0.5;
+  e->L[1][t] = 1.0;
+  e->L[2][0] = 1.0 / (2.0 * Z);
+  e->L[2][n] = 0.5;
+}
+
+/* Normal Riemann solve at one edge: waves W^p = alpha^p r^p with
+ * alpha = R^-1 (q_r - q_l), and fluctuations A-dQ = sum_{s<0} s W,
+ * A+dQ = sum_{s>0} s W.  drop_zero_wave omits the speed-0 wave. */
+static void riemann(const eig_t *e, const double ql[NM], const double qr[NM],
+                    int drop_zero_wave, double wave[NW][NM], double amdq[NM],
+                    double apdq[NM]) {
+  double dq[NM], alpha[NW];
+  for (int m = 0; m < NM; ++m) dq[m] = qr[m] - ql[m];
+  for (int p = 0; p < NW; ++p) {
+    alpha[p] = 0.0;
+    for (int m = 0; m < NM; ++m) alpha[p] += e->L[p][m] * dq[m];
+    if (drop_zero_wave && e->s[p] == 0.0) alpha[p] = 0.0;
+  }
+  for (int p = 0; p < NW; ++p)
+    for (int m = 0; m < NM; ++m) wave[p][m] = alpha[p] * e->R[m][p];
+  for (int m = 0; m < NM; ++m) amdq[m] = apdq[m] = 0.0;
+  for (int p = 0; p < NW; ++p) {
+    if (drop_zero_wave && e->s[p] == 0.0) continue;
+    for (int m = 0; m < NM; ++m) {
+      if (e->s[p] < 0.0) amdq[m] += e->s[p] * wave[p][m];
+      else if (e->s[p] > 0.0) apdq[m] += e->s[p] * wave[p][m];
+    }
+  }
+}
+
+/* Transverse Riemann solve: split a vector a by the other direction's
+ * eigen-structure into its negative- and positive-speed parts. */
+static void split(const eig_t *e, const double a[NM], double minus[NM],
+                  double plus[NM]) {
+  double beta[NW];
+  for (int p = 0; p < NW; ++p) {
+    beta[p] = 0.0;
+    for (int m = 0; m < NM; ++m) beta[p] += e->L[p][m] * a[m];
+  }
+  for (int m = 0; m < NM; ++m) minus[m] = plus[m] = 0.0;
+  for (int p = 0; p < NW; ++p)
+    for (int m = 0; m < NM; ++m) {
+      if (e->s[p] < 0.0) minus[m] += e->s[p] * beta[p] * e->R[m][p];
+      else if (e->s[p] > 0.0) plus[m] += e->s[p] * beta[p] * e->R[m][p];
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* Wave limiter                                                            */
+/* ---------------------------------------------------------------------- */
+double oracle_phi(int lim, double theta) {
+  switch (lim) {
+  case OR_LIM_MC:
+    return fmax(0.0, fmin(fmin(0.5 * (1.0 + theta), 2.0), 2.0 * theta));
+  case OR_LIM_NONE:
+    return 1.0;
+  case OR_LIM_ZERO:
+    return 0.0;
+  case OR_LIM_VANLEER:
+    return (theta + fabs(theta)) / (1.0 + fabs(theta));
+  }
+  return NAN;
+}
+
+/* Branch of the MC limiter taken at ratio theta:
+ * 0 -> phi = 0, 1 -> (1+theta)/2, 2 -> 2, 3 -> 2 theta; ties go to the
+ * lowest index.  A zero wave (W.W = 0) is branch 0. */
+int oracle_mc_branch(double ww, double theta) {
+  if (ww == 0.0 || theta <= 0.0) return 0;
+  const double b1 = 0.5 * (1.0 + theta), b2 = 2.0, b3 = 2.0 * theta;
+  if (b1 <= b2 && b1 <= b3) return 1;
+  if (b2 <= b3) return 2;
+  return 3;
+}
+
+static double dot3(const double a[NM], const double b[NM]) {
+  double s = 0.0;
+  for (int m = 0; m < NM; ++m) s += a[m] * b[m];
+  return s;
+}
+
+/* Limited wave W~ from W and its upwind neighbour.  With a frozen branch
+ * (frozen >= 0) the map is the linear one that branch selects:
+ * 0 -> 0, 1 -> (W + W_up)/2, 2 -> 2 W, 3 -> 2 W_up. */
+static void limit_wave(int lim, const double w[NM], const double wup[NM],
+                       int frozen, double out[NM], int *branch) {
+  if (frozen >= 0) {
+    for (int m = 0; m < NM; ++m) {
+      switch (frozen) {
+      case 0: out[m] = 0.0; break;
+      case 1: out[m] = 0.5 * (w[m] + wup[m]); break;
+      case 2: out[m] = 2.0 * w[m]; break;
+      default: out[m] = 2.0 * wup[m]; break;
+      }
+    }
+    if (branch) *branch = frozen;
+    return;
+  }
+  const double ww = dot3(w, w);
+  if (ww == 0.0) {
+    for (int m = 0; m < NM; ++m) out[m] = w[m];
+    if (branch) *branch = 0;
+    return;
+  }
+  const double theta = dot3(wup, w) / ww;
+  const double f = oracle_phi(lim, theta);
+  for (int m = 0; m < NM; ++m) out[m] = f * w[m];
+  if (branch) *branch = oracle_mc_branch(ww, theta);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Indexing                                                                */
+/* ---------------------------------------------------------------------- */
+#define QIX(m, i, j)                                                           \
+  ((((size_t)(m) * (size_t)(my + 4) + (size_t)((j) + 2)) * (size_t)(mx + 4)) + \
+   (size_t)((i) + 2))
+
+/* mask byte of cell (i,j), i in [0,mx], j in [0,my]:
+ *   bits 0-1 x-edge (i-1/2, j) wave -c, bits 2-3 x-edge wave +c,
+ *   bits 4-5 y-edge (i, j-1/2) wave -c, bits 6-7 y-edge wave +c. */
+#define MIX(i, j) ((size_t)(j) * (size_t)(mx + 1) + (size_t)(i))
+
+/* ---------------------------------------------------------------------- */
+/* Boundary conditions (Sec. 2.2 item 1; outflow = zero-order extrapolation) */
+/* ---------------------------------------------------------------------- */
+/* x-ghosts for the interior rows first, then y-ghosts across the full padded
+ * width, so the corner ghosts take the value of the nearest interior cell. */
+void oracle_fill_bc(double *q, int mx, int my, int bc_kind) {
+  for (int m = 0; m < NM; ++m) {
+    for (int j = 0; j < my; ++j)
+      for (int g = 1; g <= 2; ++g) {
+        if (bc_kind == OR_BC_PERIODIC) {
+          q[QIX(m, -g, j)] = q[QIX(m, mx - g, j)];
+          q[QIX(m, mx - 1 + g, j)] = q[QIX(m, g - 1, j)];
+        } else {
+          q[QIX(m, -g, j)] = q[QIX(m, 0, j)];
+          q[QIX(m, mx - 1 + g, j)] = q[QIX(m, mx - 1, j)];
+        }
+      }
+    for (int i = -2; i < mx + 2; ++i)
+      for (int g = 1; g <= 2; ++g) {
+        if (bc_kind == OR_BC_PERIODIC) {
+          q[QIX(m, i, -g)] = q[QIX(m, i, my - g)];
+          q[QIX(m, i, my - 1 + g)] = q[QIX(m, i, g - 1)];
+        } else {
+          q[QIX(m, i, -g)] = q[QIX(m, i, 0)];
+          q[QIX(m, i, my - 1 + g)] = q[QIX(m, i, my - 1)];
+        }
+      }
+  }
+}
+
+/* ---------------------------------------------------------------------- */
+/* One unsplit step of one patch                                           */
+/* ---------------------------------------------------------------------- */
+/*
+ * q_in, q_out : dense [3][my+4][mx+4]; q_out's interior receives Q^{n+1},
+ *               its ghosts are copied from q_in (the boundary fill is a
+ *               separate call made by the driver between steps).
+ * limiter     : OR_LIM_*;  drop_zero_wave: omit the speed-0 wave.
+ * frozen      : NULL, or (mx+1)*(my+1) mask bytes fixing the MC branches
+ *               (the step is then a linear map of q_in);
+ * masks_out   : NULL, or (mx+1)*(my+1) bytes receiving the branches taken.
+ * cfl_out     : max over edges of |s| dt/dx (x-edges) and |s| dt/dy (y-edges).
+ * Returns 0, or -1 on bad sizes / allocation failure.
+ */
+int oracle_step_ex(const double *q_in, double *q_out, int mx, int my,
+                   double dx, double dy, double dt, double rho, double K,
+                   int limiter, int drop_zero_wave, const uint8_t *frozen,
+                   uint8_t *masks_out, double *cfl_out, int parallel) {
+  if (mx < 1 || my < 1 || !(dx > 0.0) || !(dy > 0.0)) return -1;
+  eig_t ex, ey;
+  acoustics_eig(rho, K, 0, &ex);
+  acoustics_eig(rho, K, 1, &ey);
+  const double dtdx = dt / dx, dtdy = dt / dy;
+  const int par = parallel && ((long)mx * (long)my >= 16384);
+
+  /* x-edge arrays: rows j = -1..my, edges e = 0..mx (edge e is i-1/2 of cell e) */
+  const size_t nxe = (size_t)(my + 2) * (size_t)(mx + 1);
+  /* y-edge arrays: edges f = 0..my, columns i = -1..mx */
+  const size_t nye = (size_t)(my + 1) * (size_t)(mx + 2);
+  double *amdq_x = calloc(nxe * NM, sizeof(double));
+  double *apdq_x = calloc(nxe * NM, sizeof(double));
+  double *amdq_y = calloc(nye * NM, sizeof(double));
+  double *apdq_y = calloc(nye * NM, sizeof(double));
+  /* normal-direction corrections: F at (rows 0..my-1, edges 0..mx),
+   * G at (edges 0..my, columns 0..mx-1) */
+  double *Fc = calloc((size_t)my * (mx + 1) * NM, sizeof(double));
+  double *Gc = calloc((size_t)(my + 1) * mx * NM, sizeof(double));
+  /* transverse contributions, stored per cell they originate from:
+   * Gx_top/Gx_bot: from the x-fluctuations entering cell (i,j), to G~ at
+   *   (i, j+1/2) / (i, j-1/2); cells i = 0..mx-1, j = -1..my.
+   * Fy_right/Fy_left: from the y-fluctuations entering cell (i,j), to F~ at
+   *   (i+1/2, j) / (i-1/2, j); cells i = -1..mx, j = 0..my-1. */
+  double *Gx_top = calloc((size_t)(my + 2) * mx * NM, sizeof(double));
+  double *Gx_bot = calloc((size_t)(my + 2) * mx * NM, sizeof(double));
+  double *Fy_right = calloc((size_t)my * (mx + 2) * NM, sizeof(double));
+  double *Fy_left = calloc((size_t)my * (mx + 2) * NM, sizeof(double));
+  int rc = 0;
+  if (masks_out) memset(masks_out, 0, (size_t)(mx + 1) * (size_t)(my + 1));
+  if (!amdq_x || !apdq_x || !amdq_y || !apdq_y || !Fc || !Gc || !Gx_top ||
+      !Gx_bot || !Fy_right || !Fy_left) {
+    rc = -1;
+    goto done;
+  }
+
+#define AX(j, e) (((size_t)((j) + 1) * (size_t)(mx + 1) + (size_t)(e)) * NM)
+#define AY(f, i) (((size_t)(f) * (size_t)(mx + 2) + (size_t)((i) + 1)) * NM)
+#define FC(j, e) (((size_t)(j) * (size_t)(mx + 1) + (size_t)(e)) * NM)
+#define GC(f, i) (((size_t)(f) * (size_t)mx + (size_t)(i)) * NM)
+#define GX(j, i) (((size_t)((j) + 1) * (size_t)mx + (size_t)(i)) * NM)
+#define FY(j, i) (((size_t)(j) * (size_t)(mx + 2) + (size_t)((i) + 1)) * NM)
+
+  /* ---- x-direction: rows j = -1..my ---- */
+#pragma omp parallel for if (par) schedule(static)
+  for (int j = -1; j <= my; ++j) {
+    /* waves at edges e = -1..mx+1 of this row (the outer two feed the
+     * limiter only) */
+    double(*w)[NW][NM] = malloc(sizeof(double[NW][NM]) * (size_t)(mx + 3));
+    for (int e = -1; e <= mx + 1; ++e) {
+      double ql[NM], qr[NM], am[NM], ap[NM];
+      for (int m = 0; m < NM; ++m) {
+        ql[m] = q_in[QIX(m, e - 1, j)];
+        qr[m] = q_in[QIX(m, e, j)];
+      }
+      riemann(&ex, ql, qr, drop_zero_wave, w[e + 1], am, ap);
+      if (e >= 0 && e <= mx)
+        for (int m = 0; m < NM; ++m) {
+          amdq_x[AX(j, e) + m] = am[m];
+          apdq_x[AX(j, e) + m] = ap[m];
+        }
+    }
+    /* limited-wave correction flux on interior rows */
+    if (j >= 0 && j < my)
+      for (int e = 0; e <= mx; ++e) {
+        double F[NM] = {0.0, 0.0, 0.0};
+        int mask_bits = 0;
+        for (int p = 0; p < NW; ++p) {
+          const double s = ex.s[p];
+          const int up = (s > 0.0) ? e - 1 : (s < 0.0 ? e + 1 : e);
+          int fz = -1, br = 0;
+          if (frozen && s != 0.0)
+            fz = (frozen[MIX(e, j)] >> (p == 0 ? 0 : 2)) & 3;
+          double wl[NM];
+          limit_wave(limiter, w[e + 1][p], w[up + 1][p], fz, wl, &br);
+          if (s != 0.0) mask_bits |= br << (p == 0 ? 0 : 2);
+          const double coef = 0.5 * fabs(s) * (1.0 - dtdx * fabs(s));
+          for (int m = 0; m < NM; ++m) F[m] += coef * wl[m];
+        }
+        for (int m = 0; m < NM; ++m) Fc[FC(j, e) + m] = F[m];
+        if (masks_out) masks_out[MIX(e, j)] = (uint8_t)mask_bits;
+      }
+    /* transverse: A+dQ at edge e enters cell e, A-dQ enters cell e-1 */
+    for (int e = 0; e <= mx; ++e) {
+      double bm[NM], bp[NM];
+      if (e <= mx - 1) {
+        split(&ey, &apdq_x[AX(j, e)], bm, bp);
+        for (int m = 0; m < NM; ++m) {
+          Gx_top[GX(j, e) + m] -= 0.5 * dtdx * bp[m];
+          Gx_bot[GX(j, e) + m] -= 0.5 * dtdx * bm[m];
+        }
+      }
+      if (e >= 1) {
+        split(&ey, &amdq_x[AX(j, e)], bm, bp);
+        for (int m = 0; m < NM; ++m) {
+          Gx_top[GX(j, e - 1) + m] -= 0.5 * dtdx * bp[m];
+          Gx_bot[GX(j, e - 1) + m] -= 0.5 * dtdx * bm[m];
+        }
+      }
+    }
+    free(w);
+  }
+
+  /* ---- y-direction: columns i = -1..mx ---- */
+#pragma omp parallel for if (par) schedule(static)
+  for (int i = -1; i <= mx; ++i) {
+    double(*w)[NW][NM] = malloc(sizeof(double[NW][NM]) * (size_t)(my + 3));
+    for (int f = -1; f <= my + 1; ++f) {
+      double ql[NM], qr[NM], bm[NM], bp[NM];
+      for (int m = 0; m < NM; ++m) {
+        ql[m] = q_in[QIX(m, i, f - 1)];
+        qr[m] = q_in[QIX(m, i, f)];
+      }
+      riemann(&ey, ql, qr, drop_zero_wave, w[f + 1], bm, bp);
+      if (f >= 0 && f <= my)
+        for (int m = 0; m < NM; ++m) {
+          amdq_y[AY(f, i) + m] = bm[m];
+          apdq_y[AY(f, i) + m] = bp[m];
+        }
+    }
+    if (i >= 0 && i < mx)
+      for (int f = 0; f <= my; ++f) {
+        double G[NM] = {0.0, 0.0, 0.0};
+        int mask_bits = 0;
+        for (int p = 0; p < NW; ++p) {
+          const double s = ey.s[p];
+          const int up = (s > 0.0) ? f - 1 : (s < 0.0 ? f + 1 : f);
+          int fz = -1, br = 0;
+          if (frozen && s != 0.0)
+            fz = (frozen[MIX(i, f)] >> (p == 0 ? 4 : 6)) & 3;
+          double wl[NM];
+          limit_wave(limiter, w[f + 1][p], w[up + 1][p], fz, wl, &br);
+          if (s != 0.0) mask_bits |= br << (p == 0 ? 4 : 6);
+          const double coef = 0.5 * fabs(s) * (1.0 - dtdy * fabs(s));
+          for (int m = 0; m < NM; ++m) G[m] += coef * wl[m];
+        }
+        for (int m = 0; m < NM; ++m) Gc[GC(f, i) + m] = G[m];
+        /* the x-sweep wrote the low nibble of rows 0..my-1 only; this
+         * column's loop is the only writer of the high nibble */
+        if (masks_out) {
+          if (f < my) {
+            /* ordering: x-sweep finished before this parallel loop */
+            masks_out[MIX(i, f)] =
+                (uint8_t)((masks_out[MIX(i, f)] & 0x0F) | mask_bits);
+          } else {
+            masks_out[MIX(i, f)] = (uint8_t)mask_bits;
+          }
+        }
+      }
+    for (int f = 0; f <= my; ++f) {
+      double am[NM], ap[NM];
+      if (f <= my - 1) { /* B+dQ at edge f enters cell (i, f) */
+        split(&ex, &apdq_y[AY(f, i)], am, ap);
+        for (int m = 0; m < NM; ++m) {
+          Fy_right[FY(f, i) + m] -= 0.5 * dtdy * ap[m];
+          Fy_left[FY(f, i) + m] -= 0.5 * dtdy * am[m];
+        }
+      }
+      if (f >= 1) { /* B-dQ at edge f enters cell (i, f-1) */
+        split(&ex, &amdq_y[AY(f, i)], am, ap);
+        for (int m = 0; m < NM; ++m) {
+          Fy_right[FY(f - 1, i) + m] -= 0.5 * dtdy * ap[m];
+          Fy_left[FY(f - 1, i) + m] -= 0.5 * dtdy * am[m];
+        }
+      }
+    }
+    free(w);
+  }
+
+  /* ---- update, eq. (2.3) ---- */
+  if (q_out != q_in) memcpy(q_out, q_in, sizeof(double) * NM * (size_t)(mx + 4) * (size_t)(my + 4));
+#pragma omp parallel for if (par) schedule(static)
+  for (int j = 0; j < my; ++j)
+    for (int i = 0; i < mx; ++i)
+      for (int m = 0; m < NM; ++m) {
+        /* F~ at the left (i-1/2) and right (i+1/2) edges of the cell */
+        const double FL = Fc[FC(j, i) + m] + Fy_right[FY(j, i - 1) + m] + Fy_left[FY(j, i) + m];
+        const double FR = Fc[FC(j, i + 1) + m] + Fy_right[FY(j, i) + m] + Fy_left[FY(j, i + 1) + m];
+        /* G~ at the bottom (j-1/2) and top (j+1/2) edges of the cell */
+        const double GB = Gc[GC(j, i) + m] + Gx_top[GX(j - 1, i) + m] + Gx_bot[GX(j, i) + m];
+        const double GT = Gc[GC(j + 1, i) + m] + Gx_top[GX(j, i) + m] + Gx_bot[GX(j + 1, i) + m];
+        const double fluct_x = apdq_x[AX(j, i) + m] + amdq_x[AX(j, i + 1) + m];
+        const double fluct_y = apdq_y[AY(j, i) + m] + amdq_y[AY(j + 1, i) + m];
+        q_out[QIX(m, i, j)] = q_in[QIX(m, i, j)] - dtdx * fluct_x - dtdy * fluct_y -
+                              dtdx * (FR - FL) - dtdy * (GT - GB);
+      }
+
+  /* ---- Courant number, eq. (2.10), over the edges of interior cells ---- */
+  if (cfl_out) {
+    double cfl = 0.0;
+    for (int j = 0; j < my; ++j)
+      for (int e = 0; e <= mx; ++e)
+        for (int p = 0; p < NW; ++p) cfl = fmax(cfl, fabs(ex.s[p]) * dtdx);
+    for (int f = 0; f <= my; ++f)
+      for (int i = 0; i < mx; ++i)
+        for (int p = 0; p < NW; ++p) cfl = fmax(cfl, fabs(ey.s[p]) * dtdy);
+    *cfl_out = cfl;
+  }
+
+#undef AX
+#undef AY
+#undef FC
+#undef GC
+#undef GX
+#undef FY
+done:
+  free(amdq_x); free(apdq_x); free(amdq_y); free(apdq_y);
+  free(Fc); free(Gc); free(Gx_top); free(Gx_bot); free(Fy_right); free(Fy_left);
+  return rc;
+}
+
+int oracle_step(const double *q_in, double *q_out, int mx, int my, double dx,
+                double dy, double dt, double rho, double K, int limiter,
+                double *cfl_out) {
+  return oracle_step_ex(q_in, q_out, mx, my, dx, dy, dt, rho, K, limiter, 0,
+                        NULL, NULL, cfl_out, 1);
+}
+
+/* Many independent patches, one OpenMP task per patch.  Patch k lives at
+ * q_in + off[k] (doubles), dims mx[k] x my[k]; cfl_out[k] per patch. */
+int oracle_step_patches(int n, const double *q_in, double *q_out,
+                        const int64_t *off, const int *mx, const int *my,
+                        const double *dx, const double *dy, const double *dt,
+                        const double *rho, const double *K, int limiter,
+                        double *cfl_out) {
+  int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+  for (int k = 0; k < n; ++k) {
+    int r = oracle_step_ex(q_in + off[k], q_out + off[k], mx[k], my[k], dx[k],
+                           dy[k], dt[k], rho[k], K[k], limiter, 0, NULL, NULL,
+                           cfl_out ? &cfl_out[k] : NULL, 0);
+    bad |= (r != 0);
+  }
+  return bad ? -1 : 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Exported single-edge hooks, used by the oracle's own pin tests          */
+/* ---------------------------------------------------------------------- */
+/* Riemann solve at one edge in direction dir (0: x with A, 1: y with B).
+ * waves: 3x3 (wave-major), s: 3 speeds. */
+void oracle_riemann_edge(int dir, double rho, double K, const double *ql,
+                         const double *qr, double *waves, double *s,
+                         double *amdq, double *apdq) {
+  eig_t e;
+  acoustics_eig(rho, K, dir, &e);
+  double w[NW][NM];
+  riemann(&e, ql, qr, 0, w, amdq, apdq);
+  for (int p = 0; p < NW; ++p) {
+    s[p] = e.s[p];
+    for (int m = 0; m < NM; ++m) waves[p * NM + m] = w[p][m];
+  }
+}
+
+/* Transverse split of a vector by direction dir's eigen-structure. */
+void oracle_split_vec(int dir, double rho, double K, const double *a,
+                      double *minus, double *plus) {
+  eig_t e;
+  acoustics_eig(rho, K, dir, &e);
+  split(&e, a, minus, plus);
+}

@@ -1,0 +1,92 @@
+"""Planted mistakes in the oracle must trip at least one pin.
+
+Each case copies the oracle's C source, plants one plausible mistake (a
+dropped term, a wrong sign, a wrong index, a transposed operand), builds the
+copy in a temporary directory and runs the pins of ``test_oracle_pins``
+against it.  This runs on the CPU only and never touches the GPU library.
+"""
+
+import os
+
+import pytest
+
+import oracle
+import oracle.oracle as oracle_mod
+import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle_mod.__file__), "wave_oracle.c")
+
+MUTATIONS = {
+    "jump_reversed": ("dq[m] = qr[m] - ql[m];", "dq[m] = ql[m] - qr[m];"),
+    "left_eigvec_sign": ("e->L[0][0] = -1.0 / (2.0 * Z);", "e->L[0][0] = 1.0 / (2.0 * Z);"),
+    "x_limiter_upwind_side": (
+        "const int up = (s > 0.0) ? e - 1 : (s < 0.0 ? e + 1 : e);",
+        "const int up = (s > 0.0) ? e + 1 : (s < 0.0 ? e - 1 : e);"),
+    "y_limiter_upwind_side": (
+        "const int up = (s > 0.0) ? f - 1 : (s < 0.0 ? f + 1 : f);",
+        "const int up = (s > 0.0) ? f + 1 : (s < 0.0 ? f - 1 : f);"),
+    "correction_weight_sign": (
+        "const double coef = 0.5 * fabs(s) * (1.0 - dtdx * fabs(s));",
+        "const double coef = 0.5 * fabs(s) * (1.0 + dtdx * fabs(s));"),
+    "transverse_factor": (
+        "Gx_top[GX(j, e) + m] -= 0.5 * dtdx * bp[m];",
+        "Gx_top[GX(j, e) + m] -= 1.0 * dtdx * bp[m];"),
+    "transverse_swapped_parts": (
+        "Gx_bot[GX(j, e) + m] -= 0.5 * dtdx * bm[m];",
+        "Gx_bot[GX(j, e) + m] -= 0.5 * dtdx * bp[m];"),
+    "y_transverse_swapped_parts": (
+        "Fy_right[FY(f - 1, i) + m] -= 0.5 * dtdy * ap[m];",
+        "Fy_right[FY(f - 1, i) + m] -= 0.5 * dtdy * am[m];"),
+    "dropped_transverse_term": (
+        "const double FL = Fc[FC(j, i) + m] + Fy_right[FY(j, i - 1) + m] + Fy_left[FY(j, i) + m];",
+        "const double FL = Fc[FC(j, i) + m] + Fy_right[FY(j, i - 1) + m];"),
+    "flux_difference_sign": ("dtdx * (FR - FL) - dtdy * (GT - GB);",
+                             "dtdx * (FL - FR) - dtdy * (GT - GB);"),
+    "y_fluctuation_edges_swapped": (
+        "const double fluct_y = apdq_y[AY(j, i) + m] + amdq_y[AY(j + 1, i) + m];",
+        "const double fluct_y = apdq_y[AY(j + 1, i) + m] + amdq_y[AY(j, i) + m];"),
+    "cfl_wrong_spacing": ("cfl = fmax(cfl, fabs(ey.s[p]) * dtdy);",
+                          "cfl = fmax(cfl, fabs(ey.s[p]) * dtdx);"),
+    "corner_ghosts_skipped": ("for (int i = -2; i < mx + 2; ++i)", "for (int i = 0; i < mx; ++i)"),
+}
+
+# cheapest first; the first failing pin ends a mutant's run
+PIN_CALLS = [
+    ("ghosts", lambda o: pins.test_extrapolation_ghosts_take_nearest_interior(o)),
+    ("cfl", lambda o: pins.test_cfl_closed_form(o)),
+    ("riemann_x", lambda o: pins.test_riemann_solver_eigen_structure(o, 0.7, 2.3, 0)),
+    ("riemann_y", lambda o: pins.test_riemann_solver_eigen_structure(o, 0.7, 2.3, 1)),
+    ("split_x", lambda o: pins.test_transverse_split_matches_matrix_split(o, 0)),
+    ("split_y", lambda o: pins.test_transverse_split_matches_matrix_split(o, 1)),
+    ("constant", lambda o: pins.test_constant_state_is_preserved_bitwise(o)),
+    ("lax_wendroff", lambda o: pins.test_one_dimensional_reduction_lax_wendroff(o)),
+    ("upwind", lambda o: pins.test_one_dimensional_reduction_upwind(o)),
+    ("limited_1d", lambda o: pins.test_one_dimensional_reduction_limited_scheme(o, "mc")),
+    ("translation", lambda o: pins.test_plane_wave_translates_exactly_at_courant_one(o, "mc")),
+    ("symmetry", lambda o: pins.test_rotation_and_transpose_symmetry(o)),
+    ("conservation", lambda o: pins.test_conservation_periodic(o)),
+    ("second_order", lambda o: pins.test_second_order_convergence_oblique_plane_wave(o)),
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    orig, mutated = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(orig) == 1, f"mutation anchor for {name} not unique in the oracle"
+    mpath = tmp_path / "mutant.c"
+    mpath.write_text(src.replace(orig, mutated))
+    so = oracle_mod.build(str(mpath), str(tmp_path / "libmutant.so"))
+    saved = oracle_mod._lib
+    oracle_mod._lib = oracle_mod.load_lib(so)
+    caught = None
+    try:
+        for pin_name, call in PIN_CALLS:
+            try:
+                call(oracle)
+            except (AssertionError, ValueError, RuntimeError, FloatingPointError):
+                caught = pin_name
+                break
+    finally:
+        oracle_mod._lib = saved
+    assert caught is not None, f"planted mistake {name!r} passed every pin"
