@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of the fused unsplit acoustics step on one MI355X.
+
+Workload (the bandwidth-roofline configuration): one 2048x2048 patch, rho=1,
+K=4, radial ring pulse, extrapolation boundaries, MC limiter, FP64; every step
+is one persistent level launch plus the device-side Courant-number reduction
+and dt update (CFL 0.9), the whole step loop captured as one hipGraph.  A
+"step" is one pass of that whole hot path over the grid.
+
+Printed as ONE JSON line.  Extra objects: the FP32 variant of the same run,
+the synthetic AMR level batch (batched persistent launch vs one launch per
+patch, FP64 and FP32), conservation sums, the roofline of the step kernel and
+the oracle's throughput on the host cores (cpu_baseline).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+METRIC = "Gcell-updates/s and % HBM peak, batched-AMR vs per-patch launch, FP64 1e-12"
+RHO, K_BULK = 1.0, 4.0
+C_SOUND = math.sqrt(K_BULK / RHO)
+
+
+def algorithmic_bytes(shapes, elem_bytes, physical_bc):
+    """Bytes one step must move: every padded cell read once, every interior
+    cell written once, and on physical boundaries the ghost ring written."""
+    total = 0
+    for mx, my in shapes:
+        padded = (mx + 4) * (my + 4)
+        total += 3 * elem_bytes * (padded + mx * my)
+        if physical_bc:
+            total += 3 * elem_bytes * (padded - mx * my)
+    return total
+
+
+def run_uniform(ws, torch, n, steps, warmup, dtype, kernel_launches):
+    import workloads
+
+    dx = 1.0 / n
+    q0 = workloads.padded_state(n, n, 0.0, 0.0, dx, dx)
+    lev = ws.Level([dict(mx=n, my=n, dx=dx, dy=dx, bc="extrap")], [(RHO, K_BULK)], dtype=dtype)
+    dt0 = 0.9 * dx / C_SOUND
+
+    def reset():
+        lev.upload(0, q0)
+        lev.fill_ghosts()
+        lev.set_dt([dt0])
+
+    reset()
+    for _ in range(warmup):
+        lev.step_auto(0.9)
+    torch.cuda.synchronize()
+    reset()
+    lev.capture(steps, 0.9)
+    sums0 = lev.conservation_sums()[0]
+    stream = lev.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    lev.graph_launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    sums1 = lev.conservation_sums()[0]
+    _dt, cfl_last, cfl_max = lev.read_dt_cfl()
+    q = lev.download(0)
+    finite = bool(torch.isfinite(torch.from_numpy(q)).all())
+    # the step kernel alone, back to back (HIP events on the same stream)
+    kernel_ms = lev.time_step_kernel(kernel_launches)
+    lev.close()
+    return dict(ms=ms, wall_s=wall, sums0=sums0.tolist(), sums1=sums1.tolist(),
+                cfl_last=float(cfl_last[0]), cfl_max=float(cfl_max[0]), finite=finite,
+                kernel_ms=kernel_ms)
+
+
+def run_amr(ws, torch, dtype, level_steps):
+    import workloads
+
+    levels = workloads.amr_level_batch()
+    out = {"levels": [], "n_patches": sum(len(l) for l in levels)}
+    tot_cells = 0
+    tb = tp = 0.0
+    for specs in levels:
+        lev = ws.Level([dict(mx=p.mx, my=p.my, dx=p.dx, dy=p.dy) for p in specs], [(RHO, K_BULK)],
+                       dtype=dtype)
+        for k, p in enumerate(specs):
+            lev.upload(k, workloads.padded_state(p.mx, p.my, p.xlo, p.ylo, p.dx, p.dy))
+        lev.set_dt([0.9 * specs[0].dx / C_SOUND])
+        lev.time_step_kernel(2)
+        lev.time_step_kernel(2, per_patch=True)
+        ms_b = lev.time_step_kernel(level_steps)
+        ms_p = lev.time_step_kernel(level_steps, per_patch=True)
+        cells = sum(p.mx * p.my for p in specs)
+        tot_cells += cells
+        tb += ms_b
+        tp += ms_p
+        out["levels"].append(dict(patches=len(specs), cells=cells,
+                                  batched_gcells=cells / ms_b / 1e6,
+                                  per_patch_gcells=cells / ms_p / 1e6))
+        lev.close()
+    out["batched_gcells"] = tot_cells / tb / 1e6
+    out["per_patch_gcells"] = tot_cells / tp / 1e6
+    out["speedup"] = tp / tb
+    out["cells_per_level_step"] = tot_cells
+    return out
+
+
+def cpu_baseline(n, target_s):
+    import numpy as np  # noqa: F401
+
+    import oracle
+    import workloads
+
+    dx = 1.0 / n
+    q = workloads.padded_state(n, n, 0.0, 0.0, dx, dx)
+    oracle.fill_bc(q, "extrap")
+    dt = 0.9 * dx / C_SOUND
+    t = time.perf_counter()
+    q1, _, _ = oracle.step(q, dx, dx, dt, RHO, K_BULK, "mc")
+    one = time.perf_counter() - t
+    steps = max(1, int(target_s / max(one, 1e-3)))
+    t = time.perf_counter()
+    for _ in range(steps):
+        q1, _, _ = oracle.step(q1, dx, dx, dt, RHO, K_BULK, "mc")
+        oracle.fill_bc(q1, "extrap")
+    el = time.perf_counter() - t
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    return {"value": n * n * steps / el / 1e9, "unit": "Gcell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} oracle steps of the {n}x{n} FP64 grid ({el:.1f} s, OpenMP)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--kernel-launches", type=int, default=200)
+    ap.add_argument("--amr-steps", type=int, default=10)
+    ap.add_argument("--no-extras", action="store_true", help="skip FP32, AMR and CPU legs")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the level step is benchmarked at its single-GPU shape)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1808_02638_amd as ws
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n, K = args.n, args.steps
+    shapes = [(n, n)]
+    r64 = run_uniform(ws, torch, n, K, args.warmup, torch.float64, args.kernel_launches)
+    value = n * n * K / (r64["ms"] / 1e3) / 1e9
+    bytes64 = algorithmic_bytes(shapes, 8, True)
+    achieved = bytes64 / (r64["kernel_ms"] / 1e3) / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms"] / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"uniform {n}x{n} 2D acoustics, radial ring pulse, rho=1 K=4, "
+                               f"extrapolation BCs, MC limiter, CFL 0.9 with the device "
+                               f"max-speed reduction and dt update every step, {K} steps "
+                               f"in one hipGraph",
+                   "cells": n * n, "global_batch": 1, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "step_kernel<double, MC>",
+                     "bytes_per_launch": bytes64, "kernel_ms": r64["kernel_ms"]},
+        "pct_hbm_peak": round(100 * achieved / HBM_PEAK_GBS, 2),
+        "conservation_fp64": {"start": r64["sums0"], "end": r64["sums1"]},
+        "cfl_max": r64["cfl_max"],
+        "finite": r64["finite"],
+    }
+    if not args.no_extras:
+        r32 = run_uniform(ws, torch, n, K, args.warmup, torch.float32, args.kernel_launches)
+        b32 = algorithmic_bytes(shapes, 4, True)
+        a32 = b32 / (r32["kernel_ms"] / 1e3) / 1e9
+        line["fp32"] = {"value": round(n * n * K / (r32["ms"] / 1e3) / 1e9, 3),
+                        "ms_per_step": r32["ms"] / K,
+                        "kernel_GBs": round(a32, 1), "frac": round(a32 / HBM_PEAK_GBS, 4)}
+        line["amr_level_batch"] = {"fp64": run_amr(ws, torch, torch.float64, args.amr_steps),
+                                   "fp32": run_amr(ws, torch, torch.float32, args.amr_steps)}
+        line["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/*
+ * wavestep.h -- C ABI of the MI355X (gfx950) library that advances 2D linear
+ * acoustics with the dimensionally unsplit wave-propagation method, one AMR
+ * level (a set of ghost-padded rectangular patches) at a time.
+ *
+ * What is computed (Qin, LeVeque & Motley, arXiv 1808.02638):
+ *   - the update of paper Sec. 2.1 eq. (2.3): for every interior cell,
+ *     Q^{n+1} = Q - dt/dx (A+dQ_{i-1/2} + A-dQ_{i+1/2})
+ *                 - dt/dy (B+dQ_{j-1/2} + B-dQ_{j+1/2})
+ *                 - dt/dx (F~_{i+1/2} - F~_{i-1/2}) - dt/dy (G~_{j+1/2} - G~_{j-1/2}),
+ *     with F~, G~ holding the MC-limited wave corrections and the transverse
+ *     waves split from the first-order fluctuations (Sec. 2.1, Sec. 3.3);
+ *   - for q = (p, u, v) and the matrices A, B of Sec. 4.1 eqs. (4.1)-(4.2)
+ *     (wave speeds -c, 0, +c with c = sqrt(K/rho));
+ *   - the Courant number of Sec. 2.4 eq. (2.10), max over the level's edges of
+ *     |s| dt/dx, reduced over all patches on the device (Sec. 3.2.2), and the
+ *     time-step rule dt = nu dt_old / cfl_old of Sec. 2.5 eq. (2.11);
+ *   - physical boundaries through the two ghost layers (Sec. 2.2 item 1):
+ *     zero-order extrapolation (the outflow condition of Sec. 4.1) or periodic.
+ *
+ * Conventions
+ *   - Every function returns WS_OK (0) or a negative WS_E* code; the message
+ *     of the last failure on the calling thread is in ws_last_error().  No
+ *     function aborts and no C++ exception crosses this boundary.
+ *   - The CALLER OWNS ALL DEVICE MEMORY AND THE STREAM: the two q pools and
+ *     the workspace are device allocations the caller makes with the sizes
+ *     ws_layout() returns and keeps alive until ws_destroy().  The context
+ *     owns only host metadata, one small pinned host buffer and graph handles.
+ *     A context is not thread-safe; all work is enqueued on the caller's
+ *     stream given at init.
+ *   - "Host layout" of one patch is dense [3][my+4][mx+4] in the context's
+ *     dtype: components p, u, v; two ghost layers per side; x fastest.  The
+ *     device layout inside a pool is private (padded, aligned rows).
+ *   - Patches of one context may differ in size, cell size and material
+ *     (instance); one context is one AMR level or one ensemble.
+ */
+#ifndef WAVESTEP_H
+#define WAVESTEP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WS_OK 0
+#define WS_EINVAL (-1)  /* bad argument (sizes, indices, null pointers)      */
+#define WS_ESTATE (-2)  /* call not valid in the context's current state      */
+#define WS_EHIP (-3)    /* a HIP runtime call failed (message names it)      */
+#define WS_ENOMEM (-4)  /* caller-provided pool or workspace too small        */
+
+enum { WS_F64 = 0, WS_F32 = 1 };          /* arithmetic and storage type   */
+enum { WS_LIM_MC = 0, WS_LIM_NONE = 1 };  /* MC limiter / no limiter (phi=1) */
+enum { WS_BC_NONE = 0, WS_BC_EXTRAP = 1, WS_BC_PERIODIC = 2 };
+
+typedef struct ws_ctx ws_ctx;
+
+/* One patch.  bc = WS_BC_NONE: ghosts are input (uploaded, kept frozen);
+ * WS_BC_EXTRAP / WS_BC_PERIODIC: all four sides are physical boundaries whose
+ * ghosts the step rewrites from the new interior.  Periodic needs mx, my >= 2. */
+typedef struct {
+  int32_t mx, my;   /* interior cells, >= 1                          */
+  double dx, dy;    /* cell sizes, > 0                               */
+  int32_t instance; /* index into the material and dt arrays         */
+  int32_t bc;       /* WS_BC_*                                       */
+} ws_patch_desc;
+
+/* Medium of one instance: c = sqrt(K/rho), impedance Z = rho c. */
+typedef struct {
+  double rho, K;
+} ws_material;
+
+/* Sizes the caller must allocate: each of the two q pools (bytes) and the
+ * workspace (bytes).  Either output pointer may be NULL. */
+int ws_layout(const ws_patch_desc *patches, int32_t n_patches, int32_t n_instances,
+              int32_t dtype, int64_t *pool_bytes, int64_t *ws_bytes);
+
+/* Create a context over caller-owned device memory.  mbc must be 2.
+ * q_pool_a / q_pool_b: device buffers of >= pool_bytes; the level's state
+ * lives in pool A first and ping-pongs.  workspace: device buffer of >=
+ * ws_bytes (patch table, tile list, CFL slots, dt, counters, sums).
+ * hip_stream: the hipStream_t all work is enqueued on (NULL = null stream).
+ * Uploads the patch table and tile list and synchronises the stream. */
+int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patches,
+                    const ws_material *mats, int32_t n_instances, int32_t mbc,
+                    int32_t dtype, int32_t limiter, void *q_pool_a, void *q_pool_b,
+                    int64_t pool_bytes, void *workspace, int64_t ws_bytes,
+                    void *hip_stream);
+
+/* Tile shape per patch (arrays of n_patches; NULL keeps the default) and
+ * workgroups per CU of the persistent launch (0 keeps the default).  A tile is
+ * tile_w x tile_h cells worked by 256 threads: tile_w in {8,16,32,64,128,256},
+ * tile_h a multiple of 256/tile_w with tile_h*tile_w/256 <= 32.  Results do
+ * not depend on the tiling (bitwise).  Invalidates a captured graph. */
+int ws_set_tiling(ws_ctx *ctx, const int32_t *tile_w, const int32_t *tile_h,
+                  int32_t wg_per_cu);
+
+/* Copy one patch, host layout, into BOTH pools (ghosts included).  src may be
+ * a host or a device pointer.  Synchronises the stream. */
+int ws_upload_patch(ws_ctx *ctx, int32_t patch, const void *src);
+
+/* Copy one patch of the current state, host layout, to dst (host or device).
+ * Synchronises the stream. */
+int ws_download_patch(ws_ctx *ctx, int32_t patch, void *dst);
+
+/* Rewrite the physical-boundary ghosts of the current state from its interior
+ * (patches with bc != WS_BC_NONE).  Asynchronous. */
+int ws_fill_ghosts(ws_ctx *ctx);
+
+/* One step of every patch with the same dt, in ONE persistent launch over the
+ * level's tile list.  Writes the other pool's interior (and physical ghosts),
+ * then makes it current.  *cfl_out (may be NULL) receives the level's Courant
+ * number max |s| dt/dx over all edges, reduced in FP64 on the device; this
+ * call synchronises the stream to return it.  dt is not checked against the
+ * CFL limit: a caller may reject cfl > 1 and redo the step from a saved state. */
+int ws_step_level(ws_ctx *ctx, double dt, double *cfl_out);
+
+/* The same step as one launch PER PATCH (the per-patch baseline).  Identical
+ * arithmetic; the result is bitwise equal to ws_step_level's. */
+int ws_step_level_per_patch(ws_ctx *ctx, double dt, double *cfl_out);
+
+/* Set the device-resident time step of every instance (n_instances values). */
+int ws_set_dt(ws_ctx *ctx, const double *dt_per_instance);
+
+/* One step with the device-resident per-instance dt, followed by the dt update
+ * dt <- dt * cfl_desired / cfl of each instance.  Asynchronous (no host read). */
+int ws_step_auto(ws_ctx *ctx, double cfl_desired);
+
+/* Capture n_steps of ws_step_auto in a hipGraph (replacing any previous one).
+ * Needs n_steps >= 1. */
+int ws_capture_steps(ws_ctx *ctx, int32_t n_steps, double cfl_desired);
+
+/* Launch the captured graph on the context's stream.  Asynchronous. */
+int ws_graph_launch(ws_ctx *ctx);
+
+/* Per instance: current dt, Courant number of the last step and the largest
+ * Courant number seen since the last ws_set_dt (any pointer may be NULL).
+ * Synchronises the stream. */
+int ws_read_dt_cfl(ws_ctx *ctx, double *dt, double *cfl_last, double *cfl_max);
+
+/* Per patch: Courant number of the last step.  Synchronises the stream. */
+int ws_read_patch_cfl(ws_ctx *ctx, double *cfl);
+
+/* Conservation sums of the current state: for every instance, the sums of
+ * p dx dy, u dx dy, v dx dy over its interior cells ([n_instances][3]),
+ * accumulated in FP64 in a fixed order (deterministic for a fixed tiling).
+ * Synchronises the stream. */
+int ws_conservation_sums(ws_ctx *ctx, double *sums);
+
+/* Timing entry (for the benchmark and the tile autotuner): enqueue n_launches
+ * step kernels back to back (batched persistent launch, or per_patch != 0:
+ * one launch per patch per step) with the device-resident dt and no dt
+ * update, bracketed by HIP events on the context's stream; returns the mean
+ * milliseconds per level step.  The state advances n_launches steps.
+ * Synchronises the stream. */
+int ws_time_step_kernel(ws_ctx *ctx, int32_t n_launches, int32_t per_patch,
+                        double *ms_per_step);
+
+/* Index (0 = A, 1 = B) of the pool holding the current state. */
+int ws_current_pool(ws_ctx *ctx, int32_t *which);
+
+int ws_destroy(ws_ctx *ctx);
+const char *ws_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WAVESTEP_H */

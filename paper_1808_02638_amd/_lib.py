@@ -1,0 +1,98 @@
+"""ctypes declarations of the C ABI in ``include/wavestep.h``.
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``libwavestep.so``.  Importing this module does not touch the GPU; loading the
+library fails loudly when it has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwavestep.so")
+
+WS_OK, WS_EINVAL, WS_ESTATE, WS_EHIP, WS_ENOMEM = 0, -1, -2, -3, -4
+WS_F64, WS_F32 = 0, 1
+WS_LIM_MC, WS_LIM_NONE = 0, 1
+WS_BC_NONE, WS_BC_EXTRAP, WS_BC_PERIODIC = 0, 1, 2
+
+#: every symbol the header declares
+EXPORTS = (
+    "ws_layout", "ws_init_patches", "ws_set_tiling", "ws_upload_patch", "ws_download_patch",
+    "ws_fill_ghosts", "ws_step_level", "ws_step_level_per_patch", "ws_set_dt", "ws_step_auto",
+    "ws_capture_steps", "ws_graph_launch", "ws_read_dt_cfl", "ws_read_patch_cfl",
+    "ws_conservation_sums", "ws_time_step_kernel", "ws_current_pool", "ws_destroy",
+    "ws_last_error",
+)
+
+
+class PatchDesc(ctypes.Structure):
+    _fields_ = [
+        ("mx", ctypes.c_int32), ("my", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+        ("instance", ctypes.c_int32), ("bc", ctypes.c_int32),
+    ]
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_double), ("K", ctypes.c_double)]
+
+
+class WaveStepError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"wavestep error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libwavestep.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it first (python -m paper_1808_02638_amd.build_lib "
+            "or __graft_entry__.build()); there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "ws_layout": [P(PatchDesc), i32, i32, i32, P(i64), P(i64)],
+        "ws_init_patches": [P(vp), P(PatchDesc), i32, P(Material), i32, i32, i32, i32,
+                            vp, vp, i64, vp, i64, vp],
+        "ws_set_tiling": [vp, P(i32), P(i32), i32],
+        "ws_upload_patch": [vp, i32, vp],
+        "ws_download_patch": [vp, i32, vp],
+        "ws_fill_ghosts": [vp],
+        "ws_step_level": [vp, dbl, P(dbl)],
+        "ws_step_level_per_patch": [vp, dbl, P(dbl)],
+        "ws_set_dt": [vp, P(dbl)],
+        "ws_step_auto": [vp, dbl],
+        "ws_capture_steps": [vp, i32, dbl],
+        "ws_graph_launch": [vp],
+        "ws_read_dt_cfl": [vp, P(dbl), P(dbl), P(dbl)],
+        "ws_read_patch_cfl": [vp, P(dbl)],
+        "ws_conservation_sums": [vp, P(dbl)],
+        "ws_time_step_kernel": [vp, i32, i32, P(dbl)],
+        "ws_current_pool": [vp, P(i32)],
+        "ws_destroy": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.ws_last_error.argtypes = []
+    L.ws_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def check(rc):
+    if rc != WS_OK:
+        raise WaveStepError(rc, lib().ws_last_error().decode(errors="replace"))
+    return rc

@@ -1,0 +1,629 @@
+// Host runtime of the wave-propagation library: the C ABI declared in
+// include/wavestep.h.  It owns host metadata only; device memory and the
+// stream belong to the caller.
+//
+// Level batching (after the paper's kernel merging, Sec. 3.1.3, and its
+// largest-first patch order): every patch is cut into tiles, the tiles of all
+// patches go into one device tile list ordered by patch size (largest patch
+// first), and one persistent launch pulls tiles from an atomic counter.  The
+// per-patch baseline launches the same kernel once per patch.  The paper's
+// per-patch maximum-speed array (Sec. 3.2.2) is kept, and the level-wide
+// maximum is also reduced on the device, so dt can be updated there too.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/wavestep.h"
+#include "ws_internal.h"
+
+using namespace ws;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(WS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+constexpr int kTileWidths[] = {8, 16, 32, 64, 128, 256};
+
+struct PoolLayout {
+  std::vector<int64_t> off;  // element offsets
+  std::vector<int32_t> ld, col0;
+  std::vector<int64_t> plane;
+  int64_t elems = 0;
+};
+
+// Device layout of the q pools: per patch three planes of (my+4) rows of ld
+// elements.  Wide patches align interior column 0 to 128 bytes; every patch
+// starts on a 256-byte boundary.
+PoolLayout pool_layout(const ws_patch_desc *p, int n, int dtype) {
+  PoolLayout L;
+  const int64_t es = dtype == WS_F32 ? 4 : 8;
+  const int64_t al = 128 / es;
+  int64_t cur = 0;
+  for (int k = 0; k < n; ++k) {
+    int32_t col0, ld;
+    if (p[k].mx >= 8 * al) {
+      col0 = (int32_t)al;
+      ld = (int32_t)round_up(col0 + p[k].mx + 2, al);
+    } else {
+      col0 = 2;
+      ld = (int32_t)round_up(p[k].mx + 4, 4);
+    }
+    const int64_t plane = (int64_t)ld * (p[k].my + 4);
+    cur = round_up(cur, 256 / es);
+    L.off.push_back(cur);
+    L.ld.push_back(ld);
+    L.col0.push_back(col0);
+    L.plane.push_back(plane);
+    cur += 3 * plane;
+  }
+  L.elems = round_up(cur, 256 / es);
+  return L;
+}
+
+int64_t tiles_of(int mx, int my, int tw, int th) {
+  return (int64_t)((mx + tw - 1) / tw) * ((my + th - 1) / th);
+}
+
+int64_t max_tiles_of(const ws_patch_desc *p, int n) {
+  int64_t t = 0;
+  for (int k = 0; k < n; ++k) {
+    int64_t m = 0;
+    for (int tw : kTileWidths) m = std::max(m, tiles_of(p[k].mx, p[k].my, tw, kThreads / tw));
+    t += m;
+  }
+  return t;
+}
+
+WsLayout ws_layout_of(const ws_patch_desc *p, int n, int n_inst) {
+  WsLayout L{};
+  int64_t cur = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t o = cur;
+    cur = round_up(cur + std::max<int64_t>(bytes, 8), 256);
+    return o;
+  };
+  L.max_tiles = max_tiles_of(p, n);
+  L.patches = take((int64_t)n * sizeof(PatchRow));
+  L.inst = take((int64_t)n_inst * sizeof(InstRow));
+  L.tiles = take(L.max_tiles * (int64_t)sizeof(TileEntry));
+  L.dt = take(8LL * n_inst);
+  L.cfl_acc = take(8LL * n_inst);
+  L.cfl_last = take(8LL * n_inst);
+  L.cfl_max = take(8LL * n_inst);
+  L.cfl_patch_acc = take(8LL * n);
+  L.cfl_patch_last = take(8LL * n);
+  L.level_acc = take(8);
+  L.level_last = take(8);
+  L.counters = take(16);
+  L.partials = take(24 * L.max_tiles);
+  L.sums = take(24LL * n_inst);
+  L.total = cur;
+  return L;
+}
+
+bool valid_tile(int tw, int th) {
+  bool ok_w = false;
+  for (int w : kTileWidths) ok_w |= (w == tw);
+  if (!ok_w) return false;
+  const int nty = kThreads / tw;
+  return th >= nty && th % nty == 0 && th / nty <= kMaxRowsPerThread;
+}
+
+// Default tile: the width in {8..64} (256 for very wide patches) that wastes
+// the fewest columns, larger on ties; up to 8 rows per thread.
+void default_tile(int mx, int my, int *tw, int *th) {
+  int best = 64;
+  if (mx >= 256) {
+    best = 64;
+  } else {
+    int64_t best_waste = -1;
+    for (int w : {64, 32, 16, 8}) {
+      const int64_t waste = (int64_t)((mx + w - 1) / w) * w - mx;
+      if (best_waste < 0 || waste < best_waste) {
+        best_waste = waste;
+        best = w;
+      }
+    }
+  }
+  const int nty = kThreads / best;
+  int r = (my + nty - 1) / nty;
+  r = std::max(1, std::min(r, 8));
+  *tw = best;
+  *th = nty * r;
+}
+
+int check_desc(const ws_patch_desc *p, int n, int n_inst) {
+  if (n < 1 || !p) return fail(WS_EINVAL, "need at least one patch");
+  if (n_inst < 1) return fail(WS_EINVAL, "need at least one instance");
+  for (int k = 0; k < n; ++k) {
+    const ws_patch_desc &d = p[k];
+    if (d.mx < 1 || d.my < 1) return fail(WS_EINVAL, "patch %d: mx, my must be >= 1", k);
+    if (d.mx > 65535 * 8 || d.my > 1000000)
+      return fail(WS_EINVAL, "patch %d: too large", k);
+    if (!(d.dx > 0.0) || !(d.dy > 0.0) || !std::isfinite(d.dx) || !std::isfinite(d.dy))
+      return fail(WS_EINVAL, "patch %d: dx, dy must be finite and > 0", k);
+    if (d.instance < 0 || d.instance >= n_inst)
+      return fail(WS_EINVAL, "patch %d: instance %d out of range", k, d.instance);
+    if (d.bc != WS_BC_NONE && d.bc != WS_BC_EXTRAP && d.bc != WS_BC_PERIODIC)
+      return fail(WS_EINVAL, "patch %d: unknown bc %d", k, d.bc);
+    if (d.bc == WS_BC_PERIODIC && (d.mx < 2 || d.my < 2))
+      return fail(WS_EINVAL, "patch %d: periodic needs mx, my >= 2", k);
+  }
+  return WS_OK;
+}
+
+}  // namespace
+
+struct ws_ctx {
+  int dtype = WS_F64, limiter = WS_LIM_MC;
+  int n_patches = 0, n_inst = 0;
+  hipStream_t stream = nullptr;
+  void *pool[2] = {nullptr, nullptr};
+  int cur = 0;
+  int64_t pool_bytes = 0;
+  char *ws = nullptr;
+  WsLayout L{};
+  PoolLayout P;
+  std::vector<ws_patch_desc> desc;
+  std::vector<PatchRow> rows;
+  std::vector<TileEntry> tiles;
+  std::vector<int> order;  // patches largest first
+  int n_cu = 0, wg_per_cu = 0, grid = 0, occupancy = 0;
+  int max_padded_cells = 0;
+  double *host_buf = nullptr;
+  int64_t host_buf_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_steps = 0, graph_start_pool = 0;
+
+  CflSlots slots() {
+    CflSlots c;
+    c.dt = reinterpret_cast<double *>(ws + L.dt);
+    c.cfl_acc = reinterpret_cast<unsigned long long *>(ws + L.cfl_acc);
+    c.cfl_last = reinterpret_cast<double *>(ws + L.cfl_last);
+    c.cfl_max = reinterpret_cast<double *>(ws + L.cfl_max);
+    c.cfl_patch_acc = reinterpret_cast<unsigned long long *>(ws + L.cfl_patch_acc);
+    c.cfl_patch_last = reinterpret_cast<double *>(ws + L.cfl_patch_last);
+    c.level_acc = reinterpret_cast<unsigned long long *>(ws + L.level_acc);
+    c.level_last = reinterpret_cast<double *>(ws + L.level_last);
+    c.n_inst = n_inst;
+    c.n_patches = n_patches;
+    return c;
+  }
+  const PatchRow *d_patches() const { return reinterpret_cast<const PatchRow *>(ws + L.patches); }
+  const TileEntry *d_tiles() const { return reinterpret_cast<const TileEntry *>(ws + L.tiles); }
+
+  StepArgs step_args(int src) {
+    CflSlots c = slots();
+    StepArgs a{};
+    a.patches = d_patches();
+    a.tiles = d_tiles();
+    a.n_tiles = (int32_t)tiles.size();
+    a.tile_base = 0;
+    a.persistent = 1;
+    a.qin = pool[src];
+    a.qout = pool[1 - src];
+    a.inst = reinterpret_cast<const InstRow *>(ws + L.inst);
+    a.dt = c.dt;
+    a.cfl_acc = c.cfl_acc;
+    a.cfl_patch = c.cfl_patch_acc;
+    a.cfl_level = c.level_acc;
+    a.counters = reinterpret_cast<unsigned int *>(ws + L.counters);
+    a.masks = nullptr;
+    return a;
+  }
+
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    graph_steps = 0;
+  }
+
+  // Tile list: patches largest first, each patch's tiles row by row.
+  int build_tiles() {
+    tiles.clear();
+    for (int k : order) {
+      PatchRow &r = rows[k];
+      r.ntx = (r.mx + r.tw - 1) / r.tw;
+      r.nty = (r.my + r.th - 1) / r.th;
+      r.tile_begin = (int32_t)tiles.size();
+      for (int ty = 0; ty < r.nty; ++ty)
+        for (int tx = 0; tx < r.ntx; ++tx) tiles.push_back(TileEntry{k, (uint16_t)tx, (uint16_t)ty});
+      r.n_tiles = (int32_t)tiles.size() - r.tile_begin;
+    }
+    if ((int64_t)tiles.size() > L.max_tiles) return fail(WS_EINVAL, "tile list overflow");
+    HIPCHK(hipMemcpyAsync(ws + L.patches, rows.data(), rows.size() * sizeof(PatchRow),
+                          hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(ws + L.tiles, tiles.data(), tiles.size() * sizeof(TileEntry),
+                          hipMemcpyHostToDevice, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    grid = (int)std::min<int64_t>((int64_t)n_cu * wg_per_cu, (int64_t)tiles.size());
+    return WS_OK;
+  }
+};
+
+extern "C" {
+
+const char *ws_last_error(void) { return g_err.c_str(); }
+
+int ws_layout(const ws_patch_desc *patches, int32_t n_patches, int32_t n_instances, int32_t dtype,
+              int64_t *pool_bytes, int64_t *ws_bytes) {
+  if (dtype != WS_F64 && dtype != WS_F32) return fail(WS_EINVAL, "unknown dtype %d", dtype);
+  if (int rc = check_desc(patches, n_patches, n_instances)) return rc;
+  const PoolLayout P = pool_layout(patches, n_patches, dtype);
+  const WsLayout L = ws_layout_of(patches, n_patches, n_instances);
+  if (pool_bytes) *pool_bytes = P.elems * (dtype == WS_F32 ? 4 : 8);
+  if (ws_bytes) *ws_bytes = L.total;
+  return WS_OK;
+}
+
+int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patches,
+                    const ws_material *mats, int32_t n_instances, int32_t mbc, int32_t dtype,
+                    int32_t limiter, void *q_pool_a, void *q_pool_b, int64_t pool_bytes,
+                    void *workspace, int64_t ws_bytes, void *hip_stream) {
+  if (!out) return fail(WS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (mbc != 2) return fail(WS_EINVAL, "mbc must be 2 (got %d)", mbc);
+  if (dtype != WS_F64 && dtype != WS_F32) return fail(WS_EINVAL, "unknown dtype %d", dtype);
+  if (limiter != WS_LIM_MC && limiter != WS_LIM_NONE)
+    return fail(WS_EINVAL, "unknown limiter %d", limiter);
+  if (int rc = check_desc(patches, n_patches, n_instances)) return rc;
+  if (!mats) return fail(WS_EINVAL, "materials are NULL");
+  for (int k = 0; k < n_instances; ++k)
+    if (!(mats[k].rho > 0.0) || !(mats[k].K > 0.0) || !std::isfinite(mats[k].rho) ||
+        !std::isfinite(mats[k].K))
+      return fail(WS_EINVAL, "instance %d: rho and K must be finite and > 0", k);
+  if (!q_pool_a || !q_pool_b || !workspace) return fail(WS_EINVAL, "pool or workspace is NULL");
+  if (q_pool_a == q_pool_b) return fail(WS_EINVAL, "the two pools must differ");
+  int64_t need_pool = 0, need_ws = 0;
+  ws_layout(patches, n_patches, n_instances, dtype, &need_pool, &need_ws);
+  if (pool_bytes < need_pool)
+    return fail(WS_ENOMEM, "pool too small: %lld < %lld bytes", (long long)pool_bytes,
+                (long long)need_pool);
+  if (ws_bytes < need_ws)
+    return fail(WS_ENOMEM, "workspace too small: %lld < %lld bytes", (long long)ws_bytes,
+                (long long)need_ws);
+
+  ws_ctx *c = new ws_ctx();
+  c->dtype = dtype;
+  c->limiter = limiter;
+  c->n_patches = n_patches;
+  c->n_inst = n_instances;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->pool[0] = q_pool_a;
+  c->pool[1] = q_pool_b;
+  c->pool_bytes = pool_bytes;
+  c->ws = reinterpret_cast<char *>(workspace);
+  c->L = ws_layout_of(patches, n_patches, n_instances);
+  c->P = pool_layout(patches, n_patches, dtype);
+  c->desc.assign(patches, patches + n_patches);
+
+  int dev = 0;
+  auto bail = [&](int rc) {
+    delete c;
+    return rc;
+  };
+  if (hipGetDevice(&dev) != hipSuccess) return bail(fail(WS_EHIP, "hipGetDevice failed"));
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return bail(fail(WS_EHIP, "cannot query the CU count"));
+  if (step_occupancy(dtype, limiter, &c->occupancy) != 0 || c->occupancy < 1) c->occupancy = 1;
+  c->wg_per_cu = c->occupancy;
+
+  std::vector<InstRow> inst(n_instances);
+  for (int k = 0; k < n_instances; ++k) {
+    inst[k].c = std::sqrt(mats[k].K / mats[k].rho);
+    inst[k].Z = mats[k].rho * inst[k].c;
+  }
+  c->rows.resize(n_patches);
+  int64_t mask_off = 0;
+  for (int k = 0; k < n_patches; ++k) {
+    PatchRow &r = c->rows[k];
+    const ws_patch_desc &d = patches[k];
+    r.q_off = c->P.off[k];
+    r.mx = d.mx;
+    r.my = d.my;
+    r.ld = c->P.ld[k];
+    r.col0 = c->P.col0[k];
+    r.plane = c->P.plane[k];
+    r.inst = d.instance;
+    r.bc = d.bc;
+    default_tile(d.mx, d.my, &r.tw, &r.th);
+    r.dx = d.dx;
+    r.dy = d.dy;
+    r.mask_off = mask_off;
+    mask_off += (int64_t)(d.mx + 1) * (d.my + 1);
+    c->max_padded_cells = std::max(c->max_padded_cells, (d.mx + 4) * (d.my + 4));
+  }
+  c->order.resize(n_patches);
+  std::iota(c->order.begin(), c->order.end(), 0);
+  std::stable_sort(c->order.begin(), c->order.end(), [&](int a, int b) {
+    return (int64_t)patches[a].mx * patches[a].my > (int64_t)patches[b].mx * patches[b].my;
+  });
+
+  c->host_buf_bytes = std::max<int64_t>(4096, 8LL * 3 * std::max(n_instances, n_patches));
+  if (hipHostMalloc(reinterpret_cast<void **>(&c->host_buf), c->host_buf_bytes) != hipSuccess)
+    return bail(fail(WS_EHIP, "hipHostMalloc of %lld bytes failed", (long long)c->host_buf_bytes));
+  // clear the bookkeeping slots, then fill the tables
+  if (hipMemsetAsync(c->ws + c->L.dt, 0, c->L.partials - c->L.dt, c->stream) != hipSuccess)
+    return bail(fail(WS_EHIP, "clearing the workspace failed"));
+  if (hipMemcpyAsync(c->ws + c->L.inst, inst.data(), inst.size() * sizeof(InstRow),
+                     hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return bail(fail(WS_EHIP, "uploading the instance table failed"));
+  if (int rc = c->build_tiles()) return bail(rc);
+  *out = c;
+  return WS_OK;
+}
+
+int ws_set_tiling(ws_ctx *c, const int32_t *tile_w, const int32_t *tile_h, int32_t wg_per_cu) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if ((tile_w == nullptr) != (tile_h == nullptr))
+    return fail(WS_EINVAL, "give both tile_w and tile_h, or neither");
+  if (wg_per_cu < 0 || wg_per_cu > 64) return fail(WS_EINVAL, "wg_per_cu out of range");
+  if (tile_w)
+    for (int k = 0; k < c->n_patches; ++k)
+      if (!valid_tile(tile_w[k], tile_h[k]))
+        return fail(WS_EINVAL, "patch %d: invalid tile %dx%d", k, tile_w[k], tile_h[k]);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (tile_w)
+    for (int k = 0; k < c->n_patches; ++k) {
+      c->rows[k].tw = tile_w[k];
+      c->rows[k].th = tile_h[k];
+    }
+  if (wg_per_cu > 0) c->wg_per_cu = wg_per_cu;
+  c->drop_graph();
+  return c->build_tiles();
+}
+
+static int copy_patch(ws_ctx *c, int32_t patch, const void *src, void *dst, bool up) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (patch < 0 || patch >= c->n_patches) return fail(WS_EINVAL, "patch %d out of range", patch);
+  if (!(up ? src : dst)) return fail(WS_EINVAL, "buffer is NULL");
+  const PatchRow &r = c->rows[patch];
+  const size_t es = c->dtype == WS_F32 ? 4 : 8;
+  const size_t w = (size_t)(r.mx + 4) * es;
+  const size_t h = 3 * (size_t)(r.my + 4);
+  const int64_t first = r.q_off + r.col0 - 2;  // padded (i=-2, j=-2) of plane p
+  if (up) {
+    for (int b = 0; b < 2; ++b)
+      HIPCHK(hipMemcpy2DAsync(reinterpret_cast<char *>(c->pool[b]) + first * es, r.ld * es, src, w,
+                              w, h, hipMemcpyDefault, c->stream));
+  } else {
+    HIPCHK(hipMemcpy2DAsync(dst, w, reinterpret_cast<const char *>(c->pool[c->cur]) + first * es,
+                            r.ld * es, w, h, hipMemcpyDefault, c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return WS_OK;
+}
+
+int ws_upload_patch(ws_ctx *c, int32_t patch, const void *src) {
+  return copy_patch(c, patch, src, nullptr, true);
+}
+
+int ws_download_patch(ws_ctx *c, int32_t patch, void *dst) {
+  return copy_patch(c, patch, nullptr, dst, false);
+}
+
+int ws_fill_ghosts(ws_ctx *c) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  HIPCHK(launch_fill_ghosts(c->dtype, c->d_patches(), c->n_patches, c->max_padded_cells,
+                            c->pool[c->cur], c->stream));
+  return WS_OK;
+}
+
+static int read_level_cfl(ws_ctx *c, double *cfl_out) {
+  if (!cfl_out) return WS_OK;
+  HIPCHK(hipMemcpyAsync(c->host_buf, c->ws + c->L.level_last, 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  *cfl_out = c->host_buf[0];
+  return WS_OK;
+}
+
+int ws_step_level(ws_ctx *c, double dt, double *cfl_out) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
+  HIPCHK(launch_set_dt(c->slots(), dt, c->stream));
+  StepArgs a = c->step_args(c->cur);
+  HIPCHK(launch_step(c->dtype, c->limiter, a, c->grid, c->stream));
+  HIPCHK(launch_finish_step(c->slots(), 0.0, c->stream));
+  c->cur = 1 - c->cur;
+  return read_level_cfl(c, cfl_out);
+}
+
+int ws_step_level_per_patch(ws_ctx *c, double dt, double *cfl_out) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
+  HIPCHK(launch_set_dt(c->slots(), dt, c->stream));
+  StepArgs a = c->step_args(c->cur);
+  a.persistent = 0;
+  for (int k : c->order) {  // largest patch first
+    a.tile_base = c->rows[k].tile_begin;
+    HIPCHK(launch_step(c->dtype, c->limiter, a, c->rows[k].n_tiles, c->stream));
+  }
+  HIPCHK(launch_finish_step(c->slots(), 0.0, c->stream));
+  c->cur = 1 - c->cur;
+  return read_level_cfl(c, cfl_out);
+}
+
+int ws_set_dt(ws_ctx *c, const double *dt_per_instance) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (!dt_per_instance) return fail(WS_EINVAL, "dt is NULL");
+  for (int k = 0; k < c->n_inst; ++k)
+    if (!(dt_per_instance[k] > 0.0) || !std::isfinite(dt_per_instance[k]))
+      return fail(WS_EINVAL, "dt[%d] must be finite and > 0", k);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::memcpy(c->host_buf, dt_per_instance, 8 * (size_t)c->n_inst);
+  HIPCHK(hipMemcpyAsync(c->ws + c->L.dt, c->host_buf, 8 * (size_t)c->n_inst,
+                        hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemsetAsync(c->ws + c->L.cfl_max, 0, 8 * (size_t)c->n_inst, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return WS_OK;
+}
+
+static int enqueue_auto(ws_ctx *c, int src, double cfl_desired) {
+  StepArgs a = c->step_args(src);
+  HIPCHK(launch_step(c->dtype, c->limiter, a, c->grid, c->stream));
+  HIPCHK(launch_finish_step(c->slots(), cfl_desired, c->stream));
+  return WS_OK;
+}
+
+int ws_step_auto(ws_ctx *c, double cfl_desired) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (!(cfl_desired > 0.0) || !std::isfinite(cfl_desired))
+    return fail(WS_EINVAL, "cfl_desired must be finite and > 0");
+  if (int rc = enqueue_auto(c, c->cur, cfl_desired)) return rc;
+  c->cur = 1 - c->cur;
+  return WS_OK;
+}
+
+int ws_capture_steps(ws_ctx *c, int32_t n_steps, double cfl_desired) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (n_steps < 1) return fail(WS_EINVAL, "n_steps must be >= 1");
+  if (!(cfl_desired > 0.0) || !std::isfinite(cfl_desired))
+    return fail(WS_EINVAL, "cfl_desired must be finite and > 0");
+  c->drop_graph();
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  int rc = WS_OK;
+  for (int s = 0; s < n_steps && rc == WS_OK; ++s) rc = enqueue_auto(c, (c->cur + s) & 1, cfl_desired);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (rc != WS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(WS_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  c->graph = g;
+  HIPCHK(hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  c->graph_steps = n_steps;
+  c->graph_start_pool = c->cur;
+  return WS_OK;
+}
+
+int ws_graph_launch(ws_ctx *c) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (!c->gexec) return fail(WS_ESTATE, "no captured graph");
+  if (c->cur != c->graph_start_pool)
+    return fail(WS_ESTATE, "the state is in the other pool than at capture time; capture again");
+  HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+  c->cur = (c->cur + c->graph_steps) & 1;
+  return WS_OK;
+}
+
+int ws_read_dt_cfl(ws_ctx *c, double *dt, double *cfl_last, double *cfl_max) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  const size_t n = 8 * (size_t)c->n_inst;
+  double *h = c->host_buf;
+  HIPCHK(hipMemcpyAsync(h, c->ws + c->L.dt, n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(h + c->n_inst, c->ws + c->L.cfl_last, n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(h + 2 * c->n_inst, c->ws + c->L.cfl_max, n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (dt) std::memcpy(dt, h, n);
+  if (cfl_last) std::memcpy(cfl_last, h + c->n_inst, n);
+  if (cfl_max) std::memcpy(cfl_max, h + 2 * c->n_inst, n);
+  return WS_OK;
+}
+
+int ws_read_patch_cfl(ws_ctx *c, double *cfl) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (!cfl) return fail(WS_EINVAL, "cfl is NULL");
+  const size_t n = 8 * (size_t)c->n_patches;
+  HIPCHK(hipMemcpyAsync(c->host_buf, c->ws + c->L.cfl_patch_last, n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::memcpy(cfl, c->host_buf, n);
+  return WS_OK;
+}
+
+int ws_conservation_sums(ws_ctx *c, double *sums) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (!sums) return fail(WS_EINVAL, "sums is NULL");
+  double *partials = reinterpret_cast<double *>(c->ws + c->L.partials);
+  double *dsums = reinterpret_cast<double *>(c->ws + c->L.sums);
+  HIPCHK(launch_sums(c->dtype, c->d_patches(), c->d_tiles(), (int)c->tiles.size(), c->pool[c->cur],
+                     partials, c->n_inst, dsums, c->stream));
+  const size_t n = 24 * (size_t)c->n_inst;
+  HIPCHK(hipMemcpyAsync(c->host_buf, dsums, n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::memcpy(sums, c->host_buf, n);
+  return WS_OK;
+}
+
+int ws_time_step_kernel(ws_ctx *c, int32_t n_launches, int32_t per_patch, double *ms_per_step) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (n_launches < 1 || !ms_per_step) return fail(WS_EINVAL, "need n_launches >= 1 and an output");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(WS_EHIP, "hipEventCreate failed");
+  }
+  int rc = WS_OK;
+  hipError_t e = hipEventRecord(e0, c->stream);
+  for (int s = 0; s < n_launches && e == hipSuccess; ++s) {
+    StepArgs a = c->step_args(c->cur);
+    if (per_patch) {
+      a.persistent = 0;
+      for (int k : c->order) {
+        a.tile_base = c->rows[k].tile_begin;
+        e = launch_step(c->dtype, c->limiter, a, c->rows[k].n_tiles, c->stream);
+        if (e != hipSuccess) break;
+      }
+    } else {
+      e = launch_step(c->dtype, c->limiter, a, c->grid, c->stream);
+    }
+    c->cur = 1 - c->cur;
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e != hipSuccess) rc = fail(WS_EHIP, "timing loop: %s", hipGetErrorString(e));
+  else *ms_per_step = (double)ms / n_launches;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
+int ws_current_pool(ws_ctx *c, int32_t *which) {
+  if (!c || !which) return fail(WS_EINVAL, "NULL argument");
+  *which = c->cur;
+  return WS_OK;
+}
+
+int ws_destroy(ws_ctx *c) {
+  if (!c) return WS_OK;
+  (void)hipStreamSynchronize(c->stream);
+  c->drop_graph();
+  if (c->host_buf) (void)hipHostFree(c->host_buf);
+  delete c;
+  return WS_OK;
+}
+
+}  // extern "C"

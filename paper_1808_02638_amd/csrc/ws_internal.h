@@ -1,0 +1,89 @@
+// Internal layout shared by the host runtime and the HIP kernels of the
+// wave-propagation library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ws {
+
+constexpr int kThreads = 256;  // threads per workgroup of every tile kernel
+constexpr int kMaxRowsPerThread = 32;
+
+// One row of the device patch table.
+struct PatchRow {
+  int64_t q_off;   // element offset of padded cell (i=-2, j=-2) of plane p
+  int32_t mx, my;  // interior cells
+  int32_t ld;      // row stride (elements)
+  int32_t col0;    // storage column of interior i = 0 (ghost i=-2 sits at col0-2)
+  int64_t plane;   // plane stride (elements): ld * (my + 4)
+  int32_t inst;    // instance (material, dt)
+  int32_t bc;      // WS_BC_*
+  int32_t tw, th;  // tile shape
+  int32_t ntx, nty;  // tiles in x and y
+  double dx, dy;
+  int64_t mask_off;  // byte offset of the patch's (mx+1)*(my+1) mask bytes
+  int32_t tile_begin, n_tiles;  // the patch's tiles in the tile list
+};
+
+struct TileEntry {
+  int32_t patch;
+  uint16_t tx, ty;
+};
+
+struct InstRow {
+  double c, Z;
+};
+
+// Workspace carve-up (byte offsets inside the caller's workspace buffer).
+struct WsLayout {
+  int64_t patches, inst, tiles, dt, cfl_acc, cfl_last, cfl_max, cfl_patch_acc,
+      cfl_patch_last, level_acc, level_last, counters, partials, sums, total;
+  int64_t max_tiles;
+};
+
+// Per-step bookkeeping slots inside the workspace.
+struct CflSlots {
+  double *dt;                         // [n_inst]
+  unsigned long long *cfl_acc;        // [n_inst]   max over the step (bit patterns)
+  double *cfl_last;                   // [n_inst]   Courant number of the last step
+  double *cfl_max;                    // [n_inst]   largest since ws_set_dt
+  unsigned long long *cfl_patch_acc;  // [n_patches]
+  double *cfl_patch_last;             // [n_patches]
+  unsigned long long *level_acc;      // [1]
+  double *level_last;                 // [1]
+  int n_inst, n_patches;
+};
+
+struct StepArgs {
+  const PatchRow *patches;
+  const TileEntry *tiles;
+  int32_t n_tiles;
+  int32_t tile_base;   // direct mode: first tile of this launch
+  int32_t persistent;  // 1: pull tiles from counters[0]; 0: tile = base + blockIdx
+  const void *qin;
+  void *qout;
+  const InstRow *inst;
+  const double *dt;  // per instance
+  unsigned long long *cfl_acc;    // per instance, FP64 bit patterns (>= 0)
+  unsigned long long *cfl_patch;  // per patch
+  unsigned long long *cfl_level;  // one slot
+  unsigned int *counters;         // [0] next tile, [1] retired workgroups
+  uint8_t *masks;                 // nullptr unless the branches are recorded
+};
+
+// Kernel launchers (defined in ws_kernels.hip).
+hipError_t launch_step(int dtype, int limiter, const StepArgs &a, int grid, hipStream_t s);
+hipError_t launch_fill_ghosts(int dtype, const PatchRow *patches, int n_patches,
+                              int max_padded_cells, void *q, hipStream_t s);
+// dt[k] = value for every instance.
+hipError_t launch_set_dt(const CflSlots &c, double value, hipStream_t s);
+// Move the step's accumulated Courant numbers to the *_last slots, update the
+// running maxima, clear the accumulators and, if cfl_desired > 0, rescale
+// each instance's dt by cfl_desired / cfl.
+hipError_t launch_finish_step(const CflSlots &c, double cfl_desired, hipStream_t s);
+hipError_t launch_sums(int dtype, const PatchRow *patches, const TileEntry *tiles, int n_tiles,
+                       const void *q, double *partials, int n_inst, double *sums, hipStream_t s);
+int step_occupancy(int dtype, int limiter, int *wg_per_cu);
+
+}  // namespace ws

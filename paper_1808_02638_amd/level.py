@@ -1,0 +1,185 @@
+"""``Level``: one AMR level (or ensemble) of ghost-padded acoustics patches on
+one GPU, advanced by the HIP library through its C ABI.
+
+PyTorch provides the device memory (two q pools and a workspace, raw bytes)
+and the stream; all arithmetic happens in the library's kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as C
+
+_LIMITERS = {"mc": C.WS_LIM_MC, "none": C.WS_LIM_NONE}
+_BCS = {None: C.WS_BC_NONE, "none": C.WS_BC_NONE, "extrap": C.WS_BC_EXTRAP,
+        "periodic": C.WS_BC_PERIODIC}
+
+
+def _get(p, name, default=None):
+    if isinstance(p, dict):
+        return p.get(name, default)
+    return getattr(p, name, default)
+
+
+class Level:
+    """Patches of one level, resident in HBM, stepped by one fused launch.
+
+    patches: sequence of objects or dicts with mx, my, dx, dy and optionally
+        instance (default 0) and bc ("extrap", "periodic" or None = frozen
+        ghosts; default None).
+    materials: sequence of (rho, K), one per instance.
+    dtype: torch.float64 or torch.float32 (arithmetic and storage).
+    """
+
+    def __init__(self, patches: Sequence, materials: Sequence, *, dtype=torch.float64,
+                 limiter: str = "mc", device="cuda", stream: torch.cuda.Stream | None = None):
+        self._L = C.lib()
+        self._ctx = None
+        self.dtype = dtype
+        self.np_dtype = np.float64 if dtype == torch.float64 else np.float32
+        if dtype not in (torch.float64, torch.float32):
+            raise ValueError("dtype must be torch.float64 or torch.float32")
+        self.n = len(patches)
+        self.n_inst = len(materials)
+        self.shapes = [(int(_get(p, "mx")), int(_get(p, "my"))) for p in patches]
+        descs = (C.PatchDesc * self.n)()
+        for k, p in enumerate(patches):
+            descs[k].mx, descs[k].my = self.shapes[k]
+            descs[k].dx = float(_get(p, "dx"))
+            descs[k].dy = float(_get(p, "dy"))
+            descs[k].instance = int(_get(p, "instance", 0) or 0)
+            descs[k].bc = _BCS[_get(p, "bc", None)]
+        mats = (C.Material * self.n_inst)()
+        for k, (rho, K) in enumerate(materials):
+            mats[k].rho, mats[k].K = float(rho), float(K)
+        code = C.WS_F64 if dtype == torch.float64 else C.WS_F32
+        pool_b, ws_b = ctypes.c_int64(0), ctypes.c_int64(0)
+        C.check(self._L.ws_layout(descs, self.n, self.n_inst, code, ctypes.byref(pool_b),
+                                  ctypes.byref(ws_b)))
+        self.device = torch.device(device)
+        self.pool_bytes = pool_b.value
+        self.pools = [torch.empty(pool_b.value, dtype=torch.uint8, device=self.device)
+                      for _ in range(2)]
+        self.workspace = torch.empty(ws_b.value, dtype=torch.uint8, device=self.device)
+        # A stream of our own (default priority): graph capture cannot use the
+        # legacy null stream.  Allocation above ran on torch's stream.
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        torch.cuda.synchronize(self.device)
+        ctx = ctypes.c_void_p()
+        C.check(self._L.ws_init_patches(
+            ctypes.byref(ctx), descs, self.n, mats, self.n_inst, 2, code, _LIMITERS[limiter],
+            ctypes.c_void_p(self.pools[0].data_ptr()), ctypes.c_void_p(self.pools[1].data_ptr()),
+            pool_b.value, ctypes.c_void_p(self.workspace.data_ptr()), ws_b.value,
+            ctypes.c_void_p(self.stream.cuda_stream)))
+        self._ctx = ctx
+
+    # ------------------------------------------------------------------ data
+    def upload(self, k: int, q) -> None:
+        """Patch k's state in host layout (3, my+4, mx+4): a numpy array, or a
+        torch tensor on the CPU or this GPU; written into both pools."""
+        mx, my = self.shapes[k]
+        if isinstance(q, torch.Tensor):
+            t = q.detach().to(self.dtype).contiguous()
+            if t.shape != (3, my + 4, mx + 4):
+                raise ValueError(f"patch {k}: expected shape {(3, my + 4, mx + 4)}")
+            C.check(self._L.ws_upload_patch(self._ctx, k, ctypes.c_void_p(t.data_ptr())))
+            return
+        a = np.ascontiguousarray(q, dtype=self.np_dtype)
+        if a.shape != (3, my + 4, mx + 4):
+            raise ValueError(f"patch {k}: expected shape {(3, my + 4, mx + 4)}")
+        C.check(self._L.ws_upload_patch(self._ctx, k, a.ctypes.data_as(ctypes.c_void_p)))
+
+    def download(self, k: int) -> np.ndarray:
+        mx, my = self.shapes[k]
+        a = np.empty((3, my + 4, mx + 4), dtype=self.np_dtype)
+        C.check(self._L.ws_download_patch(self._ctx, k, a.ctypes.data_as(ctypes.c_void_p)))
+        return a
+
+    def fill_ghosts(self) -> None:
+        C.check(self._L.ws_fill_ghosts(self._ctx))
+
+    # ----------------------------------------------------------------- steps
+    def step(self, dt: float) -> float:
+        cfl = ctypes.c_double(0.0)
+        C.check(self._L.ws_step_level(self._ctx, float(dt), ctypes.byref(cfl)))
+        return cfl.value
+
+    def step_per_patch(self, dt: float) -> float:
+        cfl = ctypes.c_double(0.0)
+        C.check(self._L.ws_step_level_per_patch(self._ctx, float(dt), ctypes.byref(cfl)))
+        return cfl.value
+
+    def set_dt(self, dts: Iterable[float]) -> None:
+        arr = (ctypes.c_double * self.n_inst)(*[float(v) for v in dts])
+        C.check(self._L.ws_set_dt(self._ctx, arr))
+
+    def step_auto(self, cfl_desired: float) -> None:
+        C.check(self._L.ws_step_auto(self._ctx, float(cfl_desired)))
+
+    def capture(self, n_steps: int, cfl_desired: float) -> None:
+        C.check(self._L.ws_capture_steps(self._ctx, int(n_steps), float(cfl_desired)))
+
+    def graph_launch(self) -> None:
+        C.check(self._L.ws_graph_launch(self._ctx))
+
+    def read_dt_cfl(self):
+        n = self.n_inst
+        dt, last, mx = (ctypes.c_double * n)(), (ctypes.c_double * n)(), (ctypes.c_double * n)()
+        C.check(self._L.ws_read_dt_cfl(self._ctx, dt, last, mx))
+        return np.array(dt), np.array(last), np.array(mx)
+
+    def patch_cfl(self) -> np.ndarray:
+        out = (ctypes.c_double * self.n)()
+        C.check(self._L.ws_read_patch_cfl(self._ctx, out))
+        return np.array(out)
+
+    def conservation_sums(self) -> np.ndarray:
+        out = (ctypes.c_double * (3 * self.n_inst))()
+        C.check(self._L.ws_conservation_sums(self._ctx, out))
+        return np.array(out).reshape(self.n_inst, 3)
+
+    def set_tiling(self, tile_w=None, tile_h=None, wg_per_cu: int = 0) -> None:
+        """Tile shape per patch (scalars broadcast) and persistent workgroups per CU."""
+        if tile_w is None:
+            C.check(self._L.ws_set_tiling(self._ctx, None, None, int(wg_per_cu)))
+            return
+        tw = np.broadcast_to(np.asarray(tile_w, np.int32), (self.n,)).copy()
+        th = np.broadcast_to(np.asarray(tile_h, np.int32), (self.n,)).copy()
+        P = ctypes.POINTER(ctypes.c_int32)
+        C.check(self._L.ws_set_tiling(self._ctx, tw.ctypes.data_as(P), th.ctypes.data_as(P),
+                                      int(wg_per_cu)))
+
+    def time_step_kernel(self, n_launches: int, per_patch: bool = False) -> float:
+        """Mean milliseconds per level step of n back-to-back step launches
+        (HIP events on the level's stream; fixed device dt, no dt update)."""
+        ms = ctypes.c_double(0.0)
+        C.check(self._L.ws_time_step_kernel(self._ctx, int(n_launches), int(bool(per_patch)),
+                                            ctypes.byref(ms)))
+        return ms.value
+
+    def current_pool(self) -> int:
+        w = ctypes.c_int32(0)
+        C.check(self._L.ws_current_pool(self._ctx, ctypes.byref(w)))
+        return w.value
+
+    def close(self) -> None:
+        if self._ctx is not None:
+            self._L.ws_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
