@@ -153,6 +153,8 @@ def main():
     ap.add_argument("--amr-steps", type=int, default=10)
     ap.add_argument("--no-extras", action="store_true", help="skip FP32, AMR and CPU legs")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -165,6 +167,16 @@ def main():
     import paper_1808_02638_amd as ws
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
+        # calibrate the step kernel's counter readings
+        src = torch.ones(args.copy_probe, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
     n, K = args.n, args.steps
     shapes = [(n, n)]
     r64 = run_uniform(ws, torch, n, K, args.warmup, torch.float64, args.kernel_launches)

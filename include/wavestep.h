@@ -87,13 +87,23 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
                     int64_t pool_bytes, void *workspace, int64_t ws_bytes,
                     void *hip_stream);
 
-/* Tile shape per patch (arrays of n_patches; NULL keeps the default) and
- * workgroups per CU of the persistent launch (0 keeps the default).  A tile is
- * tile_w x tile_h cells worked by 256 threads: tile_w in {8,16,32,64,128,256},
- * tile_h a multiple of 256/tile_w with tile_h*tile_w/256 <= 32.  Results do
- * not depend on the tiling (bitwise).  Invalidates a captured graph. */
-int ws_set_tiling(ws_ctx *ctx, const int32_t *tile_w, const int32_t *tile_h,
-                  int32_t wg_per_cu);
+/* Tiling per patch (arrays of n_patches; all NULL keeps the defaults) and
+ * workgroups per CU of the persistent launch (0 keeps the default).  Every
+ * tile is worked by one workgroup of 256 threads.
+ *   variant WS_TILE_DIRECT: tile_w x tile_h cells, tile_w in {8,16,...,256},
+ *     one thread per column computing each cell from its 13-point footprint;
+ *   variant WS_TILE_MARCH: 256/tile_w lane segments of tile_w in {16,32,64}
+ *     lanes stacked vertically; each segment updates tile_w-4 columns and
+ *     tile_h/(256/tile_w) rows, carrying y-terms up the column in registers and
+ *     exchanging x-terms between neighbouring lanes.
+ * tile_h must be a multiple of 256/tile_w with at most 64 rows per thread
+ * (DIRECT) or per segment (MARCH).
+ * Periodic patches take DIRECT tiles only.
+ * variant may be NULL (all DIRECT).  Results do not depend on the tiling
+ * (bitwise).  Invalidates a captured graph. */
+enum { WS_TILE_DIRECT = 0, WS_TILE_MARCH = 1 };
+int ws_set_tiling(ws_ctx *ctx, const int32_t *variant, const int32_t *tile_w,
+                  const int32_t *tile_h, int32_t wg_per_cu);
 
 /* Copy one patch, host layout, into BOTH pools (ghosts included).  src may be
  * a host or a device pointer.  Synchronises the stream. */

@@ -13,6 +13,8 @@ from .oracle import (  # noqa: F401
     build,
     conservation_sums,
     fill_bc,
+    forward_traces,
+    frozen_step,
     lib,
     mc_branch,
     phi,

@@ -222,18 +222,32 @@ def run(q0, nsteps, dx, dy, rho, K, *, limiter="mc", bc="extrap", dt=None,
     return {"q": q, "dts": np.array(dts), "cfls": np.array(cfls)}
 
 
+def frozen_step(x, dx, dy, dt, rho, K, masks, bc="extrap"):
+    """The frozen-branch step as a map of the interior: x (3, my, mx) ->
+    (3, my, mx), ghosts filled from x by ``bc`` (or zero when None)."""
+    my, mx = x.shape[1], x.shape[2]
+    q = np.zeros((3, my + 4, mx + 4))
+    q[:, 2:-2, 2:-2] = x
+    if bc is not None:
+        fill_bc(q, bc)
+    out, _cfl, _m = step(q, dx, dy, dt, rho, K, "mc", frozen=masks)
+    return out[:, 2:-2, 2:-2].copy()
+
+
 def conservation_sums(q, dx, dy):
     """Sum of q_m * dx * dy over the interior cells, m = p, u, v (exact fsum)."""
     return np.array([math.fsum(q[m, 2:-2, 2:-2].ravel().tolist()) * dx * dy
                      for m in range(3)])
 
 
-def adjoint_step(lam_next, q, dx, dy, dt, rho, K, masks):
+def adjoint_step(lam_next, q, dx, dy, dt, rho, K, masks, bc="extrap"):
     """Oracle adjoint of one frozen-branch step including the boundary fill.
 
     lam_next: cotangent of the interior of Q^{n+1}, shape (3, my, mx).
     q: the state Q^n the forward step started from (ghosts filled), only
     used for its shape.  masks: the branches recorded on that forward step.
+    bc: "extrap" (ghosts are filled from the interior before the step) or None
+    (ghosts are frozen input and carry no cotangent).
     Returns the cotangent of the interior of Q^n, shape (3, my, mx).
     """
     L = lib()
@@ -246,22 +260,22 @@ def adjoint_step(lam_next, q, dx, dy, dt, rho, K, masks):
     out = np.zeros_like(lam_in)
     masks = np.ascontiguousarray(masks, dtype=np.uint8)
     rc = L.oracle_adjoint_step(_dptr(lam_in), _dptr(out), mx, my, float(dx), float(dy),
-                               float(dt), float(rho), float(K), _u8ptr(masks), BC["extrap"])
+                               float(dt), float(rho), float(K), _u8ptr(masks),
+                               BC[bc] if bc is not None else -1)
     if rc != 0:
         raise RuntimeError("oracle_adjoint_step failed")
     return out
 
 
-def adjoint_run(p0, nsteps, dx, dy, dt, rho, K, receivers, target):
-    """Gradient of J = 1/2 sum_n sum_r (p^n_r - d^n_r)^2 w.r.t. the interior p^0.
-
-    Forward with extrapolation ghosts and fixed dt, recording the MC branches
-    of every step; then the frozen-branch adjoint sweep in reverse.
-    receivers: int array (nr, 2) of (i, j); target: (nsteps, nr).
-    Returns (J, grad_p0 of shape (my, mx), traces (nsteps, nr)).
-    """
+def forward_traces(p0, nsteps, dx, dy, dt, rho, K, receivers, target=None, state0=None):
+    """Forward run with extrapolation ghosts and fixed dt, recording the MC
+    branches of every step and the pressure at the receivers after every step.
+    p0: interior pressure (my, mx); u = v = 0 unless ``state0`` (3, my, mx) gives
+    the velocities.  Returns (J or None, traces (nsteps, nr), states, masks)."""
     my, mx = p0.shape
     q = np.zeros((3, my + 4, mx + 4))
+    if state0 is not None:
+        q[:, 2:-2, 2:-2] = state0
     q[0, 2:-2, 2:-2] = p0
     fill_bc(q, "extrap")
     states, masks_all = [], []
@@ -273,10 +287,28 @@ def adjoint_run(p0, nsteps, dx, dy, dt, rho, K, receivers, target):
         fill_bc(q, "extrap")
         masks_all.append(m)
         traces[n] = q[0, rj + 2, ri + 2]
+    J = None
+    if target is not None:
+        resid = traces - target
+        J = 0.5 * math.fsum((resid * resid).ravel().tolist())
+    return J, traces, states, masks_all
+
+
+def adjoint_run(p0, nsteps, dx, dy, dt, rho, K, receivers, target, state0=None):
+    """Gradient of J = 1/2 sum_n sum_r (p^n_r - d^n_r)^2 w.r.t. the interior p^0.
+
+    Forward with extrapolation ghosts and fixed dt, recording the MC branches
+    of every step; then the frozen-branch adjoint sweep in reverse.
+    receivers: int array (nr, 2) of (i, j); target: (nsteps, nr).
+    Returns (J, grad_p0 of shape (my, mx), traces (nsteps, nr), masks per step).
+    """
+    my, mx = p0.shape
+    J, traces, states, masks_all = forward_traces(p0, nsteps, dx, dy, dt, rho, K, receivers,
+                                                  target, state0)
     resid = traces - target
-    J = 0.5 * math.fsum((resid * resid).ravel().tolist())
+    ri, rj = receivers[:, 0], receivers[:, 1]
     lam = np.zeros((3, my, mx))
     for n in range(nsteps - 1, -1, -1):
         np.add.at(lam[0], (rj, ri), resid[n])
         lam = adjoint_step(lam, states[n], dx, dy, dt, rho, K, masks_all[n])
-    return J, lam[0].copy(), traces
+    return J, lam[0].copy(), traces, masks_all

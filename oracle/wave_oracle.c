@@ -510,3 +510,263 @@ void oracle_split_vec(int dir, double rho, double K, const double *a,
   acoustics_eig(rho, K, dir, &e);
   split(&e, a, minus, plus);
 }
+
+/* ---------------------------------------------------------------------- */
+/* Adjoint of one frozen-branch step, boundary fill included               */
+/* ---------------------------------------------------------------------- */
+/* With the MC branches frozen (masks recorded by a forward step), one step
+ * Q^n -> Q^{n+1} of the interior is the linear map S = U o E: E fills the
+ * ghosts from the interior (extrapolation; bc_kind < 0: ghosts are frozen
+ * input, E adds nothing), U is the update above.  This applies S^T to a
+ * cotangent of the interior of Q^{n+1} by running the forward stages in
+ * reverse, each transposed in scatter form: update -> F~/G~ -> transverse
+ * splits -> limited corrections and fluctuations -> waves -> jumps -> E^T.
+ * lam_next, lam_out: [3][my][mx]. */
+
+/* coefficients (own, upwind) of the frozen limited wave for a branch */
+static void frozen_coefs(int b, double *c0, double *c1) {
+  switch (b) {
+  case 0: *c0 = 0.0; *c1 = 0.0; break;
+  case 1: *c0 = 0.5; *c1 = 0.5; break;
+  case 2: *c0 = 2.0; *c1 = 0.0; break;
+  default: *c0 = 0.0; *c1 = 2.0; break;
+  }
+}
+
+/* transpose of split(): given cotangents of the minus and plus parts, add
+ * Mm^T lm + Mp^T lp to out (M = sum over waves of s r l^T). */
+static void split_T(const eig_t *e, const double lm[NM], const double lp[NM], double out[NM]) {
+  for (int p = 0; p < NW; ++p) {
+    const double *lam = (e->s[p] < 0.0) ? lm : (e->s[p] > 0.0 ? lp : NULL);
+    if (!lam) continue;
+    double rdot = 0.0;
+    for (int m = 0; m < NM; ++m) rdot += e->R[m][p] * lam[m];
+    for (int m = 0; m < NM; ++m) out[m] += e->s[p] * rdot * e->L[p][m];
+  }
+}
+
+int oracle_adjoint_step(const double *lam_next, double *lam_out, int mx, int my, double dx,
+                        double dy, double dt, double rho, double K, const uint8_t *masks,
+                        int bc_kind) {
+  if (mx < 1 || my < 1 || !masks) return -1;
+  eig_t ex, ey;
+  acoustics_eig(rho, K, 0, &ex);
+  acoustics_eig(rho, K, 1, &ey);
+  const double dtdx = dt / dx, dtdy = dt / dy;
+  const size_t npad = (size_t)(mx + 4) * (size_t)(my + 4);
+#define LI(m, i, j) (((size_t)(m) * (size_t)my + (size_t)(j)) * (size_t)mx + (size_t)(i))
+#define PI(i, j) ((size_t)((j) + 2) * (size_t)(mx + 4) + (size_t)((i) + 2))
+  /* cotangents, laid out like the forward arrays */
+  double *lpad = calloc(npad * NM, sizeof(double));                      /* [cell][m] */
+  double *l_amdq_x = calloc((size_t)(my + 2) * (mx + 1) * NM, sizeof(double));
+  double *l_apdq_x = calloc((size_t)(my + 2) * (mx + 1) * NM, sizeof(double));
+  double *l_amdq_y = calloc((size_t)(my + 1) * (mx + 2) * NM, sizeof(double));
+  double *l_apdq_y = calloc((size_t)(my + 1) * (mx + 2) * NM, sizeof(double));
+  double *l_Ft = calloc((size_t)my * (mx + 1) * NM, sizeof(double));     /* F~ */
+  double *l_Gt = calloc((size_t)(my + 1) * mx * NM, sizeof(double));     /* G~ */
+  double *l_Gx_top = calloc((size_t)(my + 2) * mx * NM, sizeof(double));
+  double *l_Gx_bot = calloc((size_t)(my + 2) * mx * NM, sizeof(double));
+  double *l_Fy_right = calloc((size_t)my * (mx + 2) * NM, sizeof(double));
+  double *l_Fy_left = calloc((size_t)my * (mx + 2) * NM, sizeof(double));
+  /* wave cotangents: x rows -1..my, edges -1..mx+1; y columns -1..mx, edges -1..my+1 */
+  double *l_Wx = calloc((size_t)(my + 2) * (mx + 3) * NW * NM, sizeof(double));
+  double *l_Wy = calloc((size_t)(mx + 2) * (my + 3) * NW * NM, sizeof(double));
+  int rc = 0;
+  if (!lpad || !l_amdq_x || !l_apdq_x || !l_amdq_y || !l_apdq_y || !l_Ft || !l_Gt ||
+      !l_Gx_top || !l_Gx_bot || !l_Fy_right || !l_Fy_left || !l_Wx || !l_Wy) {
+    rc = -1;
+    goto done;
+  }
+#define AX(j, e) (((size_t)((j) + 1) * (size_t)(mx + 1) + (size_t)(e)) * NM)
+#define AY(f, i) (((size_t)(f) * (size_t)(mx + 2) + (size_t)((i) + 1)) * NM)
+#define FT(j, e) (((size_t)(j) * (size_t)(mx + 1) + (size_t)(e)) * NM)
+#define GT(f, i) (((size_t)(f) * (size_t)mx + (size_t)(i)) * NM)
+#define GX(j, i) (((size_t)((j) + 1) * (size_t)mx + (size_t)(i)) * NM)
+#define FY(j, i) (((size_t)(j) * (size_t)(mx + 2) + (size_t)((i) + 1)) * NM)
+#define WX(j, e, p) ((((size_t)((j) + 1) * (size_t)(mx + 3) + (size_t)((e) + 1)) * NW + (p)) * NM)
+#define WY(i, f, p) ((((size_t)((i) + 1) * (size_t)(my + 3) + (size_t)((f) + 1)) * NW + (p)) * NM)
+
+  /* ---- update, eq. (2.3), transposed ---- */
+  for (int j = 0; j < my; ++j)
+    for (int i = 0; i < mx; ++i)
+      for (int m = 0; m < NM; ++m) {
+        const double l = lam_next[LI(m, i, j)];
+        lpad[PI(i, j) * NM + m] += l;
+        l_apdq_x[AX(j, i) + m] -= dtdx * l;
+        l_amdq_x[AX(j, i + 1) + m] -= dtdx * l;
+        l_apdq_y[AY(j, i) + m] -= dtdy * l;
+        l_amdq_y[AY(j + 1, i) + m] -= dtdy * l;
+        l_Ft[FT(j, i + 1) + m] -= dtdx * l;
+        l_Ft[FT(j, i) + m] += dtdx * l;
+        l_Gt[GT(j + 1, i) + m] -= dtdy * l;
+        l_Gt[GT(j, i) + m] += dtdy * l;
+      }
+  /* ---- F~ = Fc + transverse parts; G~ likewise ---- */
+  for (int j = 0; j < my; ++j)
+    for (int e = 0; e <= mx; ++e)
+      for (int m = 0; m < NM; ++m) {
+        l_Fy_right[FY(j, e - 1) + m] += l_Ft[FT(j, e) + m];
+        l_Fy_left[FY(j, e) + m] += l_Ft[FT(j, e) + m];
+      }
+  for (int f = 0; f <= my; ++f)
+    for (int i = 0; i < mx; ++i)
+      for (int m = 0; m < NM; ++m) {
+        l_Gx_top[GX(f - 1, i) + m] += l_Gt[GT(f, i) + m];
+        l_Gx_bot[GX(f, i) + m] += l_Gt[GT(f, i) + m];
+      }
+  /* ---- transverse splits, transposed ---- */
+  for (int j = -1; j <= my; ++j)
+    for (int e = 0; e <= mx; ++e) {
+      double acc[NM] = {0, 0, 0}, lm[NM], lp[NM];
+      if (e <= mx - 1) { /* A+dQ at edge e entered cell e */
+        for (int m = 0; m < NM; ++m) {
+          lm[m] = -0.5 * dtdx * l_Gx_bot[GX(j, e) + m];
+          lp[m] = -0.5 * dtdx * l_Gx_top[GX(j, e) + m];
+        }
+        split_T(&ey, lm, lp, acc);
+        for (int m = 0; m < NM; ++m) l_apdq_x[AX(j, e) + m] += acc[m];
+      }
+      if (e >= 1) { /* A-dQ at edge e entered cell e-1 */
+        for (int m = 0; m < NM; ++m) {
+          acc[m] = 0.0;
+          lm[m] = -0.5 * dtdx * l_Gx_bot[GX(j, e - 1) + m];
+          lp[m] = -0.5 * dtdx * l_Gx_top[GX(j, e - 1) + m];
+        }
+        split_T(&ey, lm, lp, acc);
+        for (int m = 0; m < NM; ++m) l_amdq_x[AX(j, e) + m] += acc[m];
+      }
+    }
+  for (int i = -1; i <= mx; ++i)
+    for (int f = 0; f <= my; ++f) {
+      double acc[NM] = {0, 0, 0}, lm[NM], lp[NM];
+      if (f <= my - 1) {
+        for (int m = 0; m < NM; ++m) {
+          lm[m] = -0.5 * dtdy * l_Fy_left[FY(f, i) + m];
+          lp[m] = -0.5 * dtdy * l_Fy_right[FY(f, i) + m];
+        }
+        split_T(&ex, lm, lp, acc);
+        for (int m = 0; m < NM; ++m) l_apdq_y[AY(f, i) + m] += acc[m];
+      }
+      if (f >= 1) {
+        for (int m = 0; m < NM; ++m) {
+          acc[m] = 0.0;
+          lm[m] = -0.5 * dtdy * l_Fy_left[FY(f - 1, i) + m];
+          lp[m] = -0.5 * dtdy * l_Fy_right[FY(f - 1, i) + m];
+        }
+        split_T(&ex, lm, lp, acc);
+        for (int m = 0; m < NM; ++m) l_amdq_y[AY(f, i) + m] += acc[m];
+      }
+    }
+  /* ---- limited corrections (frozen branches) and fluctuations -> waves ---- */
+  for (int j = 0; j < my; ++j)
+    for (int e = 0; e <= mx; ++e)
+      for (int p = 0; p < NW; ++p) {
+        const double s = ex.s[p];
+        if (s == 0.0) continue;
+        const int up = (s > 0.0) ? e - 1 : e + 1;
+        const int b = (masks[MIX(e, j)] >> (p == 0 ? 0 : 2)) & 3;
+        double c0, c1;
+        frozen_coefs(b, &c0, &c1);
+        const double coef = 0.5 * fabs(s) * (1.0 - dtdx * fabs(s));
+        for (int m = 0; m < NM; ++m) {
+          l_Wx[WX(j, e, p) + m] += coef * c0 * l_Ft[FT(j, e) + m];
+          l_Wx[WX(j, up, p) + m] += coef * c1 * l_Ft[FT(j, e) + m];
+        }
+      }
+  for (int i = 0; i < mx; ++i)
+    for (int f = 0; f <= my; ++f)
+      for (int p = 0; p < NW; ++p) {
+        const double s = ey.s[p];
+        if (s == 0.0) continue;
+        const int up = (s > 0.0) ? f - 1 : f + 1;
+        const int b = (masks[MIX(i, f)] >> (p == 0 ? 4 : 6)) & 3;
+        double c0, c1;
+        frozen_coefs(b, &c0, &c1);
+        const double coef = 0.5 * fabs(s) * (1.0 - dtdy * fabs(s));
+        for (int m = 0; m < NM; ++m) {
+          l_Wy[WY(i, f, p) + m] += coef * c0 * l_Gt[GT(f, i) + m];
+          l_Wy[WY(i, up, p) + m] += coef * c1 * l_Gt[GT(f, i) + m];
+        }
+      }
+  for (int j = -1; j <= my; ++j)
+    for (int e = 0; e <= mx; ++e)
+      for (int p = 0; p < NW; ++p) {
+        const double s = ex.s[p];
+        for (int m = 0; m < NM; ++m) {
+          if (s < 0.0) l_Wx[WX(j, e, p) + m] += s * l_amdq_x[AX(j, e) + m];
+          else if (s > 0.0) l_Wx[WX(j, e, p) + m] += s * l_apdq_x[AX(j, e) + m];
+        }
+      }
+  for (int i = -1; i <= mx; ++i)
+    for (int f = 0; f <= my; ++f)
+      for (int p = 0; p < NW; ++p) {
+        const double s = ey.s[p];
+        for (int m = 0; m < NM; ++m) {
+          if (s < 0.0) l_Wy[WY(i, f, p) + m] += s * l_amdq_y[AY(f, i) + m];
+          else if (s > 0.0) l_Wy[WY(i, f, p) + m] += s * l_apdq_y[AY(f, i) + m];
+        }
+      }
+  /* ---- waves W = alpha r, alpha = L (q_r - q_l) -> cell cotangents ---- */
+  for (int j = -1; j <= my; ++j)
+    for (int e = -1; e <= mx + 1; ++e) {
+      double ldq[NM] = {0, 0, 0};
+      for (int p = 0; p < NW; ++p) {
+        double la = 0.0;
+        for (int m = 0; m < NM; ++m) la += ex.R[m][p] * l_Wx[WX(j, e, p) + m];
+        for (int m = 0; m < NM; ++m) ldq[m] += la * ex.L[p][m];
+      }
+      for (int m = 0; m < NM; ++m) {
+        lpad[PI(e, j) * NM + m] += ldq[m];
+        lpad[PI(e - 1, j) * NM + m] -= ldq[m];
+      }
+    }
+  for (int i = -1; i <= mx; ++i)
+    for (int f = -1; f <= my + 1; ++f) {
+      double ldq[NM] = {0, 0, 0};
+      for (int p = 0; p < NW; ++p) {
+        double la = 0.0;
+        for (int m = 0; m < NM; ++m) la += ey.R[m][p] * l_Wy[WY(i, f, p) + m];
+        for (int m = 0; m < NM; ++m) ldq[m] += la * ey.L[p][m];
+      }
+      for (int m = 0; m < NM; ++m) {
+        lpad[PI(i, f) * NM + m] += ldq[m];
+        lpad[PI(i, f - 1) * NM + m] -= ldq[m];
+      }
+    }
+  /* ---- boundary fill transposed: E = (y-ghosts over the full width) o
+   * (x-ghosts of interior rows), so E^T folds the ghost rows first, then the
+   * ghost columns of the interior rows, into the nearest interior cells ---- */
+  if (bc_kind == OR_BC_EXTRAP) {
+    for (int i = -2; i < mx + 2; ++i)
+      for (int g = 1; g <= 2; ++g)
+        for (int m = 0; m < NM; ++m) {
+          lpad[PI(i, 0) * NM + m] += lpad[PI(i, -g) * NM + m];
+          lpad[PI(i, my - 1) * NM + m] += lpad[PI(i, my - 1 + g) * NM + m];
+        }
+    for (int j = 0; j < my; ++j)
+      for (int g = 1; g <= 2; ++g)
+        for (int m = 0; m < NM; ++m) {
+          lpad[PI(0, j) * NM + m] += lpad[PI(-g, j) * NM + m];
+          lpad[PI(mx - 1, j) * NM + m] += lpad[PI(mx - 1 + g, j) * NM + m];
+        }
+  }
+  for (int m = 0; m < NM; ++m)
+    for (int j = 0; j < my; ++j)
+      for (int i = 0; i < mx; ++i) lam_out[LI(m, i, j)] = lpad[PI(i, j) * NM + m];
+
+#undef AX
+#undef AY
+#undef FT
+#undef GT
+#undef GX
+#undef FY
+#undef WX
+#undef WY
+#undef LI
+#undef PI
+done:
+  free(lpad); free(l_amdq_x); free(l_apdq_x); free(l_amdq_y); free(l_apdq_y);
+  free(l_Ft); free(l_Gt); free(l_Gx_top); free(l_Gx_bot); free(l_Fy_right); free(l_Fy_left);
+  free(l_Wx); free(l_Wy);
+  return rc;
+}

@@ -17,6 +17,7 @@ WS_OK, WS_EINVAL, WS_ESTATE, WS_EHIP, WS_ENOMEM = 0, -1, -2, -3, -4
 WS_F64, WS_F32 = 0, 1
 WS_LIM_MC, WS_LIM_NONE = 0, 1
 WS_BC_NONE, WS_BC_EXTRAP, WS_BC_PERIODIC = 0, 1, 2
+WS_TILE_DIRECT, WS_TILE_MARCH = 0, 1
 
 #: every symbol the header declares
 EXPORTS = (
@@ -65,7 +66,7 @@ def lib():
         "ws_layout": [P(PatchDesc), i32, i32, i32, P(i64), P(i64)],
         "ws_init_patches": [P(vp), P(PatchDesc), i32, P(Material), i32, i32, i32, i32,
                             vp, vp, i64, vp, i64, vp],
-        "ws_set_tiling": [vp, P(i32), P(i32), i32],
+        "ws_set_tiling": [vp, P(i32), P(i32), P(i32), i32],
         "ws_upload_patch": [vp, i32, vp],
         "ws_download_patch": [vp, i32, vp],
         "ws_fill_ghosts": [vp],

@@ -1,0 +1,166 @@
+"""Tile autotuner for a ``Level``.
+
+Patches are grouped into size classes; for each class (largest total cell
+count first) the tuner times candidate tilings with the library's timing
+entry (HIP events around back-to-back step launches), keeping the other
+classes fixed, then tunes the persistent launch's workgroups per CU.  The
+state is saved before tuning and restored afterwards, and an even number of
+steps is timed per candidate, so the level is left exactly as it was.  The
+tiling never changes results (the library's arithmetic per cell does not
+depend on it), so tuning is safe on a live level.
+
+Choices are cached in a JSON file keyed by GPU architecture, dtype, limiter
+and the patch-size histogram.
+"""
+
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from collections import defaultdict
+
+import numpy as np
+import torch
+
+DIRECT, MARCH = "direct", "march"
+_BUCKETS = (0, 12, 24, 40, 72, 136, 264, 1 << 30)
+_WG_CHOICES = (0, 1, 2, 3, 4, 6, 8)
+
+
+def _bucket(n):
+    for k in range(len(_BUCKETS) - 1):
+        if _BUCKETS[k] <= n < _BUCKETS[k + 1]:
+            return k
+    return len(_BUCKETS) - 2
+
+
+def size_classes(level):
+    """Patch indices grouped by (x bucket, y bucket, periodic)."""
+    cls = defaultdict(list)
+    for k, (mx, my) in enumerate(level.shapes):
+        cls[(_bucket(mx), _bucket(my), level.bcs[k] == "periodic")].append(k)
+    return dict(cls)
+
+
+def candidates(mx, my, periodic):
+    """Tilings worth timing for patches of about mx x my cells."""
+    out = []
+    for tw in (8, 16, 32, 64, 128):
+        if tw > 2 * mx and tw > 8:
+            continue
+        nty = 256 // tw
+        for r in (1, 2, 4, 8):
+            if nty * r > 2 * my and r > 1:
+                continue
+            out.append((DIRECT, tw, nty * r))
+    if not periodic:
+        for w in (16, 32, 64):
+            if w - 4 > 2 * mx and w > 16:
+                continue
+            nseg = 256 // w
+            for r in (4, 8, 16, 32):
+                if nseg * r > 2 * my and r > 4:
+                    continue
+                out.append((MARCH, w, nseg * r))
+    return out
+
+
+def _key(level):
+    arch = torch.cuda.get_device_properties(level.device).gcnArchName
+    hist = sorted({(mx, my, level.bcs[k]) for k, (mx, my) in enumerate(level.shapes)})
+    h = hashlib.sha1(json.dumps([hist, len(level.shapes)]).encode()).hexdigest()[:16]
+    return f"{arch}|{level.dtype}|{level.limiter}|{h}"
+
+
+def _default_cache():
+    return os.path.join(os.path.expanduser("~"), ".cache", "wavestep", "tiling.json")
+
+
+def _apply(level, classes, choice, wg):
+    var = np.zeros(level.n, dtype=object)
+    tw = np.zeros(level.n, np.int32)
+    th = np.zeros(level.n, np.int32)
+    for c, idx in classes.items():
+        v, w, h = choice[c]
+        for k in idx:
+            var[k], tw[k], th[k] = v, w, h
+    level.set_tiling(tw, th, wg_per_cu=wg, variant=list(var))
+
+
+def autotune(level, *, launches=20, use_cache=True, cache_path=None, verbose=False):
+    """Pick a tiling for ``level`` and apply it.  Returns the choice as a dict
+    {"classes": {class: (variant, tile_w, tile_h)}, "wg_per_cu": n, "ms": t}."""
+    launches += launches % 2  # even: the state returns to its pool
+    classes = size_classes(level)
+    cache_path = cache_path or _default_cache()
+    key = _key(level)
+    cache = {}
+    if use_cache and os.path.exists(cache_path):
+        try:
+            cache = json.load(open(cache_path))
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        ent = cache[key]
+        choice = {tuple(json.loads(c)): tuple(v) for c, v in ent["classes"].items()}
+        if set(choice) == set(classes):
+            _apply(level, classes, choice, ent["wg_per_cu"])
+            return {"classes": choice, "wg_per_cu": ent["wg_per_cu"], "ms": ent["ms"],
+                    "cached": True}
+
+    saved = [p.clone() for p in level.pools]
+    torch.cuda.synchronize(level.device)
+
+    def timed(choice, wg):
+        _apply(level, classes, choice, wg)
+        level.time_step_kernel(2)
+        return level.time_step_kernel(launches)
+
+    # start from each class's first-fit default: the widest DIRECT tile
+    choice = {}
+    for c, idx in classes.items():
+        mx = max(level.shapes[k][0] for k in idx)
+        my = max(level.shapes[k][1] for k in idx)
+        cands = candidates(mx, my, c[2])
+        choice[c] = cands[0]
+    wg = 0
+    best = timed(choice, wg)
+    order = sorted(classes, key=lambda c: -sum(level.shapes[k][0] * level.shapes[k][1]
+                                                for k in classes[c]))
+    for c in order:
+        idx = classes[c]
+        mx = int(np.median([level.shapes[k][0] for k in idx]))
+        my = int(np.median([level.shapes[k][1] for k in idx]))
+        for cand in candidates(mx, my, c[2]):
+            if cand == choice[c]:
+                continue
+            trial = dict(choice)
+            trial[c] = cand
+            t = timed(trial, wg)
+            if verbose:
+                print(f"class {c} {cand}: {t:.4f} ms", flush=True)
+            if t < best:
+                best, choice = t, trial
+    for w in _WG_CHOICES:
+        if w == wg:
+            continue
+        t = timed(choice, w)
+        if verbose:
+            print(f"wg_per_cu {w}: {t:.4f} ms", flush=True)
+        if t < best:
+            best, wg = t, w
+    _apply(level, classes, choice, wg)
+    torch.cuda.synchronize(level.device)
+    for p, s in zip(level.pools, saved):
+        p.copy_(s)
+    torch.cuda.synchronize(level.device)
+    if use_cache:
+        cache[key] = {"classes": {json.dumps(list(c)): list(v) for c, v in choice.items()},
+                      "wg_per_cu": wg, "ms": best}
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, cache_path)
+    return {"classes": choice, "wg_per_cu": wg, "ms": best, "cached": False}

@@ -86,15 +86,23 @@ PoolLayout pool_layout(const ws_patch_desc *p, int n, int dtype) {
   return L;
 }
 
-int64_t tiles_of(int mx, int my, int tw, int th) {
-  return (int64_t)((mx + tw - 1) / tw) * ((my + th - 1) / th);
+// Columns a tile updates: DIRECT tw, MARCH tw - 4 (two halo lanes per side).
+int tile_cols(int variant, int tw) { return variant == kMarch ? tw - 4 : tw; }
+
+int64_t tiles_of(int mx, int my, int variant, int tw, int th) {
+  const int cols = tile_cols(variant, tw);
+  return (int64_t)((mx + cols - 1) / cols) * ((my + th - 1) / th);
 }
 
+// Upper bound of the tile count over every valid tiling (sizes the workspace).
 int64_t max_tiles_of(const ws_patch_desc *p, int n) {
   int64_t t = 0;
   for (int k = 0; k < n; ++k) {
     int64_t m = 0;
-    for (int tw : kTileWidths) m = std::max(m, tiles_of(p[k].mx, p[k].my, tw, kThreads / tw));
+    for (int tw : kTileWidths) {
+      m = std::max(m, tiles_of(p[k].mx, p[k].my, kDirect, tw, kThreads / tw));
+      if (tw >= 16 && tw <= 64) m = std::max(m, tiles_of(p[k].mx, p[k].my, kMarch, tw, kThreads / tw));
+    }
     t += m;
   }
   return t;
@@ -113,35 +121,42 @@ WsLayout ws_layout_of(const ws_patch_desc *p, int n, int n_inst) {
   L.inst = take((int64_t)n_inst * sizeof(InstRow));
   L.tiles = take(L.max_tiles * (int64_t)sizeof(TileEntry));
   L.dt = take(8LL * n_inst);
-  L.cfl_acc = take(8LL * n_inst);
+  L.cfl_tile = take(8 * L.max_tiles);
   L.cfl_last = take(8LL * n_inst);
   L.cfl_max = take(8LL * n_inst);
-  L.cfl_patch_acc = take(8LL * n);
   L.cfl_patch_last = take(8LL * n);
-  L.level_acc = take(8);
   L.level_last = take(8);
-  L.counters = take(16);
+  L.retire = take(4LL * kLine * (kGroups + 1));
   L.partials = take(24 * L.max_tiles);
   L.sums = take(24LL * n_inst);
   L.total = cur;
   return L;
 }
 
-bool valid_tile(int tw, int th) {
+bool valid_tile(int variant, int tw, int th) {
+  if (variant != kDirect && variant != kMarch) return false;
   bool ok_w = false;
   for (int w : kTileWidths) ok_w |= (w == tw);
   if (!ok_w) return false;
+  if (variant == kMarch && (tw < 16 || tw > 64)) return false;
   const int nty = kThreads / tw;
-  return th >= nty && th % nty == 0 && th / nty <= kMaxRowsPerThread;
+  const int rmax = variant == kMarch ? kMaxMarchRows : kMaxRowsPerThread;
+  return th >= nty && th % nty == 0 && th / nty <= rmax;
 }
 
-// Default tile: the width in {8..64} (256 for very wide patches) that wastes
-// the fewest columns, larger on ties; up to 8 rows per thread.
-void default_tile(int mx, int my, int *tw, int *th) {
+// Default tiling.  Wide patches: MARCH segments of 64 lanes, 16 rows each.
+// Narrow patches: DIRECT tiles whose width in {8..64} wastes the fewest
+// columns (larger on ties), up to 8 rows per thread.
+void default_tile(int mx, int my, int bc, int *variant, int *tw, int *th) {
+  if (mx >= 120 && bc != WS_BC_PERIODIC) {
+    *variant = kMarch;
+    *tw = 64;
+    *th = (kThreads / 64) * std::max(1, std::min(kMaxMarchRows, (my + 3) / 4));
+    return;
+  }
+  *variant = kDirect;
   int best = 64;
-  if (mx >= 256) {
-    best = 64;
-  } else {
+  {
     int64_t best_waste = -1;
     for (int w : {64, 32, 16, 8}) {
       const int64_t waste = (int64_t)((mx + w - 1) / w) * w - mx;
@@ -195,6 +210,8 @@ struct ws_ctx {
   std::vector<TileEntry> tiles;
   std::vector<int> order;  // patches largest first
   int n_cu = 0, wg_per_cu = 0, grid = 0, occupancy = 0;
+  int vars = 1;          // tile variants present (bit 0 DIRECT, bit 1 MARCH)
+  int wg_override = 0;   // workgroups per CU set by the caller (0: occupancy)
   int max_padded_cells = 0;
   double *host_buf = nullptr;
   int64_t host_buf_bytes = 0;
@@ -205,13 +222,12 @@ struct ws_ctx {
   CflSlots slots() {
     CflSlots c;
     c.dt = reinterpret_cast<double *>(ws + L.dt);
-    c.cfl_acc = reinterpret_cast<unsigned long long *>(ws + L.cfl_acc);
+    c.cfl_tile = reinterpret_cast<double *>(ws + L.cfl_tile);
     c.cfl_last = reinterpret_cast<double *>(ws + L.cfl_last);
     c.cfl_max = reinterpret_cast<double *>(ws + L.cfl_max);
-    c.cfl_patch_acc = reinterpret_cast<unsigned long long *>(ws + L.cfl_patch_acc);
     c.cfl_patch_last = reinterpret_cast<double *>(ws + L.cfl_patch_last);
-    c.level_acc = reinterpret_cast<unsigned long long *>(ws + L.level_acc);
     c.level_last = reinterpret_cast<double *>(ws + L.level_last);
+    c.patches = d_patches();
     c.n_inst = n_inst;
     c.n_patches = n_patches;
     return c;
@@ -219,8 +235,7 @@ struct ws_ctx {
   const PatchRow *d_patches() const { return reinterpret_cast<const PatchRow *>(ws + L.patches); }
   const TileEntry *d_tiles() const { return reinterpret_cast<const TileEntry *>(ws + L.tiles); }
 
-  StepArgs step_args(int src) {
-    CflSlots c = slots();
+  StepArgs step_args(int src, double dt_override, double cfl_desired) {
     StepArgs a{};
     a.patches = d_patches();
     a.tiles = d_tiles();
@@ -230,11 +245,11 @@ struct ws_ctx {
     a.qin = pool[src];
     a.qout = pool[1 - src];
     a.inst = reinterpret_cast<const InstRow *>(ws + L.inst);
-    a.dt = c.dt;
-    a.cfl_acc = c.cfl_acc;
-    a.cfl_patch = c.cfl_patch_acc;
-    a.cfl_level = c.level_acc;
-    a.counters = reinterpret_cast<unsigned int *>(ws + L.counters);
+    a.slots = slots();
+    a.dt = a.slots.dt;
+    a.dt_override = dt_override;
+    a.cfl_desired = cfl_desired;
+    a.retire = reinterpret_cast<unsigned int *>(ws + L.retire);
     a.masks = nullptr;
     return a;
   }
@@ -252,7 +267,8 @@ struct ws_ctx {
     tiles.clear();
     for (int k : order) {
       PatchRow &r = rows[k];
-      r.ntx = (r.mx + r.tw - 1) / r.tw;
+      const int cols = tile_cols(r.variant, r.tw);
+      r.ntx = (r.mx + cols - 1) / cols;
       r.nty = (r.my + r.th - 1) / r.th;
       r.tile_begin = (int32_t)tiles.size();
       for (int ty = 0; ty < r.nty; ++ty)
@@ -260,6 +276,10 @@ struct ws_ctx {
       r.n_tiles = (int32_t)tiles.size() - r.tile_begin;
     }
     if ((int64_t)tiles.size() > L.max_tiles) return fail(WS_EINVAL, "tile list overflow");
+    vars = 0;
+    for (const PatchRow &r : rows) vars |= (r.variant == kMarch) ? 2 : 1;
+    if (step_occupancy(dtype, limiter, vars, &occupancy) != 0 || occupancy < 1) occupancy = 1;
+    wg_per_cu = wg_override > 0 ? wg_override : occupancy;
     HIPCHK(hipMemcpyAsync(ws + L.patches, rows.data(), rows.size() * sizeof(PatchRow),
                           hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(ws + L.tiles, tiles.data(), tiles.size() * sizeof(TileEntry),
@@ -334,8 +354,6 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
   if (hipGetDevice(&dev) != hipSuccess) return bail(fail(WS_EHIP, "hipGetDevice failed"));
   if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return bail(fail(WS_EHIP, "cannot query the CU count"));
-  if (step_occupancy(dtype, limiter, &c->occupancy) != 0 || c->occupancy < 1) c->occupancy = 1;
-  c->wg_per_cu = c->occupancy;
 
   std::vector<InstRow> inst(n_instances);
   for (int k = 0; k < n_instances; ++k) {
@@ -355,7 +373,7 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
     r.plane = c->P.plane[k];
     r.inst = d.instance;
     r.bc = d.bc;
-    default_tile(d.mx, d.my, &r.tw, &r.th);
+    default_tile(d.mx, d.my, d.bc, &r.variant, &r.tw, &r.th);
     r.dx = d.dx;
     r.dy = d.dy;
     r.mask_off = mask_off;
@@ -382,22 +400,29 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
   return WS_OK;
 }
 
-int ws_set_tiling(ws_ctx *c, const int32_t *tile_w, const int32_t *tile_h, int32_t wg_per_cu) {
+int ws_set_tiling(ws_ctx *c, const int32_t *variant, const int32_t *tile_w,
+                  const int32_t *tile_h, int32_t wg_per_cu) {
   if (!c) return fail(WS_EINVAL, "ctx is NULL");
-  if ((tile_w == nullptr) != (tile_h == nullptr))
-    return fail(WS_EINVAL, "give both tile_w and tile_h, or neither");
+  if ((tile_w == nullptr) != (tile_h == nullptr) || (variant != nullptr && tile_w == nullptr))
+    return fail(WS_EINVAL, "give variant, tile_w and tile_h together, or none");
   if (wg_per_cu < 0 || wg_per_cu > 64) return fail(WS_EINVAL, "wg_per_cu out of range");
   if (tile_w)
-    for (int k = 0; k < c->n_patches; ++k)
-      if (!valid_tile(tile_w[k], tile_h[k]))
-        return fail(WS_EINVAL, "patch %d: invalid tile %dx%d", k, tile_w[k], tile_h[k]);
+    for (int k = 0; k < c->n_patches; ++k) {
+      const int v = variant ? variant[k] : kDirect;
+      if (!valid_tile(v, tile_w[k], tile_h[k]))
+        return fail(WS_EINVAL, "patch %d: invalid tile variant %d, %dx%d", k, v, tile_w[k],
+                    tile_h[k]);
+      if (v == kMarch && c->rows[k].bc == WS_BC_PERIODIC)
+        return fail(WS_EINVAL, "patch %d: periodic patches take DIRECT tiles only", k);
+    }
   HIPCHK(hipStreamSynchronize(c->stream));
   if (tile_w)
     for (int k = 0; k < c->n_patches; ++k) {
+      c->rows[k].variant = variant ? variant[k] : kDirect;
       c->rows[k].tw = tile_w[k];
       c->rows[k].th = tile_h[k];
     }
-  if (wg_per_cu > 0) c->wg_per_cu = wg_per_cu;
+  if (wg_per_cu > 0) c->wg_override = wg_per_cu;
   c->drop_graph();
   return c->build_tiles();
 }
@@ -449,10 +474,9 @@ static int read_level_cfl(ws_ctx *c, double *cfl_out) {
 int ws_step_level(ws_ctx *c, double dt, double *cfl_out) {
   if (!c) return fail(WS_EINVAL, "ctx is NULL");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
-  HIPCHK(launch_set_dt(c->slots(), dt, c->stream));
-  StepArgs a = c->step_args(c->cur);
-  HIPCHK(launch_step(c->dtype, c->limiter, a, c->grid, c->stream));
-  HIPCHK(launch_finish_step(c->slots(), 0.0, c->stream));
+  // one persistent launch; its last workgroup also files the Courant numbers
+  StepArgs a = c->step_args(c->cur, dt, 0.0);
+  HIPCHK(launch_step(c->dtype, c->limiter, c->vars, a, c->grid, c->stream));
   c->cur = 1 - c->cur;
   return read_level_cfl(c, cfl_out);
 }
@@ -461,11 +485,11 @@ int ws_step_level_per_patch(ws_ctx *c, double dt, double *cfl_out) {
   if (!c) return fail(WS_EINVAL, "ctx is NULL");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
   HIPCHK(launch_set_dt(c->slots(), dt, c->stream));
-  StepArgs a = c->step_args(c->cur);
+  StepArgs a = c->step_args(c->cur, 0.0, 0.0);
   a.persistent = 0;
   for (int k : c->order) {  // largest patch first
     a.tile_base = c->rows[k].tile_begin;
-    HIPCHK(launch_step(c->dtype, c->limiter, a, c->rows[k].n_tiles, c->stream));
+    HIPCHK(launch_step(c->dtype, c->limiter, c->vars, a, c->rows[k].n_tiles, c->stream));
   }
   HIPCHK(launch_finish_step(c->slots(), 0.0, c->stream));
   c->cur = 1 - c->cur;
@@ -488,9 +512,8 @@ int ws_set_dt(ws_ctx *c, const double *dt_per_instance) {
 }
 
 static int enqueue_auto(ws_ctx *c, int src, double cfl_desired) {
-  StepArgs a = c->step_args(src);
-  HIPCHK(launch_step(c->dtype, c->limiter, a, c->grid, c->stream));
-  HIPCHK(launch_finish_step(c->slots(), cfl_desired, c->stream));
+  StepArgs a = c->step_args(src, 0.0, cfl_desired);
+  HIPCHK(launch_step(c->dtype, c->limiter, c->vars, a, c->grid, c->stream));
   return WS_OK;
 }
 
@@ -587,16 +610,16 @@ int ws_time_step_kernel(ws_ctx *c, int32_t n_launches, int32_t per_patch, double
   int rc = WS_OK;
   hipError_t e = hipEventRecord(e0, c->stream);
   for (int s = 0; s < n_launches && e == hipSuccess; ++s) {
-    StepArgs a = c->step_args(c->cur);
+    StepArgs a = c->step_args(c->cur, 0.0, 0.0);
     if (per_patch) {
       a.persistent = 0;
       for (int k : c->order) {
         a.tile_base = c->rows[k].tile_begin;
-        e = launch_step(c->dtype, c->limiter, a, c->rows[k].n_tiles, c->stream);
+        e = launch_step(c->dtype, c->limiter, c->vars, a, c->rows[k].n_tiles, c->stream);
         if (e != hipSuccess) break;
       }
     } else {
-      e = launch_step(c->dtype, c->limiter, a, c->grid, c->stream);
+      e = launch_step(c->dtype, c->limiter, c->vars, a, c->grid, c->stream);
     }
     c->cur = 1 - c->cur;
   }

@@ -8,7 +8,16 @@
 namespace ws {
 
 constexpr int kThreads = 256;  // threads per workgroup of every tile kernel
-constexpr int kMaxRowsPerThread = 32;
+constexpr int kGroups = 8;     // tile groups of the persistent launch, one per XCD
+constexpr int kLine = 32;      // retirement counters sit 128 bytes (32 uints) apart
+constexpr int kMaxRowsPerThread = 64;  // DIRECT tiles
+constexpr int kMaxMarchRows = 64;      // MARCH segments
+
+// Tile kernels.  DIRECT: one thread per column, every cell computed from its
+// 13-point footprint.  MARCH: lane segments sweep up their columns carrying
+// the y-direction terms in registers and exchanging x-direction terms with
+// neighbouring lanes; a segment of w lanes updates w-4 columns.
+enum TileVariant { kDirect = 0, kMarch = 1 };
 
 // One row of the device patch table.
 struct PatchRow {
@@ -19,11 +28,13 @@ struct PatchRow {
   int64_t plane;   // plane stride (elements): ld * (my + 4)
   int32_t inst;    // instance (material, dt)
   int32_t bc;      // WS_BC_*
-  int32_t tw, th;  // tile shape
+  int32_t variant;  // TileVariant
+  int32_t tw, th;  // DIRECT: tile of tw x th cells; MARCH: segments of tw lanes, th rows
   int32_t ntx, nty;  // tiles in x and y
   double dx, dy;
   int64_t mask_off;  // byte offset of the patch's (mx+1)*(my+1) mask bytes
   int32_t tile_begin, n_tiles;  // the patch's tiles in the tile list
+  int32_t pad_;
 };
 
 struct TileEntry {
@@ -37,21 +48,20 @@ struct InstRow {
 
 // Workspace carve-up (byte offsets inside the caller's workspace buffer).
 struct WsLayout {
-  int64_t patches, inst, tiles, dt, cfl_acc, cfl_last, cfl_max, cfl_patch_acc,
-      cfl_patch_last, level_acc, level_last, counters, partials, sums, total;
+  int64_t patches, inst, tiles, dt, cfl_tile, cfl_last, cfl_max, cfl_patch_last, level_last,
+      retire, partials, sums, total;
   int64_t max_tiles;
 };
 
-// Per-step bookkeeping slots inside the workspace.
+// Per-step Courant-number bookkeeping inside the workspace.
 struct CflSlots {
-  double *dt;                         // [n_inst]
-  unsigned long long *cfl_acc;        // [n_inst]   max over the step (bit patterns)
-  double *cfl_last;                   // [n_inst]   Courant number of the last step
-  double *cfl_max;                    // [n_inst]   largest since ws_set_dt
-  unsigned long long *cfl_patch_acc;  // [n_patches]
-  double *cfl_patch_last;             // [n_patches]
-  unsigned long long *level_acc;      // [1]
-  double *level_last;                 // [1]
+  double *dt;              // [n_inst]
+  double *cfl_tile;        // [n_tiles] Courant number of each tile of the step
+  double *cfl_last;        // [n_inst]  Courant number of the last step
+  double *cfl_max;         // [n_inst]  largest since ws_set_dt
+  double *cfl_patch_last;  // [n_patches]
+  double *level_last;      // [1]
+  const PatchRow *patches;
   int n_inst, n_patches;
 };
 
@@ -60,20 +70,22 @@ struct StepArgs {
   const TileEntry *tiles;
   int32_t n_tiles;
   int32_t tile_base;   // direct mode: first tile of this launch
-  int32_t persistent;  // 1: pull tiles from counters[0]; 0: tile = base + blockIdx
+  int32_t persistent;  // 1: persistent launch over all tiles; 0: tile = base + blockIdx
   const void *qin;
   void *qout;
   const InstRow *inst;
-  const double *dt;  // per instance
-  unsigned long long *cfl_acc;    // per instance, FP64 bit patterns (>= 0)
-  unsigned long long *cfl_patch;  // per patch
-  unsigned long long *cfl_level;  // one slot
-  unsigned int *counters;         // [0] next tile, [1] retired workgroups
-  uint8_t *masks;                 // nullptr unless the branches are recorded
+  double *dt;          // per instance
+  double dt_override;  // > 0: every instance steps with this dt (stored into dt)
+  double cfl_desired;  // > 0: after the step, dt <- dt * cfl_desired / cfl
+  CflSlots slots;
+  unsigned int *retire;  // (kGroups + 1) counters, kLine apart
+  uint8_t *masks;        // nullptr unless the branches are recorded
 };
 
 // Kernel launchers (defined in ws_kernels.hip).
-hipError_t launch_step(int dtype, int limiter, const StepArgs &a, int grid, hipStream_t s);
+// vars: bit 0 -> DIRECT tiles present, bit 1 -> MARCH tiles present.
+hipError_t launch_step(int dtype, int limiter, int vars, const StepArgs &a, int grid,
+                       hipStream_t s);
 hipError_t launch_fill_ghosts(int dtype, const PatchRow *patches, int n_patches,
                               int max_padded_cells, void *q, hipStream_t s);
 // dt[k] = value for every instance.
@@ -84,6 +96,6 @@ hipError_t launch_set_dt(const CflSlots &c, double value, hipStream_t s);
 hipError_t launch_finish_step(const CflSlots &c, double cfl_desired, hipStream_t s);
 hipError_t launch_sums(int dtype, const PatchRow *patches, const TileEntry *tiles, int n_tiles,
                        const void *q, double *partials, int n_inst, double *sums, hipStream_t s);
-int step_occupancy(int dtype, int limiter, int *wg_per_cu);
+int step_occupancy(int dtype, int limiter, int vars, int *wg_per_cu);
 
 }  // namespace ws

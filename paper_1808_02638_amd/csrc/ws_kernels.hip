@@ -34,6 +34,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "ws_internal.h"
 #include "../../include/wavestep.h"
 
@@ -52,25 +54,36 @@ struct Coef {
   T dtdx, dtdy;
 };
 
+// Wave-uniform values are moved to scalar registers.
+__device__ inline double uniform(double v) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+__device__ inline float uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 template <typename T>
 __device__ inline Coef<T> make_coef(double c, double Z, double dt, double dx, double dy) {
-  const double dtdx = dt / dx, dtdy = dt / dy;
+  const double dtdx = dt / dx, dtdy = dt / dy, iz = 1.0 / Z;
   const double fx = 0.25 * c * (1.0 - c * dtdx), fy = 0.25 * c * (1.0 - c * dtdy);
   const double gx = 0.125 * dtdx * c * c, gy = 0.125 * dtdy * c * c;
   Coef<T> k;
   k.Z = (T)Z;
   k.h = (T)(0.5 * c);
-  k.hz = (T)(0.5 * c / Z);
+  k.hz = (T)(0.5 * c * iz);
   k.fx = (T)fx;
-  k.fxz = (T)(fx / Z);
+  k.fxz = (T)(fx * iz);
   k.fy = (T)fy;
-  k.fyz = (T)(fy / Z);
+  k.fyz = (T)(fy * iz);
   k.gx = (T)gx;
-  k.gxz = (T)(gx / Z);
+  k.gxz = (T)(gx * iz);
   k.gy = (T)gy;
-  k.gyz = (T)(gy / Z);
+  k.gyz = (T)(gy * iz);
   k.dtdx = (T)dtdx;
   k.dtdy = (T)dtdy;
+  T *f = &k.Z;
+  for (int n = 0; n < (int)(sizeof(Coef<T>) / sizeof(T)); ++n) f[n] = uniform(f[n]);
   return k;
 }
 
@@ -106,6 +119,39 @@ __device__ inline T s1(T Z, T dp, T dn) { return fma(Z, dn, -dp); }
 template <typename T>
 __device__ inline T s2(T Z, T dp, T dn) { return fma(Z, dn, dp); }
 
+// F~ at an x-edge: limited correction of its two waves (wave -c takes its
+// upwind neighbour on the right, wave +c on the left) plus the transverse
+// waves A-+ split from the y-fluctuations of the cells left and right.
+template <typename T, int LIM>
+__device__ inline void ftilde(const Coef<T> &k, T a1, T a2, T a1_right, T a2_left, T ys_left,
+                              T ys_right, T &Fp, T &Fu) {
+  const T l1 = limited<T, LIM>(a1, a1_right), l2 = limited<T, LIM>(a2, a2_left);
+  const T Fcp = k.fx * (l2 - l1), Fcu = k.fxz * (l1 + l2);
+  Fp = Fcp - k.gy * (ys_left - ys_right);
+  Fu = Fcu - k.gyz * (ys_right + ys_left);
+}
+
+// G~ at a y-edge, the mirror image: transverse waves B-+ split from the
+// x-fluctuations of the cells below (lo) and above (hi).
+template <typename T, int LIM>
+__device__ inline void gtilde(const Coef<T> &k, T b1, T b2, T b1_up, T b2_down, T xs_lo, T xs_hi,
+                              T &Gp, T &Gv) {
+  const T l1 = limited<T, LIM>(b1, b1_up), l2 = limited<T, LIM>(b2, b2_down);
+  const T Gcp = k.fy * (l2 - l1), Gcv = k.fyz * (l1 + l2);
+  Gp = Gcp - k.gx * (xs_lo - xs_hi);
+  Gv = Gcv - k.gxz * (xs_hi + xs_lo);
+}
+
+// Flux-differencing update of one cell, eq. (2.3).
+template <typename T>
+__device__ inline void update(const Coef<T> &k, T p0, T u0, T v0, T xs0, T xd0, T ys0, T yd0,
+                              T FLp, T FLu, T FRp, T FRu, T GBp, T GBv, T GTp, T GTv, T &pn, T &un,
+                              T &vn) {
+  pn = p0 - k.dtdx * (k.h * xs0 + (FRp - FLp)) - k.dtdy * (k.h * ys0 + (GTp - GBp));
+  un = u0 - k.dtdx * (k.hz * xd0 + (FRu - FLu));
+  vn = v0 - k.dtdy * (k.hz * yd0 + (GTv - GBv));
+}
+
 // Padded planes of one patch, indexed by interior coordinates (i, j).
 template <typename T>
 struct Planes {
@@ -122,7 +168,8 @@ struct CellMasks {
   unsigned top;    // bits 4-7 of the top y-edge (stored at cell j+1)
 };
 
-// The whole update of one interior cell from its 13-point footprint.
+// DIRECT path: the whole update of one interior cell from its 13-point
+// footprint.
 template <typename T, int LIM, bool MASKS>
 __device__ inline void cell_update(const Planes<T> &q, int i, int j, const Coef<T> &k, T &pn,
                                    T &un, T &vn, CellMasks *mk) {
@@ -145,42 +192,27 @@ __device__ inline void cell_update(const Planes<T> &q, int i, int j, const Coef<
   const T b1T = s1(Z, qp1 - p0, vp1 - v0), b2T = s2(Z, qp1 - p0, vp1 - v0);
   const T b1TT = s1(Z, qp2 - qp1, vp2 - vp1);
 
-  // ---- normal corrections (limited waves)
-  const T l1L = limited<T, LIM>(a1L, a1R), l2L = limited<T, LIM>(a2L, a2LL);
-  const T l1R = limited<T, LIM>(a1R, a1RR), l2R = limited<T, LIM>(a2R, a2L);
-  const T l1B = limited<T, LIM>(b1B, b1T), l2B = limited<T, LIM>(b2B, b2BB);
-  const T l1T = limited<T, LIM>(b1T, b1TT), l2T = limited<T, LIM>(b2T, b2B);
-  const T FcLp = k.fx * (l2L - l1L), FcLu = k.fxz * (l1L + l2L);
-  const T FcRp = k.fx * (l2R - l1R), FcRu = k.fxz * (l1R + l2R);
-  const T GcBp = k.fy * (l2B - l1B), GcBv = k.fyz * (l1B + l2B);
-  const T GcTp = k.fy * (l2T - l1T), GcTv = k.fyz * (l1T + l2T);
-
-  // ---- first-order fluctuations entering the cell
+  // ---- first-order fluctuations entering the cell (and its neighbours)
   const T xs0 = a2L + a1R, xd0 = a2L - a1R;
   const T ys0 = b2B + b1T, yd0 = b2B - b1T;
-  // xs of the rows below and above (for the transverse split into G~)
   const T pdm = q.P(i - 1, j - 1), pdp = q.P(i + 1, j - 1);
   const T udm = q.U(i - 1, j - 1), udp = q.U(i + 1, j - 1);
   const T xsm = s2(Z, qm1 - pdm, q.U(i, j - 1) - udm) + s1(Z, pdp - qm1, udp - q.U(i, j - 1));
   const T pum = q.P(i - 1, j + 1), pup = q.P(i + 1, j + 1);
   const T uum = q.U(i - 1, j + 1), uup = q.U(i + 1, j + 1);
   const T xsp = s2(Z, qp1 - pum, q.U(i, j + 1) - uum) + s1(Z, pup - qp1, uup - q.U(i, j + 1));
-  // ys of the columns left and right (for the transverse split into F~)
   const T vlm = q.V(i - 1, j - 1), vl0 = q.V(i - 1, j), vlp = q.V(i - 1, j + 1);
   const T ysl = s2(Z, pm1 - pdm, vl0 - vlm) + s1(Z, pum - pm1, vlp - vl0);
   const T vrm = q.V(i + 1, j - 1), vr0 = q.V(i + 1, j), vrp = q.V(i + 1, j + 1);
   const T ysr = s2(Z, pp1 - pdp, vr0 - vrm) + s1(Z, pup - pp1, vrp - vr0);
 
-  // ---- corrections plus transverse waves
-  const T FLp = FcLp - k.gy * (ysl - ys0), FLu = FcLu - k.gyz * (ys0 + ysl);
-  const T FRp = FcRp - k.gy * (ys0 - ysr), FRu = FcRu - k.gyz * (ysr + ys0);
-  const T GBp = GcBp - k.gx * (xsm - xs0), GBv = GcBv - k.gxz * (xs0 + xsm);
-  const T GTp = GcTp - k.gx * (xs0 - xsp), GTv = GcTv - k.gxz * (xsp + xs0);
-
-  // ---- flux-differencing update, eq. (2.3)
-  pn = p0 - k.dtdx * (k.h * xs0 + (FRp - FLp)) - k.dtdy * (k.h * ys0 + (GTp - GBp));
-  un = u0 - k.dtdx * (k.hz * xd0 + (FRu - FLu));
-  vn = v0 - k.dtdy * (k.hz * yd0 + (GTv - GBv));
+  // ---- F~ and G~ on the four edges, then the update
+  T FLp, FLu, FRp, FRu, GBp, GBv, GTp, GTv;
+  ftilde<T, LIM>(k, a1L, a2L, a1R, a2LL, ysl, ys0, FLp, FLu);
+  ftilde<T, LIM>(k, a1R, a2R, a1RR, a2L, ys0, ysr, FRp, FRu);
+  gtilde<T, LIM>(k, b1B, b2B, b1T, b2BB, xsm, xs0, GBp, GBv);
+  gtilde<T, LIM>(k, b1T, b2T, b1TT, b2B, xs0, xsp, GTp, GTv);
+  update<T>(k, p0, u0, v0, xs0, xd0, ys0, yd0, FLp, FLu, FRp, FRu, GBp, GBv, GTp, GTv, pn, un, vn);
 
   if constexpr (MASKS) {
     mk->own = mc_branch(a1L, a1R) | (mc_branch(a2L, a2LL) << 2) | (mc_branch(b1B, b1T) << 4) |
@@ -190,32 +222,194 @@ __device__ inline void cell_update(const Planes<T> &q, int i, int j, const Coef<
   }
 }
 
-// Store a new cell value and, on physical boundaries, its ghost images.
+// Store a new cell value and, on physical boundaries, its ghost images.  Up
+// to 5 column and 5 row positions (the cell and its images); the loops are
+// fully unrolled so everything stays in registers.
 template <typename T>
 __device__ inline void store_cell(T *op, T *ou, T *ov, int64_t ld, int i, int j, int mx, int my,
                                   int bc, T pn, T un, T vn) {
-  int xi[5], yj[5];
-  int nx = 0, ny = 0;
-  xi[nx++] = i;
-  yj[ny++] = j;
+  constexpr int kNone = INT_MIN;
+  int xi[5] = {i, kNone, kNone, kNone, kNone};
+  int yj[5] = {j, kNone, kNone, kNone, kNone};
   if (bc == WS_BC_EXTRAP) {
-    if (i == 0) { xi[nx++] = -1; xi[nx++] = -2; }
-    if (i == mx - 1) { xi[nx++] = mx; xi[nx++] = mx + 1; }
-    if (j == 0) { yj[ny++] = -1; yj[ny++] = -2; }
-    if (j == my - 1) { yj[ny++] = my; yj[ny++] = my + 1; }
+    if (i == 0) { xi[1] = -1; xi[2] = -2; }
+    if (i == mx - 1) { xi[3] = mx; xi[4] = mx + 1; }
+    if (j == 0) { yj[1] = -1; yj[2] = -2; }
+    if (j == my - 1) { yj[3] = my; yj[4] = my + 1; }
   } else if (bc == WS_BC_PERIODIC) {
-    if (i < 2) xi[nx++] = mx + i;
-    if (i >= mx - 2) xi[nx++] = i - mx;
-    if (j < 2) yj[ny++] = my + j;
-    if (j >= my - 2) yj[ny++] = j - my;
+    if (i < 2) xi[1] = mx + i;
+    if (i >= mx - 2) xi[2] = i - mx;
+    if (j < 2) yj[1] = my + j;
+    if (j >= my - 2) yj[2] = j - my;
   }
-  for (int b = 0; b < ny; ++b)
-    for (int a = 0; a < nx; ++a) {
-      const int64_t o = (int64_t)yj[b] * ld + xi[a];
-      op[o] = pn;
-      ou[o] = un;
-      ov[o] = vn;
+#pragma unroll
+  for (int b = 0; b < 5; ++b)
+#pragma unroll
+    for (int a = 0; a < 5; ++a)
+      if (xi[a] != kNone && yj[b] != kNone) {
+        const int64_t o = (int64_t)yj[b] * ld + xi[a];
+        op[o] = pn;
+        ou[o] = un;
+        ov[o] = vn;
+      }
+}
+
+// Store, taking the ghost-image path only for cells next to a physical side.
+template <typename T>
+__device__ inline void store(T *qo, int64_t plane, int64_t ld, int i, int j, int mx, int my, int bc,
+                             T pn, T un, T vn) {
+  if (bc != WS_BC_NONE && (i < 2 || i >= mx - 2 || j < 2 || j >= my - 2)) {
+    store_cell<T>(qo, qo + plane, qo + 2 * plane, ld, i, j, mx, my, bc, pn, un, vn);
+  } else {
+    const int64_t o = (int64_t)j * ld + i;
+    qo[o] = pn;
+    qo[plane + o] = un;
+    qo[2 * plane + o] = vn;
+  }
+}
+
+// Whole-wavefront lane shifts (DPP): shr gives lane l the value of lane l-1,
+// shl the value of lane l+1.  Lanes without a source read 0 (never used).
+__device__ inline int dpp_shr_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ inline int dpp_shl_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ inline double shr(double v) {
+  return __hiloint2double(dpp_shr_i(__double2hiint(v)), dpp_shr_i(__double2loint(v)));
+}
+__device__ inline double shl(double v) {
+  return __hiloint2double(dpp_shl_i(__double2hiint(v)), dpp_shl_i(__double2loint(v)));
+}
+__device__ inline float shr(float v) { return __int_as_float(dpp_shr_i(__float_as_int(v))); }
+__device__ inline float shl(float v) { return __int_as_float(dpp_shl_i(__float_as_int(v))); }
+
+// MARCH path for one segment: lanes l = 0..w-1 hold columns i = c0-2+l, the
+// segment updates columns c0..c0+w-5 (lanes 2..w-3) over rows [r0, r1).
+// Every lane loads its own column only; x-neighbour terms come through lane
+// shifts; y-direction terms slide up the column in registers.  Each quantity
+// uses the same expression as in cell_update, so the result is bitwise equal.
+template <typename T, int LIM, bool MASKS>
+__device__ inline void march_segment(const T *qi, T *qo, const PatchRow &pr, const Coef<T> &k,
+                                     int l, int w, int i, int r0, int r1, uint8_t *masks) {
+  const T Z = k.Z;
+  const unsigned ld = (unsigned)pr.ld, pl = (unsigned)pr.plane;
+  // lanes past the last ghost column read that column instead (never used)
+  const int ic = min(i, pr.mx + 1);
+  // Unsigned 32-bit byte offsets from the padded origin (cell -2,-2 of plane
+  // p) off a wave-uniform base: ((row+2) * ld + column+2) * sizeof(T); planes
+  // u, v follow at +plb, +2 plb.  Patches hold < 2^29 elements.
+  const char *base = reinterpret_cast<const char *>(qi - 2 * (int64_t)ld - 2);
+  const unsigned plb = pl * (unsigned)sizeof(T);
+  auto at = [&](int r) {
+    return ((unsigned)(r + 2) * ld + (unsigned)(ic + 2)) * (unsigned)sizeof(T);
+  };
+  auto get = [&](unsigned boff) { return *reinterpret_cast<const T *>(base + boff); };
+  const bool out = l >= 2 && l <= w - 3 && i < pr.mx;
+  // physical (extrapolation) sides this segment writes ghosts for; periodic
+  // patches are worked by DIRECT tiles only
+  const bool ybc = pr.bc == WS_BC_EXTRAP;
+  const int c0 = i - l + 2;  // first column this segment updates
+  const bool xbc = ybc && (c0 == 0 || c0 + w - 4 >= pr.mx);
+  // ---- prologue: rows r0-2 .. r0+1
+  const unsigned om2 = at(r0 - 2), om1 = at(r0 - 1), o0 = at(r0), o1 = at(r0 + 1);
+  const T Pm2 = get(om2), Pm1 = get(om1);
+  const T Vm2 = get(om2 + 2 * plb), Vm1 = get(om1 + 2 * plb);
+  const T Um1 = get(om1 + plb);
+  T P0 = get(o0), U0 = get(o0 + plb), V0 = get(o0 + 2 * plb);
+  T P1 = get(o1), U1 = get(o1 + plb), V1 = get(o1 + 2 * plb);
+  const unsigned o2 = at(r0 + 2);  // r0 + 2 <= my + 1 always
+  T Pn = get(o2), Un = get(o2 + plb), Vn = get(o2 + 2 * plb);
+  const T b2mm = s2(Z, Pm1 - Pm2, Vm1 - Vm2);                                // y-edge r0-3/2
+  const T b1m = s1(Z, P0 - Pm1, V0 - Vm1), b2m = s2(Z, P0 - Pm1, V0 - Vm1);  // r0-1/2
+  T b1h = s1(Z, P1 - P0, V1 - V0), b2h = s2(Z, P1 - P0, V1 - V0);            // r0+1/2
+  T yb2 = b2m;  // b2 of the cell's bottom edge
+  // x-edges of rows r0-1 and r0
+  const T pl_m = shr(Pm1), ul_m = shr(Um1);
+  const T a2Lm = s2(Z, Pm1 - pl_m, Um1 - ul_m);
+  const T a1Lm = s1(Z, Pm1 - pl_m, Um1 - ul_m);
+  const T xsm = a2Lm + shl(a1Lm);
+  const T pl_0 = shr(P0), ul_0 = shr(U0);
+  T a1L = s1(Z, P0 - pl_0, U0 - ul_0), a2L = s2(Z, P0 - pl_0, U0 - ul_0);
+  T a1R = shl(a1L);
+  T xs0 = a2L + a1R;
+  T GBp, GBv;
+  gtilde<T, LIM>(k, b1m, b2m, b1h, b2mm, xsm, xs0, GBp, GBv);
+  unsigned ybits = 0;
+  if constexpr (MASKS) ybits = (mc_branch(b1m, b1h) << 4) | (mc_branch(b2m, b2mm) << 6);
+  const int64_t mld = pr.mx + 1;
+
+  for (int r = r0; r < r1; ++r) {
+    // row r+2 arrives; row r+3 is requested (the last ghost row is re-read
+    // past the end, never used)
+    const T P2 = Pn, U2 = Un, V2 = Vn;
+    const unsigned on = at(min(r + 3, pr.my + 1));
+    Pn = get(on);
+    Un = get(on + plb);
+    Vn = get(on + 2 * plb);
+    // y-edge r+3/2 of this column and the y-fluctuations of cell (i, r)
+    const T b1hh = s1(Z, P2 - P1, V2 - V1), b2hh = s2(Z, P2 - P1, V2 - V1);
+    const T ys0 = yb2 + b1h, yd0 = yb2 - b1h;
+    // left x-edge of row r+1
+    const T pl_1 = shr(P1), ul_1 = shr(U1);
+    const T a1Ln = s1(Z, P1 - pl_1, U1 - ul_1), a2Ln = s2(Z, P1 - pl_1, U1 - ul_1);
+    const T a1Rn = shl(a1Ln);
+    const T xsp = a2Ln + a1Rn;
+    const T xd0 = a2L - a1R;
+    const T a2LL = shr(a2L);
+    const T ysl = shr(ys0);
+    T FLp, FLu, GTp, GTv;
+    ftilde<T, LIM>(k, a1L, a2L, a1R, a2LL, ysl, ys0, FLp, FLu);
+    const T FRp = shl(FLp), FRu = shl(FLu);
+    gtilde<T, LIM>(k, b1h, b2h, b1hh, yb2, xs0, xsp, GTp, GTv);
+    T pn, un, vn;
+    update<T>(k, P0, U0, V0, xs0, xd0, ys0, yd0, FLp, FLu, FRp, FRu, GBp, GBv, GTp, GTv, pn, un, vn);
+    // Extrapolation boundaries: the lanes on ghost columns take the new value
+    // of the nearest interior column from their neighbours, and the first and
+    // last rows are repeated into the ghost rows (corners included).
+    bool st = out;
+    if (xbc) {
+      const T p1 = shl(pn), u1 = shl(un), v1 = shl(vn);
+      const T p2 = shl(p1), u2 = shl(u1), v2 = shl(v1);
+      const T p3 = shr(pn), u3 = shr(un), v3 = shr(vn);
+      const T p4 = shr(p3), u4 = shr(u3), v4 = shr(v3);
+      if (i == -1) { pn = p1; un = u1; vn = v1; st = true; }
+      if (i == -2) { pn = p2; un = u2; vn = v2; st = true; }
+      if (i == pr.mx && l <= w - 2) { pn = p3; un = u3; vn = v3; st = true; }
+      if (i == pr.mx + 1 && l <= w - 1) { pn = p4; un = u4; vn = v4; st = true; }
     }
+    if (st) {
+      const int64_t o = (int64_t)r * pr.ld + i;
+      qo[o] = pn;
+      qo[pr.plane + o] = un;
+      qo[2 * pr.plane + o] = vn;
+      if (ybc && (r == 0 || r == pr.my - 1)) {
+        const int g = r == 0 ? -1 : r + 1;  // the two ghost rows
+        const int h = r == 0 ? -2 : r + 2;
+        const int64_t og = (int64_t)g * pr.ld + i, oh = (int64_t)h * pr.ld + i;
+        qo[og] = pn;
+        qo[pr.plane + og] = un;
+        qo[2 * pr.plane + og] = vn;
+        qo[oh] = pn;
+        qo[pr.plane + oh] = un;
+        qo[2 * pr.plane + oh] = vn;
+      }
+    }
+    if constexpr (MASKS) {
+      const unsigned xbits = mc_branch(a1L, a1R) | (mc_branch(a2L, a2LL) << 2);
+      const unsigned tbits = (mc_branch(b1h, b1hh) << 4) | (mc_branch(b2h, yb2) << 6);
+      if (out) {
+        masks[(int64_t)r * mld + i] = (uint8_t)(xbits | ybits);
+        if (r == pr.my - 1) masks[(int64_t)(r + 1) * mld + i] = (uint8_t)tbits;
+      } else if (i == pr.mx && l >= 2 && l <= w - 2) {
+        masks[(int64_t)r * mld + i] = (uint8_t)xbits;
+      }
+      ybits = tbits;
+    }
+    // slide up one row
+    P0 = P1; U0 = U1; V0 = V1;
+    P1 = P2; U1 = U2; V1 = V2;
+    yb2 = b2h; b1h = b1hh; b2h = b2hh;
+    GBp = GTp; GBv = GTv;
+    xs0 = xsp; a1L = a1Ln; a2L = a2Ln; a1R = a1Rn;
+  }
 }
 
 __device__ inline unsigned long long dbits(double v) {
@@ -228,88 +422,187 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// One tile of one patch.  Every thread of the workgroup reaches the barrier
-// at the end (the persistent loop relies on it).
-template <typename T, int LIM, bool MASKS>
-__device__ inline void do_tile(const StepArgs &a, int t, double *s_red) {
+// One tile of one patch; returns (in thread 0) the tile's Courant number.
+// Every thread of the workgroup reaches the barrier at the end (the
+// persistent loop relies on it).
+// VARS: bit 0 -> DIRECT tiles may occur, bit 1 -> MARCH tiles may occur.
+template <typename T, int LIM, bool MASKS, int VARS>
+__device__ inline double do_tile(const StepArgs &a, int t, double *s_red) {
   const TileEntry te = a.tiles[t];
   const PatchRow pr = a.patches[te.patch];
   const InstRow in = a.inst[pr.inst];
-  const double dt = a.dt[pr.inst];
+  const double dt = a.dt_override > 0.0 ? a.dt_override : a.dt[pr.inst];
   const Coef<T> k = make_coef<T>(in.c, in.Z, dt, pr.dx, pr.dy);
-  const int tw = pr.tw;
-  const int rows_per_thread = pr.th / (kThreads / tw);
-  const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
-  const int i = te.tx * tw + lx;
-  const int j0 = te.ty * pr.th + ly * rows_per_thread;
-  const int j1 = min(j0 + rows_per_thread, pr.my);
   const int64_t org = pr.q_off + 2 * (int64_t)pr.ld + pr.col0;
   const T *qi = reinterpret_cast<const T *>(a.qin) + org;
   T *qo = reinterpret_cast<T *>(a.qout) + org;
-  const Planes<T> q{qi, qi + pr.plane, qi + 2 * pr.plane, pr.ld};
+  uint8_t *masks = MASKS ? a.masks + pr.mask_off : nullptr;
+  const int tw = pr.tw;
+  const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
+  const int rows_per_thread = pr.th / (kThreads / tw);
   double cfl = 0.0;
-  if (i < pr.mx && j0 < j1) {
-    for (int j = j0; j < j1; ++j) {
-      T pn, un, vn;
-      CellMasks mk;
-      cell_update<T, LIM, MASKS>(q, i, j, k, pn, un, vn, &mk);
-      store_cell<T>(qo, qo + pr.plane, qo + 2 * pr.plane, pr.ld, i, j, pr.mx, pr.my, pr.bc, pn,
-                    un, vn);
-      if constexpr (MASKS) {
-        uint8_t *m = a.masks + pr.mask_off;
-        const int64_t mld = pr.mx + 1;
-        m[(int64_t)j * mld + i] = (uint8_t)mk.own;
-        if (i == pr.mx - 1) m[(int64_t)j * mld + i + 1] = (uint8_t)mk.right;
-        if (j == pr.my - 1) m[(int64_t)(j + 1) * mld + i] = (uint8_t)mk.top;
-      }
+  if ((VARS & 2) && (!(VARS & 1) || pr.variant == kMarch)) {
+    const int i = te.tx * (tw - 4) - 2 + lx;
+    const int r0 = te.ty * pr.th + ly * rows_per_thread;
+    const int r1 = min(r0 + rows_per_thread, pr.my);
+    if (r0 < r1) {
+      march_segment<T, LIM, MASKS>(qi, qo, pr, k, lx, tw, i, r0, r1, masks);
+      if (lx >= 2 && lx <= tw - 3 && i < pr.mx) cfl = 1.0;
     }
-    // Courant number of the edges this thread owns: speeds are +-c everywhere
-    // in a homogeneous instance, so each edge gives c dt/dx or c dt/dy.
-    cfl = fmax(in.c * (dt / pr.dx), in.c * (dt / pr.dy));
+  } else if (VARS & 1) {
+    const int i = te.tx * tw + lx;
+    const int j0 = te.ty * pr.th + ly * rows_per_thread;
+    const int j1 = min(j0 + rows_per_thread, pr.my);
+    const Planes<T> q{qi, qi + pr.plane, qi + 2 * pr.plane, pr.ld};
+    if (i < pr.mx && j0 < j1) {
+      for (int j = j0; j < j1; ++j) {
+        T pn, un, vn;
+        CellMasks mk;
+        cell_update<T, LIM, MASKS>(q, i, j, k, pn, un, vn, &mk);
+        store<T>(qo, pr.plane, pr.ld, i, j, pr.mx, pr.my, pr.bc, pn, un, vn);
+        if constexpr (MASKS) {
+          const int64_t mld = pr.mx + 1;
+          masks[(int64_t)j * mld + i] = (uint8_t)mk.own;
+          if (i == pr.mx - 1) masks[(int64_t)j * mld + i + 1] = (uint8_t)mk.right;
+          if (j == pr.my - 1) masks[(int64_t)(j + 1) * mld + i] = (uint8_t)mk.top;
+        }
+      }
+      cfl = 1.0;
+    }
   }
+  // Courant number of the edges this thread's cells own: the speeds are +-c
+  // on every edge of a homogeneous instance, so each edge gives c dt/dx or
+  // c dt/dy.
+  if (cfl > 0.0) cfl = fmax(in.c * (dt / pr.dx), in.c * (dt / pr.dy));
   // ---- max reduction: wavefront shuffle, then LDS across the 4 wavefronts
   cfl = wave_max(cfl);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0) s_red[wave] = cfl;
   __syncthreads();
+  double m = 0.0;
   if (threadIdx.x == 0) {
-    double m = s_red[0];
+    m = s_red[0];
     for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, s_red[w]);
-    if (m > 0.0) {
-      const unsigned long long b = dbits(m);
-      atomicMax(a.cfl_level, b);
-      atomicMax(&a.cfl_acc[pr.inst], b);
-      atomicMax(&a.cfl_patch[te.patch], b);
-    }
   }
   __syncthreads();
+  return m;
 }
 
-template <typename T, int LIM, bool MASKS>
-__global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a) {
-  __shared__ int s_tile;
+__device__ inline double load_agent(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// File the step's Courant numbers from the per-tile values: per patch (max
+// over its tiles), per instance and per level; running maxima; dt set
+// (dt_override > 0) and rescaled by cfl_desired / cfl (cfl_desired > 0),
+// Sec. 2.5 eq. (2.11).  Run by one whole workgroup after every tile of the
+// step has finished.
+__device__ inline void finish_step(const CflSlots &c, double dt_override, double cfl_desired) {
+  constexpr int kChunk = 1024;  // instances per pass over the patches
+  __shared__ unsigned long long s_inst[kChunk];
+  __shared__ double s_lvl[kThreads / 64];
+  const int tid = (int)threadIdx.x;
+  double lvl = 0.0;
+  for (int k = tid; k < c.n_patches; k += kThreads) {
+    const PatchRow &pr = c.patches[k];
+    double m = 0.0;
+    for (int t = pr.tile_begin; t < pr.tile_begin + pr.n_tiles; ++t) m = fmax(m, load_agent(&c.cfl_tile[t]));
+    c.cfl_patch_last[k] = m;
+    lvl = fmax(lvl, m);
+  }
+  lvl = wave_max(lvl);
+  if ((tid & 63) == 0) s_lvl[tid >> 6] = lvl;
+  __syncthreads();  // also makes cfl_patch_last visible to the workgroup
+  if (tid == 0) {
+    double m = s_lvl[0];
+    for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, s_lvl[w]);
+    c.level_last[0] = m;
+  }
+  for (int k0 = 0; k0 < c.n_inst; k0 += kChunk) {
+    for (int k = tid; k < kChunk; k += kThreads) s_inst[k] = 0ull;
+    __syncthreads();
+    for (int k = tid; k < c.n_patches; k += kThreads) {
+      const int in = c.patches[k].inst - k0;
+      if (in >= 0 && in < kChunk) atomicMax(&s_inst[in], dbits(c.cfl_patch_last[k]));
+    }
+    __syncthreads();
+    for (int k = k0 + tid; k < min(c.n_inst, k0 + kChunk); k += kThreads) {
+      const double cfl = __longlong_as_double((long long)s_inst[k - k0]);
+      c.cfl_last[k] = cfl;
+      c.cfl_max[k] = fmax(c.cfl_max[k], cfl);
+      double dt = dt_override > 0.0 ? dt_override : c.dt[k];
+      if (cfl_desired > 0.0 && cfl > 0.0) dt = dt * cfl_desired / cfl;
+      c.dt[k] = dt;
+    }
+    __syncthreads();
+  }
+}
+
+// Record a tile's Courant number where every XCD can read it.
+__device__ inline void store_tile_cfl(const StepArgs &a, int t, double m) {
+  __hip_atomic_store(&a.slots.cfl_tile[t], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Persistent launch.  Tiles are split into up to kGroups contiguous runs, one
+// per XCD: workgroups are dispatched round-robin over the XCDs, so workgroup b
+// takes run b % groups, and the run's neighbouring tiles (whose halos
+// overlap) share that XCD's L2.  Within a run the workgroups take tiles
+// round-robin (largest patches first), with no atomics.
+template <typename T, int LIM, bool MASKS, int VARS>
+__device__ inline void step_body(const StepArgs &a) {
   __shared__ double s_red[kThreads / 64];
   if (!a.persistent) {
     const int t = a.tile_base + (int)blockIdx.x;
-    if (t < a.n_tiles) do_tile<T, LIM, MASKS>(a, t, s_red);
+    if (t < a.n_tiles) {
+      const double m = do_tile<T, LIM, MASKS, VARS>(a, t, s_red);
+      if (threadIdx.x == 0) store_tile_cfl(a, t, m);
+    }
     return;
   }
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = (int)atomicAdd(&a.counters[0], 1u);
-    __syncthreads();
-    const int t = s_tile;
-    if (t >= a.n_tiles) break;
-    do_tile<T, LIM, MASKS>(a, t, s_red);  // ends with a barrier
+  const int G = (int)gridDim.x;
+  const int groups = min(kGroups, G);
+  const int x = (int)blockIdx.x % groups, y = (int)blockIdx.x / groups;
+  const int in_group = G / groups + (x < G % groups ? 1 : 0);
+  const int beg = (int)((int64_t)a.n_tiles * x / groups);
+  const int end = (int)((int64_t)a.n_tiles * (x + 1) / groups);
+  for (int t = beg + y; t < end; t += in_group) {
+    const double m = do_tile<T, LIM, MASKS, VARS>(a, t, s_red);  // ends with a barrier
+    if (threadIdx.x == 0) store_tile_cfl(a, t, m);
   }
-  // The last workgroup to retire rewinds the tile counter for the next launch:
-  // every other workgroup has finished its final fetch before it retires.
+  // Retire: the tile values are stored before the counts (waited for); the
+  // last workgroup of each run counts the run, and the last run's last
+  // workgroup files the step and rewinds the counters for the next launch.
+  __shared__ int s_last;
   if (threadIdx.x == 0) {
-    const unsigned done = atomicAdd(&a.counters[1], 1u);
-    if (done == gridDim.x - 1) {
-      atomicExch(&a.counters[0], 0u);
-      atomicExch(&a.counters[1], 0u);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    int last = 0;
+    const unsigned d = __hip_atomic_fetch_add(&a.retire[x * kLine], 1u, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    if ((int)d == in_group - 1) {
+      const unsigned g = __hip_atomic_fetch_add(&a.retire[kGroups * kLine], 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+      last = (int)g == groups - 1;
     }
+    s_last = last;
   }
+  __syncthreads();
+  if (s_last) {
+    finish_step(a.slots, a.dt_override, a.cfl_desired);
+    if (threadIdx.x <= kGroups)
+      __hip_atomic_store(&a.retire[threadIdx.x * kLine], 0u, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <typename T, int LIM, bool MASKS, int VARS>
+__global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a) {
+  step_body<T, LIM, MASKS, VARS>(a);
+}
+
+// MARCH-only levels: a kernel of their own, free of the DIRECT path's registers.
+template <typename T, int LIM, bool MASKS>
+__global__ __launch_bounds__(kThreads) void step_kernel_march(StepArgs a) {
+  step_body<T, LIM, MASKS, 2>(a);
 }
 
 // --------------------------------------------------------------------------
@@ -346,22 +639,8 @@ __global__ void set_dt_kernel(double *dt, int n, double value) {
   for (int k = threadIdx.x; k < n; k += blockDim.x) dt[k] = value;
 }
 
-__global__ void finish_step_kernel(CflSlots c, double cfl_desired) {
-  for (int k = threadIdx.x; k < c.n_inst; k += blockDim.x) {
-    const double cfl = __longlong_as_double((long long)c.cfl_acc[k]);
-    c.cfl_last[k] = cfl;
-    c.cfl_max[k] = fmax(c.cfl_max[k], cfl);
-    if (cfl_desired > 0.0 && cfl > 0.0) c.dt[k] = c.dt[k] * cfl_desired / cfl;
-    c.cfl_acc[k] = 0ull;
-  }
-  for (int k = threadIdx.x; k < c.n_patches; k += blockDim.x) {
-    c.cfl_patch_last[k] = __longlong_as_double((long long)c.cfl_patch_acc[k]);
-    c.cfl_patch_acc[k] = 0ull;
-  }
-  if (threadIdx.x == 0) {
-    c.level_last[0] = __longlong_as_double((long long)c.level_acc[0]);
-    c.level_acc[0] = 0ull;
-  }
+__global__ __launch_bounds__(kThreads) void finish_step_kernel(CflSlots c, double cfl_desired) {
+  finish_step(c, 0.0, cfl_desired);
 }
 
 // --------------------------------------------------------------------------
@@ -407,44 +686,62 @@ __global__ void instance_sums_kernel(const PatchRow *patches, const TileEntry *t
   }
 }
 
-template <typename T, int LIM, bool MASKS>
+template <typename T, int LIM, bool MASKS, int VARS>
 hipError_t launch_step_t(const StepArgs &a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((step_kernel<T, LIM, MASKS>), dim3(grid), dim3(kThreads), 0, s, a);
+  if constexpr (VARS == 2)
+    hipLaunchKernelGGL((step_kernel_march<T, LIM, MASKS>), dim3(grid), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL((step_kernel<T, LIM, MASKS, VARS>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
+template <typename T, int LIM, bool MASKS>
+hipError_t launch_step_v(int vars, const StepArgs &a, int grid, hipStream_t s) {
+  switch (vars) {
+    case 1: return launch_step_t<T, LIM, MASKS, 1>(a, grid, s);
+    case 2: return launch_step_t<T, LIM, MASKS, 2>(a, grid, s);
+    default: return launch_step_t<T, LIM, MASKS, 3>(a, grid, s);
+  }
+}
+
 template <typename T, int LIM>
-hipError_t launch_step_m(const StepArgs &a, int grid, hipStream_t s) {
-  return a.masks ? launch_step_t<T, LIM, true>(a, grid, s) : launch_step_t<T, LIM, false>(a, grid, s);
+hipError_t launch_step_m(int vars, const StepArgs &a, int grid, hipStream_t s) {
+  return a.masks ? launch_step_v<T, LIM, true>(vars, a, grid, s)
+                 : launch_step_v<T, LIM, false>(vars, a, grid, s);
 }
 
 template <typename T>
-hipError_t launch_step_l(int limiter, const StepArgs &a, int grid, hipStream_t s) {
-  return limiter == WS_LIM_NONE ? launch_step_m<T, WS_LIM_NONE>(a, grid, s)
-                                : launch_step_m<T, WS_LIM_MC>(a, grid, s);
+hipError_t launch_step_l(int limiter, int vars, const StepArgs &a, int grid, hipStream_t s) {
+  return limiter == WS_LIM_NONE ? launch_step_m<T, WS_LIM_NONE>(vars, a, grid, s)
+                                : launch_step_m<T, WS_LIM_MC>(vars, a, grid, s);
+}
+
+template <typename T, int LIM>
+int occupancy_of(int vars, int *n) {
+  hipError_t e;
+  switch (vars) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel<T, LIM, false, 1>, kThreads, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel_march<T, LIM, false>, kThreads, 0); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel<T, LIM, false, 3>, kThreads, 0); break;
+  }
+  return e == hipSuccess ? 0 : -1;
 }
 
 }  // namespace
 
-hipError_t launch_step(int dtype, int limiter, const StepArgs &a, int grid, hipStream_t s) {
+hipError_t launch_step(int dtype, int limiter, int vars, const StepArgs &a, int grid,
+                       hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  return dtype == WS_F32 ? launch_step_l<float>(limiter, a, grid, s)
-                         : launch_step_l<double>(limiter, a, grid, s);
+  return dtype == WS_F32 ? launch_step_l<float>(limiter, vars, a, grid, s)
+                         : launch_step_l<double>(limiter, vars, a, grid, s);
 }
 
-int step_occupancy(int dtype, int limiter, int *wg_per_cu) {
-  int n = 0;
-  hipError_t e;
+int step_occupancy(int dtype, int limiter, int vars, int *wg_per_cu) {
   if (dtype == WS_F32)
-    e = limiter == WS_LIM_NONE
-            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, WS_LIM_NONE, false>, kThreads, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<float, WS_LIM_MC, false>, kThreads, 0);
-  else
-    e = limiter == WS_LIM_NONE
-            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<double, WS_LIM_NONE, false>, kThreads, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_kernel<double, WS_LIM_MC, false>, kThreads, 0);
-  *wg_per_cu = n;
-  return e == hipSuccess ? 0 : -1;
+    return limiter == WS_LIM_NONE ? occupancy_of<float, WS_LIM_NONE>(vars, wg_per_cu)
+                                  : occupancy_of<float, WS_LIM_MC>(vars, wg_per_cu);
+  return limiter == WS_LIM_NONE ? occupancy_of<double, WS_LIM_NONE>(vars, wg_per_cu)
+                                : occupancy_of<double, WS_LIM_MC>(vars, wg_per_cu);
 }
 
 hipError_t launch_fill_ghosts(int dtype, const PatchRow *patches, int n_patches,
@@ -467,7 +764,7 @@ hipError_t launch_set_dt(const CflSlots &c, double value, hipStream_t s) {
 }
 
 hipError_t launch_finish_step(const CflSlots &c, double cfl_desired, hipStream_t s) {
-  hipLaunchKernelGGL(finish_step_kernel, dim3(1), dim3(1024), 0, s, c, cfl_desired);
+  hipLaunchKernelGGL(finish_step_kernel, dim3(1), dim3(kThreads), 0, s, c, cfl_desired);
   return hipGetLastError();
 }
 

@@ -47,6 +47,8 @@ class Level:
         self.n = len(patches)
         self.n_inst = len(materials)
         self.shapes = [(int(_get(p, "mx")), int(_get(p, "my"))) for p in patches]
+        self.bcs = [_get(p, "bc", None) for p in patches]
+        self.limiter = limiter
         descs = (C.PatchDesc * self.n)()
         for k, p in enumerate(patches):
             descs[k].mx, descs[k].my = self.shapes[k]
@@ -143,16 +145,21 @@ class Level:
         C.check(self._L.ws_conservation_sums(self._ctx, out))
         return np.array(out).reshape(self.n_inst, 3)
 
-    def set_tiling(self, tile_w=None, tile_h=None, wg_per_cu: int = 0) -> None:
-        """Tile shape per patch (scalars broadcast) and persistent workgroups per CU."""
+    def set_tiling(self, tile_w=None, tile_h=None, wg_per_cu: int = 0, variant="direct") -> None:
+        """Tiling per patch (scalars broadcast): variant "direct" or "march"
+        (or 0/1 codes), tile width and height; and persistent workgroups per CU."""
         if tile_w is None:
-            C.check(self._L.ws_set_tiling(self._ctx, None, None, int(wg_per_cu)))
+            C.check(self._L.ws_set_tiling(self._ctx, None, None, None, int(wg_per_cu)))
             return
+        codes = {"direct": C.WS_TILE_DIRECT, "march": C.WS_TILE_MARCH}
+        var = np.asarray([codes.get(v, v) if isinstance(v, str) else v
+                          for v in np.broadcast_to(np.asarray(variant, dtype=object), (self.n,))],
+                         np.int32)
         tw = np.broadcast_to(np.asarray(tile_w, np.int32), (self.n,)).copy()
         th = np.broadcast_to(np.asarray(tile_h, np.int32), (self.n,)).copy()
         P = ctypes.POINTER(ctypes.c_int32)
-        C.check(self._L.ws_set_tiling(self._ctx, tw.ctypes.data_as(P), th.ctypes.data_as(P),
-                                      int(wg_per_cu)))
+        C.check(self._L.ws_set_tiling(self._ctx, var.ctypes.data_as(P), tw.ctypes.data_as(P),
+                                      th.ctypes.data_as(P), int(wg_per_cu)))
 
     def time_step_kernel(self, n_launches: int, per_patch: bool = False) -> float:
         """Mean milliseconds per level step of n back-to-back step launches

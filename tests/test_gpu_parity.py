@@ -223,21 +223,48 @@ def test_amr_level_batched_equals_per_patch_and_oracle(ws, oracle_lib, dtype):
     assert np.array_equal(lev_b.patch_cfl(), lev_p.patch_cfl())
 
 
-def test_results_do_not_depend_on_tiling(ws):
+TILINGS = [("direct", 8, 32), ("direct", 16, 16), ("direct", 32, 8), ("direct", 64, 4),
+           ("direct", 64, 32), ("direct", 128, 2), ("direct", 256, 1), ("direct", 256, 32),
+           ("direct", 32, 256), ("march", 64, 4), ("march", 64, 36), ("march", 64, 64),
+           ("march", 64, 256), ("march", 32, 8), ("march", 32, 64), ("march", 32, 128),
+           ("march", 16, 16), ("march", 16, 160), ("march", 16, 256)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("bc", ["extrap", "periodic"])
+def test_results_do_not_depend_on_tiling(ws, dtype, bc):
+    """Every tiling and both tile kernels (direct footprint, marching lane
+    segments) give bitwise-identical states."""
     nx, ny = 200, 136  # ragged for every tile shape
     rng = np.random.default_rng(5)
     q = workloads.padded_state(nx, ny, 0, 0, 1 / nx, 1 / ny, 0.4, 0.6)
     q[1:, 2:-2, 2:-2] += 0.1 * rng.normal(size=(2, ny, nx))
     outs = []
-    shapes = [(8, 32), (16, 16), (32, 8), (64, 4), (64, 32), (128, 2), (256, 1), (256, 32), (32, 256)]
-    for tw, th in shapes:
-        lev, _ = uniform_level(ws, nx, ny=ny, state=q)
-        lev.set_tiling(tw, th)
+    tilings = [t for t in TILINGS if bc != "periodic" or t[0] == "direct"]
+    for var, tw, th in tilings:
+        lev, _ = uniform_level(ws, nx, ny=ny, state=q, dtype=dtype, bc=bc)
+        lev.set_tiling(tw, th, variant=var)
         for _ in range(5):
             lev.step(0.4 / nx)
         outs.append(lev.download(0))
-    for (tw, th), o in zip(shapes[1:], outs[1:]):
-        assert np.array_equal(o, outs[0]), (tw, th)
+    for t, o in zip(tilings[1:], outs[1:]):
+        assert np.array_equal(o, outs[0]), t
+
+
+def test_march_matches_oracle_on_small_and_ragged_patches(ws, oracle_lib):
+    for (mx, my, tw, th) in [(5, 3, 16, 16), (13, 40, 16, 32), (29, 29, 32, 8), (61, 7, 64, 4),
+                             (120, 70, 64, 32)]:
+        rng = np.random.default_rng(mx * 100 + my)
+        q = rng.normal(size=(3, my + 4, mx + 4))
+        dx, dy = 1 / mx, 1 / my
+        dt = 0.5 * min(dx, dy) / C0
+        ref = oracle_lib.run(q, 4, dx, dy, RHO, KB, limiter="mc", bc="extrap", dt=dt)
+        lev, _ = uniform_level(ws, mx, ny=my, state=q)
+        lev.set_tiling(tw, th, variant="march")
+        for _ in range(4):
+            lev.step(dt)
+        err = rel_linf(lev.download(0), ref["q"])
+        assert err.max() <= FP64_TOL, (mx, my, err)
 
 
 def test_ensemble_per_instance_dt(ws, oracle_lib):

@@ -12,6 +12,7 @@ import pytest
 
 import oracle
 import oracle.oracle as oracle_mod
+import test_oracle_adjoint as adj
 import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oracle_mod.__file__), "wave_oracle.c")
@@ -47,7 +48,23 @@ MUTATIONS = {
         "const double fluct_y = apdq_y[AY(j + 1, i) + m] + amdq_y[AY(j, i) + m];"),
     "cfl_wrong_spacing": ("cfl = fmax(cfl, fabs(ey.s[p]) * dtdy);",
                           "cfl = fmax(cfl, fabs(ey.s[p]) * dtdx);"),
-    "corner_ghosts_skipped": ("for (int i = -2; i < mx + 2; ++i)", "for (int i = 0; i < mx; ++i)"),
+    "corner_ghosts_skipped": (
+        "for (int i = -2; i < mx + 2; ++i)\n      for (int g = 1; g <= 2; ++g) {\n        if",
+        "for (int i = 0; i < mx; ++i)\n      for (int g = 1; g <= 2; ++g) {\n        if"),
+    # frozen-branch forward and adjoint
+    "frozen_average_sign": ("case 1: out[m] = 0.5 * (w[m] + wup[m]); break;",
+                            "case 1: out[m] = 0.5 * (w[m] - wup[m]); break;"),
+    "adjoint_upwind_side": ("const int up = (s > 0.0) ? e - 1 : e + 1;",
+                            "const int up = (s > 0.0) ? e + 1 : e - 1;"),
+    "adjoint_split_parts_swapped": ("lm[m] = -0.5 * dtdx * l_Gx_bot[GX(j, e) + m];",
+                                    "lm[m] = -0.5 * dtdx * l_Gx_top[GX(j, e) + m];"),
+    "adjoint_ghost_fold_dropped": (
+        "lpad[PI(0, j) * NM + m] += lpad[PI(-g, j) * NM + m];", "(void)0;"),
+    "adjoint_correction_weight": (
+        "const double coef = 0.5 * fabs(s) * (1.0 - dtdx * fabs(s));",
+        "const double coef = 0.5 * fabs(s) * (1.0 - dtdy * fabs(s));"),
+    "adjoint_jump_sign": ("lpad[PI(e - 1, j) * NM + m] -= ldq[m];",
+                          "lpad[PI(e - 1, j) * NM + m] += ldq[m];"),
 }
 
 # cheapest first; the first failing pin ends a mutant's run
@@ -65,17 +82,32 @@ PIN_CALLS = [
     ("translation", lambda o: pins.test_plane_wave_translates_exactly_at_courant_one(o, "mc")),
     ("symmetry", lambda o: pins.test_rotation_and_transpose_symmetry(o)),
     ("conservation", lambda o: pins.test_conservation_periodic(o)),
+    ("frozen_forward", lambda o: adj.test_frozen_forward_equals_nonlinear_step(o)),
+    ("dot_product", lambda o: adj.test_dot_product_identity(o, "extrap")),
+    ("dense_jacobian", lambda o: adj.test_dense_jacobian_of_small_patch(o)),
     ("second_order", lambda o: pins.test_second_order_convergence_oblique_plane_wave(o)),
 ]
 
 
+# anchors that occur in both the forward step and the adjoint: which occurrence
+OCCURRENCE = {"correction_weight_sign": (0, 2), "adjoint_correction_weight": (1, 2)}
+
+
+def _plant(src, name):
+    orig, mutated = MUTATIONS[name]
+    which, count = OCCURRENCE.get(name, (0, 1))
+    assert src.count(orig) == count, f"mutation anchor for {name} occurs {src.count(orig)} times"
+    pos = -1
+    for _ in range(which + 1):
+        pos = src.index(orig, pos + 1)
+    return src[:pos] + mutated + src[pos + len(orig):]
+
+
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_planted_mistake_is_caught(name, tmp_path):
-    orig, mutated = MUTATIONS[name]
     src = open(SRC).read()
-    assert src.count(orig) == 1, f"mutation anchor for {name} not unique in the oracle"
     mpath = tmp_path / "mutant.c"
-    mpath.write_text(src.replace(orig, mutated))
+    mpath.write_text(_plant(src, name))
     so = oracle_mod.build(str(mpath), str(tmp_path / "libmutant.so"))
     saved = oracle_mod._lib
     oracle_mod._lib = oracle_mod.load_lib(so)
