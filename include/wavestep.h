@@ -157,6 +157,60 @@ int ws_read_patch_cfl(ws_ctx *ctx, double *cfl);
  * Synchronises the stream. */
 int ws_conservation_sums(ws_ctx *ctx, double *sums);
 
+/* ---- Frozen-limiter adjoint (FP64 contexts with the MC limiter; patches
+ * with WS_BC_EXTRAP or WS_BC_NONE).  With the limiter branches of one step
+ * frozen, the step of Sec. 2.1 eq. (2.3) is a linear map S = U o E of the
+ * interior state (E: the ghost fill, U: the update); ws_adjoint_step applies
+ * S^T: the discrete adjoint of the step, used for gradients of misfits of
+ * receiver traces with respect to the initial state.  (The paper has no
+ * adjoint; this is the transpose of its step with the limiter of Sec. 2.1
+ * held at the branches the forward step took.)
+ *
+ * Branch masks: one byte per cell (i, j), i in [0, mx], j in [0, my], row-
+ * major with row length mx + 1, patches concatenated in patch order.  Bits
+ * 0-1 and 2-3: the MC branch of the waves of speed -c and +c at x-edge
+ * i - 1/2 (rows j < my); bits 4-5 and 6-7: the same at y-edge j - 1/2
+ * (columns i < mx); unused bits are 0.  Branch 0: zero, 1: (a + a_up)/2,
+ * 2: 2a, 3: 2 a_up, with a_up the strength of the same wave at the upwind
+ * edge; on ties the lowest code. */
+
+/* Bytes of the branch masks of all patches. */
+int ws_mask_bytes(ws_ctx *ctx, int64_t *bytes);
+
+/* Where patch `patch` sits in any buffer with the pools' layout: element
+ * offset of padded cell (i, j) = (-2, -2) of component p, the row stride and
+ * the component (plane) stride, in elements.  Component m, cell (i, j) is at
+ * offset + m * plane + (j + 2) * ld + (i + 2). */
+int ws_patch_layout(ws_ctx *ctx, int32_t patch, int64_t *offset, int64_t *ld, int64_t *plane);
+
+/* ws_step_level(dt) recording the branches into masks_dev (device buffer of
+ * ws_mask_bytes, cleared first).  cfl_out may be NULL; when given the call
+ * synchronises the stream. */
+int ws_step_record_masks(ws_ctx *ctx, double dt, void *masks_dev, double *cfl_out);
+
+/* lam_out <- S^T lam_in for the step recorded in masks_dev with time step dt.
+ * lam_in, lam_out: distinct device buffers of pool_bytes in the pools'
+ * layout.  lam_in: cotangent of the interior of Q^{n+1} (its ghosts are not
+ * read); lam_out: cotangent of the interior of Q^n, ghosts set to 0.  For
+ * WS_BC_EXTRAP patches the ghost cells' cotangents are folded into the
+ * interior cells they were copied from; for WS_BC_NONE patches ghosts are
+ * inputs held fixed and get no cotangent.  Asynchronous on the context's
+ * stream; periodic patches and FP32 or unlimited contexts return WS_EINVAL. */
+int ws_adjoint_step(ws_ctx *ctx, double dt, const void *masks_dev, const void *lam_in,
+                    void *lam_out);
+
+/* Cell access in a pool-layout buffer (buf = NULL: the current state) of an
+ * FP64 context, for n cells (i_k, j_k) of component comp of one patch:
+ *   ws_gather: out[k] = buf(comp, i_k, j_k)  (NaN for a cell outside the interior)
+ *   ws_add_at: buf(comp, i_k, j_k) += val[k] (cells outside the interior are
+ *              skipped; repeated cells all add, in an unspecified order).
+ * ij: n pairs (i, j) of int32; out, val: FP64; all device pointers.
+ * Asynchronous on the context's stream. */
+int ws_gather(ws_ctx *ctx, const void *buf, int32_t patch, int32_t comp, int32_t n,
+              const int32_t *ij, double *out);
+int ws_add_at(ws_ctx *ctx, void *buf, int32_t patch, int32_t comp, int32_t n,
+              const int32_t *ij, const double *val);
+
 /* Timing entry (for the benchmark and the tile autotuner): enqueue n_launches
  * step kernels back to back (batched persistent launch, or per_patch != 0:
  * one launch per patch per step) with the device-resident dt and no dt

@@ -8,3 +8,4 @@ PyTorch for device memory and streams only.
 
 from ._lib import WaveStepError  # noqa: F401
 from .level import Level  # noqa: F401
+from .adjoint import AcousticsAdjoint  # noqa: F401

@@ -24,8 +24,9 @@ EXPORTS = (
     "ws_layout", "ws_init_patches", "ws_set_tiling", "ws_upload_patch", "ws_download_patch",
     "ws_fill_ghosts", "ws_step_level", "ws_step_level_per_patch", "ws_set_dt", "ws_step_auto",
     "ws_capture_steps", "ws_graph_launch", "ws_read_dt_cfl", "ws_read_patch_cfl",
-    "ws_conservation_sums", "ws_time_step_kernel", "ws_current_pool", "ws_destroy",
-    "ws_last_error",
+    "ws_conservation_sums", "ws_mask_bytes", "ws_patch_layout", "ws_step_record_masks",
+    "ws_adjoint_step", "ws_gather", "ws_add_at", "ws_time_step_kernel", "ws_current_pool",
+    "ws_destroy", "ws_last_error",
 )
 
 
@@ -79,6 +80,12 @@ def lib():
         "ws_read_dt_cfl": [vp, P(dbl), P(dbl), P(dbl)],
         "ws_read_patch_cfl": [vp, P(dbl)],
         "ws_conservation_sums": [vp, P(dbl)],
+        "ws_mask_bytes": [vp, P(i64)],
+        "ws_patch_layout": [vp, i32, P(i64), P(i64), P(i64)],
+        "ws_step_record_masks": [vp, dbl, vp, P(dbl)],
+        "ws_adjoint_step": [vp, dbl, vp, vp, vp],
+        "ws_gather": [vp, vp, i32, i32, i32, vp, vp],
+        "ws_add_at": [vp, vp, i32, i32, i32, vp, vp],
         "ws_time_step_kernel": [vp, i32, i32, P(dbl)],
         "ws_current_pool": [vp, P(i32)],
         "ws_destroy": [vp],

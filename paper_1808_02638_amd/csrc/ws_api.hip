@@ -5,8 +5,8 @@
 // Level batching (after the paper's kernel merging, Sec. 3.1.3, and its
 // largest-first patch order): every patch is cut into tiles, the tiles of all
 // patches go into one device tile list ordered by patch size (largest patch
-// first), and one persistent launch pulls tiles from an atomic counter.  The
-// per-patch baseline launches the same kernel once per patch.  The paper's
+// first), and one persistent launch works the list, split into one contiguous
+// run per XCD.  The per-patch baseline launches the same kernel once per patch.  The paper's
 // per-patch maximum-speed array (Sec. 3.2.2) is kept, and the level-wide
 // maximum is also reduced on the device, so dt can be updated there too.
 
@@ -122,6 +122,7 @@ WsLayout ws_layout_of(const ws_patch_desc *p, int n, int n_inst) {
   L.tiles = take(L.max_tiles * (int64_t)sizeof(TileEntry));
   L.dt = take(8LL * n_inst);
   L.cfl_tile = take(8 * L.max_tiles);
+  L.inst_acc = take(8LL * kGroups * n_inst);
   L.cfl_last = take(8LL * n_inst);
   L.cfl_max = take(8LL * n_inst);
   L.cfl_patch_last = take(8LL * n);
@@ -213,6 +214,8 @@ struct ws_ctx {
   int vars = 1;          // tile variants present (bit 0 DIRECT, bit 1 MARCH)
   int wg_override = 0;   // workgroups per CU set by the caller (0: occupancy)
   int max_padded_cells = 0;
+  int max_ring = 0;  // interior cells next to a side, largest patch
+  int64_t mask_total = 0;  // bytes of the branch masks of all patches
   double *host_buf = nullptr;
   int64_t host_buf_bytes = 0;
   hipGraph_t graph = nullptr;
@@ -223,13 +226,11 @@ struct ws_ctx {
     CflSlots c;
     c.dt = reinterpret_cast<double *>(ws + L.dt);
     c.cfl_tile = reinterpret_cast<double *>(ws + L.cfl_tile);
+    c.inst_acc = reinterpret_cast<unsigned long long *>(ws + L.inst_acc);
     c.cfl_last = reinterpret_cast<double *>(ws + L.cfl_last);
     c.cfl_max = reinterpret_cast<double *>(ws + L.cfl_max);
-    c.cfl_patch_last = reinterpret_cast<double *>(ws + L.cfl_patch_last);
     c.level_last = reinterpret_cast<double *>(ws + L.level_last);
-    c.patches = d_patches();
     c.n_inst = n_inst;
-    c.n_patches = n_patches;
     return c;
   }
   const PatchRow *d_patches() const { return reinterpret_cast<const PatchRow *>(ws + L.patches); }
@@ -379,7 +380,9 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
     r.mask_off = mask_off;
     mask_off += (int64_t)(d.mx + 1) * (d.my + 1);
     c->max_padded_cells = std::max(c->max_padded_cells, (d.mx + 4) * (d.my + 4));
+    c->max_ring = std::max(c->max_ring, 2 * (d.mx + d.my));
   }
+  c->mask_total = mask_off;
   c->order.resize(n_patches);
   std::iota(c->order.begin(), c->order.end(), 0);
   std::stable_sort(c->order.begin(), c->order.end(), [&](int a, int b) {
@@ -577,8 +580,10 @@ int ws_read_dt_cfl(ws_ctx *c, double *dt, double *cfl_last, double *cfl_max) {
 int ws_read_patch_cfl(ws_ctx *c, double *cfl) {
   if (!c) return fail(WS_EINVAL, "ctx is NULL");
   if (!cfl) return fail(WS_EINVAL, "cfl is NULL");
+  double *dpatch = reinterpret_cast<double *>(c->ws + c->L.cfl_patch_last);
+  HIPCHK(launch_patch_cfl(c->d_patches(), c->n_patches, c->slots().cfl_tile, dpatch, c->stream));
   const size_t n = 8 * (size_t)c->n_patches;
-  HIPCHK(hipMemcpyAsync(c->host_buf, c->ws + c->L.cfl_patch_last, n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(c->host_buf, dpatch, n, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   std::memcpy(cfl, c->host_buf, n);
   return WS_OK;
@@ -623,6 +628,8 @@ int ws_time_step_kernel(ws_ctx *c, int32_t n_launches, int32_t per_patch, double
     }
     c->cur = 1 - c->cur;
   }
+  // per-patch launches leave their Courant numbers in the accumulators
+  if (e == hipSuccess && per_patch) e = launch_finish_step(c->slots(), 0.0, c->stream);
   if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;
@@ -632,6 +639,88 @@ int ws_time_step_kernel(ws_ctx *c, int32_t n_launches, int32_t per_patch, double
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return rc;
+}
+
+int ws_mask_bytes(ws_ctx *c, int64_t *bytes) {
+  if (!c || !bytes) return fail(WS_EINVAL, "NULL argument");
+  *bytes = c->mask_total;
+  return WS_OK;
+}
+
+int ws_patch_layout(ws_ctx *c, int32_t patch, int64_t *offset, int64_t *ld, int64_t *plane) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (patch < 0 || patch >= c->n_patches) return fail(WS_EINVAL, "patch %d out of range", patch);
+  const PatchRow &r = c->rows[patch];
+  if (offset) *offset = r.q_off + r.col0 - 2;
+  if (ld) *ld = r.ld;
+  if (plane) *plane = r.plane;
+  return WS_OK;
+}
+
+int ws_step_record_masks(ws_ctx *c, double dt, void *masks_dev, double *cfl_out) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (!masks_dev) return fail(WS_EINVAL, "masks buffer is NULL");
+  if (c->limiter != WS_LIM_MC) return fail(WS_EINVAL, "branches exist for the MC limiter only");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
+  // bytes no edge owns (cell (mx, my) of each patch) stay 0
+  HIPCHK(hipMemsetAsync(masks_dev, 0, (size_t)c->mask_total, c->stream));
+  StepArgs a = c->step_args(c->cur, dt, 0.0);
+  a.masks = reinterpret_cast<uint8_t *>(masks_dev);
+  HIPCHK(launch_step(c->dtype, c->limiter, c->vars, a, c->grid, c->stream));
+  c->cur = 1 - c->cur;
+  return read_level_cfl(c, cfl_out);
+}
+
+static int check_adjoint_ctx(ws_ctx *c) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (c->dtype != WS_F64) return fail(WS_EINVAL, "the adjoint needs an FP64 context");
+  return WS_OK;
+}
+
+int ws_adjoint_step(ws_ctx *c, double dt, const void *masks_dev, const void *lam_in,
+                    void *lam_out) {
+  if (int rc = check_adjoint_ctx(c)) return rc;
+  if (c->limiter != WS_LIM_MC) return fail(WS_EINVAL, "the adjoint needs the MC limiter");
+  if (!masks_dev || !lam_in || !lam_out) return fail(WS_EINVAL, "NULL buffer");
+  if (lam_in == lam_out) return fail(WS_EINVAL, "lam_in and lam_out must be distinct buffers");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
+  for (int k = 0; k < c->n_patches; ++k)
+    if (c->rows[k].bc == WS_BC_PERIODIC)
+      return fail(WS_EINVAL, "patch %d: the adjoint does not take periodic patches", k);
+  HIPCHK(launch_adjoint(c->d_patches(), c->n_patches, c->max_padded_cells, c->max_ring,
+                        reinterpret_cast<const InstRow *>(c->ws + c->L.inst), dt,
+                        reinterpret_cast<const uint8_t *>(masks_dev),
+                        reinterpret_cast<const double *>(lam_in),
+                        reinterpret_cast<double *>(lam_out), c->stream));
+  return WS_OK;
+}
+
+static int check_cells(ws_ctx *c, int32_t patch, int32_t comp, int32_t n, const void *ij,
+                       const void *vals) {
+  if (int rc = check_adjoint_ctx(c)) return rc;
+  if (patch < 0 || patch >= c->n_patches) return fail(WS_EINVAL, "patch %d out of range", patch);
+  if (comp < 0 || comp > 2) return fail(WS_EINVAL, "component %d out of range", comp);
+  if (n < 0) return fail(WS_EINVAL, "n must be >= 0");
+  if (n > 0 && (!ij || !vals)) return fail(WS_EINVAL, "NULL buffer");
+  return WS_OK;
+}
+
+int ws_gather(ws_ctx *c, const void *buf, int32_t patch, int32_t comp, int32_t n,
+              const int32_t *ij, double *out) {
+  if (int rc = check_cells(c, patch, comp, n, ij, out)) return rc;
+  const void *src = buf ? buf : c->pool[c->cur];
+  HIPCHK(launch_gather(c->d_patches(), patch, comp, n, ij, reinterpret_cast<const double *>(src),
+                       out, c->stream));
+  return WS_OK;
+}
+
+int ws_add_at(ws_ctx *c, void *buf, int32_t patch, int32_t comp, int32_t n, const int32_t *ij,
+              const double *val) {
+  if (int rc = check_cells(c, patch, comp, n, ij, val)) return rc;
+  void *dst = buf ? buf : c->pool[c->cur];
+  HIPCHK(launch_add_at(c->d_patches(), patch, comp, n, ij, val, reinterpret_cast<double *>(dst),
+                       c->stream));
+  return WS_OK;
 }
 
 int ws_current_pool(ws_ctx *c, int32_t *which) {

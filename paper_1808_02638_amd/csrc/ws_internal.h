@@ -21,7 +21,7 @@ enum TileVariant { kDirect = 0, kMarch = 1 };
 
 // One row of the device patch table.
 struct PatchRow {
-  int64_t q_off;   // element offset of padded cell (i=-2, j=-2) of plane p
+  int64_t q_off;   // element offset of the patch's storage (row j = -2 of plane p)
   int32_t mx, my;  // interior cells
   int32_t ld;      // row stride (elements)
   int32_t col0;    // storage column of interior i = 0 (ghost i=-2 sits at col0-2)
@@ -48,21 +48,20 @@ struct InstRow {
 
 // Workspace carve-up (byte offsets inside the caller's workspace buffer).
 struct WsLayout {
-  int64_t patches, inst, tiles, dt, cfl_tile, cfl_last, cfl_max, cfl_patch_last, level_last,
-      retire, partials, sums, total;
+  int64_t patches, inst, tiles, dt, cfl_tile, inst_acc, cfl_last, cfl_max, cfl_patch_last,
+      level_last, retire, partials, sums, total;
   int64_t max_tiles;
 };
 
 // Per-step Courant-number bookkeeping inside the workspace.
 struct CflSlots {
-  double *dt;              // [n_inst]
-  double *cfl_tile;        // [n_tiles] Courant number of each tile of the step
-  double *cfl_last;        // [n_inst]  Courant number of the last step
-  double *cfl_max;         // [n_inst]  largest since ws_set_dt
-  double *cfl_patch_last;  // [n_patches]
-  double *level_last;      // [1]
-  const PatchRow *patches;
-  int n_inst, n_patches;
+  double *dt;                    // [n_inst]
+  double *cfl_tile;              // [n_tiles] Courant number of each tile of the step
+  unsigned long long *inst_acc;  // [kGroups][n_inst] per-XCD-group maxima (FP64 bits)
+  double *cfl_last;              // [n_inst]  Courant number of the last step
+  double *cfl_max;               // [n_inst]  largest since ws_set_dt
+  double *level_last;            // [1]
+  int n_inst;
 };
 
 struct StepArgs {
@@ -94,8 +93,23 @@ hipError_t launch_set_dt(const CflSlots &c, double value, hipStream_t s);
 // running maxima, clear the accumulators and, if cfl_desired > 0, rescale
 // each instance's dt by cfl_desired / cfl.
 hipError_t launch_finish_step(const CflSlots &c, double cfl_desired, hipStream_t s);
+// cfl_patch[k] = max of cfl_tile over patch k's tiles.
+hipError_t launch_patch_cfl(const PatchRow *patches, int n_patches, const double *cfl_tile,
+                            double *cfl_patch, hipStream_t s);
 hipError_t launch_sums(int dtype, const PatchRow *patches, const TileEntry *tiles, int n_tiles,
                        const void *q, double *partials, int n_inst, double *sums, hipStream_t s);
 int step_occupancy(int dtype, int limiter, int vars, int *wg_per_cu);
+
+// Adjoint and receiver helpers (defined in ws_adjoint.hip), FP64 buffers in
+// the pools' layout.
+// lam_out <- E^T U^T lam_in (two launches: the gather-form update transpose
+// over every padded cell, then the ghost fold over each patch's boundary ring).
+hipError_t launch_adjoint(const PatchRow *patches, int n_patches, int max_padded_cells,
+                          int max_ring, const InstRow *inst, double dt, const uint8_t *masks,
+                          const double *lam_in, double *lam_out, hipStream_t s);
+hipError_t launch_gather(const PatchRow *patches, int patch, int comp, int n, const int32_t *ij,
+                         const double *buf, double *out, hipStream_t s);
+hipError_t launch_add_at(const PatchRow *patches, int patch, int comp, int n, const int32_t *ij,
+                         const double *val, double *buf, hipStream_t s);
 
 }  // namespace ws

@@ -36,56 +36,12 @@
 
 #include <climits>
 
+#include "ws_device.h"
 #include "ws_internal.h"
 #include "../../include/wavestep.h"
 
 namespace ws {
 namespace {
-
-// --------------------------------------------------------------------------
-// Per-tile coefficients (computed in FP64, rounded once to T)
-// --------------------------------------------------------------------------
-template <typename T>
-struct Coef {
-  T Z;
-  T h, hz;                // c/2, c/(2Z): fluctuation factors
-  T fx, fxz, fy, fyz;     // c(1-nu)/4 and /Z: correction factors
-  T gx, gxz, gy, gyz;     // dtdx c^2/8 and /Z: transverse factors
-  T dtdx, dtdy;
-};
-
-// Wave-uniform values are moved to scalar registers.
-__device__ inline double uniform(double v) {
-  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
-                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
-}
-__device__ inline float uniform(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-
-template <typename T>
-__device__ inline Coef<T> make_coef(double c, double Z, double dt, double dx, double dy) {
-  const double dtdx = dt / dx, dtdy = dt / dy, iz = 1.0 / Z;
-  const double fx = 0.25 * c * (1.0 - c * dtdx), fy = 0.25 * c * (1.0 - c * dtdy);
-  const double gx = 0.125 * dtdx * c * c, gy = 0.125 * dtdy * c * c;
-  Coef<T> k;
-  k.Z = (T)Z;
-  k.h = (T)(0.5 * c);
-  k.hz = (T)(0.5 * c * iz);
-  k.fx = (T)fx;
-  k.fxz = (T)(fx * iz);
-  k.fy = (T)fy;
-  k.fyz = (T)(fy * iz);
-  k.gx = (T)gx;
-  k.gxz = (T)(gx * iz);
-  k.gy = (T)gy;
-  k.gyz = (T)(gy * iz);
-  k.dtdx = (T)dtdx;
-  k.dtdy = (T)dtdy;
-  T *f = &k.Z;
-  for (int n = 0; n < (int)(sizeof(Coef<T>) / sizeof(T)); ++n) f[n] = uniform(f[n]);
-  return k;
-}
 
 // --------------------------------------------------------------------------
 // Limiter on unscaled strengths: psi(a, a_up) = phi(a_up/a) a.
@@ -488,59 +444,73 @@ __device__ inline double do_tile(const StepArgs &a, int t, double *s_red) {
   return m;
 }
 
-__device__ inline double load_agent(const double *p) {
+__device__ inline unsigned long long load_agent(const unsigned long long *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// File the step's Courant numbers from the per-tile values: per patch (max
-// over its tiles), per instance and per level; running maxima; dt set
+// File the step's Courant numbers: per instance the max over the XCD groups'
+// accumulators (which are cleared), the level max, running maxima, and dt set
 // (dt_override > 0) and rescaled by cfl_desired / cfl (cfl_desired > 0),
 // Sec. 2.5 eq. (2.11).  Run by one whole workgroup after every tile of the
 // step has finished.
 __device__ inline void finish_step(const CflSlots &c, double dt_override, double cfl_desired) {
-  constexpr int kChunk = 1024;  // instances per pass over the patches
-  __shared__ unsigned long long s_inst[kChunk];
   __shared__ double s_lvl[kThreads / 64];
   const int tid = (int)threadIdx.x;
   double lvl = 0.0;
-  for (int k = tid; k < c.n_patches; k += kThreads) {
-    const PatchRow &pr = c.patches[k];
-    double m = 0.0;
-    for (int t = pr.tile_begin; t < pr.tile_begin + pr.n_tiles; ++t) m = fmax(m, load_agent(&c.cfl_tile[t]));
-    c.cfl_patch_last[k] = m;
-    lvl = fmax(lvl, m);
+  for (int k = tid; k < c.n_inst; k += kThreads) {
+    unsigned long long b = 0;
+    for (int g = 0; g < kGroups; ++g) {
+      unsigned long long *slot = &c.inst_acc[(int64_t)g * c.n_inst + k];
+      b = max(b, load_agent(slot));
+      __hip_atomic_store(slot, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const double cfl = __longlong_as_double((long long)b);
+    c.cfl_last[k] = cfl;
+    c.cfl_max[k] = fmax(c.cfl_max[k], cfl);
+    double dt = dt_override > 0.0 ? dt_override : c.dt[k];
+    if (cfl_desired > 0.0 && cfl > 0.0) dt = dt * cfl_desired / cfl;
+    c.dt[k] = dt;
+    lvl = fmax(lvl, cfl);
   }
   lvl = wave_max(lvl);
   if ((tid & 63) == 0) s_lvl[tid >> 6] = lvl;
-  __syncthreads();  // also makes cfl_patch_last visible to the workgroup
+  __syncthreads();
   if (tid == 0) {
     double m = s_lvl[0];
     for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, s_lvl[w]);
     c.level_last[0] = m;
   }
-  for (int k0 = 0; k0 < c.n_inst; k0 += kChunk) {
-    for (int k = tid; k < kChunk; k += kThreads) s_inst[k] = 0ull;
-    __syncthreads();
-    for (int k = tid; k < c.n_patches; k += kThreads) {
-      const int in = c.patches[k].inst - k0;
-      if (in >= 0 && in < kChunk) atomicMax(&s_inst[in], dbits(c.cfl_patch_last[k]));
-    }
-    __syncthreads();
-    for (int k = k0 + tid; k < min(c.n_inst, k0 + kChunk); k += kThreads) {
-      const double cfl = __longlong_as_double((long long)s_inst[k - k0]);
-      c.cfl_last[k] = cfl;
-      c.cfl_max[k] = fmax(c.cfl_max[k], cfl);
-      double dt = dt_override > 0.0 ? dt_override : c.dt[k];
-      if (cfl_desired > 0.0 && cfl > 0.0) dt = dt * cfl_desired / cfl;
-      c.dt[k] = dt;
-    }
-    __syncthreads();
-  }
 }
 
-// Record a tile's Courant number where every XCD can read it.
-__device__ inline void store_tile_cfl(const StepArgs &a, int t, double m) {
+// A workgroup's running maximum over consecutive tiles of one instance, filed
+// into its XCD group's slot with one atomic max per run.  The atomic returns
+// and is waited for before the workgroup retires.
+struct CflRun {
+  int inst = -1;
+  double val = 0.0;
+};
+
+__device__ inline void flush_cfl(const StepArgs &a, int group, CflRun &run) {
+  if (run.inst >= 0 && run.val > 0.0) {
+    const unsigned long long old = __hip_atomic_fetch_max(
+        &a.slots.inst_acc[(int64_t)group * a.slots.n_inst + run.inst], dbits(run.val),
+        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("s_waitcnt vmcnt(0)" : : "v"(old) : "memory");
+  }
+  run.inst = -1;
+  run.val = 0.0;
+}
+
+// Thread 0 after a tile: record the tile's value (for the per-patch array)
+// where every XCD can read it, and fold it into the running maximum.
+__device__ inline void file_tile(const StepArgs &a, int group, CflRun &run, int t, double m) {
   __hip_atomic_store(&a.slots.cfl_tile[t], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int inst = a.patches[a.tiles[t].patch].inst;
+  if (inst != run.inst) {
+    flush_cfl(a, group, run);
+    run.inst = inst;
+  }
+  run.val = fmax(run.val, m);
 }
 
 // Persistent launch.  Tiles are split into up to kGroups contiguous runs, one
@@ -551,11 +521,15 @@ __device__ inline void store_tile_cfl(const StepArgs &a, int t, double m) {
 template <typename T, int LIM, bool MASKS, int VARS>
 __device__ inline void step_body(const StepArgs &a) {
   __shared__ double s_red[kThreads / 64];
+  CflRun run;  // meaningful in thread 0 only
   if (!a.persistent) {
     const int t = a.tile_base + (int)blockIdx.x;
     if (t < a.n_tiles) {
       const double m = do_tile<T, LIM, MASKS, VARS>(a, t, s_red);
-      if (threadIdx.x == 0) store_tile_cfl(a, t, m);
+      if (threadIdx.x == 0) {
+        file_tile(a, 0, run, t, m);
+        flush_cfl(a, 0, run);
+      }
     }
     return;
   }
@@ -567,13 +541,14 @@ __device__ inline void step_body(const StepArgs &a) {
   const int end = (int)((int64_t)a.n_tiles * (x + 1) / groups);
   for (int t = beg + y; t < end; t += in_group) {
     const double m = do_tile<T, LIM, MASKS, VARS>(a, t, s_red);  // ends with a barrier
-    if (threadIdx.x == 0) store_tile_cfl(a, t, m);
+    if (threadIdx.x == 0) file_tile(a, x, run, t, m);
   }
-  // Retire: the tile values are stored before the counts (waited for); the
-  // last workgroup of each run counts the run, and the last run's last
-  // workgroup files the step and rewinds the counters for the next launch.
+  // Retire: this workgroup's values are filed (and waited for) before its
+  // count; the last workgroup of each run counts the run, and the last run's
+  // last workgroup files the step and rewinds the counters for the next launch.
   __shared__ int s_last;
   if (threadIdx.x == 0) {
+    flush_cfl(a, x, run);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     int last = 0;
     const unsigned d = __hip_atomic_fetch_add(&a.retire[x * kLine], 1u, __ATOMIC_RELAXED,
@@ -641,6 +616,27 @@ __global__ void set_dt_kernel(double *dt, int n, double value) {
 
 __global__ __launch_bounds__(kThreads) void finish_step_kernel(CflSlots c, double cfl_desired) {
   finish_step(c, 0.0, cfl_desired);
+}
+
+// Per-patch Courant numbers of the last step (the per-patch maximum-speed array
+// of Sec. 3.2.2), reduced from the per-tile values when they are read.
+__global__ __launch_bounds__(kThreads) void patch_cfl_kernel(const PatchRow *patches,
+                                                           int n_patches, const double *cfl_tile,
+                                                           double *cfl_patch) {
+  __shared__ double s_red[kThreads / 64];
+  const int k = blockIdx.x;
+  if (k >= n_patches) return;
+  const PatchRow pr = patches[k];
+  double m = 0.0;
+  for (int t = pr.tile_begin + (int)threadIdx.x; t < pr.tile_begin + pr.n_tiles; t += kThreads)
+    m = fmax(m, cfl_tile[t]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, s_red[w]);
+    cfl_patch[k] = fmax(m, s_red[0]);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -765,6 +761,14 @@ hipError_t launch_set_dt(const CflSlots &c, double value, hipStream_t s) {
 
 hipError_t launch_finish_step(const CflSlots &c, double cfl_desired, hipStream_t s) {
   hipLaunchKernelGGL(finish_step_kernel, dim3(1), dim3(kThreads), 0, s, c, cfl_desired);
+  return hipGetLastError();
+}
+
+hipError_t launch_patch_cfl(const PatchRow *patches, int n_patches, const double *cfl_tile,
+                            double *cfl_patch, hipStream_t s) {
+  if (n_patches <= 0) return hipSuccess;
+  hipLaunchKernelGGL(patch_cfl_kernel, dim3(n_patches), dim3(kThreads), 0, s, patches, n_patches,
+                     cfl_tile, cfl_patch);
   return hipGetLastError();
 }
 

@@ -89,6 +89,8 @@ class Level:
             t = q.detach().to(self.dtype).contiguous()
             if t.shape != (3, my + 4, mx + 4):
                 raise ValueError(f"patch {k}: expected shape {(3, my + 4, mx + 4)}")
+            if t.is_cuda:
+                self.stream.wait_stream(torch.cuda.current_stream(self.device))
             C.check(self._L.ws_upload_patch(self._ctx, k, ctypes.c_void_p(t.data_ptr())))
             return
         a = np.ascontiguousarray(q, dtype=self.np_dtype)
@@ -106,7 +108,12 @@ class Level:
         C.check(self._L.ws_fill_ghosts(self._ctx))
 
     # ----------------------------------------------------------------- steps
-    def step(self, dt: float) -> float:
+    def step(self, dt: float, read_cfl: bool = True):
+        """One level step with fixed dt; returns the level's Courant number
+        (read_cfl=False: asynchronous, returns None)."""
+        if not read_cfl:
+            C.check(self._L.ws_step_level(self._ctx, float(dt), None))
+            return None
         cfl = ctypes.c_double(0.0)
         C.check(self._L.ws_step_level(self._ctx, float(dt), ctypes.byref(cfl)))
         return cfl.value
@@ -160,6 +167,110 @@ class Level:
         P = ctypes.POINTER(ctypes.c_int32)
         C.check(self._L.ws_set_tiling(self._ctx, var.ctypes.data_as(P), tw.ctypes.data_as(P),
                                       th.ctypes.data_as(P), int(wg_per_cu)))
+
+    # --------------------------------------------------------------- adjoint
+    # Buffers passed in come from torch's current stream: the level's stream
+    # waits for it before the library reads them, and torch's stream waits
+    # for the level's stream before it reads what the library wrote.
+    def _sync_in(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _sync_out(self):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
+    def mask_bytes(self) -> int:
+        b = ctypes.c_int64(0)
+        C.check(self._L.ws_mask_bytes(self._ctx, ctypes.byref(b)))
+        return b.value
+
+    def new_masks(self) -> torch.Tensor:
+        """A device buffer for the branches of one step."""
+        return torch.empty(self.mask_bytes(), dtype=torch.uint8, device=self.device)
+
+    def new_buffer(self) -> torch.Tensor:
+        """A zeroed FP64 device buffer in the pools' layout (for cotangents)."""
+        if self.dtype != torch.float64:
+            raise ValueError("cotangent buffers are FP64")
+        return torch.zeros(self.pool_bytes // 8, dtype=torch.float64, device=self.device)
+
+    def patch_view(self, buf: torch.Tensor, k: int) -> torch.Tensor:
+        """Patch k of a pool-layout buffer as a (3, my+4, mx+4) strided view
+        (ghost-padded; interior is [:, 2:-2, 2:-2])."""
+        off, ld, plane = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+        C.check(self._L.ws_patch_layout(self._ctx, int(k), ctypes.byref(off), ctypes.byref(ld),
+                                        ctypes.byref(plane)))
+        mx, my = self.shapes[k]
+        return buf.as_strided((3, my + 4, mx + 4), (plane.value, ld.value, 1), off.value)
+
+    def state_view(self, k: int) -> torch.Tensor:
+        """Patch k of the current state (a view into the live pool)."""
+        pool = self.pools[self.current_pool()].view(self.dtype)
+        return self.patch_view(pool, k)
+
+    def step_record_masks(self, dt: float, masks: torch.Tensor) -> None:
+        """One level step with fixed dt that records its MC branches."""
+        self._check_masks(masks)
+        self._sync_in()
+        C.check(self._L.ws_step_record_masks(self._ctx, float(dt),
+                                             ctypes.c_void_p(masks.data_ptr()), None))
+        self._sync_out()
+
+    def adjoint_step(self, dt: float, masks: torch.Tensor, lam_in: torch.Tensor,
+                     lam_out: torch.Tensor) -> None:
+        """lam_out <- S^T lam_in for the step recorded in ``masks``."""
+        self._check_masks(masks)
+        for b in (lam_in, lam_out):
+            self._check_buffer(b)
+        self._sync_in()
+        C.check(self._L.ws_adjoint_step(self._ctx, float(dt), ctypes.c_void_p(masks.data_ptr()),
+                                        ctypes.c_void_p(lam_in.data_ptr()),
+                                        ctypes.c_void_p(lam_out.data_ptr())))
+        self._sync_out()
+
+    def _cells(self, k, ij):
+        mx, my = self.shapes[k]
+        if not (isinstance(ij, torch.Tensor) and ij.dtype == torch.int32 and ij.is_cuda
+                and ij.is_contiguous() and ij.dim() == 2 and ij.shape[1] == 2):
+            raise ValueError("ij must be a contiguous int32 device tensor of shape (n, 2)")
+        return ij.shape[0]
+
+    def gather(self, k: int, comp: int, ij: torch.Tensor, out: torch.Tensor,
+               buf: torch.Tensor | None = None) -> None:
+        """out[n] = buf(comp, i_n, j_n) of patch k (buf None: the current state)."""
+        n = self._cells(k, ij)
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() < n:
+            raise ValueError("out must be a contiguous FP64 device tensor of n values")
+        if buf is not None:
+            self._check_buffer(buf)
+        self._sync_in()
+        C.check(self._L.ws_gather(self._ctx, None if buf is None else ctypes.c_void_p(buf.data_ptr()),
+                                  int(k), int(comp), n, ctypes.c_void_p(ij.data_ptr()),
+                                  ctypes.c_void_p(out.data_ptr())))
+        self._sync_out()
+
+    def add_at(self, k: int, comp: int, ij: torch.Tensor, val: torch.Tensor,
+               buf: torch.Tensor | None = None) -> None:
+        """buf(comp, i_n, j_n) += val[n] of patch k (buf None: the current state)."""
+        n = self._cells(k, ij)
+        if val.dtype != torch.float64 or not val.is_contiguous() or val.numel() < n:
+            raise ValueError("val must be a contiguous FP64 device tensor of n values")
+        if buf is not None:
+            self._check_buffer(buf)
+        self._sync_in()
+        C.check(self._L.ws_add_at(self._ctx, None if buf is None else ctypes.c_void_p(buf.data_ptr()),
+                                  int(k), int(comp), n, ctypes.c_void_p(ij.data_ptr()),
+                                  ctypes.c_void_p(val.data_ptr())))
+        self._sync_out()
+
+    def _check_masks(self, masks):
+        if not (isinstance(masks, torch.Tensor) and masks.dtype == torch.uint8 and masks.is_cuda
+                and masks.is_contiguous() and masks.numel() >= self.mask_bytes()):
+            raise ValueError("masks must be a contiguous uint8 device tensor of mask_bytes()")
+
+    def _check_buffer(self, b):
+        if not (isinstance(b, torch.Tensor) and b.dtype == torch.float64 and b.is_cuda
+                and b.is_contiguous() and b.numel() * 8 >= self.pool_bytes):
+            raise ValueError("buffers must be contiguous FP64 device tensors of pool_bytes")
 
     def time_step_kernel(self, n_launches: int, per_patch: bool = False) -> float:
         """Mean milliseconds per level step of n back-to-back step launches
