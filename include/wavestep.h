@@ -92,16 +92,23 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
  * tile is worked by one workgroup of 256 threads.
  *   variant WS_TILE_DIRECT: tile_w x tile_h cells, tile_w in {8,16,...,256},
  *     one thread per column computing each cell from its 13-point footprint;
- *   variant WS_TILE_MARCH: 256/tile_w lane segments of tile_w in {16,32,64}
- *     lanes stacked vertically; each segment updates tile_w-4 columns and
- *     tile_h/(256/tile_w) rows, carrying y-terms up the column in registers and
- *     exchanging x-terms between neighbouring lanes.
+ *   variant WS_TILE_MARCH: tile_w = 64; four one-wavefront segments of 64
+ *     lanes stacked vertically; each segment updates 60 columns and tile_h/4
+ *     rows, carrying y-terms up the column in registers and exchanging
+ *     x-terms between neighbouring lanes.  Patches of more than 2^31 bytes
+ *     (three planes) take DIRECT tiles only.
  * tile_h must be a multiple of 256/tile_w with at most 64 rows per thread
  * (DIRECT) or per segment (MARCH).
  * Periodic patches take DIRECT tiles only.
  * variant may be NULL (all DIRECT).  Results do not depend on the tiling
  * (bitwise).  Invalidates a captured graph. */
 enum { WS_TILE_DIRECT = 0, WS_TILE_MARCH = 1 };
+
+/* The tiling in use: per patch variant, tile_w, tile_h (arrays of n_patches,
+ * each may be NULL) and the persistent launch's workgroups per CU and grid
+ * size (either may be NULL). */
+int ws_get_tiling(ws_ctx *ctx, int32_t *variant, int32_t *tile_w, int32_t *tile_h,
+                  int32_t *wg_per_cu, int32_t *grid);
 int ws_set_tiling(ws_ctx *ctx, const int32_t *variant, const int32_t *tile_w,
                   const int32_t *tile_h, int32_t wg_per_cu);
 

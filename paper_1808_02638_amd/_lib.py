@@ -21,7 +21,7 @@ WS_TILE_DIRECT, WS_TILE_MARCH = 0, 1
 
 #: every symbol the header declares
 EXPORTS = (
-    "ws_layout", "ws_init_patches", "ws_set_tiling", "ws_upload_patch", "ws_download_patch",
+    "ws_layout", "ws_init_patches", "ws_set_tiling", "ws_get_tiling", "ws_upload_patch", "ws_download_patch",
     "ws_fill_ghosts", "ws_step_level", "ws_step_level_per_patch", "ws_set_dt", "ws_step_auto",
     "ws_capture_steps", "ws_graph_launch", "ws_read_dt_cfl", "ws_read_patch_cfl",
     "ws_conservation_sums", "ws_mask_bytes", "ws_patch_layout", "ws_step_record_masks",
@@ -68,6 +68,7 @@ def lib():
         "ws_init_patches": [P(vp), P(PatchDesc), i32, P(Material), i32, i32, i32, i32,
                             vp, vp, i64, vp, i64, vp],
         "ws_set_tiling": [vp, P(i32), P(i32), P(i32), i32],
+        "ws_get_tiling": [vp, P(i32), P(i32), P(i32), P(i32), P(i32)],
         "ws_upload_patch": [vp, i32, vp],
         "ws_download_patch": [vp, i32, vp],
         "ws_fill_ghosts": [vp],

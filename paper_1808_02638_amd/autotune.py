@@ -9,8 +9,8 @@ steps is timed per candidate, so the level is left exactly as it was.  The
 tiling never changes results (the library's arithmetic per cell does not
 depend on it), so tuning is safe on a live level.
 
-Choices are cached in a JSON file keyed by GPU architecture, dtype, limiter
-and the patch-size histogram.
+Choices are cached in a JSON file keyed by GPU architecture, the library
+build, dtype, limiter and the patch-size histogram.
 """
 
 from __future__ import annotations
@@ -55,22 +55,24 @@ def candidates(mx, my, periodic):
                 continue
             out.append((DIRECT, tw, nty * r))
     if not periodic:
-        for w in (16, 32, 64):
-            if w - 4 > 2 * mx and w > 16:
+        for r in (4, 8, 12, 16, 18, 20, 24, 32, 48, 64):  # rows per one-wavefront segment
+            if 4 * r > 2 * my and r > 4:
                 continue
-            nseg = 256 // w
-            for r in (4, 8, 16, 32):
-                if nseg * r > 2 * my and r > 4:
-                    continue
-                out.append((MARCH, w, nseg * r))
+            out.append((MARCH, 64, 4 * r))
     return out
+
+
+def _library_version():
+    from . import _lib
+    with open(_lib.LIB_PATH, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
 
 
 def _key(level):
     arch = torch.cuda.get_device_properties(level.device).gcnArchName
-    hist = sorted({(mx, my, level.bcs[k]) for k, (mx, my) in enumerate(level.shapes)})
+    hist = sorted({(mx, my, str(level.bcs[k])) for k, (mx, my) in enumerate(level.shapes)})
     h = hashlib.sha1(json.dumps([hist, len(level.shapes)]).encode()).hexdigest()[:16]
-    return f"{arch}|{level.dtype}|{level.limiter}|{h}"
+    return f"{arch}|{_library_version()}|{level.dtype}|{level.limiter}|{h}"
 
 
 def _default_cache():
@@ -117,13 +119,9 @@ def autotune(level, *, launches=20, use_cache=True, cache_path=None, verbose=Fal
         level.time_step_kernel(2)
         return level.time_step_kernel(launches)
 
-    # start from each class's first-fit default: the widest DIRECT tile
-    choice = {}
-    for c, idx in classes.items():
-        mx = max(level.shapes[k][0] for k in idx)
-        my = max(level.shapes[k][1] for k in idx)
-        cands = candidates(mx, my, c[2])
-        choice[c] = cands[0]
+    # start from the library's default tiling (the class's first patch)
+    var0, tw0, th0, _wg0, _grid0 = level.get_tiling()
+    choice = {c: (var0[idx[0]], int(tw0[idx[0]]), int(th0[idx[0]])) for c, idx in classes.items()}
     wg = 0
     best = timed(choice, wg)
     order = sorted(classes, key=lambda c: -sum(level.shapes[k][0] * level.shapes[k][1]

@@ -101,7 +101,8 @@ int64_t max_tiles_of(const ws_patch_desc *p, int n) {
     int64_t m = 0;
     for (int tw : kTileWidths) {
       m = std::max(m, tiles_of(p[k].mx, p[k].my, kDirect, tw, kThreads / tw));
-      if (tw >= 16 && tw <= 64) m = std::max(m, tiles_of(p[k].mx, p[k].my, kMarch, tw, kThreads / tw));
+      if (tw == kMarchWidth)
+        m = std::max(m, tiles_of(p[k].mx, p[k].my, kMarch, tw, kThreads / tw));
     }
     t += m;
   }
@@ -139,20 +140,26 @@ bool valid_tile(int variant, int tw, int th) {
   bool ok_w = false;
   for (int w : kTileWidths) ok_w |= (w == tw);
   if (!ok_w) return false;
-  if (variant == kMarch && (tw < 16 || tw > 64)) return false;
+  if (variant == kMarch && tw != kMarchWidth) return false;
   const int nty = kThreads / tw;
   const int rmax = variant == kMarch ? kMaxMarchRows : kMaxRowsPerThread;
   return th >= nty && th % nty == 0 && th / nty <= rmax;
 }
 
-// Default tiling.  Wide patches: MARCH segments of 64 lanes, 16 rows each.
-// Narrow patches: DIRECT tiles whose width in {8..64} wastes the fewest
-// columns (larger on ties), up to 8 rows per thread.
-void default_tile(int mx, int my, int bc, int *variant, int *tw, int *th) {
+// Default tiling.  Wide patches: MARCH tiles of four 60-column segments whose
+// height makes the patch's tile count just fit one round of resident
+// workgroups (assumed 4 per CU; at least 8 rows per segment, so the two halo
+// rows at each end stay a small share); up to 64 rows per segment.  Narrow
+// patches: DIRECT tiles whose width in {8..64} wastes the fewest columns
+// (larger on ties), up to 8 rows per thread.
+void default_tile(int mx, int my, int bc, int n_cu, int *variant, int *tw, int *th) {
   if (mx >= 120 && bc != WS_BC_PERIODIC) {
     *variant = kMarch;
-    *tw = 64;
-    *th = (kThreads / 64) * std::max(1, std::min(kMaxMarchRows, (my + 3) / 4));
+    *tw = kMarchWidth;
+    const int ntx = (mx + kMarchWidth - 5) / (kMarchWidth - 4);
+    const int tile_rows = std::max(1, 4 * std::max(n_cu, 1) / ntx);  // rows of tiles
+    const int seg = (my + 4 * tile_rows - 1) / (4 * tile_rows);      // rows per segment
+    *th = 4 * std::max(std::min(seg, kMaxMarchRows), std::min(8, (my + 3) / 4));
     return;
   }
   *variant = kDirect;
@@ -172,6 +179,11 @@ void default_tile(int mx, int my, int bc, int *variant, int *tw, int *th) {
   r = std::max(1, std::min(r, 8));
   *tw = best;
   *th = nty * r;
+}
+
+// MARCH tiles address a patch with 32-bit byte offsets (all three planes).
+bool march_fits(int64_t plane, int dtype) {
+  return 3 * plane * (dtype == WS_F32 ? 4 : 8) < (int64_t{1} << 31);
 }
 
 int check_desc(const ws_patch_desc *p, int n, int n_inst) {
@@ -374,7 +386,10 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
     r.plane = c->P.plane[k];
     r.inst = d.instance;
     r.bc = d.bc;
-    default_tile(d.mx, d.my, d.bc, &r.variant, &r.tw, &r.th);
+    default_tile(d.mx, d.my, d.bc, c->n_cu, &r.variant, &r.tw, &r.th);
+    if (r.variant == kMarch && !march_fits(r.plane, dtype)) {
+      default_tile(d.mx, d.my, WS_BC_PERIODIC, c->n_cu, &r.variant, &r.tw, &r.th);  // DIRECT
+    }
     r.dx = d.dx;
     r.dy = d.dy;
     r.mask_off = mask_off;
@@ -417,6 +432,8 @@ int ws_set_tiling(ws_ctx *c, const int32_t *variant, const int32_t *tile_w,
                     tile_h[k]);
       if (v == kMarch && c->rows[k].bc == WS_BC_PERIODIC)
         return fail(WS_EINVAL, "patch %d: periodic patches take DIRECT tiles only", k);
+      if (v == kMarch && !march_fits(c->rows[k].plane, c->dtype))
+        return fail(WS_EINVAL, "patch %d: too large for MARCH tiles (32-bit offsets)", k);
     }
   HIPCHK(hipStreamSynchronize(c->stream));
   if (tile_w)
@@ -428,6 +445,19 @@ int ws_set_tiling(ws_ctx *c, const int32_t *variant, const int32_t *tile_w,
   if (wg_per_cu > 0) c->wg_override = wg_per_cu;
   c->drop_graph();
   return c->build_tiles();
+}
+
+int ws_get_tiling(ws_ctx *c, int32_t *variant, int32_t *tile_w, int32_t *tile_h,
+                  int32_t *wg_per_cu, int32_t *grid) {
+  if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  for (int k = 0; k < c->n_patches; ++k) {
+    if (variant) variant[k] = c->rows[k].variant;
+    if (tile_w) tile_w[k] = c->rows[k].tw;
+    if (tile_h) tile_h[k] = c->rows[k].th;
+  }
+  if (wg_per_cu) *wg_per_cu = c->wg_per_cu;
+  if (grid) *grid = c->grid;
+  return WS_OK;
 }
 
 static int copy_patch(ws_ctx *c, int32_t patch, const void *src, void *dst, bool up) {

@@ -18,6 +18,7 @@ constexpr int kMaxMarchRows = 64;      // MARCH segments
 // the y-direction terms in registers and exchanging x-direction terms with
 // neighbouring lanes; a segment of w lanes updates w-4 columns.
 enum TileVariant { kDirect = 0, kMarch = 1 };
+constexpr int kMarchWidth = 64;  // MARCH segments are one wavefront wide
 
 // One row of the device patch table.
 struct PatchRow {

@@ -237,21 +237,59 @@ __device__ inline double shl(double v) {
 __device__ inline float shr(float v) { return __int_as_float(dpp_shr_i(__float_as_int(v))); }
 __device__ inline float shl(float v) { return __int_as_float(dpp_shl_i(__float_as_int(v))); }
 
-// MARCH path for one segment: lanes l = 0..w-1 hold columns i = c0-2+l, the
+// Raw buffer stores (gfx9 buffer resource, no format conversion).  An offset
+// at or past the resource's size is dropped by the hardware.
+constexpr int kRawBufferWord3 = 0x00020000;
+constexpr unsigned kDropOffset = 0x80000000u;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ inline void bstore(__amdgpu_buffer_rsrc_t r, double v, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ inline void bstore(__amdgpu_buffer_rsrc_t r, float v, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+
+// s_waitcnt immediate (gfx9 encoding) waiting for vmcnt(0) only.
+constexpr int kWaitVmcnt0 = 0x0F70;
+
+// One row of (p, u, v) of a MARCH segment's column.
+template <typename T>
+struct Row3 {
+  T p, u, v;
+};
+
+// A table row read by a whole workgroup, moved to scalar registers word by
+// word (the kernel stores to memory, so the compiler cannot use scalar loads
+// for it and would otherwise treat its fields as per-lane values).
+template <typename S>
+__device__ inline S uniform_row(const S &v) {
+  static_assert(sizeof(S) % 4 == 0, "row must be whole words");
+  uint32_t w[sizeof(S) / 4];
+  __builtin_memcpy(w, &v, sizeof(S));
+#pragma unroll
+  for (int n = 0; n < (int)(sizeof(S) / 4); ++n) w[n] = __builtin_amdgcn_readfirstlane(w[n]);
+  S out;
+  __builtin_memcpy(&out, w, sizeof(S));
+  return out;
+}
+
+// MARCH path for one segment of one wavefront (w = 64 lanes): lanes
+// l = 0..w-1 hold columns i = c0-2+l, the
 // segment updates columns c0..c0+w-5 (lanes 2..w-3) over rows [r0, r1).
 // Every lane loads its own column only; x-neighbour terms come through lane
 // shifts; y-direction terms slide up the column in registers.  Each quantity
 // uses the same expression as in cell_update, so the result is bitwise equal.
 template <typename T, int LIM, bool MASKS>
 __device__ inline void march_segment(const T *qi, T *qo, const PatchRow &pr, const Coef<T> &k,
-                                     int l, int w, int i, int r0, int r1, uint8_t *masks) {
+                                     int l, int i, int r0, int r1, uint8_t *masks) {
+  constexpr int w = kMarchWidth;
   const T Z = k.Z;
   const unsigned ld = (unsigned)pr.ld, pl = (unsigned)pr.plane;
   // lanes past the last ghost column read that column instead (never used)
   const int ic = min(i, pr.mx + 1);
   // Unsigned 32-bit byte offsets from the padded origin (cell -2,-2 of plane
   // p) off a wave-uniform base: ((row+2) * ld + column+2) * sizeof(T); planes
-  // u, v follow at +plb, +2 plb.  Patches hold < 2^29 elements.
+  // u, v follow at +plb, +2 plb.  MARCH patches span < 2^31 bytes.
   const char *base = reinterpret_cast<const char *>(qi - 2 * (int64_t)ld - 2);
   const unsigned plb = pl * (unsigned)sizeof(T);
   auto at = [&](int r) {
@@ -264,15 +302,50 @@ __device__ inline void march_segment(const T *qi, T *qo, const PatchRow &pr, con
   const bool ybc = pr.bc == WS_BC_EXTRAP;
   const int c0 = i - l + 2;  // first column this segment updates
   const bool xbc = ybc && (c0 == 0 || c0 + w - 4 >= pr.mx);
-  // ---- prologue: rows r0-2 .. r0+1
-  const unsigned om2 = at(r0 - 2), om1 = at(r0 - 1), o0 = at(r0), o1 = at(r0 + 1);
+  // lanes that store: interior columns of the segment, and on physical sides
+  // the ghost columns (gx: 1, 2 -> i = -1, -2 copy column 0; 3, 4 -> i = mx,
+  // mx+1 copy column mx-1)
+  int gx = 0;
+  if (xbc) {
+    if (i == -1) gx = 1;
+    if (i == -2) gx = 2;
+    if (i == pr.mx && l <= w - 2) gx = 3;
+    if (i == pr.mx + 1 && l <= w - 1) gx = 4;
+  }
+  const bool st = out || gx != 0;
+  // output through a buffer resource over the patch (byte offsets from the
+  // padded origin, like the loads)
+  const __amdgpu_buffer_rsrc_t ob = __builtin_amdgcn_make_buffer_rsrc(
+      reinterpret_cast<char *>(qo - 2 * (int64_t)ld - 2), 0, (int)(3 * plb), kRawBufferWord3);
+  auto oat = [&](int r) {
+    return ((unsigned)(r + 2) * ld + (unsigned)(i + 2)) * (unsigned)sizeof(T);
+  };
+  // Six row sets: set k holds the row r with (r - r0) % 6 == k from its load
+  // until its last use (as row r+2, r+1, then r of the row being updated),
+  // and is then refilled in place with row r+6.  Rows past the last ghost
+  // row are clamped to it (never used).
+  Row3<T> R0, R1, R2, R3, R4, R5;
+  auto fetch = [&](Row3<T> &S, int rr) {
+    const unsigned o = at(min(rr, pr.my + 1));
+    S.p = get(o);
+    S.u = get(o + plb);
+    S.v = get(o + 2 * plb);
+  };
+  // ---- prologue: rows r0-2, r0-1, and the six sets (r0 .. r0+5)
+  const unsigned om2 = at(r0 - 2), om1 = at(r0 - 1);
   const T Pm2 = get(om2), Pm1 = get(om1);
   const T Vm2 = get(om2 + 2 * plb), Vm1 = get(om1 + 2 * plb);
   const T Um1 = get(om1 + plb);
-  T P0 = get(o0), U0 = get(o0 + plb), V0 = get(o0 + 2 * plb);
-  T P1 = get(o1), U1 = get(o1 + plb), V1 = get(o1 + 2 * plb);
-  const unsigned o2 = at(r0 + 2);  // r0 + 2 <= my + 1 always
-  T Pn = get(o2), Un = get(o2 + plb), Vn = get(o2 + 2 * plb);
+  fetch(R0, r0);
+  fetch(R1, r0 + 1);
+  fetch(R2, r0 + 2);
+  fetch(R3, r0 + 3);
+  fetch(R4, r0 + 4);
+  fetch(R5, r0 + 5);
+  // all of them have landed before the loop (the loop's waits then follow
+  // its steady state); vmcnt(0) with expcnt and lgkmcnt left open
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  const T P0 = R0.p, U0 = R0.u, V0 = R0.v, P1 = R1.p, V1 = R1.v;
   const T b2mm = s2(Z, Pm1 - Pm2, Vm1 - Vm2);                                // y-edge r0-3/2
   const T b1m = s1(Z, P0 - Pm1, V0 - Vm1), b2m = s2(Z, P0 - Pm1, V0 - Vm1);  // r0-1/2
   T b1h = s1(Z, P1 - P0, V1 - V0), b2h = s2(Z, P1 - P0, V1 - V0);            // r0+1/2
@@ -292,14 +365,14 @@ __device__ inline void march_segment(const T *qi, T *qo, const PatchRow &pr, con
   if constexpr (MASKS) ybits = (mc_branch(b1m, b1h) << 4) | (mc_branch(b2m, b2mm) << 6);
   const int64_t mld = pr.mx + 1;
 
-  for (int r = r0; r < r1; ++r) {
-    // row r+2 arrives; row r+3 is requested (the last ghost row is re-read
-    // past the end, never used)
-    const T P2 = Pn, U2 = Un, V2 = Vn;
-    const unsigned on = at(min(r + 3, pr.my + 1));
-    Pn = get(on);
-    Un = get(on + plb);
-    Vn = get(on + 2 * plb);
+  // One row r: A, B, C hold rows r, r+1, r+2; A is refilled with row r+6 at
+  // the end (the barriers keep the scheduler from moving the refill above
+  // the row's last use of A, or the next row's arithmetic above this row's).
+  auto row = [&](Row3<T> &A, const Row3<T> &B, const Row3<T> &C, int r, bool refill) {
+    __builtin_amdgcn_sched_barrier(0);
+    const T P0 = A.p, U0 = A.u, V0 = A.v;
+    const T P1 = B.p, U1 = B.u, V1 = B.v;
+    const T P2 = C.p, V2 = C.v;
     // y-edge r+3/2 of this column and the y-fluctuations of cell (i, r)
     const T b1hh = s1(Z, P2 - P1, V2 - V1), b2hh = s2(Z, P2 - P1, V2 - V1);
     const T ys0 = yb2 + b1h, yd0 = yb2 - b1h;
@@ -320,32 +393,34 @@ __device__ inline void march_segment(const T *qi, T *qo, const PatchRow &pr, con
     // Extrapolation boundaries: the lanes on ghost columns take the new value
     // of the nearest interior column from their neighbours, and the first and
     // last rows are repeated into the ghost rows (corners included).
-    bool st = out;
     if (xbc) {
       const T p1 = shl(pn), u1 = shl(un), v1 = shl(vn);
       const T p2 = shl(p1), u2 = shl(u1), v2 = shl(v1);
       const T p3 = shr(pn), u3 = shr(un), v3 = shr(vn);
       const T p4 = shr(p3), u4 = shr(u3), v4 = shr(v3);
-      if (i == -1) { pn = p1; un = u1; vn = v1; st = true; }
-      if (i == -2) { pn = p2; un = u2; vn = v2; st = true; }
-      if (i == pr.mx && l <= w - 2) { pn = p3; un = u3; vn = v3; st = true; }
-      if (i == pr.mx + 1 && l <= w - 1) { pn = p4; un = u4; vn = v4; st = true; }
+      if (gx == 1) { pn = p1; un = u1; vn = v1; }
+      if (gx == 2) { pn = p2; un = u2; vn = v2; }
+      if (gx == 3) { pn = p3; un = u3; vn = v3; }
+      if (gx == 4) { pn = p4; un = u4; vn = v4; }
     }
-    if (st) {
-      const int64_t o = (int64_t)r * pr.ld + i;
-      qo[o] = pn;
-      qo[pr.plane + o] = un;
-      qo[2 * pr.plane + o] = vn;
-      if (ybc && (r == 0 || r == pr.my - 1)) {
-        const int g = r == 0 ? -1 : r + 1;  // the two ghost rows
-        const int h = r == 0 ? -2 : r + 2;
-        const int64_t og = (int64_t)g * pr.ld + i, oh = (int64_t)h * pr.ld + i;
-        qo[og] = pn;
-        qo[pr.plane + og] = un;
-        qo[2 * pr.plane + og] = vn;
-        qo[oh] = pn;
-        qo[pr.plane + oh] = un;
-        qo[2 * pr.plane + oh] = vn;
+    // every lane issues the stores (lanes that write nothing get an offset
+    // past the buffer, which the hardware drops): the wait counts before each
+    // use of a prefetched row then do not depend on which lanes stored
+    const unsigned so = st ? oat(r) : kDropOffset;
+    bstore(ob, pn, so);
+    bstore(ob, un, so + plb);
+    bstore(ob, vn, so + 2 * plb);
+    // extrapolation: the first and last interior rows repeated into the two
+    // ghost rows (corners through the ghost-column lanes).  A wave-uniform
+    // branch taken on two rows only: the wait counts stay those of the
+    // common path.
+    if (ybc && (r == 0 || r == pr.my - 1)) {
+      const int g0 = r == 0 ? -2 : pr.my;
+      for (int g = g0; g <= g0 + 1; ++g) {
+        const unsigned o = st ? oat(g) : kDropOffset;
+        bstore(ob, pn, o);
+        bstore(ob, un, o + plb);
+        bstore(ob, vn, o + 2 * plb);
       }
     }
     if constexpr (MASKS) {
@@ -360,12 +435,27 @@ __device__ inline void march_segment(const T *qi, T *qo, const PatchRow &pr, con
       ybits = tbits;
     }
     // slide up one row
-    P0 = P1; U0 = U1; V0 = V1;
-    P1 = P2; U1 = U2; V1 = V2;
     yb2 = b2h; b1h = b1hh; b2h = b2hh;
     GBp = GTp; GBv = GTv;
     xs0 = xsp; a1L = a1Ln; a2L = a2Ln; a1R = a1Rn;
+    __builtin_amdgcn_sched_barrier(0);
+    if (refill) fetch(A, r + 6);
+  };
+  int r = r0;
+  for (; r + 6 <= r1; r += 6) {
+    row(R0, R1, R2, r, true);
+    row(R1, R2, R3, r + 1, true);
+    row(R2, R3, R4, r + 2, true);
+    row(R3, R4, R5, r + 3, true);
+    row(R4, R5, R0, r + 4, true);
+    row(R5, R0, R1, r + 5, true);
   }
+  // the last rows refill only what a later row still reads (rows <= r1+1)
+  if (r < r1) { row(R0, R1, R2, r, r + 6 <= r1 + 1); ++r; }
+  if (r < r1) { row(R1, R2, R3, r, r + 6 <= r1 + 1); ++r; }
+  if (r < r1) { row(R2, R3, R4, r, r + 6 <= r1 + 1); ++r; }
+  if (r < r1) { row(R3, R4, R5, r, r + 6 <= r1 + 1); ++r; }
+  if (r < r1) { row(R4, R5, R0, r, r + 6 <= r1 + 1); ++r; }
 }
 
 __device__ inline unsigned long long dbits(double v) {
@@ -378,15 +468,15 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// One tile of one patch; returns (in thread 0) the tile's Courant number.
-// Every thread of the workgroup reaches the barrier at the end (the
-// persistent loop relies on it).
+// One tile of one patch; returns the tile's Courant number.  No barrier:
+// the wavefronts of a workgroup go through the persistent loop's tiles
+// independently.
 // VARS: bit 0 -> DIRECT tiles may occur, bit 1 -> MARCH tiles may occur.
 template <typename T, int LIM, bool MASKS, int VARS>
-__device__ inline double do_tile(const StepArgs &a, int t, double *s_red) {
-  const TileEntry te = a.tiles[t];
-  const PatchRow pr = a.patches[te.patch];
-  const InstRow in = a.inst[pr.inst];
+__device__ inline double do_tile(const StepArgs &a, int t) {
+  const TileEntry te = uniform_row(a.tiles[t]);
+  const PatchRow pr = uniform_row(a.patches[te.patch]);
+  const InstRow in = uniform_row(a.inst[pr.inst]);
   const double dt = a.dt_override > 0.0 ? a.dt_override : a.dt[pr.inst];
   const Coef<T> k = make_coef<T>(in.c, in.Z, dt, pr.dx, pr.dy);
   const int64_t org = pr.q_off + 2 * (int64_t)pr.ld + pr.col0;
@@ -394,18 +484,20 @@ __device__ inline double do_tile(const StepArgs &a, int t, double *s_red) {
   T *qo = reinterpret_cast<T *>(a.qout) + org;
   uint8_t *masks = MASKS ? a.masks + pr.mask_off : nullptr;
   const int tw = pr.tw;
-  const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
-  const int rows_per_thread = pr.th / (kThreads / tw);
-  double cfl = 0.0;
   if ((VARS & 2) && (!(VARS & 1) || pr.variant == kMarch)) {
-    const int i = te.tx * (tw - 4) - 2 + lx;
-    const int r0 = te.ty * pr.th + ly * rows_per_thread;
-    const int r1 = min(r0 + rows_per_thread, pr.my);
+    // one segment per wavefront; its rows are wave-uniform
+    const int lx = (int)threadIdx.x & 63;
+    const int seg = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int rows = pr.th / (kThreads / kMarchWidth);
+    const int i = te.tx * (kMarchWidth - 4) - 2 + lx;
+    const int r0 = te.ty * pr.th + seg * rows;
+    const int r1 = min(r0 + rows, pr.my);
     if (r0 < r1) {
-      march_segment<T, LIM, MASKS>(qi, qo, pr, k, lx, tw, i, r0, r1, masks);
-      if (lx >= 2 && lx <= tw - 3 && i < pr.mx) cfl = 1.0;
+      march_segment<T, LIM, MASKS>(qi, qo, pr, k, lx, i, r0, r1, masks);
     }
   } else if (VARS & 1) {
+    const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
+    const int rows_per_thread = pr.th / (kThreads / tw);
     const int i = te.tx * tw + lx;
     const int j0 = te.ty * pr.th + ly * rows_per_thread;
     const int j1 = min(j0 + rows_per_thread, pr.my);
@@ -423,25 +515,12 @@ __device__ inline double do_tile(const StepArgs &a, int t, double *s_red) {
           if (j == pr.my - 1) masks[(int64_t)(j + 1) * mld + i] = (uint8_t)mk.top;
         }
       }
-      cfl = 1.0;
     }
   }
-  // Courant number of the edges this thread's cells own: the speeds are +-c
-  // on every edge of a homogeneous instance, so each edge gives c dt/dx or
-  // c dt/dy.
-  if (cfl > 0.0) cfl = fmax(in.c * (dt / pr.dx), in.c * (dt / pr.dy));
-  // ---- max reduction: wavefront shuffle, then LDS across the 4 wavefronts
-  cfl = wave_max(cfl);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  if (lane == 0) s_red[wave] = cfl;
-  __syncthreads();
-  double m = 0.0;
-  if (threadIdx.x == 0) {
-    m = s_red[0];
-    for (int w = 1; w < kThreads / 64; ++w) m = fmax(m, s_red[w]);
-  }
-  __syncthreads();
-  return m;
+  // Courant number of the tile (Sec. 2.4 eq. (2.10)): every edge of a
+  // homogeneous instance carries the speeds -c, 0, +c, so each x-edge gives
+  // c dt/dx and each y-edge c dt/dy, and every tile holds edges of both kinds.
+  return fmax(in.c * (dt / pr.dx), in.c * (dt / pr.dy));
 }
 
 __device__ inline unsigned long long load_agent(const unsigned long long *p) {
@@ -520,12 +599,11 @@ __device__ inline void file_tile(const StepArgs &a, int group, CflRun &run, int 
 // round-robin (largest patches first), with no atomics.
 template <typename T, int LIM, bool MASKS, int VARS>
 __device__ inline void step_body(const StepArgs &a) {
-  __shared__ double s_red[kThreads / 64];
   CflRun run;  // meaningful in thread 0 only
   if (!a.persistent) {
     const int t = a.tile_base + (int)blockIdx.x;
     if (t < a.n_tiles) {
-      const double m = do_tile<T, LIM, MASKS, VARS>(a, t, s_red);
+      const double m = do_tile<T, LIM, MASKS, VARS>(a, t);
       if (threadIdx.x == 0) {
         file_tile(a, 0, run, t, m);
         flush_cfl(a, 0, run);
@@ -540,7 +618,7 @@ __device__ inline void step_body(const StepArgs &a) {
   const int beg = (int)((int64_t)a.n_tiles * x / groups);
   const int end = (int)((int64_t)a.n_tiles * (x + 1) / groups);
   for (int t = beg + y; t < end; t += in_group) {
-    const double m = do_tile<T, LIM, MASKS, VARS>(a, t, s_red);  // ends with a barrier
+    const double m = do_tile<T, LIM, MASKS, VARS>(a, t);
     if (threadIdx.x == 0) file_tile(a, x, run, t, m);
   }
   // Retire: this workgroup's values are filed (and waited for) before its

@@ -272,6 +272,19 @@ class Level:
                 and b.is_contiguous() and b.numel() * 8 >= self.pool_bytes):
             raise ValueError("buffers must be contiguous FP64 device tensors of pool_bytes")
 
+    def get_tiling(self):
+        """(variants, tile_w, tile_h, wg_per_cu, grid) in use; variants as
+        "direct"/"march" strings."""
+        P = ctypes.POINTER(ctypes.c_int32)
+        var = np.zeros(self.n, np.int32)
+        tw = np.zeros(self.n, np.int32)
+        th = np.zeros(self.n, np.int32)
+        wg, grid = ctypes.c_int32(0), ctypes.c_int32(0)
+        C.check(self._L.ws_get_tiling(self._ctx, var.ctypes.data_as(P), tw.ctypes.data_as(P),
+                                      th.ctypes.data_as(P), ctypes.byref(wg), ctypes.byref(grid)))
+        names = {C.WS_TILE_DIRECT: "direct", C.WS_TILE_MARCH: "march"}
+        return [names[int(v)] for v in var], tw, th, wg.value, grid.value
+
     def time_step_kernel(self, n_launches: int, per_patch: bool = False) -> float:
         """Mean milliseconds per level step of n back-to-back step launches
         (HIP events on the level's stream; fixed device dt, no dt update)."""

@@ -226,8 +226,8 @@ def test_amr_level_batched_equals_per_patch_and_oracle(ws, oracle_lib, dtype):
 TILINGS = [("direct", 8, 32), ("direct", 16, 16), ("direct", 32, 8), ("direct", 64, 4),
            ("direct", 64, 32), ("direct", 128, 2), ("direct", 256, 1), ("direct", 256, 32),
            ("direct", 32, 256), ("march", 64, 4), ("march", 64, 36), ("march", 64, 64),
-           ("march", 64, 256), ("march", 32, 8), ("march", 32, 64), ("march", 32, 128),
-           ("march", 16, 16), ("march", 16, 160), ("march", 16, 256)]
+           ("march", 64, 256), ("march", 64, 8), ("march", 64, 12), ("march", 64, 28),
+           ("march", 64, 40), ("march", 64, 100), ("march", 64, 160)]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -252,8 +252,8 @@ def test_results_do_not_depend_on_tiling(ws, dtype, bc):
 
 
 def test_march_matches_oracle_on_small_and_ragged_patches(ws, oracle_lib):
-    for (mx, my, tw, th) in [(5, 3, 16, 16), (13, 40, 16, 32), (29, 29, 32, 8), (61, 7, 64, 4),
-                             (120, 70, 64, 32)]:
+    for (mx, my, tw, th) in [(5, 3, 64, 16), (13, 40, 64, 32), (29, 29, 64, 8), (61, 7, 64, 4),
+                             (120, 70, 64, 32), (121, 9, 64, 12), (250, 33, 64, 20)]:
         rng = np.random.default_rng(mx * 100 + my)
         q = rng.normal(size=(3, my + 4, mx + 4))
         dx, dy = 1 / mx, 1 / my
