@@ -127,6 +127,32 @@ def run_amr(ws, torch, dtype, level_steps):
     return out
 
 
+PROFILE = os.path.join(ROOT, "profiles", "step_kernel_march_f64_2048sq.md")
+
+
+def measured_traffic(tiling, profile=PROFILE):
+    """HBM bytes per launch of the FP64 step kernel from the committed counter
+    summary, or None when the library has been rebuilt since the counters were
+    taken or the tiling differs from the one they were taken with."""
+    import hashlib
+
+    from paper_1808_02638_amd import _lib
+
+    try:
+        text = open(profile).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines()
+                  if line.startswith(("library_sha1: ", "traffic_bytes_per_launch: ", "tiling: ")))
+    with open(_lib.LIB_PATH, "rb") as f:
+        sha = hashlib.sha1(f.read()).hexdigest()
+    if fields.get("library_sha1", "").strip() != sha:
+        return None
+    if fields.get("tiling", "").strip() != f"{tiling['variant']}/{tiling['tile_w']}/{tiling['tile_h']}":
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(n, target_s):
     import numpy as np  # noqa: F401
 
@@ -214,7 +240,8 @@ def main():
                    "cells": n * n, "global_batch": 1, "parallelism": "single GPU",
                    "tiling": r64["tiling"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(r64["tiling"]) if n == 2048 else None,
                      "kernel": "step_kernel<double, MC>",
                      "bytes_per_launch": bytes64, "kernel_ms": r64["kernel_ms"]},
         "pct_hbm_peak": round(100 * achieved / HBM_PEAK_GBS, 2),

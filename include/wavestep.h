@@ -219,11 +219,12 @@ int ws_add_at(ws_ctx *ctx, void *buf, int32_t patch, int32_t comp, int32_t n,
               const int32_t *ij, const double *val);
 
 /* Timing entry (for the benchmark and the tile autotuner): enqueue n_launches
- * step kernels back to back (batched persistent launch, or per_patch != 0:
- * one launch per patch per step) with the device-resident dt and no dt
- * update, bracketed by HIP events on the context's stream; returns the mean
- * milliseconds per level step.  The state advances n_launches steps.
- * Synchronises the stream. */
+ * level steps back to back (batched persistent launch, or per_patch != 0:
+ * one launch per patch and the Courant-number filing kernel) with the
+ * device-resident dt and no dt update, each step bracketed by its own pair
+ * of HIP events on the context's stream; returns the mean bracketed
+ * milliseconds per level step (1 <= n_launches <= 100000).  The state
+ * advances n_launches steps.  Synchronises the stream. */
 int ws_time_step_kernel(ws_ctx *ctx, int32_t n_launches, int32_t per_patch,
                         double *ms_per_step);
 

@@ -635,39 +635,44 @@ int ws_conservation_sums(ws_ctx *c, double *sums) {
 
 int ws_time_step_kernel(ws_ctx *c, int32_t n_launches, int32_t per_patch, double *ms_per_step) {
   if (!c) return fail(WS_EINVAL, "ctx is NULL");
-  if (n_launches < 1 || !ms_per_step) return fail(WS_EINVAL, "need n_launches >= 1 and an output");
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIPCHK(hipEventCreate(&e0));
-  if (hipEventCreate(&e1) != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return fail(WS_EHIP, "hipEventCreate failed");
-  }
-  int rc = WS_OK;
-  hipError_t e = hipEventRecord(e0, c->stream);
+  if (n_launches < 1 || n_launches > 100000 || !ms_per_step)
+    return fail(WS_EINVAL, "need 1 <= n_launches <= 100000 and an output");
+  // one event pair per level step: the mean bracketed duration, without the
+  // gaps between back-to-back launches
+  std::vector<hipEvent_t> ev(2 * (size_t)n_launches, nullptr);
+  hipError_t e = hipSuccess;
+  size_t made = 0;
+  for (; made < ev.size() && e == hipSuccess; ++made) e = hipEventCreate(&ev[made]);
+  if (e != hipSuccess) --made;
   for (int s = 0; s < n_launches && e == hipSuccess; ++s) {
+    e = hipEventRecord(ev[2 * s], c->stream);
     StepArgs a = c->step_args(c->cur, 0.0, 0.0);
-    if (per_patch) {
+    if (e == hipSuccess && per_patch) {
       a.persistent = 0;
       for (int k : c->order) {
         a.tile_base = c->rows[k].tile_begin;
         e = launch_step(c->dtype, c->limiter, c->vars, a, c->rows[k].n_tiles, c->stream);
         if (e != hipSuccess) break;
       }
-    } else {
+      // per-patch launches leave their Courant numbers in the accumulators
+      if (e == hipSuccess) e = launch_finish_step(c->slots(), 0.0, c->stream);
+    } else if (e == hipSuccess) {
       e = launch_step(c->dtype, c->limiter, c->vars, a, c->grid, c->stream);
     }
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], c->stream);
     c->cur = 1 - c->cur;
   }
-  // per-patch launches leave their Courant numbers in the accumulators
-  if (e == hipSuccess && per_patch) e = launch_finish_step(c->slots(), 0.0, c->stream);
-  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-  if (e == hipSuccess) e = hipEventSynchronize(e1);
-  float ms = 0.f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[2 * (size_t)n_launches - 1]);
+  double total = 0.0;
+  for (int s = 0; s < n_launches && e == hipSuccess; ++s) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, ev[2 * s], ev[2 * s + 1]);
+    total += ms;
+  }
+  int rc = WS_OK;
   if (e != hipSuccess) rc = fail(WS_EHIP, "timing loop: %s", hipGetErrorString(e));
-  else *ms_per_step = (double)ms / n_launches;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  else *ms_per_step = total / n_launches;
+  for (size_t k = 0; k < made; ++k) (void)hipEventDestroy(ev[k]);
   return rc;
 }
 
