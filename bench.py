@@ -87,7 +87,8 @@ def run_uniform(ws, torch, n, steps, warmup, dtype, kernel_launches, tune=True):
     _dt, cfl_last, cfl_max = lev.read_dt_cfl()
     q = lev.download(0)
     finite = bool(torch.isfinite(torch.from_numpy(q)).all())
-    # the step kernel alone, back to back (HIP events on the same stream)
+    # each step launch bracketed by its own HIP event pair (reported for
+    # reference; the pairs add their own overhead to every launch)
     kernel_ms = lev.time_step_kernel(kernel_launches)
     lev.close()
     return dict(ms=ms, wall_s=wall, sums0=sums0.tolist(), sums1=sums1.tolist(),
@@ -95,7 +96,7 @@ def run_uniform(ws, torch, n, steps, warmup, dtype, kernel_launches, tune=True):
                 kernel_ms=kernel_ms, tiling=tiling)
 
 
-def run_amr(ws, torch, dtype, level_steps):
+def run_amr(ws, torch, dtype, level_steps, tune=True):
     import workloads
 
     levels = workloads.amr_level_batch()
@@ -108,6 +109,9 @@ def run_amr(ws, torch, dtype, level_steps):
         for k, p in enumerate(specs):
             lev.upload(k, workloads.padded_state(p.mx, p.my, p.xlo, p.ylo, p.dx, p.dy))
         lev.set_dt([0.9 * specs[0].dx / C_SOUND])
+        if tune:
+            from paper_1808_02638_amd.autotune import autotune
+            autotune(lev)
         lev.time_step_kernel(2)
         lev.time_step_kernel(2, per_patch=True)
         ms_b = lev.time_step_kernel(level_steps)
@@ -219,7 +223,11 @@ def main():
                       tune=not args.no_tune)
     value = n * n * K / (r64["ms"] / 1e3) / 1e9
     bytes64 = algorithmic_bytes(shapes, 8, True)
-    achieved = bytes64 / (r64["kernel_ms"] / 1e3) / 1e9
+    # the timed region is K launches of the step kernel and nothing else (the
+    # Courant-number reduction and dt update run inside it): its HIP-event
+    # time over K is the kernel's average launch duration
+    kernel_ms = r64["ms"] / K
+    achieved = bytes64 / (kernel_ms / 1e3) / 1e9
     line = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -242,8 +250,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(r64["tiling"]) if n == 2048 else None,
-                     "kernel": "step_kernel<double, MC>",
-                     "bytes_per_launch": bytes64, "kernel_ms": r64["kernel_ms"]},
+                     "kernel": "step_kernel_march<double, MC>",
+                     "bytes_per_launch": bytes64, "kernel_ms": kernel_ms,
+                     "kernel_ms_bracketed": r64["kernel_ms"]},
         "pct_hbm_peak": round(100 * achieved / HBM_PEAK_GBS, 2),
         "conservation_fp64": {"start": r64["sums0"], "end": r64["sums1"]},
         "cfl_max": r64["cfl_max"],
@@ -253,13 +262,14 @@ def main():
         r32 = run_uniform(ws, torch, n, K, args.warmup, torch.float32, args.kernel_launches,
                           tune=not args.no_tune)
         b32 = algorithmic_bytes(shapes, 4, True)
-        a32 = b32 / (r32["kernel_ms"] / 1e3) / 1e9
+        a32 = b32 / (r32["ms"] / K / 1e3) / 1e9
         line["fp32"] = {"value": round(n * n * K / (r32["ms"] / 1e3) / 1e9, 3),
                         "tiling": r32["tiling"],
                         "ms_per_step": r32["ms"] / K,
                         "kernel_GBs": round(a32, 1), "frac": round(a32 / HBM_PEAK_GBS, 4)}
-        line["amr_level_batch"] = {"fp64": run_amr(ws, torch, torch.float64, args.amr_steps),
-                                   "fp32": run_amr(ws, torch, torch.float32, args.amr_steps)}
+        line["amr_level_batch"] = {
+            "fp64": run_amr(ws, torch, torch.float64, args.amr_steps, tune=not args.no_tune),
+            "fp32": run_amr(ws, torch, torch.float32, args.amr_steps, tune=not args.no_tune)}
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

@@ -423,7 +423,7 @@ int ws_set_tiling(ws_ctx *c, const int32_t *variant, const int32_t *tile_w,
   if (!c) return fail(WS_EINVAL, "ctx is NULL");
   if ((tile_w == nullptr) != (tile_h == nullptr) || (variant != nullptr && tile_w == nullptr))
     return fail(WS_EINVAL, "give variant, tile_w and tile_h together, or none");
-  if (wg_per_cu < 0 || wg_per_cu > 64) return fail(WS_EINVAL, "wg_per_cu out of range");
+  if (wg_per_cu < 0 || wg_per_cu > 1024) return fail(WS_EINVAL, "wg_per_cu out of range");
   if (tile_w)
     for (int k = 0; k < c->n_patches; ++k) {
       const int v = variant ? variant[k] : kDirect;

@@ -238,19 +238,29 @@ __device__ inline float shr(float v) { return __int_as_float(dpp_shr_i(__float_a
 __device__ inline float shl(float v) { return __int_as_float(dpp_shl_i(__float_as_int(v))); }
 
 // Raw buffer stores (gfx9 buffer resource, no format conversion).  An offset
-// at or past the resource's size is dropped by the hardware.
+// at or past the resource's size is dropped by the hardware.  The stores are
+// device-scope (cache policy SC1: written through the XCD's L2), so the L2s
+// hold no dirty output to write back when the launch ends; the next step's
+// workgroups read it on whichever XCD they run.
 constexpr int kRawBufferWord3 = 0x00020000;
 constexpr unsigned kDropOffset = 0x80000000u;
+constexpr int kStoreDeviceScope = 16;  // SC1
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 __device__ inline void bstore(__amdgpu_buffer_rsrc_t r, double v, unsigned off) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0,
+                                        kStoreDeviceScope);
 }
 __device__ inline void bstore(__amdgpu_buffer_rsrc_t r, float v, unsigned off) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0,
+                                        kStoreDeviceScope);
 }
 
 // s_waitcnt immediate (gfx9 encoding) waiting for vmcnt(0) only.
 constexpr int kWaitVmcnt0 = 0x0F70;
+
+// Row sets of a MARCH segment (its row loop is unrolled by this count and
+// names eight sets).
+constexpr int kSets = 8;
 
 // One row of (p, u, v) of a MARCH segment's column.
 template <typename T>
@@ -273,77 +283,131 @@ __device__ inline S uniform_row(const S &v) {
   return out;
 }
 
-// MARCH path for one segment of one wavefront (w = 64 lanes): lanes
-// l = 0..w-1 hold columns i = c0-2+l, the
-// segment updates columns c0..c0+w-5 (lanes 2..w-3) over rows [r0, r1).
-// Every lane loads its own column only; x-neighbour terms come through lane
-// shifts; y-direction terms slide up the column in registers.  Each quantity
-// uses the same expression as in cell_update, so the result is bitwise equal.
-template <typename T, int LIM, bool MASKS>
-__device__ inline void march_segment(const T *qi, T *qo, const PatchRow &pr, const Coef<T> &k,
-                                     int l, int i, int r0, int r1, uint8_t *masks) {
-  constexpr int w = kMarchWidth;
-  const T Z = k.Z;
-  const unsigned ld = (unsigned)pr.ld, pl = (unsigned)pr.plane;
-  // lanes past the last ghost column read that column instead (never used)
-  const int ic = min(i, pr.mx + 1);
-  // Unsigned 32-bit byte offsets from the padded origin (cell -2,-2 of plane
-  // p) off a wave-uniform base: ((row+2) * ld + column+2) * sizeof(T); planes
-  // u, v follow at +plb, +2 plb.  MARCH patches span < 2^31 bytes.
-  const char *base = reinterpret_cast<const char *>(qi - 2 * (int64_t)ld - 2);
-  const unsigned plb = pl * (unsigned)sizeof(T);
-  auto at = [&](int r) {
-    return ((unsigned)(r + 2) * ld + (unsigned)(ic + 2)) * (unsigned)sizeof(T);
-  };
-  auto get = [&](unsigned boff) { return *reinterpret_cast<const T *>(base + boff); };
-  const bool out = l >= 2 && l <= w - 3 && i < pr.mx;
-  // physical (extrapolation) sides this segment writes ghosts for; periodic
-  // patches are worked by DIRECT tiles only
-  const bool ybc = pr.bc == WS_BC_EXTRAP;
-  const int c0 = i - l + 2;  // first column this segment updates
-  const bool xbc = ybc && (c0 == 0 || c0 + w - 4 >= pr.mx);
-  // lanes that store: interior columns of the segment, and on physical sides
-  // the ghost columns (gx: 1, 2 -> i = -1, -2 copy column 0; 3, 4 -> i = mx,
-  // mx+1 copy column mx-1)
-  int gx = 0;
-  if (xbc) {
-    if (i == -1) gx = 1;
-    if (i == -2) gx = 2;
-    if (i == pr.mx && l <= w - 2) gx = 3;
-    if (i == pr.mx + 1 && l <= w - 1) gx = 4;
+// Lanes of one MARCH segment (one wavefront, w = 64 lanes): lane l holds
+// column i = c0-2+l, the segment updates columns c0..c0+w-5 (lanes 2..w-3)
+// over a range of rows.  Loads and stores use unsigned 32-bit byte offsets
+// from the patch's padded origin (cell -2,-2 of plane p) off wave-uniform
+// bases: ((row+2) * ld + column+2) * sizeof(T); planes u, v follow at +plb,
+// +2 plb.  MARCH patches span < 2^31 bytes.
+template <typename T>
+struct MarchLanes {
+  static constexpr int w = kMarchWidth;
+  const char *base;
+  __amdgpu_buffer_rsrc_t ob;  // the output patch as a raw buffer
+  unsigned ld, plb;
+  int l, i, ic, mx, my;
+  bool out;  // lane updates an interior column of the segment
+  bool ybc;  // extrapolation sides: ghost rows are written
+  bool xbc;  // the segment touches a physical x side
+  int gx;    // ghost-column lane: 1, 2 -> i = -1, -2 (copy column 0); 3, 4 -> i = mx, mx+1
+  bool st;   // lane stores
+
+  __device__ MarchLanes(const T *qi, T *qo, const PatchRow &pr, int l_, int i_) {
+    ld = (unsigned)pr.ld;
+    plb = (unsigned)pr.plane * (unsigned)sizeof(T);
+    l = l_;
+    i = i_;
+    mx = pr.mx;
+    my = pr.my;
+    // lanes past the last ghost column read that column instead (never used)
+    ic = min(i, mx + 1);
+    base = reinterpret_cast<const char *>(qi - 2 * (int64_t)ld - 2);
+    ob = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<char *>(qo - 2 * (int64_t)ld - 2), 0,
+                                           (int)(3 * plb), kRawBufferWord3);
+    out = l >= 2 && l <= w - 3 && i < mx;
+    // periodic patches are worked by DIRECT tiles only
+    ybc = pr.bc == WS_BC_EXTRAP;
+    const int c0 = i - l + 2;  // first column this segment updates
+    xbc = ybc && (c0 == 0 || c0 + w - 4 >= mx);
+    gx = 0;
+    if (xbc) {
+      if (i == -1) gx = 1;
+      if (i == -2) gx = 2;
+      if (i == mx && l <= w - 2) gx = 3;
+      if (i == mx + 1 && l <= w - 1) gx = 4;
+    }
+    st = out || gx != 0;
   }
-  const bool st = out || gx != 0;
-  // output through a buffer resource over the patch (byte offsets from the
-  // padded origin, like the loads)
-  const __amdgpu_buffer_rsrc_t ob = __builtin_amdgcn_make_buffer_rsrc(
-      reinterpret_cast<char *>(qo - 2 * (int64_t)ld - 2), 0, (int)(3 * plb), kRawBufferWord3);
-  auto oat = [&](int r) {
+  __device__ unsigned at(int r) const {
+    return ((unsigned)(r + 2) * ld + (unsigned)(ic + 2)) * (unsigned)sizeof(T);
+  }
+  __device__ unsigned oat(int r) const {
     return ((unsigned)(r + 2) * ld + (unsigned)(i + 2)) * (unsigned)sizeof(T);
-  };
-  // Six row sets: set k holds the row r with (r - r0) % 6 == k from its load
-  // until its last use (as row r+2, r+1, then r of the row being updated),
-  // and is then refilled in place with row r+6.  Rows past the last ghost
-  // row are clamped to it (never used).
-  Row3<T> R0, R1, R2, R3, R4, R5;
-  auto fetch = [&](Row3<T> &S, int rr) {
-    const unsigned o = at(min(rr, pr.my + 1));
+  }
+  __device__ T get(unsigned boff) const { return *reinterpret_cast<const T *>(base + boff); }
+  // rows past the ghost rows are clamped to them (the values are never used)
+  __device__ void fetch(Row3<T> &S, int r) const {
+    const unsigned o = at(min(max(r, -2), my + 1));
     S.p = get(o);
     S.u = get(o + plb);
     S.v = get(o + 2 * plb);
-  };
-  // ---- prologue: rows r0-2, r0-1, and the six sets (r0 .. r0+5)
-  const unsigned om2 = at(r0 - 2), om1 = at(r0 - 1);
-  const T Pm2 = get(om2), Pm1 = get(om1);
-  const T Vm2 = get(om2 + 2 * plb), Vm1 = get(om1 + 2 * plb);
-  const T Um1 = get(om1 + plb);
-  fetch(R0, r0);
-  fetch(R1, r0 + 1);
-  fetch(R2, r0 + 2);
-  fetch(R3, r0 + 3);
-  fetch(R4, r0 + 4);
-  fetch(R5, r0 + 5);
-  // all of them have landed before the loop (the loop's waits then follow
-  // its steady state); vmcnt(0) with expcnt and lgkmcnt left open
+  }
+  // Store the new values of row r.  Extrapolation boundaries: the lanes on
+  // ghost columns take the new value of the nearest interior column from
+  // their neighbours, and the first and last rows are repeated into the ghost
+  // rows (corners through the ghost-column lanes).  Every lane issues the
+  // stores (lanes that write nothing get an offset past the buffer, which the
+  // hardware drops), so the compiler's wait counts before each use of a
+  // prefetched row do not depend on which lanes stored; the ghost rows are a
+  // wave-uniform branch taken on two rows only.
+  __device__ void emit(T pn, T un, T vn, int r) const {
+    if (xbc) {
+      const T p1 = shl(pn), u1 = shl(un), v1 = shl(vn);
+      const T p2 = shl(p1), u2 = shl(u1), v2 = shl(v1);
+      const T p3 = shr(pn), u3 = shr(un), v3 = shr(vn);
+      const T p4 = shr(p3), u4 = shr(u3), v4 = shr(v3);
+      if (gx == 1) { pn = p1; un = u1; vn = v1; }
+      if (gx == 2) { pn = p2; un = u2; vn = v2; }
+      if (gx == 3) { pn = p3; un = u3; vn = v3; }
+      if (gx == 4) { pn = p4; un = u4; vn = v4; }
+    }
+    const unsigned so = st ? oat(r) : kDropOffset;
+    bstore(ob, pn, so);
+    bstore(ob, un, so + plb);
+    bstore(ob, vn, so + 2 * plb);
+    if (ybc && (r == 0 || r == my - 1)) {
+      const int g0 = r == 0 ? -2 : my;
+      for (int g = g0; g <= g0 + 1; ++g) {
+        const unsigned o = st ? oat(g) : kDropOffset;
+        bstore(ob, pn, o);
+        bstore(ob, un, o + plb);
+        bstore(ob, vn, o + 2 * plb);
+      }
+    }
+  }
+};
+
+// Row sets of a MARCH segment: set k holds one row from its load until its
+// last use (as row r+2, r+1, then r of the row being updated; mirrored for a
+// downward march), and is then refilled in place with the row kSets further
+// on, so kSets-2 rows are in flight and no in-flight register is copied.
+// The row loops are unrolled by kSets and name eight sets; the prologues
+// wait for everything they requested (vmcnt(0)), so the loops' waits are
+// those of their steady state.
+
+// Upward MARCH over rows [r0, r1).  x-neighbour terms come through lane
+// shifts; y-direction terms slide up the column in registers.  Each quantity
+// uses the same expression as in cell_update, so the result is bitwise equal.
+template <typename T, int LIM, bool MASKS>
+__device__ inline void march_up(const MarchLanes<T> &M, const Coef<T> &k, int r0, int r1,
+                                uint8_t *masks) {
+  constexpr int w = kMarchWidth;
+  const T Z = k.Z;
+  const int l = M.l, i = M.i;
+  Row3<T> R0, R1, R2, R3, R4, R5, R6, R7;
+  // ---- prologue: rows r0-2, r0-1 and the sets (rows r0 .. r0+7)
+  const unsigned om2 = M.at(r0 - 2), om1 = M.at(r0 - 1);
+  const T Pm2 = M.get(om2), Pm1 = M.get(om1);
+  const T Vm2 = M.get(om2 + 2 * M.plb), Vm1 = M.get(om1 + 2 * M.plb);
+  const T Um1 = M.get(om1 + M.plb);
+  M.fetch(R0, r0);
+  M.fetch(R1, r0 + 1);
+  M.fetch(R2, r0 + 2);
+  M.fetch(R3, r0 + 3);
+  M.fetch(R4, r0 + 4);
+  M.fetch(R5, r0 + 5);
+  M.fetch(R6, r0 + 6);
+  M.fetch(R7, r0 + 7);
   __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   const T P0 = R0.p, U0 = R0.u, V0 = R0.v, P1 = R1.p, V1 = R1.v;
   const T b2mm = s2(Z, Pm1 - Pm2, Vm1 - Vm2);                                // y-edge r0-3/2
@@ -363,10 +427,10 @@ __device__ inline void march_segment(const T *qi, T *qo, const PatchRow &pr, con
   gtilde<T, LIM>(k, b1m, b2m, b1h, b2mm, xsm, xs0, GBp, GBv);
   unsigned ybits = 0;
   if constexpr (MASKS) ybits = (mc_branch(b1m, b1h) << 4) | (mc_branch(b2m, b2mm) << 6);
-  const int64_t mld = pr.mx + 1;
+  const int64_t mld = M.mx + 1;
 
-  // One row r: A, B, C hold rows r, r+1, r+2; A is refilled with row r+6 at
-  // the end (the barriers keep the scheduler from moving the refill above
+  // One row r: A, B, C hold rows r, r+1, r+2; A is refilled with row r+kSets
+  // at the end (the barriers keep the scheduler from moving the refill above
   // the row's last use of A, or the next row's arithmetic above this row's).
   auto row = [&](Row3<T> &A, const Row3<T> &B, const Row3<T> &C, int r, bool refill) {
     __builtin_amdgcn_sched_barrier(0);
@@ -390,46 +454,14 @@ __device__ inline void march_segment(const T *qi, T *qo, const PatchRow &pr, con
     gtilde<T, LIM>(k, b1h, b2h, b1hh, yb2, xs0, xsp, GTp, GTv);
     T pn, un, vn;
     update<T>(k, P0, U0, V0, xs0, xd0, ys0, yd0, FLp, FLu, FRp, FRu, GBp, GBv, GTp, GTv, pn, un, vn);
-    // Extrapolation boundaries: the lanes on ghost columns take the new value
-    // of the nearest interior column from their neighbours, and the first and
-    // last rows are repeated into the ghost rows (corners included).
-    if (xbc) {
-      const T p1 = shl(pn), u1 = shl(un), v1 = shl(vn);
-      const T p2 = shl(p1), u2 = shl(u1), v2 = shl(v1);
-      const T p3 = shr(pn), u3 = shr(un), v3 = shr(vn);
-      const T p4 = shr(p3), u4 = shr(u3), v4 = shr(v3);
-      if (gx == 1) { pn = p1; un = u1; vn = v1; }
-      if (gx == 2) { pn = p2; un = u2; vn = v2; }
-      if (gx == 3) { pn = p3; un = u3; vn = v3; }
-      if (gx == 4) { pn = p4; un = u4; vn = v4; }
-    }
-    // every lane issues the stores (lanes that write nothing get an offset
-    // past the buffer, which the hardware drops): the wait counts before each
-    // use of a prefetched row then do not depend on which lanes stored
-    const unsigned so = st ? oat(r) : kDropOffset;
-    bstore(ob, pn, so);
-    bstore(ob, un, so + plb);
-    bstore(ob, vn, so + 2 * plb);
-    // extrapolation: the first and last interior rows repeated into the two
-    // ghost rows (corners through the ghost-column lanes).  A wave-uniform
-    // branch taken on two rows only: the wait counts stay those of the
-    // common path.
-    if (ybc && (r == 0 || r == pr.my - 1)) {
-      const int g0 = r == 0 ? -2 : pr.my;
-      for (int g = g0; g <= g0 + 1; ++g) {
-        const unsigned o = st ? oat(g) : kDropOffset;
-        bstore(ob, pn, o);
-        bstore(ob, un, o + plb);
-        bstore(ob, vn, o + 2 * plb);
-      }
-    }
+    M.emit(pn, un, vn, r);
     if constexpr (MASKS) {
       const unsigned xbits = mc_branch(a1L, a1R) | (mc_branch(a2L, a2LL) << 2);
       const unsigned tbits = (mc_branch(b1h, b1hh) << 4) | (mc_branch(b2h, yb2) << 6);
-      if (out) {
+      if (M.out) {
         masks[(int64_t)r * mld + i] = (uint8_t)(xbits | ybits);
-        if (r == pr.my - 1) masks[(int64_t)(r + 1) * mld + i] = (uint8_t)tbits;
-      } else if (i == pr.mx && l >= 2 && l <= w - 2) {
+        if (r == M.my - 1) masks[(int64_t)(r + 1) * mld + i] = (uint8_t)tbits;
+      } else if (i == M.mx && l >= 2 && l <= w - 2) {
         masks[(int64_t)r * mld + i] = (uint8_t)xbits;
       }
       ybits = tbits;
@@ -439,23 +471,121 @@ __device__ inline void march_segment(const T *qi, T *qo, const PatchRow &pr, con
     GBp = GTp; GBv = GTv;
     xs0 = xsp; a1L = a1Ln; a2L = a2Ln; a1R = a1Rn;
     __builtin_amdgcn_sched_barrier(0);
-    if (refill) fetch(A, r + 6);
+    if (refill) M.fetch(A, r + kSets);
   };
   int r = r0;
-  for (; r + 6 <= r1; r += 6) {
+  for (; r + kSets <= r1; r += kSets) {
     row(R0, R1, R2, r, true);
     row(R1, R2, R3, r + 1, true);
     row(R2, R3, R4, r + 2, true);
     row(R3, R4, R5, r + 3, true);
-    row(R4, R5, R0, r + 4, true);
-    row(R5, R0, R1, r + 5, true);
+    row(R4, R5, R6, r + 4, true);
+    row(R5, R6, R7, r + 5, true);
+    row(R6, R7, R0, r + 6, true);
+    row(R7, R0, R1, r + 7, true);
   }
   // the last rows refill only what a later row still reads (rows <= r1+1)
-  if (r < r1) { row(R0, R1, R2, r, r + 6 <= r1 + 1); ++r; }
-  if (r < r1) { row(R1, R2, R3, r, r + 6 <= r1 + 1); ++r; }
-  if (r < r1) { row(R2, R3, R4, r, r + 6 <= r1 + 1); ++r; }
-  if (r < r1) { row(R3, R4, R5, r, r + 6 <= r1 + 1); ++r; }
-  if (r < r1) { row(R4, R5, R0, r, r + 6 <= r1 + 1); ++r; }
+  if (r < r1) { row(R0, R1, R2, r, r + kSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R1, R2, R3, r, r + kSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R2, R3, R4, r, r + kSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R3, R4, R5, r, r + kSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R4, R5, R6, r, r + kSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R5, R6, R7, r, r + kSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R6, R7, R0, r, r + kSets <= r1 + 1); ++r; }
+}
+
+// Downward MARCH over rows [r0, r1), from row r1-1 down to r0: the mirror of
+// march_up (the carried y-terms are those of the cell's top edge), with every
+// quantity again computed by the same expression as in cell_update.  Vertically
+// neighbouring segments march in opposite directions, so the rows two of them
+// share are read by both at about the same time (both at their start, or
+// both at their end) and the second read finds them in L2.
+template <typename T, int LIM>
+__device__ inline void march_down(const MarchLanes<T> &M, const Coef<T> &k, int r0, int r1) {
+  const T Z = k.Z;
+  Row3<T> R0, R1, R2, R3, R4, R5, R6, R7;
+  // ---- prologue: rows r1+1, r1 and the sets (rows r1-1 down to r1-8)
+  const unsigned oa2 = M.at(r1 + 1), oa1 = M.at(r1);
+  const T Pa2 = M.get(oa2), Pa1 = M.get(oa1);
+  const T Va2 = M.get(oa2 + 2 * M.plb), Va1 = M.get(oa1 + 2 * M.plb);
+  const T Ua1 = M.get(oa1 + M.plb);
+  M.fetch(R0, r1 - 1);
+  M.fetch(R1, r1 - 2);
+  M.fetch(R2, r1 - 3);
+  M.fetch(R3, r1 - 4);
+  M.fetch(R4, r1 - 5);
+  M.fetch(R5, r1 - 6);
+  M.fetch(R6, r1 - 7);
+  M.fetch(R7, r1 - 8);
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  // the top row r = r1-1 (P0) and the one below it (Pm)
+  const T P0 = R0.p, U0 = R0.u, V0 = R0.v, Pm = R1.p, Vm = R1.v;
+  const T b1aa = s1(Z, Pa2 - Pa1, Va2 - Va1);                                // y-edge r1+1/2
+  const T b1a = s1(Z, Pa1 - P0, Va1 - V0), b2a = s2(Z, Pa1 - P0, Va1 - V0);  // r1-1/2
+  T b1B = s1(Z, P0 - Pm, V0 - Vm), b2B = s2(Z, P0 - Pm, V0 - Vm);            // r1-3/2
+  T b1T = b1a;  // b1 of the cell's top edge
+  // x-edges of rows r1 and r1-1
+  const T pl_a = shr(Pa1), ul_a = shr(Ua1);
+  const T a2La = s2(Z, Pa1 - pl_a, Ua1 - ul_a);
+  const T a1La = s1(Z, Pa1 - pl_a, Ua1 - ul_a);
+  const T xsa = a2La + shl(a1La);
+  const T pl_0 = shr(P0), ul_0 = shr(U0);
+  T a1L = s1(Z, P0 - pl_0, U0 - ul_0), a2L = s2(Z, P0 - pl_0, U0 - ul_0);
+  T a1R = shl(a1L);
+  T xs0 = a2L + a1R;
+  T GTp, GTv;  // G~ of the cell's top edge
+  gtilde<T, LIM>(k, b1a, b2a, b1aa, b2B, xs0, xsa, GTp, GTv);
+
+  // One row r: A, B, C hold rows r, r-1, r-2; A is refilled with row r-kSets.
+  auto row = [&](Row3<T> &A, const Row3<T> &B, const Row3<T> &C, int r, bool refill) {
+    __builtin_amdgcn_sched_barrier(0);
+    const T P0 = A.p, U0 = A.u, V0 = A.v;
+    const T Pm = B.p, Um = B.u, Vm = B.v;
+    const T Pmm = C.p, Vmm = C.v;
+    // y-edge r-3/2 of this column and the y-fluctuations of cell (i, r)
+    const T b1BB = s1(Z, Pm - Pmm, Vm - Vmm), b2BB = s2(Z, Pm - Pmm, Vm - Vmm);
+    const T ys0 = b2B + b1T, yd0 = b2B - b1T;
+    // left x-edge of row r-1
+    const T pl_m = shr(Pm), ul_m = shr(Um);
+    const T a1Lm = s1(Z, Pm - pl_m, Um - ul_m), a2Lm = s2(Z, Pm - pl_m, Um - ul_m);
+    const T a1Rm = shl(a1Lm);
+    const T xsm = a2Lm + a1Rm;
+    const T xd0 = a2L - a1R;
+    const T a2LL = shr(a2L);
+    const T ysl = shr(ys0);
+    T FLp, FLu, GBp, GBv;
+    ftilde<T, LIM>(k, a1L, a2L, a1R, a2LL, ysl, ys0, FLp, FLu);
+    const T FRp = shl(FLp), FRu = shl(FLu);
+    gtilde<T, LIM>(k, b1B, b2B, b1T, b2BB, xsm, xs0, GBp, GBv);
+    T pn, un, vn;
+    update<T>(k, P0, U0, V0, xs0, xd0, ys0, yd0, FLp, FLu, FRp, FRu, GBp, GBv, GTp, GTv, pn, un, vn);
+    M.emit(pn, un, vn, r);
+    // slide down one row
+    b1T = b1B; b1B = b1BB; b2B = b2BB;
+    GTp = GBp; GTv = GBv;
+    xs0 = xsm; a1L = a1Lm; a2L = a2Lm; a1R = a1Rm;
+    __builtin_amdgcn_sched_barrier(0);
+    if (refill) M.fetch(A, r - kSets);
+  };
+  int r = r1 - 1;
+  for (; r - kSets + 1 >= r0; r -= kSets) {
+    row(R0, R1, R2, r, true);
+    row(R1, R2, R3, r - 1, true);
+    row(R2, R3, R4, r - 2, true);
+    row(R3, R4, R5, r - 3, true);
+    row(R4, R5, R6, r - 4, true);
+    row(R5, R6, R7, r - 5, true);
+    row(R6, R7, R0, r - 6, true);
+    row(R7, R0, R1, r - 7, true);
+  }
+  // the last rows refill only what a later row still reads (rows >= r0-2)
+  if (r >= r0) { row(R0, R1, R2, r, r - kSets >= r0 - 2); --r; }
+  if (r >= r0) { row(R1, R2, R3, r, r - kSets >= r0 - 2); --r; }
+  if (r >= r0) { row(R2, R3, R4, r, r - kSets >= r0 - 2); --r; }
+  if (r >= r0) { row(R3, R4, R5, r, r - kSets >= r0 - 2); --r; }
+  if (r >= r0) { row(R4, R5, R6, r, r - kSets >= r0 - 2); --r; }
+  if (r >= r0) { row(R5, R6, R7, r, r - kSets >= r0 - 2); --r; }
+  if (r >= r0) { row(R6, R7, R0, r, r - kSets >= r0 - 2); --r; }
 }
 
 __device__ inline unsigned long long dbits(double v) {
@@ -468,12 +598,12 @@ __device__ inline double wave_max(double v) {
   return v;
 }
 
-// One tile of one patch; returns the tile's Courant number.  No barrier:
-// the wavefronts of a workgroup go through the persistent loop's tiles
-// independently.
+// One work unit, quarter q of tile t (MARCH: segment q; DIRECT: threads
+// q*64 .. q*64+63 of the tile), worked by one wavefront; returns the tile's
+// Courant number.  No barrier: wavefronts take units independently.
 // VARS: bit 0 -> DIRECT tiles may occur, bit 1 -> MARCH tiles may occur.
 template <typename T, int LIM, bool MASKS, int VARS>
-__device__ inline double do_tile(const StepArgs &a, int t) {
+__device__ inline double do_unit(const StepArgs &a, int t, int q) {
   const TileEntry te = uniform_row(a.tiles[t]);
   const PatchRow pr = uniform_row(a.patches[te.patch]);
   const InstRow in = uniform_row(a.inst[pr.inst]);
@@ -485,18 +615,24 @@ __device__ inline double do_tile(const StepArgs &a, int t) {
   uint8_t *masks = MASKS ? a.masks + pr.mask_off : nullptr;
   const int tw = pr.tw;
   if ((VARS & 2) && (!(VARS & 1) || pr.variant == kMarch)) {
-    // one segment per wavefront; its rows are wave-uniform
+    // segment q of the tile; its rows are wave-uniform
     const int lx = (int)threadIdx.x & 63;
-    const int seg = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int rows = pr.th / (kThreads / kMarchWidth);
     const int i = te.tx * (kMarchWidth - 4) - 2 + lx;
-    const int r0 = te.ty * pr.th + seg * rows;
+    const int r0 = te.ty * pr.th + q * rows;
     const int r1 = min(r0 + rows, pr.my);
     if (r0 < r1) {
-      march_segment<T, LIM, MASKS>(qi, qo, pr, k, lx, i, r0, r1, masks);
+      const MarchLanes<T> M(qi, qo, pr, lx, i);
+      // segments alternate direction up the patch (the recording step marches up)
+      if (MASKS || ((te.ty * (kThreads / kMarchWidth) + q) & 1) == 0)
+        march_up<T, LIM, MASKS>(M, k, r0, r1, masks);
+      else
+        march_down<T, LIM>(M, k, r0, r1);
     }
   } else if (VARS & 1) {
-    const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
+    // the threads q*64 .. q*64+63 of the tile's 256
+    const int tid = q * 64 + ((int)threadIdx.x & 63);
+    const int lx = tid % tw, ly = tid / tw;
     const int rows_per_thread = pr.th / (kThreads / tw);
     const int i = te.tx * tw + lx;
     const int j0 = te.ty * pr.th + ly * rows_per_thread;
@@ -596,15 +732,19 @@ __device__ inline void file_tile(const StepArgs &a, int group, CflRun &run, int 
 // per XCD: workgroups are dispatched round-robin over the XCDs, so workgroup b
 // takes run b % groups, and the run's neighbouring tiles (whose halos
 // overlap) share that XCD's L2.  Within a run the workgroups take tiles
-// round-robin (largest patches first), with no atomics.
+// round-robin (largest patches first), with no atomics; the four wavefronts
+// of a workgroup work the four quarters of its tile independently.  With a
+// grid of one workgroup per tile the hardware dispatcher balances the load.
 template <typename T, int LIM, bool MASKS, int VARS>
 __device__ inline void step_body(const StepArgs &a) {
-  CflRun run;  // meaningful in thread 0 only
+  CflRun run;  // meaningful in lane 0 of each wavefront
+  const int lane = (int)threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   if (!a.persistent) {
     const int t = a.tile_base + (int)blockIdx.x;
     if (t < a.n_tiles) {
-      const double m = do_tile<T, LIM, MASKS, VARS>(a, t);
-      if (threadIdx.x == 0) {
+      const double m = do_unit<T, LIM, MASKS, VARS>(a, t, wave);
+      if (lane == 0) {
         file_tile(a, 0, run, t, m);
         flush_cfl(a, 0, run);
       }
@@ -618,10 +758,10 @@ __device__ inline void step_body(const StepArgs &a) {
   const int beg = (int)((int64_t)a.n_tiles * x / groups);
   const int end = (int)((int64_t)a.n_tiles * (x + 1) / groups);
   for (int t = beg + y; t < end; t += in_group) {
-    const double m = do_tile<T, LIM, MASKS, VARS>(a, t);
-    if (threadIdx.x == 0) file_tile(a, x, run, t, m);
+    const double m = do_unit<T, LIM, MASKS, VARS>(a, t, wave);
+    if (lane == 0 && wave == 0) file_tile(a, x, run, t, m);
   }
-  // Retire: this workgroup's values are filed (and waited for) before its
+  // Retire: the workgroup's values are filed (and waited for) before its
   // count; the last workgroup of each run counts the run, and the last run's
   // last workgroup files the step and rewinds the counters for the next launch.
   __shared__ int s_last;

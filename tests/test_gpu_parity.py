@@ -337,3 +337,35 @@ def test_invalid_use_reports_errors(ws):
     lev.step(0.01)  # the state moves to the other pool than at capture time
     with pytest.raises(ws.WaveStepError):
         lev.graph_launch()
+
+
+def test_autotune_restores_state_and_keeps_results(ws, tmp_path):
+    """The tuner times candidate tilings on the live level: afterwards the
+    state is exactly what it was, and a step gives bitwise the same result as
+    with the default tiling."""
+    from paper_1808_02638_amd.autotune import autotune
+
+    rng = np.random.default_rng(12)
+    shapes = [(150, 40), (33, 17), (33, 20), (9, 30), (64, 64)]
+    patches = [dict(mx=mx, my=my, dx=1 / mx, dy=1 / my, bc="extrap") for mx, my in shapes]
+    states = [rng.normal(size=(3, my + 4, mx + 4)) for mx, my in shapes]
+    levels = []
+    for tuned in (False, True):
+        lev = ws.Level(patches, [(RHO, KB)])
+        for k, q in enumerate(states):
+            lev.upload(k, q)
+        lev.fill_ghosts()
+        lev.set_dt([0.002])
+        before = [lev.download(k) for k in range(len(shapes))]
+        if tuned:
+            choice = autotune(lev, launches=4, cache_path=str(tmp_path / "tiling.json"))
+            assert not choice["cached"]
+            for k in range(len(shapes)):
+                assert np.array_equal(lev.download(k), before[k])
+            again = autotune(lev, launches=4, cache_path=str(tmp_path / "tiling.json"))
+            assert again["cached"] and again["classes"] == choice["classes"]
+        lev.step(0.002)
+        levels.append([lev.download(k) for k in range(len(shapes))])
+        lev.close()
+    for a, b in zip(*levels):
+        assert np.array_equal(a, b)
