@@ -9,8 +9,10 @@ and dt update (CFL 0.9), the whole step loop captured as one hipGraph.  A
 
 Printed as ONE JSON line.  Extra objects: the FP32 variant of the same run,
 the synthetic AMR level batch (batched persistent launch vs one launch per
-patch, FP64 and FP32), conservation sums, the roofline of the step kernel and
-the oracle's throughput on the host cores (cpu_baseline).
+patch, FP64 and FP32), the 64-instance ensemble (graph vs eager, default vs
+autotuned tiling), the 512^2 adjoint run (forward, backward, adjoint step),
+conservation sums, the roofline of the step kernel and the
+oracle's throughput on the host cores (cpu_baseline).
 """
 
 from __future__ import annotations
@@ -131,6 +133,122 @@ def run_amr(ws, torch, dtype, level_steps, tune=True):
     return out
 
 
+def run_ensemble(ws, torch, steps, tune=True):
+    """64 independent instances of uneven sizes in one level: default vs
+    autotuned tiling (step kernel alone), then the steps eager (one launch per
+    step from the host) and as one captured graph, FP64, per-instance dt."""
+    import workloads
+
+    insts = workloads.ensemble()
+    lev = ws.Level([dict(mx=e.mx, my=e.my, dx=e.dx, dy=e.dy, instance=k, bc="extrap")
+                    for k, e in enumerate(insts)], [(e.rho, e.K) for e in insts])
+    dt0 = [0.9 * min(e.dx, e.dy) / math.sqrt(e.K / e.rho) for e in insts]
+    cells = sum(e.mx * e.my for e in insts)
+
+    def reset():
+        for k, e in enumerate(insts):
+            lev.upload(k, e.state())
+        lev.fill_ghosts()
+        lev.set_dt(dt0)
+
+    reset()
+    lev.time_step_kernel(2)
+    default_ms = lev.time_step_kernel(20)
+    if tune:
+        from paper_1808_02638_amd.autotune import autotune
+        autotune(lev)
+    lev.time_step_kernel(2)
+    tuned_ms = lev.time_step_kernel(20)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reset()
+    torch.cuda.synchronize()
+    e0.record(lev.stream)
+    for _ in range(steps):
+        lev.step_auto(0.9)
+    e1.record(lev.stream)
+    torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1)
+    reset()
+    lev.capture(steps, 0.9)
+    torch.cuda.synchronize()
+    e0.record(lev.stream)
+    lev.graph_launch()
+    e1.record(lev.stream)
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1)
+    _dt, cfl_last, _ = lev.read_dt_cfl()
+    var, _tw, _th, wg, grid = lev.get_tiling()
+    lev.close()
+    return {"instances": len(insts), "cells": cells, "steps": steps,
+            "graph_gcells": round(cells * steps / graph_ms / 1e6, 3),
+            "eager_gcells": round(cells * steps / eager_ms / 1e6, 3),
+            "graph_us_per_step": round(graph_ms * 1e3 / steps, 2),
+            "eager_us_per_step": round(eager_ms * 1e3 / steps, 2),
+            "default_tiling_kernel_us": round(default_ms * 1e3, 2),
+            "tuned_tiling_kernel_us": round(tuned_ms * 1e3, 2),
+            "tuned_variants": {v: var.count(v) for v in sorted(set(var))},
+            "cfl_last_min_max": [float(cfl_last.min()), float(cfl_last.max())]}
+
+
+def run_adjoint(ws, torch):
+    """The adjoint workload: 512^2 FP64, 200 fixed-dt steps at Courant 0.8, 16
+    receivers, checkpoints every 20 steps: forward traces and the backward
+    sweep (re-run forward segments recording the branches, then the adjoint
+    steps), and the adjoint step kernel alone."""
+    import numpy as np
+
+    import workloads
+
+    setup = workloads.adjoint_setup()
+    n, steps = setup.n, setup.steps
+    run = ws.AcousticsAdjoint(n, n, setup.dx, setup.dx, RHO, K_BULK, setup.receivers, steps,
+                              setup.dt, checkpoint_every=setup.checkpoint_every)
+    target = torch.zeros((steps, len(setup.receivers)), dtype=torch.float64, device="cuda")
+    p0 = torch.tensor(setup.p0(), device="cuda", requires_grad=True)
+    for _ in range(2):  # warm
+        p0.grad = None
+        run.misfit(p0, target).backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    traces = run.traces(p0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss = 0.5 * ((traces - target) ** 2).sum()
+    p0.grad = None
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    grad_ok = bool(torch.isfinite(p0.grad).all())
+    # the adjoint step alone: lam' -> S^T lam' on the recorded branches
+    lev = run.level
+    masks = lev.new_masks()
+    lev.step_record_masks(setup.dt, masks)
+    a, b = lev.new_buffer(), lev.new_buffer()
+    lev.patch_view(a, 0)[:, 2:-2, 2:-2] = torch.from_numpy(
+        np.random.default_rng(1).normal(size=(3, n, n))).cuda()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 100
+    with torch.cuda.stream(lev.stream):
+        for _ in range(3):
+            lev.adjoint_step(setup.dt, masks, a, b)
+        e0.record(lev.stream)
+        for _ in range(reps):
+            lev.adjoint_step(setup.dt, masks, a, b)
+            a, b = b, a
+        e1.record(lev.stream)
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / reps
+    byts = n * n * (48 + 1)  # lam in, lam out (3 FP64 each), one mask byte per cell
+    run.close()
+    return {"grid": f"{n}x{n}", "steps": steps, "checkpoint_every": setup.checkpoint_every,
+            "forward_ms": round((t1 - t0) * 1e3, 3), "backward_ms": round((t2 - t1) * 1e3, 3),
+            "adjoint_step_us": round(adj_ms * 1e3, 2),
+            "adjoint_step_gcells": round(n * n / adj_ms / 1e6, 2),
+            "adjoint_step_GBs": round(byts / (adj_ms / 1e3) / 1e9, 1), "grad_finite": grad_ok}
+
+
 PROFILE = os.path.join(ROOT, "profiles", "step_kernel_march_f64_2048sq.md")
 
 
@@ -190,6 +308,7 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--kernel-launches", type=int, default=200)
     ap.add_argument("--amr-steps", type=int, default=10)
+    ap.add_argument("--ensemble-steps", type=int, default=200)
     ap.add_argument("--no-extras", action="store_true", help="skip FP32, AMR and CPU legs")
     ap.add_argument("--no-tune", action="store_true", help="time the default tiling")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -270,6 +389,8 @@ def main():
         line["amr_level_batch"] = {
             "fp64": run_amr(ws, torch, torch.float64, args.amr_steps, tune=not args.no_tune),
             "fp32": run_amr(ws, torch, torch.float32, args.amr_steps, tune=not args.no_tune)}
+        line["ensemble_fp64"] = run_ensemble(ws, torch, args.ensemble_steps, tune=not args.no_tune)
+        line["adjoint_fp64"] = run_adjoint(ws, torch)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

@@ -130,6 +130,7 @@ WsLayout ws_layout_of(const ws_patch_desc *p, int n, int n_inst) {
   L.level_last = take(8);
   L.retire = take(4LL * kLine * (kGroups + 1));
   L.partials = take(24 * L.max_tiles);
+  L.patch_sums = take(24LL * n);
   L.sums = take(24LL * n_inst);
   L.total = cur;
   return L;
@@ -624,8 +625,9 @@ int ws_conservation_sums(ws_ctx *c, double *sums) {
   if (!sums) return fail(WS_EINVAL, "sums is NULL");
   double *partials = reinterpret_cast<double *>(c->ws + c->L.partials);
   double *dsums = reinterpret_cast<double *>(c->ws + c->L.sums);
-  HIPCHK(launch_sums(c->dtype, c->d_patches(), c->d_tiles(), (int)c->tiles.size(), c->pool[c->cur],
-                     partials, c->n_inst, dsums, c->stream));
+  double *psums = reinterpret_cast<double *>(c->ws + c->L.patch_sums);
+  HIPCHK(launch_sums(c->dtype, c->d_patches(), c->n_patches, c->d_tiles(), (int)c->tiles.size(),
+                     c->pool[c->cur], partials, psums, c->n_inst, dsums, c->stream));
   const size_t n = 24 * (size_t)c->n_inst;
   HIPCHK(hipMemcpyAsync(c->host_buf, dsums, n, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));

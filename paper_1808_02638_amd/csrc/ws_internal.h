@@ -50,7 +50,7 @@ struct InstRow {
 // Workspace carve-up (byte offsets inside the caller's workspace buffer).
 struct WsLayout {
   int64_t patches, inst, tiles, dt, cfl_tile, inst_acc, cfl_last, cfl_max, cfl_patch_last,
-      level_last, retire, partials, sums, total;
+      level_last, retire, partials, patch_sums, sums, total;
   int64_t max_tiles;
 };
 
@@ -97,8 +97,9 @@ hipError_t launch_finish_step(const CflSlots &c, double cfl_desired, hipStream_t
 // cfl_patch[k] = max of cfl_tile over patch k's tiles.
 hipError_t launch_patch_cfl(const PatchRow *patches, int n_patches, const double *cfl_tile,
                             double *cfl_patch, hipStream_t s);
-hipError_t launch_sums(int dtype, const PatchRow *patches, const TileEntry *tiles, int n_tiles,
-                       const void *q, double *partials, int n_inst, double *sums, hipStream_t s);
+hipError_t launch_sums(int dtype, const PatchRow *patches, int n_patches, const TileEntry *tiles,
+                       int n_tiles, const void *q, double *partials, double *patch_sums,
+                       int n_inst, double *sums, hipStream_t s);
 int step_occupancy(int dtype, int limiter, int vars, int *wg_per_cu);
 
 // Adjoint and receiver helpers (defined in ws_adjoint.hip), FP64 buffers in

@@ -858,8 +858,8 @@ __global__ __launch_bounds__(kThreads) void patch_cfl_kernel(const PatchRow *pat
 }
 
 // --------------------------------------------------------------------------
-// Conservation sums: FP64 per-tile partials in a fixed order, then a fixed-
-// order pass over the tile list per instance.
+// Conservation sums: FP64 per-tile partials, per-patch sums of those, per-
+// instance sums of those; every stage in a fixed order.
 // --------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kThreads) void tile_sums_kernel(const PatchRow *patches,
@@ -889,15 +889,42 @@ __global__ __launch_bounds__(kThreads) void tile_sums_kernel(const PatchRow *pat
   if (threadIdx.x < 3) partials[3 * (int64_t)blockIdx.x + threadIdx.x] = s[threadIdx.x][0] * pr.dx * pr.dy;
 }
 
-__global__ void instance_sums_kernel(const PatchRow *patches, const TileEntry *tiles, int n_tiles,
-                                     const double *partials, int n_inst, double *sums) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_inst; k += gridDim.x * blockDim.x) {
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (int t = 0; t < n_tiles; ++t)
-      if (patches[tiles[t].patch].inst == k)
-        for (int m = 0; m < 3; ++m) acc[m] += partials[3 * (int64_t)t + m];
-    for (int m = 0; m < 3; ++m) sums[3 * k + m] = acc[m];
+// Fixed-order FP64 reduction of 3-vectors over a workgroup: thread t adds the
+// items t, t + 256, ... of its range, then a tree over the threads.
+__device__ inline void block_sum3(double acc[3], double *out) {
+  __shared__ double s[3][kThreads];
+  for (int m = 0; m < 3; ++m) s[m][threadIdx.x] = acc[m];
+  __syncthreads();
+  for (int w = kThreads / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int m = 0; m < 3; ++m) s[m][threadIdx.x] += s[m][threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x < 3) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+// One workgroup per patch: the sums of its tiles' partials.
+__global__ __launch_bounds__(kThreads) void patch_sums_kernel(const PatchRow *patches,
+                                                            const double *partials,
+                                                            double *patch_sums) {
+  const PatchRow pr = patches[blockIdx.x];
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int t = pr.tile_begin + (int)threadIdx.x; t < pr.tile_begin + pr.n_tiles; t += kThreads)
+    for (int m = 0; m < 3; ++m) acc[m] += partials[3 * (int64_t)t + m];
+  block_sum3(acc, patch_sums + 3 * (int64_t)blockIdx.x);
+}
+
+// One workgroup per instance: the sums over its patches, in patch order.
+__global__ __launch_bounds__(kThreads) void instance_sums_kernel(const PatchRow *patches,
+                                                               int n_patches,
+                                                               const double *patch_sums,
+                                                               double *sums) {
+  const int inst = (int)blockIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int k = (int)threadIdx.x; k < n_patches; k += kThreads)
+    if (patches[k].inst == inst)
+      for (int m = 0; m < 3; ++m) acc[m] += patch_sums[3 * (int64_t)k + m];
+  block_sum3(acc, sums + 3 * (int64_t)inst);
 }
 
 template <typename T, int LIM, bool MASKS, int VARS>
@@ -990,8 +1017,9 @@ hipError_t launch_patch_cfl(const PatchRow *patches, int n_patches, const double
   return hipGetLastError();
 }
 
-hipError_t launch_sums(int dtype, const PatchRow *patches, const TileEntry *tiles, int n_tiles,
-                       const void *q, double *partials, int n_inst, double *sums, hipStream_t s) {
+hipError_t launch_sums(int dtype, const PatchRow *patches, int n_patches, const TileEntry *tiles,
+                       int n_tiles, const void *q, double *partials, double *patch_sums,
+                       int n_inst, double *sums, hipStream_t s) {
   if (n_tiles > 0) {
     if (dtype == WS_F32)
       hipLaunchKernelGGL(tile_sums_kernel<float>, dim3(n_tiles), dim3(kThreads), 0, s, patches,
@@ -1000,8 +1028,10 @@ hipError_t launch_sums(int dtype, const PatchRow *patches, const TileEntry *tile
       hipLaunchKernelGGL(tile_sums_kernel<double>, dim3(n_tiles), dim3(kThreads), 0, s, patches,
                          tiles, reinterpret_cast<const double *>(q), partials);
   }
-  hipLaunchKernelGGL(instance_sums_kernel, dim3((n_inst + 63) / 64), dim3(64), 0, s, patches,
-                     tiles, n_tiles, partials, n_inst, sums);
+  hipLaunchKernelGGL(patch_sums_kernel, dim3(n_patches), dim3(kThreads), 0, s, patches, partials,
+                     patch_sums);
+  hipLaunchKernelGGL(instance_sums_kernel, dim3(n_inst), dim3(kThreads), 0, s, patches, n_patches,
+                     patch_sums, sums);
   return hipGetLastError();
 }
 

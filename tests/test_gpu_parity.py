@@ -369,3 +369,43 @@ def test_autotune_restores_state_and_keeps_results(ws, tmp_path):
         lev.close()
     for a, b in zip(*levels):
         assert np.array_equal(a, b)
+
+
+def test_ensemble_full_size_graph(ws, oracle_lib):
+    """The 64-instance ensemble (sides 128-512, K in [1, 9], rho in [0.5, 2]),
+    autotuned, 200 steps as one graph with per-instance FP64 Courant numbers:
+    the three smallest instances against the oracle over all 200 steps, and
+    for every instance the dt rule (after the first step each instance steps
+    at Courant number 0.9)."""
+    from paper_1808_02638_amd.autotune import autotune
+
+    insts = workloads.ensemble()
+    lev = ws.Level([dict(mx=e.mx, my=e.my, dx=e.dx, dy=e.dy, instance=k, bc="extrap")
+                    for k, e in enumerate(insts)], [(e.rho, e.K) for e in insts])
+    dt0 = [0.9 * min(e.dx, e.dy) / math.sqrt(e.K / e.rho) for e in insts]
+    for k, e in enumerate(insts):
+        lev.upload(k, e.state())
+    lev.fill_ghosts()
+    lev.set_dt(dt0)
+    autotune(lev, launches=4, use_cache=False)
+    lev.capture(200, 0.9)
+    lev.graph_launch()
+    dts, cfl_last, cfl_max = lev.read_dt_cfl()
+    for k, e in enumerate(insts):
+        c = math.sqrt(e.K / e.rho)
+        assert abs(cfl_last[k] - 0.9) <= 1e-14, (k, cfl_last[k])
+        assert abs(dts[k] - 0.9 * min(e.dx, e.dy) / c) <= 1e-12 * dts[k], k
+        assert abs(cfl_max[k] - 0.9) <= 1e-14
+    order = sorted(range(len(insts)), key=lambda k: insts[k].mx * insts[k].my)[:3]
+    for k in order:
+        e = insts[k]
+        ref = oracle_lib.run(e.state(), 200, e.dx, e.dy, e.rho, e.K, limiter="mc", bc="extrap",
+                             cfl_desired=0.9)
+        err = rel_linf(lev.download(k), ref["q"])
+        print(f"ensemble instance {k} ({e.mx}x{e.my}, K={e.K:.3f}, rho={e.rho:.3f}): "
+              f"rel Linf {err.max():.2e}")
+        assert err.max() <= FP64_TOL, (k, err)
+        assert cfl_last[k] == ref["cfls"][-1]
+    sums = lev.conservation_sums()
+    assert np.isfinite(sums).all()
+    lev.close()
