@@ -191,8 +191,8 @@ int ws_mask_bytes(ws_ctx *ctx, int64_t *bytes);
 int ws_patch_layout(ws_ctx *ctx, int32_t patch, int64_t *offset, int64_t *ld, int64_t *plane);
 
 /* ws_step_level(dt) recording the branches into masks_dev (device buffer of
- * ws_mask_bytes, cleared first).  cfl_out may be NULL; when given the call
- * synchronises the stream. */
+ * ws_mask_bytes; the step writes every byte, the one no edge owns as 0).
+ * cfl_out may be NULL; when given the call synchronises the stream. */
 int ws_step_record_masks(ws_ctx *ctx, double dt, void *masks_dev, double *cfl_out);
 
 /* lam_out <- S^T lam_in for the step recorded in masks_dev with time step dt.

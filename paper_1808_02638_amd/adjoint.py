@@ -17,10 +17,12 @@ stream; torch provides the buffers.
 
 from __future__ import annotations
 
+import ctypes
 import math
 
 import torch
 
+from . import _lib as C
 from .level import Level
 
 
@@ -93,38 +95,52 @@ class AcousticsAdjoint:
         lev.upload(0, q)
         lev.fill_ghosts()
 
+    # The step loops call the C entry points directly with arguments built
+    # once (every buffer lives on the level's stream, so no stream waits are
+    # needed); the Level methods' checks have been done on the buffers here.
     def _forward(self, p0):
         lev = self.level
         if p0.shape != (self.my, self.mx):
             raise ValueError(f"p0 must have shape {(self.my, self.mx)}")
         p0 = p0.detach().to(device=lev.device, dtype=torch.float64)
+        L, ctx = lev._L, lev._ctx
         with torch.cuda.stream(lev.stream):
             traces = torch.empty((self.nsteps, self.nr), dtype=torch.float64, device=lev.device)
             self._start(p0)
             ckpts = []
+            ij, nr, dt = ctypes.c_void_p(self.ij.data_ptr()), self.nr, self.dt
+            base = traces.data_ptr()
             for n in range(self.nsteps):
                 if n % self.k == 0:
                     ckpts.append(lev.state_view(0).clone())
-                lev.step(self.dt, read_cfl=False)
-                lev.gather(0, 0, self.ij, traces[n])
+                C.check(L.ws_step_level(ctx, dt, None))
+                C.check(L.ws_gather(ctx, None, 0, 0, nr, ij, ctypes.c_void_p(base + 8 * nr * n)))
         lev.stream.synchronize()
         return traces, ckpts
 
     def _backward(self, ckpts, g):
         lev = self.level
+        L, ctx = lev._L, lev._ctx
         with torch.cuda.stream(lev.stream):
             g = g.detach().to(device=lev.device, dtype=torch.float64).contiguous()
+            if g.shape != (self.nsteps, self.nr):
+                raise ValueError("trace cotangent has the wrong shape")
             lam, lam_next = lev.new_buffer(), lev.new_buffer()
             masks = [lev.new_masks() for _ in range(min(self.k, self.nsteps))]
+            mp = [ctypes.c_void_p(m.data_ptr()) for m in masks]
+            bufs = [ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(lam_next.data_ptr())]
+            ij, nr, dt, gb = ctypes.c_void_p(self.ij.data_ptr()), self.nr, self.dt, g.data_ptr()
+            cur = 0
             for seg in range(len(ckpts) - 1, -1, -1):
                 s0, s1 = seg * self.k, min(self.nsteps, (seg + 1) * self.k)
-                lev.upload(0, ckpts[seg])
+                lev.state_view(0).copy_(ckpts[seg])  # restore, asynchronously
                 for s in range(s0, s1):
-                    lev.step_record_masks(self.dt, masks[s - s0])
+                    C.check(L.ws_step_record_masks(ctx, dt, mp[s - s0], None))
                 for n in range(s1 - 1, s0 - 1, -1):
-                    lev.add_at(0, 0, self.ij, g[n], buf=lam)
-                    lev.adjoint_step(self.dt, masks[n - s0], lam, lam_next)
-                    lam, lam_next = lam_next, lam
-            grad = lev.patch_view(lam, 0)[0, 2:-2, 2:-2].clone()
+                    C.check(L.ws_add_at(ctx, bufs[cur], 0, 0, nr, ij,
+                                        ctypes.c_void_p(gb + 8 * nr * n)))
+                    C.check(L.ws_adjoint_step(ctx, dt, mp[n - s0], bufs[cur], bufs[1 - cur]))
+                    cur = 1 - cur
+            grad = lev.patch_view(lam if cur == 0 else lam_next, 0)[0, 2:-2, 2:-2].clone()
         lev.stream.synchronize()
         return grad

@@ -25,6 +25,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "ws_device.h"
 #include "ws_internal.h"
 #include "../../include/wavestep.h"
@@ -155,8 +157,8 @@ __device__ inline AdjPatch make_adj(const PatchRow &pr, const InstRow &in, doubl
 __global__ __launch_bounds__(kThreads) void adjoint_update_kernel(
     const PatchRow *patches, const InstRow *inst, double dt, const uint8_t *masks,
     const double *lam_in, double *lam_out) {
-  const PatchRow pr = patches[blockIdx.y];
-  const AdjPatch A = make_adj(pr, inst[pr.inst], dt, masks, lam_in);
+  const PatchRow pr = uniform_row(patches[blockIdx.y]);
+  const AdjPatch A = make_adj(pr, uniform_row(inst[pr.inst]), dt, masks, lam_in);
   double *out = lam_out + pr.q_off + 2 * (int64_t)pr.ld + pr.col0;
   const int wx = pr.mx + 4;
   const int64_t n = (int64_t)wx * (pr.my + 4);
@@ -172,45 +174,57 @@ __global__ __launch_bounds__(kThreads) void adjoint_update_kernel(
   }
 }
 
-// E^T: the ghost cotangents of extrapolation patches are added to the interior
-// cells they were copied from (each ghost has one such cell: clamp its
-// indices); then every ghost is set to 0.  One thread per interior cell next
-// to a side, so each ghost is read and cleared by exactly one thread.
+// E^T: the ghost cotangents of extrapolation patches are added to the
+// interior cell they were copied from (each ghost has one: clamp its
+// indices), and every ghost is set to 0.  One thread per (interior cell next
+// to a side, component), so each ghost value is read and cleared by exactly
+// one thread; all reads come before the writes.
 __global__ __launch_bounds__(kThreads) void adjoint_fold_kernel(const PatchRow *patches,
                                                               double *lam) {
-  const PatchRow pr = patches[blockIdx.y];
-  double *base = lam + pr.q_off + 2 * (int64_t)pr.ld + pr.col0;
+  const PatchRow pr = uniform_row(patches[blockIdx.y]);
   const bool fold = pr.bc == WS_BC_EXTRAP;
   // the boundary ring of the interior: rows 0 and my-1, then columns 0 and
   // mx-1 of the rows between
   const int top = pr.my > 1 ? pr.mx : 0;
   const int mid = max(pr.my - 2, 0) * (pr.mx > 1 ? 2 : 1);
-  const int n = pr.mx + top + mid;
-  for (int idx = blockIdx.x * kThreads + threadIdx.x; idx < n; idx += gridDim.x * kThreads) {
+  const int ring = pr.mx + top + mid;
+  for (int idx = blockIdx.x * kThreads + threadIdx.x; idx < 3 * ring;
+       idx += gridDim.x * kThreads) {
+    const int m = idx / ring, c = idx % ring;
     int i, j;
-    if (idx < pr.mx) {
-      i = idx, j = 0;
-    } else if (idx < pr.mx + top) {
-      i = idx - pr.mx, j = pr.my - 1;
+    if (c < pr.mx) {
+      i = c, j = 0;
+    } else if (c < pr.mx + top) {
+      i = c - pr.mx, j = pr.my - 1;
     } else {
-      const int r = idx - pr.mx - top, per = pr.mx > 1 ? 2 : 1;
+      const int r = c - pr.mx - top, per = pr.mx > 1 ? 2 : 1;
       j = 1 + r / per;
       i = (r % per) ? pr.mx - 1 : 0;
     }
-    const int x_lo = (i == 0) ? -2 : i, x_hi = (i == pr.mx - 1) ? pr.mx + 1 : i;
-    const int y_lo = (j == 0) ? -2 : j, y_hi = (j == pr.my - 1) ? pr.my + 1 : j;
-    for (int m = 0; m < 3; ++m) {
-      double *q = base + m * pr.plane;
-      double s = q[(int64_t)j * pr.ld + i];
-      for (int b = y_lo; b <= y_hi; ++b)
-        for (int a = x_lo; a <= x_hi; ++a) {
-          if (a == i && b == j) continue;
-          double *g = q + (int64_t)b * pr.ld + a;
-          if (fold) s += *g;
-          *g = 0.0;
-        }
-      q[(int64_t)j * pr.ld + i] = s;
+    double *q = lam + pr.q_off + 2 * (int64_t)pr.ld + pr.col0 + m * pr.plane;
+    // ghost images of (i, j): up to two ghost columns on each side of its
+    // row and two ghost rows on each side of its column, and their crossings
+    constexpr int kNone = INT_MIN;
+    const int xs[5] = {i, i == 0 ? -1 : kNone, i == 0 ? -2 : kNone, i == pr.mx - 1 ? pr.mx : kNone,
+                       i == pr.mx - 1 ? pr.mx + 1 : kNone};
+    const int ys[5] = {j, j == 0 ? -1 : kNone, j == 0 ? -2 : kNone, j == pr.my - 1 ? pr.my : kNone,
+                       j == pr.my - 1 ? pr.my + 1 : kNone};
+    double s = q[(int64_t)j * pr.ld + i];
+    if (fold) {
+#pragma unroll
+      for (int b = 0; b < 5; ++b)
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+          if ((a | b) != 0 && xs[a] != kNone && ys[b] != kNone)
+            s += q[(int64_t)ys[b] * pr.ld + xs[a]];
     }
+#pragma unroll
+    for (int b = 0; b < 5; ++b)
+#pragma unroll
+      for (int a = 0; a < 5; ++a)
+        if ((a | b) != 0 && xs[a] != kNone && ys[b] != kNone)
+          q[(int64_t)ys[b] * pr.ld + xs[a]] = 0.0;
+    q[(int64_t)j * pr.ld + i] = s;
   }
 }
 
@@ -247,7 +261,7 @@ hipError_t launch_adjoint(const PatchRow *patches, int n_patches, int max_padded
                      inst, dt, masks, lam_in, lam_out);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int gr = max(1, min(64, (max_ring + kThreads - 1) / kThreads));
+  const int gr = max(1, min(256, (3 * max_ring + kThreads - 1) / kThreads));
   hipLaunchKernelGGL(adjoint_fold_kernel, dim3(gr, n_patches), dim3(kThreads), 0, s, patches,
                      lam_out);
   return hipGetLastError();

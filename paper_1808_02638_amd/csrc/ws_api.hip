@@ -699,8 +699,6 @@ int ws_step_record_masks(ws_ctx *c, double dt, void *masks_dev, double *cfl_out)
   if (!masks_dev) return fail(WS_EINVAL, "masks buffer is NULL");
   if (c->limiter != WS_LIM_MC) return fail(WS_EINVAL, "branches exist for the MC limiter only");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
-  // bytes no edge owns (cell (mx, my) of each patch) stay 0
-  HIPCHK(hipMemsetAsync(masks_dev, 0, (size_t)c->mask_total, c->stream));
   StepArgs a = c->step_args(c->cur, dt, 0.0);
   a.masks = reinterpret_cast<uint8_t *>(masks_dev);
   HIPCHK(launch_step(c->dtype, c->limiter, c->vars, a, c->grid, c->stream));

@@ -52,4 +52,19 @@ __device__ inline Coef<T> make_coef(double c, double Z, double dt, double dx, do
   return k;
 }
 
+// A table row read by a whole workgroup, moved to scalar registers word by
+// word (the kernel stores to memory, so the compiler cannot use scalar loads
+// for it and would otherwise treat its fields as per-lane values).
+template <typename S>
+__device__ inline S uniform_row(const S &v) {
+  static_assert(sizeof(S) % 4 == 0, "row must be whole words");
+  uint32_t w[sizeof(S) / 4];
+  __builtin_memcpy(w, &v, sizeof(S));
+#pragma unroll
+  for (int n = 0; n < (int)(sizeof(S) / 4); ++n) w[n] = __builtin_amdgcn_readfirstlane(w[n]);
+  S out;
+  __builtin_memcpy(&out, w, sizeof(S));
+  return out;
+}
+
 }  // namespace ws

@@ -268,20 +268,6 @@ struct Row3 {
   T p, u, v;
 };
 
-// A table row read by a whole workgroup, moved to scalar registers word by
-// word (the kernel stores to memory, so the compiler cannot use scalar loads
-// for it and would otherwise treat its fields as per-lane values).
-template <typename S>
-__device__ inline S uniform_row(const S &v) {
-  static_assert(sizeof(S) % 4 == 0, "row must be whole words");
-  uint32_t w[sizeof(S) / 4];
-  __builtin_memcpy(w, &v, sizeof(S));
-#pragma unroll
-  for (int n = 0; n < (int)(sizeof(S) / 4); ++n) w[n] = __builtin_amdgcn_readfirstlane(w[n]);
-  S out;
-  __builtin_memcpy(&out, w, sizeof(S));
-  return out;
-}
 
 // Lanes of one MARCH segment (one wavefront, w = 64 lanes): lane l holds
 // column i = c0-2+l, the segment updates columns c0..c0+w-5 (lanes 2..w-3)
@@ -460,7 +446,10 @@ __device__ inline void march_up(const MarchLanes<T> &M, const Coef<T> &k, int r0
       const unsigned tbits = (mc_branch(b1h, b1hh) << 4) | (mc_branch(b2h, yb2) << 6);
       if (M.out) {
         masks[(int64_t)r * mld + i] = (uint8_t)(xbits | ybits);
-        if (r == M.my - 1) masks[(int64_t)(r + 1) * mld + i] = (uint8_t)tbits;
+        if (r == M.my - 1) {
+          masks[(int64_t)(r + 1) * mld + i] = (uint8_t)tbits;
+          if (i == M.mx - 1) masks[(int64_t)(r + 1) * mld + i + 1] = 0;  // no edge owns it
+        }
       } else if (i == M.mx && l >= 2 && l <= w - 2) {
         masks[(int64_t)r * mld + i] = (uint8_t)xbits;
       }
@@ -648,7 +637,10 @@ __device__ inline double do_unit(const StepArgs &a, int t, int q) {
           const int64_t mld = pr.mx + 1;
           masks[(int64_t)j * mld + i] = (uint8_t)mk.own;
           if (i == pr.mx - 1) masks[(int64_t)j * mld + i + 1] = (uint8_t)mk.right;
-          if (j == pr.my - 1) masks[(int64_t)(j + 1) * mld + i] = (uint8_t)mk.top;
+          if (j == pr.my - 1) {
+            masks[(int64_t)(j + 1) * mld + i] = (uint8_t)mk.top;
+            if (i == pr.mx - 1) masks[(int64_t)(j + 1) * mld + i + 1] = 0;  // no edge owns it
+          }
         }
       }
     }

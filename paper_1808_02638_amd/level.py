@@ -172,11 +172,16 @@ class Level:
     # Buffers passed in come from torch's current stream: the level's stream
     # waits for it before the library reads them, and torch's stream waits
     # for the level's stream before it reads what the library wrote.
+    def _on_level_stream(self):
+        return torch.cuda.current_stream(self.device).cuda_stream == self.stream.cuda_stream
+
     def _sync_in(self):
-        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        if not self._on_level_stream():
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
 
     def _sync_out(self):
-        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        if not self._on_level_stream():
+            torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
     def mask_bytes(self) -> int:
         b = ctypes.c_int64(0)
