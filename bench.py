@@ -279,9 +279,20 @@ def measured_traffic(tiling, profile=PROFILE):
     return int(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(n, target_s):
-    import numpy as np  # noqa: F401
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def cpu_baseline(n, target_s):
+    """The oracle on the host cores: steps of the n x n FP64 grid for about
+    target_s seconds with every thread the process may use, then a short
+    single-threaded sample (the oracle's OpenMP loops over rows)."""
     import oracle
     import workloads
 
@@ -299,9 +310,35 @@ def cpu_baseline(n, target_s):
         oracle.fill_bc(q1, "extrap")
     el = time.perf_counter() - t
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    # one thread: a single step (the process-wide OpenMP setting is left alone)
+    t = time.perf_counter()
+    oracle.step(q1, dx, dx, dt, RHO, K_BULK, "mc", parallel=False)
+    el1 = time.perf_counter() - t
     return {"value": n * n * steps / el / 1e9, "unit": "Gcell-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{steps} oracle steps of the {n}x{n} FP64 grid ({el:.1f} s, OpenMP)"}
+            "sample": f"{steps} oracle steps of the {n}x{n} FP64 grid ({el:.1f} s, OpenMP "
+                      f"over {threads} threads)",
+            "single_thread_value": n * n / el1 / 1e9, "cpu_model": cpu_model()}
+
+
+def copy_bandwidth(torch, nbytes):
+    """A plain device copy of nbytes (read + write), the practical reference
+    for the step's traffic."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        dst.copy_(src)
+    times = []
+    for _ in range(10):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = sorted(times)[len(times) // 2]
+    return {"bytes_each_way": nbytes, "GBs": round(2 * nbytes / (ms / 1e3) / 1e9, 1)}
 
 
 def main():
@@ -393,6 +430,18 @@ def main():
         line["amr_level_batch"] = {
             "fp64": run_amr(ws, torch, torch.float64, args.amr_steps, tune=not args.no_tune),
             "fp32": run_amr(ws, torch, torch.float32, args.amr_steps, tune=not args.no_tune)}
+        # the same workload on a 4096^2 grid: its 806 MB ping-pong set does not
+        # fit the 256 MB Infinity Cache (a cache-free check of the roofline)
+        big = 4096
+        rb = run_uniform(ws, torch, big, 100, 5, torch.float64, 20, tune=not args.no_tune)
+        bb = algorithmic_bytes([(big, big)], 8, True)
+        line["uniform_4096_fp64"] = {
+            "value": round(big * big * 100 / (rb["ms"] / 1e3) / 1e9, 3), "steps": 100,
+            "kernel_ms": rb["ms"] / 100,
+            "frac": round(bb / (rb["ms"] / 100 / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "tiling": rb["tiling"]}
+        line["copy_reference"] = {"pool_size": copy_bandwidth(torch, bytes64 // 2),
+                                  "cache_free": copy_bandwidth(torch, 4 * bytes64)}
         line["ensemble_fp64"] = run_ensemble(ws, torch, args.ensemble_steps, tune=not args.no_tune)
         line["adjoint_fp64"] = run_adjoint(ws, torch)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)

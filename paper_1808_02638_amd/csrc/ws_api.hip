@@ -147,20 +147,21 @@ bool valid_tile(int variant, int tw, int th) {
   return th >= nty && th % nty == 0 && th / nty <= rmax;
 }
 
-// Default tiling.  Wide patches: MARCH tiles of four 60-column segments whose
-// height makes the patch's tile count just fit one round of resident
-// workgroups (assumed 4 per CU; at least 8 rows per segment, so the two halo
-// rows at each end stay a small share); up to 64 rows per segment.  Narrow
-// patches: DIRECT tiles whose width in {8..64} wastes the fewest columns
-// (larger on ties), up to 8 rows per thread.
+// Default tiling.  Patches at least 24 cells wide (not periodic): MARCH tiles
+// of four 60-column segments.  A large patch gets the segment height that
+// makes its tile count just fit one round of resident workgroups (assumed 4
+// per CU); a small one spreads its rows over the four segments (up to 16
+// rows each, so that many patches fill the GPU together); up to 64 rows per
+// segment.  Narrower patches: DIRECT tiles whose width in {8..64} wastes the
+// fewest columns (larger on ties), up to 8 rows per thread.
 void default_tile(int mx, int my, int bc, int n_cu, int *variant, int *tw, int *th) {
-  if (mx >= 120 && bc != WS_BC_PERIODIC) {
+  if (mx >= 24 && bc != WS_BC_PERIODIC) {
     *variant = kMarch;
     *tw = kMarchWidth;
     const int ntx = (mx + kMarchWidth - 5) / (kMarchWidth - 4);
     const int tile_rows = std::max(1, 4 * std::max(n_cu, 1) / ntx);  // rows of tiles
     const int seg = (my + 4 * tile_rows - 1) / (4 * tile_rows);      // rows per segment
-    *th = 4 * std::max(std::min(seg, kMaxMarchRows), std::min(8, (my + 3) / 4));
+    *th = 4 * std::max(std::min(seg, kMaxMarchRows), std::min(16, (my + 3) / 4));
     return;
   }
   *variant = kDirect;
