@@ -50,7 +50,9 @@ extern "C" {
 #define WS_ENOMEM (-4)  /* caller-provided pool or workspace too small        */
 
 enum { WS_F64 = 0, WS_F32 = 1 };          /* arithmetic and storage type   */
-enum { WS_LIM_MC = 0, WS_LIM_NONE = 1 };  /* MC limiter / no limiter (phi=1) */
+/* Wave limiters (Sec. 2.1): MC, none (phi = 1), van Leer (the paper's own
+ * benchmark limiter, Sec. 4.1). */
+enum { WS_LIM_MC = 0, WS_LIM_NONE = 1, WS_LIM_VANLEER = 2 };
 enum { WS_BC_NONE = 0, WS_BC_EXTRAP = 1, WS_BC_PERIODIC = 2 };
 
 typedef struct ws_ctx ws_ctx;

@@ -328,7 +328,7 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
   *out = nullptr;
   if (mbc != 2) return fail(WS_EINVAL, "mbc must be 2 (got %d)", mbc);
   if (dtype != WS_F64 && dtype != WS_F32) return fail(WS_EINVAL, "unknown dtype %d", dtype);
-  if (limiter != WS_LIM_MC && limiter != WS_LIM_NONE)
+  if (limiter != WS_LIM_MC && limiter != WS_LIM_NONE && limiter != WS_LIM_VANLEER)
     return fail(WS_EINVAL, "unknown limiter %d", limiter);
   if (int rc = check_desc(patches, n_patches, n_instances)) return rc;
   if (!mats) return fail(WS_EINVAL, "materials are NULL");

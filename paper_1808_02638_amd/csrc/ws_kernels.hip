@@ -44,13 +44,19 @@ namespace ws {
 namespace {
 
 // --------------------------------------------------------------------------
-// Limiter on unscaled strengths: psi(a, a_up) = phi(a_up/a) a.
-// MC: minmod(2a, 2a_up, (a + a_up)/2), written branch-free.
+// Limiter on unscaled strengths: psi(a, a_up) = phi(a_up/a) a (the limiters
+// are positively homogeneous).  MC: minmod(2a, 2a_up, (a + a_up)/2), written
+// branch-free.
 // --------------------------------------------------------------------------
 template <typename T, int LIM>
 __device__ inline T limited(T a, T b) {
   if constexpr (LIM == WS_LIM_NONE) {
     return a;
+  } else if constexpr (LIM == WS_LIM_VANLEER) {
+    // van Leer, phi(theta) = (theta + |theta|)/(1 + |theta|) with theta = b/a:
+    // 0 unless a and b share a sign, then 2ab/(a + b)
+    const T ab = a * b;
+    return ab > T(0) ? (ab + ab) / (a + b) : T(0);
   } else {
     const T ta = a + a, tb = b + b, m = (a + b) * T(0.5);
     const T lo = fmin(fmin(ta, tb), m);
@@ -937,16 +943,24 @@ hipError_t launch_step_v(int vars, const StepArgs &a, int grid, hipStream_t s) {
   }
 }
 
+// Branch recording exists for the MC limiter only.
 template <typename T, int LIM>
 hipError_t launch_step_m(int vars, const StepArgs &a, int grid, hipStream_t s) {
-  return a.masks ? launch_step_v<T, LIM, true>(vars, a, grid, s)
-                 : launch_step_v<T, LIM, false>(vars, a, grid, s);
+  if constexpr (LIM == WS_LIM_MC) {
+    if (a.masks) return launch_step_v<T, LIM, true>(vars, a, grid, s);
+  } else {
+    if (a.masks) return hipErrorInvalidValue;
+  }
+  return launch_step_v<T, LIM, false>(vars, a, grid, s);
 }
 
 template <typename T>
 hipError_t launch_step_l(int limiter, int vars, const StepArgs &a, int grid, hipStream_t s) {
-  return limiter == WS_LIM_NONE ? launch_step_m<T, WS_LIM_NONE>(vars, a, grid, s)
-                                : launch_step_m<T, WS_LIM_MC>(vars, a, grid, s);
+  switch (limiter) {
+    case WS_LIM_NONE: return launch_step_m<T, WS_LIM_NONE>(vars, a, grid, s);
+    case WS_LIM_VANLEER: return launch_step_m<T, WS_LIM_VANLEER>(vars, a, grid, s);
+    default: return launch_step_m<T, WS_LIM_MC>(vars, a, grid, s);
+  }
 }
 
 template <typename T, int LIM>
@@ -969,12 +983,18 @@ hipError_t launch_step(int dtype, int limiter, int vars, const StepArgs &a, int 
                          : launch_step_l<double>(limiter, vars, a, grid, s);
 }
 
+template <typename T>
+int occupancy_l(int limiter, int vars, int *wg_per_cu) {
+  switch (limiter) {
+    case WS_LIM_NONE: return occupancy_of<T, WS_LIM_NONE>(vars, wg_per_cu);
+    case WS_LIM_VANLEER: return occupancy_of<T, WS_LIM_VANLEER>(vars, wg_per_cu);
+    default: return occupancy_of<T, WS_LIM_MC>(vars, wg_per_cu);
+  }
+}
+
 int step_occupancy(int dtype, int limiter, int vars, int *wg_per_cu) {
-  if (dtype == WS_F32)
-    return limiter == WS_LIM_NONE ? occupancy_of<float, WS_LIM_NONE>(vars, wg_per_cu)
-                                  : occupancy_of<float, WS_LIM_MC>(vars, wg_per_cu);
-  return limiter == WS_LIM_NONE ? occupancy_of<double, WS_LIM_NONE>(vars, wg_per_cu)
-                                : occupancy_of<double, WS_LIM_MC>(vars, wg_per_cu);
+  return dtype == WS_F32 ? occupancy_l<float>(limiter, vars, wg_per_cu)
+                         : occupancy_l<double>(limiter, vars, wg_per_cu);
 }
 
 hipError_t launch_fill_ghosts(int dtype, const PatchRow *patches, int n_patches,

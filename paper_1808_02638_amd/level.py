@@ -15,7 +15,7 @@ import torch
 
 from . import _lib as C
 
-_LIMITERS = {"mc": C.WS_LIM_MC, "none": C.WS_LIM_NONE}
+_LIMITERS = {"mc": C.WS_LIM_MC, "none": C.WS_LIM_NONE, "vanleer": C.WS_LIM_VANLEER}
 _BCS = {None: C.WS_BC_NONE, "none": C.WS_BC_NONE, "extrap": C.WS_BC_EXTRAP,
         "periodic": C.WS_BC_PERIODIC}
 

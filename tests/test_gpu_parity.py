@@ -409,3 +409,47 @@ def test_ensemble_full_size_graph(ws, oracle_lib):
     sums = lev.conservation_sums()
     assert np.isfinite(sums).all()
     lev.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_vanleer_matches_oracle(ws, oracle_lib, dtype):
+    """The van Leer limiter (the paper's own benchmark limiter): 128^2 radial
+    pulse, 100 steps at CFL 0.9 with the device dt rule, against the oracle's
+    van Leer step (theta from wave dot products; the kernels use the
+    equivalent 2ab/(a+b) on wave strengths)."""
+    n = 128
+    dx = 1.0 / n
+    lev, q0 = uniform_level(ws, n, dtype=dtype, limiter="vanleer")
+    lev.set_dt([0.9 * dx / C0])
+    lev.capture(100, 0.9)
+    lev.graph_launch()
+    ref = oracle_lib.run(q0, 100, dx, dx, RHO, KB, limiter="vanleer", bc="extrap",
+                         cfl_desired=0.9)
+    err = rel_linf(lev.download(0), ref["q"])
+    tol = FP64_TOL if dtype == torch.float64 else FP32_TOL
+    print(f"van Leer {dtype} rel Linf: p={err[0]:.3e} u={err[1]:.3e} v={err[2]:.3e}")
+    assert err.max() <= tol, err
+    # the limiters differ on this data
+    mc = oracle_lib.run(q0, 100, dx, dx, RHO, KB, limiter="mc", bc="extrap", cfl_desired=0.9)
+    assert np.abs(mc["q"] - ref["q"]).max() > 1e-3
+    lev.close()
+
+
+def test_vanleer_tiling_independent_and_no_branches(ws):
+    rng = np.random.default_rng(31)
+    nx, ny = 150, 77
+    q = rng.normal(size=(3, ny + 4, nx + 4))
+    outs = []
+    for var, tw, th in [("direct", 64, 4), ("direct", 16, 48), ("march", 64, 8),
+                        ("march", 64, 36), ("march", 64, 100)]:
+        lev, _ = uniform_level(ws, nx, ny=ny, state=q, limiter="vanleer")
+        lev.set_tiling(tw, th, variant=var)
+        for _ in range(3):
+            lev.step(0.5 / nx / C0)
+        outs.append(lev.download(0))
+        if var == "direct" and tw == 64:
+            with pytest.raises(ws.WaveStepError):
+                lev.step_record_masks(0.5 / nx / C0, lev.new_masks())
+        lev.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
