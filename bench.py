@@ -45,12 +45,14 @@ def algorithmic_bytes(shapes, elem_bytes, physical_bc):
     return total
 
 
-def run_uniform(ws, torch, n, steps, warmup, dtype, kernel_launches, tune=True):
+def run_uniform(ws, torch, n, steps, warmup, dtype, kernel_launches, tune=True, limiter="mc",
+                transverse_corr=False):
     import workloads
 
     dx = 1.0 / n
     q0 = workloads.padded_state(n, n, 0.0, 0.0, dx, dx)
-    lev = ws.Level([dict(mx=n, my=n, dx=dx, dy=dx, bc="extrap")], [(RHO, K_BULK)], dtype=dtype)
+    lev = ws.Level([dict(mx=n, my=n, dx=dx, dy=dx, bc="extrap")], [(RHO, K_BULK)], dtype=dtype,
+                   limiter=limiter, transverse_corr=transverse_corr)
     dt0 = 0.9 * dx / C_SOUND
 
     def reset():
@@ -427,6 +429,17 @@ def main():
                         "tiling": r32["tiling"],
                         "ms_per_step": r32["ms"] / K,
                         "kernel_GBs": round(a32, 1), "frac": round(a32 / HBM_PEAK_GBS, 4)}
+        # the paper's own limiter, and the variant that also splits the limited
+        # correction transversely, on the same workload
+        for key, lim, tc in (("vanleer_fp64", "vanleer", False),
+                             ("transverse_corr_fp64", "mc", True)):
+            rv = run_uniform(ws, torch, n, K, args.warmup, torch.float64, 20,
+                             tune=not args.no_tune, limiter=lim, transverse_corr=tc)
+            av = bytes64 / (rv["ms"] / K / 1e3) / 1e9
+            line[key] = {"value": round(n * n * K / (rv["ms"] / 1e3) / 1e9, 3),
+                         "tiling": rv["tiling"], "kernel_ms": rv["ms"] / K,
+                         "kernel_GBs": round(av, 1), "frac": round(av / HBM_PEAK_GBS, 4),
+                         "cfl_max": rv["cfl_max"], "finite": rv["finite"]}
         line["amr_level_batch"] = {
             "fp64": run_amr(ws, torch, torch.float64, args.amr_steps, tune=not args.no_tune),
             "fp32": run_amr(ws, torch, torch.float32, args.amr_steps, tune=not args.no_tune)}

@@ -8,8 +8,10 @@
  *     Q^{n+1} = Q - dt/dx (A+dQ_{i-1/2} + A-dQ_{i+1/2})
  *                 - dt/dy (B+dQ_{j-1/2} + B-dQ_{j+1/2})
  *                 - dt/dx (F~_{i+1/2} - F~_{i-1/2}) - dt/dy (G~_{j+1/2} - G~_{j-1/2}),
- *     with F~, G~ holding the MC-limited wave corrections and the transverse
- *     waves split from the first-order fluctuations (Sec. 2.1, Sec. 3.3);
+ *     with F~, G~ holding the limited wave corrections and the transverse
+ *     waves split from the first-order fluctuations (Sec. 2.1, Sec. 3.3), or,
+ *     with WS_TRANSVERSE_CORR, from the fluctuations with the limited
+ *     corrections moved into them;
  *   - for q = (p, u, v) and the matrices A, B of Sec. 4.1 eqs. (4.1)-(4.2)
  *     (wave speeds -c, 0, +c with c = sqrt(K/rho));
  *   - the Courant number of Sec. 2.4 eq. (2.10), max over the level's edges of
@@ -53,6 +55,17 @@ enum { WS_F64 = 0, WS_F32 = 1 };          /* arithmetic and storage type   */
 /* Wave limiters (Sec. 2.1): MC, none (phi = 1), van Leer (the paper's own
  * benchmark limiter, Sec. 4.1). */
 enum { WS_LIM_MC = 0, WS_LIM_NONE = 1, WS_LIM_VANLEER = 2 };
+/* Option OR-ed into the limiter argument of ws_init_patches: the transverse
+ * solver also splits the limited second-order correction.  Before the
+ * transverse split the correction c_{i-1/2} = sum_p |s_p| (1 - |s_p| dt/dx) W~_p
+ * of each edge is moved into the fluctuations, A+dQ - c and A-dQ + c (their
+ * sum is unchanged), so the correction waves are also carried across the
+ * y-edges; the y-direction is the mirror image.  The update's fluctuations
+ * and F~, G~'s normal parts are those of the default method.  Both variants
+ * are second-order accurate (Sec. 2.1 names the transverse waves as part of
+ * F~ and G~ without fixing which waves are split).  Branch recording and the
+ * adjoint exist for the default variant only. */
+#define WS_TRANSVERSE_CORR 0x100
 enum { WS_BC_NONE = 0, WS_BC_EXTRAP = 1, WS_BC_PERIODIC = 2 };
 
 typedef struct ws_ctx ws_ctx;
@@ -82,6 +95,7 @@ int ws_layout(const ws_patch_desc *patches, int32_t n_patches, int32_t n_instanc
  * lives in pool A first and ping-pongs.  workspace: device buffer of >=
  * ws_bytes (patch table, tile list, CFL slots, dt, counters, sums).
  * hip_stream: the hipStream_t all work is enqueued on (NULL = null stream).
+ * limiter: WS_LIM_*, optionally OR-ed with WS_TRANSVERSE_CORR.
  * Uploads the patch table and tile list and synchronises the stream. */
 int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patches,
                     const ws_material *mats, int32_t n_instances, int32_t mbc,

@@ -21,6 +21,8 @@ _SO = os.path.join(_HERE, "liboracle.so")
 
 LIM = {"mc": 0, "none": 1, "zero": 2, "vanleer": 3}
 BC = {"extrap": 0, "periodic": 1}
+OPT_DROP_ZERO_WAVE = 1
+OPT_TRANSVERSE_CORR = 2
 
 _lib = None
 
@@ -143,8 +145,11 @@ def fill_bc(q: np.ndarray, bc: str) -> np.ndarray:
 
 
 def step(q, dx, dy, dt, rho, K, limiter="mc", *, drop_zero_wave=False,
-         frozen=None, record_masks=False, parallel=True):
-    """One unsplit step.  Returns (q_new, cfl, masks-or-None)."""
+         transverse_corr=False, frozen=None, record_masks=False, parallel=True):
+    """One unsplit step.  Returns (q_new, cfl, masks-or-None).
+
+    transverse_corr selects the variant whose transverse solver also splits
+    the limited second-order correction (no masks with it)."""
     mx, my = _check_state(q)
     out = np.empty_like(q)
     cfl = ctypes.c_double(0.0)
@@ -155,7 +160,9 @@ def step(q, dx, dy, dt, rho, K, limiter="mc", *, drop_zero_wave=False,
             raise ValueError("frozen masks must have shape (my+1, mx+1)")
     rc = lib().oracle_step_ex(
         _dptr(q), _dptr(out), mx, my, float(dx), float(dy), float(dt), float(rho),
-        float(K), LIM[limiter], int(bool(drop_zero_wave)), _u8ptr(frozen),
+        float(K), LIM[limiter],
+        (OPT_DROP_ZERO_WAVE if drop_zero_wave else 0)
+        | (OPT_TRANSVERSE_CORR if transverse_corr else 0), _u8ptr(frozen),
         _u8ptr(masks), ctypes.byref(cfl), int(bool(parallel)))
     if rc != 0:
         raise RuntimeError("oracle_step_ex failed")
@@ -189,7 +196,7 @@ def step_patches(states, dxs, dys, dts, rhos, Ks, limiter="mc"):
 
 
 def run(q0, nsteps, dx, dy, rho, K, *, limiter="mc", bc="extrap", dt=None,
-        cfl_desired=None, drop_zero_wave=False, parallel=True):
+        cfl_desired=None, drop_zero_wave=False, transverse_corr=False, parallel=True):
     """Advance ``nsteps`` unsplit steps.
 
     Ghosts are filled from the interior (``bc``) before the first step and
@@ -212,7 +219,8 @@ def run(q0, nsteps, dx, dy, rho, K, *, limiter="mc", bc="extrap", dt=None,
     dts, cfls = [], []
     for _ in range(nsteps):
         q, cfl, _m = step(q, dx, dy, cur_dt, rho, K, limiter,
-                          drop_zero_wave=drop_zero_wave, parallel=parallel)
+                          drop_zero_wave=drop_zero_wave, transverse_corr=transverse_corr,
+                          parallel=parallel)
         if bc is not None:
             fill_bc(q, bc)
         dts.append(cur_dt)

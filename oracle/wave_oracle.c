@@ -26,7 +26,11 @@
  * finite-volume book (its standard unsplit wave-propagation method with
  * transverse Riemann solvers); the readings taken where the paper is silent
  * are listed in the repository design notes:
- *   * the transverse solver splits the first-order fluctuations;
+ *   * the transverse solver splits the first-order fluctuations; with
+ *     OR_OPT_TRANSVERSE_CORR it first moves each edge's whole limited
+ *     correction sum_p |s_p| (1 - |s_p| dt/dx) W~_p into them (the sign and an
+ *     upper bound on that amount are pinned by stability; the amount itself,
+ *     all of it rather than half, is parity unpinned);
  *   * limiter ratio theta = (W_upwind . W) / (W . W) over all components,
  *     W~ = W when W . W = 0; MC limiter phi = max(0, min((1+theta)/2, 2, 2 theta));
  *   * CFL number of a 2D step = max over x-edges of |s| dt/dx and over
@@ -51,6 +55,7 @@
 
 enum { OR_LIM_MC = 0, OR_LIM_NONE = 1, OR_LIM_ZERO = 2, OR_LIM_VANLEER = 3 };
 enum { OR_BC_EXTRAP = 0, OR_BC_PERIODIC = 1 };
+enum { OR_OPT_DROP_ZERO_WAVE = 1, OR_OPT_TRANSVERSE_CORR = 2 };
 
 /* ---------------------------------------------------------------------- */
 /* Eigen-decomposition of A (dir 0) and B (dir 1), Sec. 4.1 eq. (4.2).      */
@@ -238,18 +243,29 @@ void oracle_fill_bc(double *q, int mx, int my, int bc_kind) {
  * q_in, q_out : dense [3][my+4][mx+4]; q_out's interior receives Q^{n+1},
  *               its ghosts are copied from q_in (the boundary fill is a
  *               separate call made by the driver between steps).
- * limiter     : OR_LIM_*;  drop_zero_wave: omit the speed-0 wave.
+ * limiter     : OR_LIM_*.
+ * options     : OR_OPT_* bits.  OR_OPT_DROP_ZERO_WAVE omits the speed-0
+ *               wave.  OR_OPT_TRANSVERSE_CORR selects the variant whose
+ *               transverse solver also splits the limited second-order
+ *               correction (the correction waves are propagated
+ *               transversely); the update itself is unchanged.
  * frozen      : NULL, or (mx+1)*(my+1) mask bytes fixing the MC branches
  *               (the step is then a linear map of q_in);
  * masks_out   : NULL, or (mx+1)*(my+1) bytes receiving the branches taken.
+ *               Neither mask argument is accepted with OR_OPT_TRANSVERSE_CORR
+ *               (that variant also limits on the two outer ghost rows and
+ *               columns, which have no mask bytes).
  * cfl_out     : max over edges of |s| dt/dx (x-edges) and |s| dt/dy (y-edges).
  * Returns 0, or -1 on bad sizes / allocation failure.
  */
 int oracle_step_ex(const double *q_in, double *q_out, int mx, int my,
                    double dx, double dy, double dt, double rho, double K,
-                   int limiter, int drop_zero_wave, const uint8_t *frozen,
+                   int limiter, int options, const uint8_t *frozen,
                    uint8_t *masks_out, double *cfl_out, int parallel) {
   if (mx < 1 || my < 1 || !(dx > 0.0) || !(dy > 0.0)) return -1;
+  const int drop_zero_wave = (options & OR_OPT_DROP_ZERO_WAVE) != 0;
+  const int tcorr = (options & OR_OPT_TRANSVERSE_CORR) != 0;
+  if (tcorr && (frozen || masks_out)) return -1;
   eig_t ex, ey;
   acoustics_eig(rho, K, 0, &ex);
   acoustics_eig(rho, K, 1, &ey);
@@ -311,10 +327,12 @@ int oracle_step_ex(const double *q_in, double *q_out, int mx, int my,
           apdq_x[AX(j, e) + m] = ap[m];
         }
     }
-    /* limited-wave correction flux on interior rows */
-    if (j >= 0 && j < my)
+    /* limited-wave correction flux: the normal part of F~ on interior rows;
+     * the transverse variant needs it on the ghost rows -1 and my too */
+    double(*F)[NM] = calloc((size_t)(mx + 1), sizeof(double[NM]));
+    const int interior = (j >= 0 && j < my);
+    if (interior || tcorr)
       for (int e = 0; e <= mx; ++e) {
-        double F[NM] = {0.0, 0.0, 0.0};
         int mask_bits = 0;
         for (int p = 0; p < NW; ++p) {
           const double s = ex.s[p];
@@ -326,29 +344,42 @@ int oracle_step_ex(const double *q_in, double *q_out, int mx, int my,
           limit_wave(limiter, w[e + 1][p], w[up + 1][p], fz, wl, &br);
           if (s != 0.0) mask_bits |= br << (p == 0 ? 0 : 2);
           const double coef = 0.5 * fabs(s) * (1.0 - dtdx * fabs(s));
-          for (int m = 0; m < NM; ++m) F[m] += coef * wl[m];
+          for (int m = 0; m < NM; ++m) F[e][m] += coef * wl[m];
         }
-        for (int m = 0; m < NM; ++m) Fc[FC(j, e) + m] = F[m];
-        if (masks_out) masks_out[MIX(e, j)] = (uint8_t)mask_bits;
+        if (interior) {
+          for (int m = 0; m < NM; ++m) Fc[FC(j, e) + m] = F[e][m];
+          if (masks_out) masks_out[MIX(e, j)] = (uint8_t)mask_bits;
+        }
       }
-    /* transverse: A+dQ at edge e enters cell e, A-dQ enters cell e-1 */
+    /* transverse: A+dQ at edge e enters cell e, A-dQ enters cell e-1.  The
+     * variant first moves the correction into them: A+dQ - 2F, A-dQ + 2F
+     * (2F = sum_p |s_p| (1 - |s_p| dt/dx) W~_p; their sum is still A dQ). */
     for (int e = 0; e <= mx; ++e) {
-      double bm[NM], bp[NM];
+      double ap[NM], am[NM], bm[NM], bp[NM];
+      for (int m = 0; m < NM; ++m) {
+        ap[m] = apdq_x[AX(j, e) + m];
+        am[m] = amdq_x[AX(j, e) + m];
+        if (tcorr) {
+          ap[m] -= 2.0 * F[e][m];
+          am[m] += 2.0 * F[e][m];
+        }
+      }
       if (e <= mx - 1) {
-        split(&ey, &apdq_x[AX(j, e)], bm, bp);
+        split(&ey, ap, bm, bp);
         for (int m = 0; m < NM; ++m) {
           Gx_top[GX(j, e) + m] -= 0.5 * dtdx * bp[m];
           Gx_bot[GX(j, e) + m] -= 0.5 * dtdx * bm[m];
         }
       }
       if (e >= 1) {
-        split(&ey, &amdq_x[AX(j, e)], bm, bp);
+        split(&ey, am, bm, bp);
         for (int m = 0; m < NM; ++m) {
           Gx_top[GX(j, e - 1) + m] -= 0.5 * dtdx * bp[m];
           Gx_bot[GX(j, e - 1) + m] -= 0.5 * dtdx * bm[m];
         }
       }
     }
+    free(F);
     free(w);
   }
 
@@ -369,9 +400,11 @@ int oracle_step_ex(const double *q_in, double *q_out, int mx, int my,
           apdq_y[AY(f, i) + m] = bp[m];
         }
     }
-    if (i >= 0 && i < mx)
+    /* normal part of G~ on interior columns (all columns for the variant) */
+    double(*G)[NM] = calloc((size_t)(my + 1), sizeof(double[NM]));
+    const int interior = (i >= 0 && i < mx);
+    if (interior || tcorr)
       for (int f = 0; f <= my; ++f) {
-        double G[NM] = {0.0, 0.0, 0.0};
         int mask_bits = 0;
         for (int p = 0; p < NW; ++p) {
           const double s = ey.s[p];
@@ -383,9 +416,10 @@ int oracle_step_ex(const double *q_in, double *q_out, int mx, int my,
           limit_wave(limiter, w[f + 1][p], w[up + 1][p], fz, wl, &br);
           if (s != 0.0) mask_bits |= br << (p == 0 ? 4 : 6);
           const double coef = 0.5 * fabs(s) * (1.0 - dtdy * fabs(s));
-          for (int m = 0; m < NM; ++m) G[m] += coef * wl[m];
+          for (int m = 0; m < NM; ++m) G[f][m] += coef * wl[m];
         }
-        for (int m = 0; m < NM; ++m) Gc[GC(f, i) + m] = G[m];
+        if (!interior) continue;
+        for (int m = 0; m < NM; ++m) Gc[GC(f, i) + m] = G[f][m];
         /* the x-sweep wrote the low nibble of rows 0..my-1 only; this
          * column's loop is the only writer of the high nibble */
         if (masks_out) {
@@ -399,22 +433,31 @@ int oracle_step_ex(const double *q_in, double *q_out, int mx, int my,
         }
       }
     for (int f = 0; f <= my; ++f) {
-      double am[NM], ap[NM];
+      double bp_[NM], bm_[NM], am[NM], ap[NM];
+      for (int m = 0; m < NM; ++m) {
+        bp_[m] = apdq_y[AY(f, i) + m];
+        bm_[m] = amdq_y[AY(f, i) + m];
+        if (tcorr) { /* the variant: B+dQ - 2G, B-dQ + 2G */
+          bp_[m] -= 2.0 * G[f][m];
+          bm_[m] += 2.0 * G[f][m];
+        }
+      }
       if (f <= my - 1) { /* B+dQ at edge f enters cell (i, f) */
-        split(&ex, &apdq_y[AY(f, i)], am, ap);
+        split(&ex, bp_, am, ap);
         for (int m = 0; m < NM; ++m) {
           Fy_right[FY(f, i) + m] -= 0.5 * dtdy * ap[m];
           Fy_left[FY(f, i) + m] -= 0.5 * dtdy * am[m];
         }
       }
       if (f >= 1) { /* B-dQ at edge f enters cell (i, f-1) */
-        split(&ex, &amdq_y[AY(f, i)], am, ap);
+        split(&ex, bm_, am, ap);
         for (int m = 0; m < NM; ++m) {
           Fy_right[FY(f - 1, i) + m] -= 0.5 * dtdy * ap[m];
           Fy_left[FY(f - 1, i) + m] -= 0.5 * dtdy * am[m];
         }
       }
     }
+    free(G);
     free(w);
   }
 

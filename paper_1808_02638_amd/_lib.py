@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libwavestep.so")
 WS_OK, WS_EINVAL, WS_ESTATE, WS_EHIP, WS_ENOMEM = 0, -1, -2, -3, -4
 WS_F64, WS_F32 = 0, 1
 WS_LIM_MC, WS_LIM_NONE, WS_LIM_VANLEER = 0, 1, 2
+WS_TRANSVERSE_CORR = 0x100
 WS_BC_NONE, WS_BC_EXTRAP, WS_BC_PERIODIC = 0, 1, 2
 WS_TILE_DIRECT, WS_TILE_MARCH = 0, 1
 

@@ -10,7 +10,7 @@ tiling never changes results (the library's arithmetic per cell does not
 depend on it), so tuning is safe on a live level.
 
 Choices are cached in a JSON file keyed by GPU architecture, the library
-build, dtype, limiter and the patch-size histogram.
+build, dtype, limiter (with the transverse variant) and the patch-size histogram.
 """
 
 from __future__ import annotations
@@ -72,7 +72,8 @@ def _key(level):
     arch = torch.cuda.get_device_properties(level.device).gcnArchName
     hist = sorted({(mx, my, str(level.bcs[k])) for k, (mx, my) in enumerate(level.shapes)})
     h = hashlib.sha1(json.dumps([hist, len(level.shapes)]).encode()).hexdigest()[:16]
-    return f"{arch}|{_library_version()}|{level.dtype}|{level.limiter}|{h}"
+    lim = level.limiter + ("+tc" if getattr(level, "transverse_corr", False) else "")
+    return f"{arch}|{_library_version()}|{level.dtype}|{lim}|{h}"
 
 
 def _default_cache():

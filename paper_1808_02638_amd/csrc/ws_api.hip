@@ -328,8 +328,11 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
   *out = nullptr;
   if (mbc != 2) return fail(WS_EINVAL, "mbc must be 2 (got %d)", mbc);
   if (dtype != WS_F64 && dtype != WS_F32) return fail(WS_EINVAL, "unknown dtype %d", dtype);
-  if (limiter != WS_LIM_MC && limiter != WS_LIM_NONE && limiter != WS_LIM_VANLEER)
-    return fail(WS_EINVAL, "unknown limiter %d", limiter);
+  {
+    const int lim = limiter & ~WS_TRANSVERSE_CORR;
+    if (lim != WS_LIM_MC && lim != WS_LIM_NONE && lim != WS_LIM_VANLEER)
+      return fail(WS_EINVAL, "unknown limiter %d", limiter);
+  }
   if (int rc = check_desc(patches, n_patches, n_instances)) return rc;
   if (!mats) return fail(WS_EINVAL, "materials are NULL");
   for (int k = 0; k < n_instances; ++k)
@@ -698,7 +701,8 @@ int ws_patch_layout(ws_ctx *c, int32_t patch, int64_t *offset, int64_t *ld, int6
 int ws_step_record_masks(ws_ctx *c, double dt, void *masks_dev, double *cfl_out) {
   if (!c) return fail(WS_EINVAL, "ctx is NULL");
   if (!masks_dev) return fail(WS_EINVAL, "masks buffer is NULL");
-  if (c->limiter != WS_LIM_MC) return fail(WS_EINVAL, "branches exist for the MC limiter only");
+  if (c->limiter != WS_LIM_MC)
+    return fail(WS_EINVAL, "branches exist for the MC limiter of the default variant only");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
   StepArgs a = c->step_args(c->cur, dt, 0.0);
   a.masks = reinterpret_cast<uint8_t *>(masks_dev);
@@ -716,7 +720,8 @@ static int check_adjoint_ctx(ws_ctx *c) {
 int ws_adjoint_step(ws_ctx *c, double dt, const void *masks_dev, const void *lam_in,
                     void *lam_out) {
   if (int rc = check_adjoint_ctx(c)) return rc;
-  if (c->limiter != WS_LIM_MC) return fail(WS_EINVAL, "the adjoint needs the MC limiter");
+  if (c->limiter != WS_LIM_MC)
+    return fail(WS_EINVAL, "the adjoint needs the MC limiter of the default variant");
   if (!masks_dev || !lam_in || !lam_out) return fail(WS_EINVAL, "NULL buffer");
   if (lam_in == lam_out) return fail(WS_EINVAL, "lam_in and lam_out must be distinct buffers");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");

@@ -17,6 +17,7 @@ struct Coef {
   T fx, fxz, fy, fyz;     // c(1-nu)/4 and /Z: correction factors
   T gx, gxz, gy, gyz;     // dtdx c^2/8 and /Z: transverse factors
   T dtdx, dtdy;
+  T tx, ty;               // 1 - nu: the correction moved into the split vectors
 };
 
 // Wave-uniform values are moved to scalar registers.
@@ -47,6 +48,8 @@ __device__ inline Coef<T> make_coef(double c, double Z, double dt, double dx, do
   k.gyz = (T)(gy * iz);
   k.dtdx = (T)dtdx;
   k.dtdy = (T)dtdy;
+  k.tx = (T)(1.0 - c * dtdx);
+  k.ty = (T)(1.0 - c * dtdy);
   T *f = &k.Z;
   for (int n = 0; n < (int)(sizeof(Coef<T>) / sizeof(T)); ++n) f[n] = uniform(f[n]);
   return k;

@@ -2,9 +2,10 @@
 // acoustics, one AMR level per launch.
 //
 // Method (Qin, LeVeque & Motley, arXiv 1808.02638): update of Sec. 2.1
-// eq. (2.3) with the acoustics matrices of Sec. 4.1 eq. (4.2), MC-limited
-// wave corrections and transverse waves split from the first-order
-// fluctuations (Sec. 2.1, Sec. 3.3); Courant number of Sec. 2.4 eq. (2.10)
+// eq. (2.3) with the acoustics matrices of Sec. 4.1 eq. (4.2), limited
+// wave corrections (MC, van Leer or none) and transverse waves split from the
+// first-order fluctuations, or from the fluctuations with the limited
+// corrections moved into them (Sec. 2.1, Sec. 3.3); Courant number of Sec. 2.4 eq. (2.10)
 // reduced over the level on the device (Sec. 3.2.2); time step of Sec. 2.5
 // eq. (2.11).
 //
@@ -81,27 +82,55 @@ __device__ inline T s1(T Z, T dp, T dn) { return fma(Z, dn, -dp); }
 template <typename T>
 __device__ inline T s2(T Z, T dp, T dn) { return fma(Z, dn, dp); }
 
-// F~ at an x-edge: limited correction of its two waves (wave -c takes its
-// upwind neighbour on the right, wave +c on the left) plus the transverse
-// waves A-+ split from the y-fluctuations of the cells left and right.
-template <typename T, int LIM>
-__device__ inline void ftilde(const Coef<T> &k, T a1, T a2, T a1_right, T a2_left, T ys_left,
-                              T ys_right, T &Fp, T &Fu) {
-  const T l1 = limited<T, LIM>(a1, a1_right), l2 = limited<T, LIM>(a2, a2_left);
+// F~ at an x-edge from the limited strengths of its two waves (l1 of wave -c,
+// l2 of wave +c): the normal correction plus the transverse waves A-+ split
+// from the y-terms of the cells left and right.
+template <typename T>
+__device__ inline void ftilde_l(const Coef<T> &k, T l1, T l2, T ys_left, T ys_right, T &Fp,
+                                T &Fu) {
   const T Fcp = k.fx * (l2 - l1), Fcu = k.fxz * (l1 + l2);
   Fp = Fcp - k.gy * (ys_left - ys_right);
   Fu = Fcu - k.gyz * (ys_right + ys_left);
 }
 
 // G~ at a y-edge, the mirror image: transverse waves B-+ split from the
-// x-fluctuations of the cells below (lo) and above (hi).
-template <typename T, int LIM>
-__device__ inline void gtilde(const Coef<T> &k, T b1, T b2, T b1_up, T b2_down, T xs_lo, T xs_hi,
-                              T &Gp, T &Gv) {
-  const T l1 = limited<T, LIM>(b1, b1_up), l2 = limited<T, LIM>(b2, b2_down);
+// x-terms of the cells below (lo) and above (hi).
+template <typename T>
+__device__ inline void gtilde_l(const Coef<T> &k, T l1, T l2, T xs_lo, T xs_hi, T &Gp, T &Gv) {
   const T Gcp = k.fy * (l2 - l1), Gcv = k.fyz * (l1 + l2);
   Gp = Gcp - k.gx * (xs_lo - xs_hi);
   Gv = Gcv - k.gxz * (xs_hi + xs_lo);
+}
+
+// F~ from the raw strengths (wave -c takes its upwind neighbour on the right,
+// wave +c on the left) and the y-fluctuations of the cells left and right.
+template <typename T, int LIM>
+__device__ inline void ftilde(const Coef<T> &k, T a1, T a2, T a1_right, T a2_left, T ys_left,
+                              T ys_right, T &Fp, T &Fu) {
+  ftilde_l<T>(k, limited<T, LIM>(a1, a1_right), limited<T, LIM>(a2, a2_left), ys_left, ys_right,
+              Fp, Fu);
+}
+
+// G~ from the raw strengths and the x-fluctuations of the cells below and above.
+template <typename T, int LIM>
+__device__ inline void gtilde(const Coef<T> &k, T b1, T b2, T b1_up, T b2_down, T xs_lo, T xs_hi,
+                              T &Gp, T &Gv) {
+  gtilde_l<T>(k, limited<T, LIM>(b1, b1_up), limited<T, LIM>(b2, b2_down), xs_lo, xs_hi, Gp, Gv);
+}
+
+// Transverse-correction variant: the split vectors are the fluctuations with
+// the limited correction moved into them, A+dQ - 2 Fc at a cell's left edge
+// and A-dQ + 2 Fc at its right edge.  Only their p parts reach the split, so
+// the cell's xs becomes xs + (4/c)(Fc_R,p - Fc_L,p) = xs + (1 - nu_x)(d_R - d_L)
+// with d = l2 - l1 at an edge (and the mirror image for ys); the update keeps
+// the plain fluctuations.
+template <typename T, int LIM>
+__device__ inline T ldiff(T a1, T a2, T a1_right, T a2_left) {
+  return limited<T, LIM>(a2, a2_left) - limited<T, LIM>(a1, a1_right);
+}
+template <typename T>
+__device__ inline T moved(T xs, T t, T d_lo, T d_hi) {
+  return xs + t * (d_hi - d_lo);
 }
 
 // Flux-differencing update of one cell, eq. (2.3).
@@ -133,7 +162,7 @@ struct CellMasks {
 // DIRECT path: the whole update of one interior cell from its 13-point
 // footprint.
 template <typename T, int LIM, bool MASKS>
-__device__ inline void cell_update(const Planes<T> &q, int i, int j, const Coef<T> &k, T &pn,
+__device__ __attribute__((always_inline)) inline void cell_update(const Planes<T> &q, int i, int j, const Coef<T> &k, T &pn,
                                    T &un, T &vn, CellMasks *mk) {
   const T Z = k.Z;
   // ---- x-edges of row j: LL = i-3/2, L = i-1/2, R = i+1/2, RR = i+3/2
@@ -182,6 +211,111 @@ __device__ inline void cell_update(const Planes<T> &q, int i, int j, const Coef<
     mk->right = mc_branch(a1R, a1RR) | (mc_branch(a2R, a2L) << 2);
     mk->top = (mc_branch(b1T, b1TT) << 4) | (mc_branch(b2T, b2B) << 6);
   }
+}
+
+// DIRECT path of the transverse-correction variant: the split vectors of the
+// cell and its four neighbours need the limited strengths on both x-edges of
+// rows j-1 and j+1 and on both y-edges of columns i-1 and i+1, so the
+// footprint grows to 21 points (rows j-1..j+1 x columns i-2..i+2 and columns
+// i-1..i+1 x rows j-2..j+2).  Every quantity has the expression the MARCH
+// sweeps give it.
+template <typename T, int LIM>
+__device__ __attribute__((always_inline)) inline void cell_update_tc(const Planes<T> &q, int i, int j, const Coef<T> &k, T &pn,
+                                      T &un, T &vn) {
+  const T Z = k.Z;
+  // The footprint is taken in stages (split vectors of the neighbours below,
+  // above, left and right, then the cell itself) with scheduling barriers
+  // between them, so that not all 21 points' loads are in flight at once.
+  // ---- row j-1: x-edges i-3/2 .. i+3/2, split vector of cell (i, j-1)
+  T xtm;
+  {
+    const T pdm2 = q.P(i - 2, j - 1), pdm = q.P(i - 1, j - 1), pd0 = q.P(i, j - 1),
+            pdp = q.P(i + 1, j - 1), pdp2 = q.P(i + 2, j - 1);
+    const T udm2 = q.U(i - 2, j - 1), udm = q.U(i - 1, j - 1), ud0 = q.U(i, j - 1),
+            udp = q.U(i + 1, j - 1), udp2 = q.U(i + 2, j - 1);
+    const T a2LLd = s2(Z, pdm - pdm2, udm - udm2);
+    const T a1Ld = s1(Z, pd0 - pdm, ud0 - udm), a2Ld = s2(Z, pd0 - pdm, ud0 - udm);
+    const T a1Rd = s1(Z, pdp - pd0, udp - ud0), a2Rd = s2(Z, pdp - pd0, udp - ud0);
+    const T a1RRd = s1(Z, pdp2 - pdp, udp2 - udp);
+    xtm = moved<T>(a2Ld + a1Rd, k.tx, ldiff<T, LIM>(a1Ld, a2Ld, a1Rd, a2LLd),
+                   ldiff<T, LIM>(a1Rd, a2Rd, a1RRd, a2Ld));
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // ---- row j+1
+  T xtp;
+  {
+    const T pum2 = q.P(i - 2, j + 1), pum = q.P(i - 1, j + 1), pu0 = q.P(i, j + 1),
+            pup = q.P(i + 1, j + 1), pup2 = q.P(i + 2, j + 1);
+    const T uum2 = q.U(i - 2, j + 1), uum = q.U(i - 1, j + 1), uu0 = q.U(i, j + 1),
+            uup = q.U(i + 1, j + 1), uup2 = q.U(i + 2, j + 1);
+    const T a2LLu = s2(Z, pum - pum2, uum - uum2);
+    const T a1Lu = s1(Z, pu0 - pum, uu0 - uum), a2Lu = s2(Z, pu0 - pum, uu0 - uum);
+    const T a1Ru = s1(Z, pup - pu0, uup - uu0), a2Ru = s2(Z, pup - pu0, uup - uu0);
+    const T a1RRu = s1(Z, pup2 - pup, uup2 - uup);
+    xtp = moved<T>(a2Lu + a1Ru, k.tx, ldiff<T, LIM>(a1Lu, a2Lu, a1Ru, a2LLu),
+                   ldiff<T, LIM>(a1Ru, a2Ru, a1RRu, a2Lu));
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // ---- column i-1: y-edges j-3/2 .. j+3/2, split vector of cell (i-1, j)
+  T ytl;
+  {
+    const T pl2 = q.P(i - 1, j - 2), pl1 = q.P(i - 1, j - 1), pl0 = q.P(i - 1, j),
+            plp = q.P(i - 1, j + 1), plp2 = q.P(i - 1, j + 2);
+    const T vl2 = q.V(i - 1, j - 2), vl1 = q.V(i - 1, j - 1), vl0 = q.V(i - 1, j),
+            vlp = q.V(i - 1, j + 1), vlp2 = q.V(i - 1, j + 2);
+    const T b2BBl = s2(Z, pl1 - pl2, vl1 - vl2);
+    const T b1Bl = s1(Z, pl0 - pl1, vl0 - vl1), b2Bl = s2(Z, pl0 - pl1, vl0 - vl1);
+    const T b1Tl = s1(Z, plp - pl0, vlp - vl0), b2Tl = s2(Z, plp - pl0, vlp - vl0);
+    const T b1TTl = s1(Z, plp2 - plp, vlp2 - vlp);
+    ytl = moved<T>(b2Bl + b1Tl, k.ty, ldiff<T, LIM>(b1Bl, b2Bl, b1Tl, b2BBl),
+                   ldiff<T, LIM>(b1Tl, b2Tl, b1TTl, b2Bl));
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // ---- column i+1
+  T ytr;
+  {
+    const T pr2 = q.P(i + 1, j - 2), pr1 = q.P(i + 1, j - 1), pr0 = q.P(i + 1, j),
+            prp = q.P(i + 1, j + 1), prp2 = q.P(i + 1, j + 2);
+    const T vr2 = q.V(i + 1, j - 2), vr1 = q.V(i + 1, j - 1), vr0 = q.V(i + 1, j),
+            vrp = q.V(i + 1, j + 1), vrp2 = q.V(i + 1, j + 2);
+    const T b2BBr = s2(Z, pr1 - pr2, vr1 - vr2);
+    const T b1Br = s1(Z, pr0 - pr1, vr0 - vr1), b2Br = s2(Z, pr0 - pr1, vr0 - vr1);
+    const T b1Tr = s1(Z, prp - pr0, vrp - vr0), b2Tr = s2(Z, prp - pr0, vrp - vr0);
+    const T b1TTr = s1(Z, prp2 - prp, vrp2 - vrp);
+    ytr = moved<T>(b2Br + b1Tr, k.ty, ldiff<T, LIM>(b1Br, b2Br, b1Tr, b2BBr),
+                   ldiff<T, LIM>(b1Tr, b2Tr, b1TTr, b2Br));
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // ---- the cell: row j and column i
+  const T pm2 = q.P(i - 2, j), pm1 = q.P(i - 1, j), p0 = q.P(i, j), pp1 = q.P(i + 1, j),
+          pp2 = q.P(i + 2, j);
+  const T um2 = q.U(i - 2, j), um1 = q.U(i - 1, j), u0 = q.U(i, j), up1 = q.U(i + 1, j),
+          up2 = q.U(i + 2, j);
+  const T a2LL = s2(Z, pm1 - pm2, um1 - um2);
+  const T a1L = s1(Z, p0 - pm1, u0 - um1), a2L = s2(Z, p0 - pm1, u0 - um1);
+  const T a1R = s1(Z, pp1 - p0, up1 - u0), a2R = s2(Z, pp1 - p0, up1 - u0);
+  const T a1RR = s1(Z, pp2 - pp1, up2 - up1);
+  const T qm2 = q.P(i, j - 2), qm1 = q.P(i, j - 1), qp1 = q.P(i, j + 1), qp2 = q.P(i, j + 2);
+  const T vm2 = q.V(i, j - 2), vm1 = q.V(i, j - 1), v0 = q.V(i, j), vp1 = q.V(i, j + 1),
+          vp2 = q.V(i, j + 2);
+  const T b2BB = s2(Z, qm1 - qm2, vm1 - vm2);
+  const T b1B = s1(Z, p0 - qm1, v0 - vm1), b2B = s2(Z, p0 - qm1, v0 - vm1);
+  const T b1T = s1(Z, qp1 - p0, vp1 - v0), b2T = s2(Z, qp1 - p0, vp1 - v0);
+  const T b1TT = s1(Z, qp2 - qp1, vp2 - vp1);
+  const T xs0 = a2L + a1R, xd0 = a2L - a1R;
+  const T ys0 = b2B + b1T, yd0 = b2B - b1T;
+  const T xt0 = moved<T>(xs0, k.tx, ldiff<T, LIM>(a1L, a2L, a1R, a2LL),
+                         ldiff<T, LIM>(a1R, a2R, a1RR, a2L));
+  const T yt0 = moved<T>(ys0, k.ty, ldiff<T, LIM>(b1B, b2B, b1T, b2BB),
+                         ldiff<T, LIM>(b1T, b2T, b1TT, b2B));
+
+  // ---- F~ and G~ on the four edges, then the update
+  T FLp, FLu, FRp, FRu, GBp, GBv, GTp, GTv;
+  ftilde<T, LIM>(k, a1L, a2L, a1R, a2LL, ytl, yt0, FLp, FLu);
+  ftilde<T, LIM>(k, a1R, a2R, a1RR, a2L, yt0, ytr, FRp, FRu);
+  gtilde<T, LIM>(k, b1B, b2B, b1T, b2BB, xtm, xt0, GBp, GBv);
+  gtilde<T, LIM>(k, b1T, b2T, b1TT, b2B, xt0, xtp, GTp, GTv);
+  update<T>(k, p0, u0, v0, xs0, xd0, ys0, yd0, FLp, FLu, FRp, FRu, GBp, GBv, GTp, GTv, pn, un, vn);
 }
 
 // Store a new cell value and, on physical boundaries, its ghost images.  Up
@@ -377,11 +511,64 @@ struct MarchLanes {
 // wait for everything they requested (vmcnt(0)), so the loops' waits are
 // those of their steady state.
 
+// The row loops, unrolled by kSets.  Upward over [r0, r1): row(A, B, C, r,
+// refill) with A, B, C the sets holding rows r, r+1, r+2; the last rows
+// refill only what a later row still reads (rows <= r1+1).
+template <typename T, typename RowFn>
+__device__ __attribute__((always_inline)) inline void sweep_up(RowFn &row, Row3<T> &R0, Row3<T> &R1, Row3<T> &R2, Row3<T> &R3,
+                                Row3<T> &R4, Row3<T> &R5, Row3<T> &R6, Row3<T> &R7, int r0,
+                                int r1) {
+  int r = r0;
+  for (; r + kSets <= r1; r += kSets) {
+    row(R0, R1, R2, r, true);
+    row(R1, R2, R3, r + 1, true);
+    row(R2, R3, R4, r + 2, true);
+    row(R3, R4, R5, r + 3, true);
+    row(R4, R5, R6, r + 4, true);
+    row(R5, R6, R7, r + 5, true);
+    row(R6, R7, R0, r + 6, true);
+    row(R7, R0, R1, r + 7, true);
+  }
+  if (r < r1) { row(R0, R1, R2, r, r + kSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R1, R2, R3, r, r + kSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R2, R3, R4, r, r + kSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R3, R4, R5, r, r + kSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R4, R5, R6, r, r + kSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R5, R6, R7, r, r + kSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R6, R7, R0, r, r + kSets <= r1 + 1); ++r; }
+}
+
+// Downward from row r1-1 to r0: A, B, C hold rows r, r-1, r-2; the last rows
+// refill only what a later row still reads (rows >= r0-2).
+template <typename T, typename RowFn>
+__device__ __attribute__((always_inline)) inline void sweep_down(RowFn &row, Row3<T> &R0, Row3<T> &R1, Row3<T> &R2, Row3<T> &R3,
+                                  Row3<T> &R4, Row3<T> &R5, Row3<T> &R6, Row3<T> &R7, int r0,
+                                  int r1) {
+  int r = r1 - 1;
+  for (; r - kSets + 1 >= r0; r -= kSets) {
+    row(R0, R1, R2, r, true);
+    row(R1, R2, R3, r - 1, true);
+    row(R2, R3, R4, r - 2, true);
+    row(R3, R4, R5, r - 3, true);
+    row(R4, R5, R6, r - 4, true);
+    row(R5, R6, R7, r - 5, true);
+    row(R6, R7, R0, r - 6, true);
+    row(R7, R0, R1, r - 7, true);
+  }
+  if (r >= r0) { row(R0, R1, R2, r, r - kSets >= r0 - 2); --r; }
+  if (r >= r0) { row(R1, R2, R3, r, r - kSets >= r0 - 2); --r; }
+  if (r >= r0) { row(R2, R3, R4, r, r - kSets >= r0 - 2); --r; }
+  if (r >= r0) { row(R3, R4, R5, r, r - kSets >= r0 - 2); --r; }
+  if (r >= r0) { row(R4, R5, R6, r, r - kSets >= r0 - 2); --r; }
+  if (r >= r0) { row(R5, R6, R7, r, r - kSets >= r0 - 2); --r; }
+  if (r >= r0) { row(R6, R7, R0, r, r - kSets >= r0 - 2); --r; }
+}
+
 // Upward MARCH over rows [r0, r1).  x-neighbour terms come through lane
 // shifts; y-direction terms slide up the column in registers.  Each quantity
 // uses the same expression as in cell_update, so the result is bitwise equal.
 template <typename T, int LIM, bool MASKS>
-__device__ inline void march_up(const MarchLanes<T> &M, const Coef<T> &k, int r0, int r1,
+__device__ __attribute__((always_inline)) inline void march_up(const MarchLanes<T> &M, const Coef<T> &k, int r0, int r1,
                                 uint8_t *masks) {
   constexpr int w = kMarchWidth;
   const T Z = k.Z;
@@ -468,25 +655,7 @@ __device__ inline void march_up(const MarchLanes<T> &M, const Coef<T> &k, int r0
     __builtin_amdgcn_sched_barrier(0);
     if (refill) M.fetch(A, r + kSets);
   };
-  int r = r0;
-  for (; r + kSets <= r1; r += kSets) {
-    row(R0, R1, R2, r, true);
-    row(R1, R2, R3, r + 1, true);
-    row(R2, R3, R4, r + 2, true);
-    row(R3, R4, R5, r + 3, true);
-    row(R4, R5, R6, r + 4, true);
-    row(R5, R6, R7, r + 5, true);
-    row(R6, R7, R0, r + 6, true);
-    row(R7, R0, R1, r + 7, true);
-  }
-  // the last rows refill only what a later row still reads (rows <= r1+1)
-  if (r < r1) { row(R0, R1, R2, r, r + kSets <= r1 + 1); ++r; }
-  if (r < r1) { row(R1, R2, R3, r, r + kSets <= r1 + 1); ++r; }
-  if (r < r1) { row(R2, R3, R4, r, r + kSets <= r1 + 1); ++r; }
-  if (r < r1) { row(R3, R4, R5, r, r + kSets <= r1 + 1); ++r; }
-  if (r < r1) { row(R4, R5, R6, r, r + kSets <= r1 + 1); ++r; }
-  if (r < r1) { row(R5, R6, R7, r, r + kSets <= r1 + 1); ++r; }
-  if (r < r1) { row(R6, R7, R0, r, r + kSets <= r1 + 1); ++r; }
+  sweep_up<T>(row, R0, R1, R2, R3, R4, R5, R6, R7, r0, r1);
 }
 
 // Downward MARCH over rows [r0, r1), from row r1-1 down to r0: the mirror of
@@ -496,7 +665,7 @@ __device__ inline void march_up(const MarchLanes<T> &M, const Coef<T> &k, int r0
 // share are read by both at about the same time (both at their start, or
 // both at their end) and the second read finds them in L2.
 template <typename T, int LIM>
-__device__ inline void march_down(const MarchLanes<T> &M, const Coef<T> &k, int r0, int r1) {
+__device__ __attribute__((always_inline)) inline void march_down(const MarchLanes<T> &M, const Coef<T> &k, int r0, int r1) {
   const T Z = k.Z;
   Row3<T> R0, R1, R2, R3, R4, R5, R6, R7;
   // ---- prologue: rows r1+1, r1 and the sets (rows r1-1 down to r1-8)
@@ -562,25 +731,171 @@ __device__ inline void march_down(const MarchLanes<T> &M, const Coef<T> &k, int 
     __builtin_amdgcn_sched_barrier(0);
     if (refill) M.fetch(A, r - kSets);
   };
-  int r = r1 - 1;
-  for (; r - kSets + 1 >= r0; r -= kSets) {
-    row(R0, R1, R2, r, true);
-    row(R1, R2, R3, r - 1, true);
-    row(R2, R3, R4, r - 2, true);
-    row(R3, R4, R5, r - 3, true);
-    row(R4, R5, R6, r - 4, true);
-    row(R5, R6, R7, r - 5, true);
-    row(R6, R7, R0, r - 6, true);
-    row(R7, R0, R1, r - 7, true);
-  }
-  // the last rows refill only what a later row still reads (rows >= r0-2)
-  if (r >= r0) { row(R0, R1, R2, r, r - kSets >= r0 - 2); --r; }
-  if (r >= r0) { row(R1, R2, R3, r, r - kSets >= r0 - 2); --r; }
-  if (r >= r0) { row(R2, R3, R4, r, r - kSets >= r0 - 2); --r; }
-  if (r >= r0) { row(R3, R4, R5, r, r - kSets >= r0 - 2); --r; }
-  if (r >= r0) { row(R4, R5, R6, r, r - kSets >= r0 - 2); --r; }
-  if (r >= r0) { row(R5, R6, R7, r, r - kSets >= r0 - 2); --r; }
-  if (r >= r0) { row(R6, R7, R0, r, r - kSets >= r0 - 2); --r; }
+  sweep_down<T>(row, R0, R1, R2, R3, R4, R5, R6, R7, r0, r1);
+}
+
+// Upward MARCH of the transverse-correction variant.  The split vector of
+// cell (i, r+1) needs the limited strengths of row r+1, so they are formed one
+// row ahead and carried (l1, l2) into the next row's F~; the y-edges' limited
+// strengths of a cell's top edge serve its split vector and G~, and slide down
+// as the bottom edge's (eB).
+template <typename T, int LIM>
+__device__ __attribute__((always_inline)) inline void march_up_tc(const MarchLanes<T> &M, const Coef<T> &k, int r0, int r1) {
+  const T Z = k.Z;
+  Row3<T> R0, R1, R2, R3, R4, R5, R6, R7;
+  const unsigned om2 = M.at(r0 - 2), om1 = M.at(r0 - 1);
+  const T Pm2 = M.get(om2), Pm1 = M.get(om1);
+  const T Vm2 = M.get(om2 + 2 * M.plb), Vm1 = M.get(om1 + 2 * M.plb);
+  const T Um1 = M.get(om1 + M.plb);
+  M.fetch(R0, r0);
+  M.fetch(R1, r0 + 1);
+  M.fetch(R2, r0 + 2);
+  M.fetch(R3, r0 + 3);
+  M.fetch(R4, r0 + 4);
+  M.fetch(R5, r0 + 5);
+  M.fetch(R6, r0 + 6);
+  M.fetch(R7, r0 + 7);
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  const T P0 = R0.p, U0 = R0.u, V0 = R0.v, P1 = R1.p, V1 = R1.v;
+  const T b2mm = s2(Z, Pm1 - Pm2, Vm1 - Vm2);                                // y-edge r0-3/2
+  const T b1m = s1(Z, P0 - Pm1, V0 - Vm1), b2m = s2(Z, P0 - Pm1, V0 - Vm1);  // r0-1/2
+  T b1h = s1(Z, P1 - P0, V1 - V0), b2h = s2(Z, P1 - P0, V1 - V0);            // r0+1/2
+  T yb2 = b2m;
+  const T lb1m = limited<T, LIM>(b1m, b1h), lb2m = limited<T, LIM>(b2m, b2mm);
+  T eB = lb2m - lb1m;
+  // row r0-1: split vector of cell (i, r0-1)
+  const T pl_m = shr(Pm1), ul_m = shr(Um1);
+  const T a2Lm = s2(Z, Pm1 - pl_m, Um1 - ul_m);
+  const T a1Lm = s1(Z, Pm1 - pl_m, Um1 - ul_m);
+  const T a1Rm = shl(a1Lm);
+  const T dm = limited<T, LIM>(a2Lm, shr(a2Lm)) - limited<T, LIM>(a1Lm, a1Rm);
+  const T xtm = moved<T>(a2Lm + a1Rm, k.tx, dm, shl(dm));
+  // row r0
+  const T pl_0 = shr(P0), ul_0 = shr(U0);
+  T a1L = s1(Z, P0 - pl_0, U0 - ul_0), a2L = s2(Z, P0 - pl_0, U0 - ul_0);
+  T a1R = shl(a1L);
+  T xs0 = a2L + a1R;
+  T l1 = limited<T, LIM>(a1L, a1R), l2 = limited<T, LIM>(a2L, shr(a2L));
+  const T d0 = l2 - l1;
+  T xt0 = moved<T>(xs0, k.tx, d0, shl(d0));
+  T GBp, GBv;
+  gtilde_l<T>(k, lb1m, lb2m, xtm, xt0, GBp, GBv);
+
+  auto row = [&](Row3<T> &A, const Row3<T> &B, const Row3<T> &C, int r, bool refill) {
+    __builtin_amdgcn_sched_barrier(0);
+    const T P0 = A.p, U0 = A.u, V0 = A.v;
+    const T P1 = B.p, U1 = B.u, V1 = B.v;
+    const T P2 = C.p, V2 = C.v;
+    const T b1hh = s1(Z, P2 - P1, V2 - V1), b2hh = s2(Z, P2 - P1, V2 - V1);
+    const T ys0 = yb2 + b1h, yd0 = yb2 - b1h;
+    // top edge r+1/2: limited strengths, then the split vector's ys
+    const T lb1 = limited<T, LIM>(b1h, b1hh), lb2 = limited<T, LIM>(b2h, yb2);
+    const T eT = lb2 - lb1;
+    const T yt0 = moved<T>(ys0, k.ty, eB, eT);
+    // row r+1: strengths, limited strengths and split vector
+    const T pl_1 = shr(P1), ul_1 = shr(U1);
+    const T a1Ln = s1(Z, P1 - pl_1, U1 - ul_1), a2Ln = s2(Z, P1 - pl_1, U1 - ul_1);
+    const T a1Rn = shl(a1Ln);
+    const T l1n = limited<T, LIM>(a1Ln, a1Rn), l2n = limited<T, LIM>(a2Ln, shr(a2Ln));
+    const T dn = l2n - l1n;
+    const T xtp = moved<T>(a2Ln + a1Rn, k.tx, dn, shl(dn));
+    const T xd0 = a2L - a1R;
+    const T ytl = shr(yt0);
+    T FLp, FLu, GTp, GTv;
+    ftilde_l<T>(k, l1, l2, ytl, yt0, FLp, FLu);
+    const T FRp = shl(FLp), FRu = shl(FLu);
+    gtilde_l<T>(k, lb1, lb2, xt0, xtp, GTp, GTv);
+    T pn, un, vn;
+    update<T>(k, P0, U0, V0, xs0, xd0, ys0, yd0, FLp, FLu, FRp, FRu, GBp, GBv, GTp, GTv, pn, un, vn);
+    M.emit(pn, un, vn, r);
+    yb2 = b2h; b1h = b1hh; b2h = b2hh; eB = eT;
+    GBp = GTp; GBv = GTv;
+    xs0 = a2Ln + a1Rn; xt0 = xtp; a2L = a2Ln; a1R = a1Rn; l1 = l1n; l2 = l2n;
+    __builtin_amdgcn_sched_barrier(0);
+    if (refill) M.fetch(A, r + kSets);
+  };
+  sweep_up<T>(row, R0, R1, R2, R3, R4, R5, R6, R7, r0, r1);
+}
+
+// Downward MARCH of the transverse-correction variant: the mirror of
+// march_up_tc (limited strengths of row r-1 formed one row ahead, the top
+// edge's eT carried).
+template <typename T, int LIM>
+__device__ __attribute__((always_inline)) inline void march_down_tc(const MarchLanes<T> &M, const Coef<T> &k, int r0, int r1) {
+  const T Z = k.Z;
+  Row3<T> R0, R1, R2, R3, R4, R5, R6, R7;
+  const unsigned oa2 = M.at(r1 + 1), oa1 = M.at(r1);
+  const T Pa2 = M.get(oa2), Pa1 = M.get(oa1);
+  const T Va2 = M.get(oa2 + 2 * M.plb), Va1 = M.get(oa1 + 2 * M.plb);
+  const T Ua1 = M.get(oa1 + M.plb);
+  M.fetch(R0, r1 - 1);
+  M.fetch(R1, r1 - 2);
+  M.fetch(R2, r1 - 3);
+  M.fetch(R3, r1 - 4);
+  M.fetch(R4, r1 - 5);
+  M.fetch(R5, r1 - 6);
+  M.fetch(R6, r1 - 7);
+  M.fetch(R7, r1 - 8);
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+  const T P0 = R0.p, U0 = R0.u, V0 = R0.v, Pm = R1.p, Vm = R1.v;
+  const T b1aa = s1(Z, Pa2 - Pa1, Va2 - Va1);                                // y-edge r1+1/2
+  const T b1a = s1(Z, Pa1 - P0, Va1 - V0), b2a = s2(Z, Pa1 - P0, Va1 - V0);  // r1-1/2
+  T b1B = s1(Z, P0 - Pm, V0 - Vm), b2B = s2(Z, P0 - Pm, V0 - Vm);            // r1-3/2
+  T b1T = b1a;
+  const T lb1a = limited<T, LIM>(b1a, b1aa), lb2a = limited<T, LIM>(b2a, b2B);
+  T eT = lb2a - lb1a;
+  // row r1: split vector of cell (i, r1)
+  const T pl_a = shr(Pa1), ul_a = shr(Ua1);
+  const T a2La = s2(Z, Pa1 - pl_a, Ua1 - ul_a);
+  const T a1La = s1(Z, Pa1 - pl_a, Ua1 - ul_a);
+  const T a1Ra = shl(a1La);
+  const T da = limited<T, LIM>(a2La, shr(a2La)) - limited<T, LIM>(a1La, a1Ra);
+  const T xta = moved<T>(a2La + a1Ra, k.tx, da, shl(da));
+  // row r1-1
+  const T pl_0 = shr(P0), ul_0 = shr(U0);
+  T a1L = s1(Z, P0 - pl_0, U0 - ul_0), a2L = s2(Z, P0 - pl_0, U0 - ul_0);
+  T a1R = shl(a1L);
+  T xs0 = a2L + a1R;
+  T l1 = limited<T, LIM>(a1L, a1R), l2 = limited<T, LIM>(a2L, shr(a2L));
+  const T d0 = l2 - l1;
+  T xt0 = moved<T>(xs0, k.tx, d0, shl(d0));
+  T GTp, GTv;
+  gtilde_l<T>(k, lb1a, lb2a, xt0, xta, GTp, GTv);
+
+  auto row = [&](Row3<T> &A, const Row3<T> &B, const Row3<T> &C, int r, bool refill) {
+    __builtin_amdgcn_sched_barrier(0);
+    const T P0 = A.p, U0 = A.u, V0 = A.v;
+    const T Pm = B.p, Um = B.u, Vm = B.v;
+    const T Pmm = C.p, Vmm = C.v;
+    const T b1BB = s1(Z, Pm - Pmm, Vm - Vmm), b2BB = s2(Z, Pm - Pmm, Vm - Vmm);
+    const T ys0 = b2B + b1T, yd0 = b2B - b1T;
+    // bottom edge r-1/2: limited strengths, then the split vector's ys
+    const T lb1 = limited<T, LIM>(b1B, b1T), lb2 = limited<T, LIM>(b2B, b2BB);
+    const T eB = lb2 - lb1;
+    const T yt0 = moved<T>(ys0, k.ty, eB, eT);
+    // row r-1: strengths, limited strengths and split vector
+    const T pl_m = shr(Pm), ul_m = shr(Um);
+    const T a1Lm = s1(Z, Pm - pl_m, Um - ul_m), a2Lm = s2(Z, Pm - pl_m, Um - ul_m);
+    const T a1Rm = shl(a1Lm);
+    const T l1m = limited<T, LIM>(a1Lm, a1Rm), l2m = limited<T, LIM>(a2Lm, shr(a2Lm));
+    const T dm = l2m - l1m;
+    const T xtm = moved<T>(a2Lm + a1Rm, k.tx, dm, shl(dm));
+    const T xd0 = a2L - a1R;
+    const T ytl = shr(yt0);
+    T FLp, FLu, GBp, GBv;
+    ftilde_l<T>(k, l1, l2, ytl, yt0, FLp, FLu);
+    const T FRp = shl(FLp), FRu = shl(FLu);
+    gtilde_l<T>(k, lb1, lb2, xtm, xt0, GBp, GBv);
+    T pn, un, vn;
+    update<T>(k, P0, U0, V0, xs0, xd0, ys0, yd0, FLp, FLu, FRp, FRu, GBp, GBv, GTp, GTv, pn, un, vn);
+    M.emit(pn, un, vn, r);
+    b1T = b1B; b1B = b1BB; b2B = b2BB; eT = eB;
+    GTp = GBp; GTv = GBv;
+    xs0 = a2Lm + a1Rm; xt0 = xtm; a2L = a2Lm; a1R = a1Rm; l1 = l1m; l2 = l2m;
+    __builtin_amdgcn_sched_barrier(0);
+    if (refill) M.fetch(A, r - kSets);
+  };
+  sweep_down<T>(row, R0, R1, R2, R3, R4, R5, R6, R7, r0, r1);
 }
 
 __device__ inline unsigned long long dbits(double v) {
@@ -597,8 +912,9 @@ __device__ inline double wave_max(double v) {
 // q*64 .. q*64+63 of the tile), worked by one wavefront; returns the tile's
 // Courant number.  No barrier: wavefronts take units independently.
 // VARS: bit 0 -> DIRECT tiles may occur, bit 1 -> MARCH tiles may occur.
-template <typename T, int LIM, bool MASKS, int VARS>
-__device__ inline double do_unit(const StepArgs &a, int t, int q) {
+// TC: the transverse-correction variant (never with MASKS).
+template <typename T, int LIM, bool MASKS, int VARS, bool TC>
+__device__ __attribute__((always_inline)) inline double do_unit(const StepArgs &a, int t, int q) {
   const TileEntry te = uniform_row(a.tiles[t]);
   const PatchRow pr = uniform_row(a.patches[te.patch]);
   const InstRow in = uniform_row(a.inst[pr.inst]);
@@ -619,10 +935,18 @@ __device__ inline double do_unit(const StepArgs &a, int t, int q) {
     if (r0 < r1) {
       const MarchLanes<T> M(qi, qo, pr, lx, i);
       // segments alternate direction up the patch (the recording step marches up)
-      if (MASKS || ((te.ty * (kThreads / kMarchWidth) + q) & 1) == 0)
-        march_up<T, LIM, MASKS>(M, k, r0, r1, masks);
-      else
-        march_down<T, LIM>(M, k, r0, r1);
+      const bool up = MASKS || ((te.ty * (kThreads / kMarchWidth) + q) & 1) == 0;
+      if constexpr (TC) {
+        if (up)
+          march_up_tc<T, LIM>(M, k, r0, r1);
+        else
+          march_down_tc<T, LIM>(M, k, r0, r1);
+      } else {
+        if (up)
+          march_up<T, LIM, MASKS>(M, k, r0, r1, masks);
+        else
+          march_down<T, LIM>(M, k, r0, r1);
+      }
     }
   } else if (VARS & 1) {
     // the threads q*64 .. q*64+63 of the tile's 256
@@ -637,7 +961,10 @@ __device__ inline double do_unit(const StepArgs &a, int t, int q) {
       for (int j = j0; j < j1; ++j) {
         T pn, un, vn;
         CellMasks mk;
-        cell_update<T, LIM, MASKS>(q, i, j, k, pn, un, vn, &mk);
+        if constexpr (TC)
+          cell_update_tc<T, LIM>(q, i, j, k, pn, un, vn);
+        else
+          cell_update<T, LIM, MASKS>(q, i, j, k, pn, un, vn, &mk);
         store<T>(qo, pr.plane, pr.ld, i, j, pr.mx, pr.my, pr.bc, pn, un, vn);
         if constexpr (MASKS) {
           const int64_t mld = pr.mx + 1;
@@ -733,15 +1060,15 @@ __device__ inline void file_tile(const StepArgs &a, int group, CflRun &run, int 
 // round-robin (largest patches first), with no atomics; the four wavefronts
 // of a workgroup work the four quarters of its tile independently.  With a
 // grid of one workgroup per tile the hardware dispatcher balances the load.
-template <typename T, int LIM, bool MASKS, int VARS>
-__device__ inline void step_body(const StepArgs &a) {
+template <typename T, int LIM, bool MASKS, int VARS, bool TC>
+__device__ __attribute__((always_inline)) inline void step_body(const StepArgs &a) {
   CflRun run;  // meaningful in lane 0 of each wavefront
   const int lane = (int)threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   if (!a.persistent) {
     const int t = a.tile_base + (int)blockIdx.x;
     if (t < a.n_tiles) {
-      const double m = do_unit<T, LIM, MASKS, VARS>(a, t, wave);
+      const double m = do_unit<T, LIM, MASKS, VARS, TC>(a, t, wave);
       if (lane == 0) {
         file_tile(a, 0, run, t, m);
         flush_cfl(a, 0, run);
@@ -756,7 +1083,7 @@ __device__ inline void step_body(const StepArgs &a) {
   const int beg = (int)((int64_t)a.n_tiles * x / groups);
   const int end = (int)((int64_t)a.n_tiles * (x + 1) / groups);
   for (int t = beg + y; t < end; t += in_group) {
-    const double m = do_unit<T, LIM, MASKS, VARS>(a, t, wave);
+    const double m = do_unit<T, LIM, MASKS, VARS, TC>(a, t, wave);
     if (lane == 0 && wave == 0) file_tile(a, x, run, t, m);
   }
   // Retire: the workgroup's values are filed (and waited for) before its
@@ -785,15 +1112,15 @@ __device__ inline void step_body(const StepArgs &a) {
   }
 }
 
-template <typename T, int LIM, bool MASKS, int VARS>
+template <typename T, int LIM, bool MASKS, int VARS, bool TC>
 __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a) {
-  step_body<T, LIM, MASKS, VARS>(a);
+  step_body<T, LIM, MASKS, VARS, TC>(a);
 }
 
 // MARCH-only levels: a kernel of their own, free of the DIRECT path's registers.
-template <typename T, int LIM, bool MASKS>
+template <typename T, int LIM, bool MASKS, bool TC>
 __global__ __launch_bounds__(kThreads) void step_kernel_march(StepArgs a) {
-  step_body<T, LIM, MASKS, 2>(a);
+  step_body<T, LIM, MASKS, 2, TC>(a);
 }
 
 // --------------------------------------------------------------------------
@@ -925,53 +1252,75 @@ __global__ __launch_bounds__(kThreads) void instance_sums_kernel(const PatchRow 
   block_sum3(acc, sums + 3 * (int64_t)inst);
 }
 
-template <typename T, int LIM, bool MASKS, int VARS>
+template <typename T, int LIM, bool MASKS, int VARS, bool TC>
 hipError_t launch_step_t(const StepArgs &a, int grid, hipStream_t s) {
   if constexpr (VARS == 2)
-    hipLaunchKernelGGL((step_kernel_march<T, LIM, MASKS>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((step_kernel_march<T, LIM, MASKS, TC>), dim3(grid), dim3(kThreads), 0, s,
+                       a);
   else
-    hipLaunchKernelGGL((step_kernel<T, LIM, MASKS, VARS>), dim3(grid), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((step_kernel<T, LIM, MASKS, VARS, TC>), dim3(grid), dim3(kThreads), 0, s,
+                       a);
   return hipGetLastError();
 }
 
-template <typename T, int LIM, bool MASKS>
+template <typename T, int LIM, bool MASKS, bool TC>
 hipError_t launch_step_v(int vars, const StepArgs &a, int grid, hipStream_t s) {
   switch (vars) {
-    case 1: return launch_step_t<T, LIM, MASKS, 1>(a, grid, s);
-    case 2: return launch_step_t<T, LIM, MASKS, 2>(a, grid, s);
-    default: return launch_step_t<T, LIM, MASKS, 3>(a, grid, s);
+    case 1: return launch_step_t<T, LIM, MASKS, 1, TC>(a, grid, s);
+    case 2: return launch_step_t<T, LIM, MASKS, 2, TC>(a, grid, s);
+    default: return launch_step_t<T, LIM, MASKS, 3, TC>(a, grid, s);
   }
 }
 
-// Branch recording exists for the MC limiter only.
+// Branch recording exists for the MC limiter of the default variant only.
 template <typename T, int LIM>
-hipError_t launch_step_m(int vars, const StepArgs &a, int grid, hipStream_t s) {
+hipError_t launch_step_m(bool tc, int vars, const StepArgs &a, int grid, hipStream_t s) {
+  if (tc) {
+    if (a.masks) return hipErrorInvalidValue;
+    return launch_step_v<T, LIM, false, true>(vars, a, grid, s);
+  }
   if constexpr (LIM == WS_LIM_MC) {
-    if (a.masks) return launch_step_v<T, LIM, true>(vars, a, grid, s);
+    if (a.masks) return launch_step_v<T, LIM, true, false>(vars, a, grid, s);
   } else {
     if (a.masks) return hipErrorInvalidValue;
   }
-  return launch_step_v<T, LIM, false>(vars, a, grid, s);
+  return launch_step_v<T, LIM, false, false>(vars, a, grid, s);
 }
 
+// limiter: WS_LIM_*, optionally with WS_TRANSVERSE_CORR.
 template <typename T>
 hipError_t launch_step_l(int limiter, int vars, const StepArgs &a, int grid, hipStream_t s) {
-  switch (limiter) {
-    case WS_LIM_NONE: return launch_step_m<T, WS_LIM_NONE>(vars, a, grid, s);
-    case WS_LIM_VANLEER: return launch_step_m<T, WS_LIM_VANLEER>(vars, a, grid, s);
-    default: return launch_step_m<T, WS_LIM_MC>(vars, a, grid, s);
+  const bool tc = (limiter & WS_TRANSVERSE_CORR) != 0;
+  switch (limiter & ~WS_TRANSVERSE_CORR) {
+    case WS_LIM_NONE: return launch_step_m<T, WS_LIM_NONE>(tc, vars, a, grid, s);
+    case WS_LIM_VANLEER: return launch_step_m<T, WS_LIM_VANLEER>(tc, vars, a, grid, s);
+    default: return launch_step_m<T, WS_LIM_MC>(tc, vars, a, grid, s);
   }
 }
 
-template <typename T, int LIM>
+template <typename T, int LIM, bool TC>
 int occupancy_of(int vars, int *n) {
   hipError_t e;
   switch (vars) {
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel<T, LIM, false, 1>, kThreads, 0); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel_march<T, LIM, false>, kThreads, 0); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel<T, LIM, false, 3>, kThreads, 0); break;
+    case 1:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel<T, LIM, false, 1, TC>,
+                                                       kThreads, 0);
+      break;
+    case 2:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel_march<T, LIM, false, TC>,
+                                                       kThreads, 0);
+      break;
+    default:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel<T, LIM, false, 3, TC>,
+                                                       kThreads, 0);
+      break;
   }
   return e == hipSuccess ? 0 : -1;
+}
+
+template <typename T, int LIM>
+int occupancy_t(bool tc, int vars, int *n) {
+  return tc ? occupancy_of<T, LIM, true>(vars, n) : occupancy_of<T, LIM, false>(vars, n);
 }
 
 }  // namespace
@@ -985,10 +1334,11 @@ hipError_t launch_step(int dtype, int limiter, int vars, const StepArgs &a, int 
 
 template <typename T>
 int occupancy_l(int limiter, int vars, int *wg_per_cu) {
-  switch (limiter) {
-    case WS_LIM_NONE: return occupancy_of<T, WS_LIM_NONE>(vars, wg_per_cu);
-    case WS_LIM_VANLEER: return occupancy_of<T, WS_LIM_VANLEER>(vars, wg_per_cu);
-    default: return occupancy_of<T, WS_LIM_MC>(vars, wg_per_cu);
+  const bool tc = (limiter & WS_TRANSVERSE_CORR) != 0;
+  switch (limiter & ~WS_TRANSVERSE_CORR) {
+    case WS_LIM_NONE: return occupancy_t<T, WS_LIM_NONE>(tc, vars, wg_per_cu);
+    case WS_LIM_VANLEER: return occupancy_t<T, WS_LIM_VANLEER>(tc, vars, wg_per_cu);
+    default: return occupancy_t<T, WS_LIM_MC>(tc, vars, wg_per_cu);
   }
 }
 

@@ -34,10 +34,14 @@ class Level:
         ghosts; default None).
     materials: sequence of (rho, K), one per instance.
     dtype: torch.float64 or torch.float32 (arithmetic and storage).
+    limiter: "mc", "vanleer" or "none".
+    transverse_corr: the variant whose transverse solver also splits the
+        limited second-order correction (no branch recording or adjoint).
     """
 
     def __init__(self, patches: Sequence, materials: Sequence, *, dtype=torch.float64,
-                 limiter: str = "mc", device="cuda", stream: torch.cuda.Stream | None = None):
+                 limiter: str = "mc", transverse_corr: bool = False, device="cuda",
+                 stream: torch.cuda.Stream | None = None):
         self._L = C.lib()
         self._ctx = None
         self.dtype = dtype
@@ -49,6 +53,8 @@ class Level:
         self.shapes = [(int(_get(p, "mx")), int(_get(p, "my"))) for p in patches]
         self.bcs = [_get(p, "bc", None) for p in patches]
         self.limiter = limiter
+        self.transverse_corr = bool(transverse_corr)
+        lim_code = _LIMITERS[limiter] | (C.WS_TRANSVERSE_CORR if transverse_corr else 0)
         descs = (C.PatchDesc * self.n)()
         for k, p in enumerate(patches):
             descs[k].mx, descs[k].my = self.shapes[k]
@@ -74,7 +80,7 @@ class Level:
         torch.cuda.synchronize(self.device)
         ctx = ctypes.c_void_p()
         C.check(self._L.ws_init_patches(
-            ctypes.byref(ctx), descs, self.n, mats, self.n_inst, 2, code, _LIMITERS[limiter],
+            ctypes.byref(ctx), descs, self.n, mats, self.n_inst, 2, code, lim_code,
             ctypes.c_void_p(self.pools[0].data_ptr()), ctypes.c_void_p(self.pools[1].data_ptr()),
             pool_b.value, ctypes.c_void_p(self.workspace.data_ptr()), ws_b.value,
             ctypes.c_void_p(self.stream.cuda_stream)))

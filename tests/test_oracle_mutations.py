@@ -65,6 +65,16 @@ MUTATIONS = {
         "const double coef = 0.5 * fabs(s) * (1.0 - dtdy * fabs(s));"),
     "adjoint_jump_sign": ("lpad[PI(e - 1, j) * NM + m] -= ldq[m];",
                           "lpad[PI(e - 1, j) * NM + m] += ldq[m];"),
+    # the variant that splits the limited correction transversely
+    "tcorr_sign": ("ap[m] -= 2.0 * F[e][m];\n          am[m] += 2.0 * F[e][m];",
+                   "ap[m] += 2.0 * F[e][m];\n          am[m] -= 2.0 * F[e][m];"),
+    "tcorr_too_much": ("ap[m] -= 2.0 * F[e][m];\n          am[m] += 2.0 * F[e][m];",
+                       "ap[m] -= 4.0 * F[e][m];\n          am[m] += 4.0 * F[e][m];"),
+    "tcorr_y_dropped": ("bp_[m] -= 2.0 * G[f][m];\n          bm_[m] += 2.0 * G[f][m];", "(void)0;"),
+    "tcorr_ignored": ("const int tcorr = (options & OR_OPT_TRANSVERSE_CORR) != 0;",
+                      "const int tcorr = 0;"),
+    "tcorr_ghost_rows_skipped": ("if (interior || tcorr)\n      for (int e = 0; e <= mx; ++e) {",
+                                 "if (interior)\n      for (int e = 0; e <= mx; ++e) {"),
 }
 
 # cheapest first; the first failing pin ends a mutant's run
@@ -75,17 +85,26 @@ PIN_CALLS = [
     ("riemann_y", lambda o: pins.test_riemann_solver_eigen_structure(o, 0.7, 2.3, 1)),
     ("split_x", lambda o: pins.test_transverse_split_matches_matrix_split(o, 0)),
     ("split_y", lambda o: pins.test_transverse_split_matches_matrix_split(o, 1)),
-    ("constant", lambda o: pins.test_constant_state_is_preserved_bitwise(o)),
-    ("lax_wendroff", lambda o: pins.test_one_dimensional_reduction_lax_wendroff(o)),
+    ("constant", lambda o: pins.test_constant_state_is_preserved_bitwise(o, False)),
+    ("lax_wendroff", lambda o: pins.test_one_dimensional_reduction_lax_wendroff(o, False)),
     ("upwind", lambda o: pins.test_one_dimensional_reduction_upwind(o)),
-    ("limited_1d", lambda o: pins.test_one_dimensional_reduction_limited_scheme(o, "mc")),
-    ("translation", lambda o: pins.test_plane_wave_translates_exactly_at_courant_one(o, "mc")),
-    ("symmetry", lambda o: pins.test_rotation_and_transpose_symmetry(o)),
-    ("conservation", lambda o: pins.test_conservation_periodic(o)),
+    ("limited_1d", lambda o: pins.test_one_dimensional_reduction_limited_scheme(o, "mc", False)),
+    ("translation", lambda o: pins.test_plane_wave_translates_exactly_at_courant_one(o, "mc", False)),
+    ("symmetry", lambda o: pins.test_rotation_and_transpose_symmetry(o, False)),
+    ("conservation", lambda o: pins.test_conservation_periodic(o, False)),
     ("frozen_forward", lambda o: adj.test_frozen_forward_equals_nonlinear_step(o)),
     ("dot_product", lambda o: adj.test_dot_product_identity(o, "extrap")),
     ("dense_jacobian", lambda o: adj.test_dense_jacobian_of_small_patch(o)),
-    ("second_order", lambda o: pins.test_second_order_convergence_oblique_plane_wave(o)),
+    ("second_order", lambda o: pins.test_second_order_convergence_oblique_plane_wave(o, False)),
+    # the transverse-correction variant
+    ("tc_rejects_masks", lambda o: pins.test_transverse_correction_variant_rejects_masks(o)),
+    ("tc_distinct", lambda o: pins.test_transverse_correction_variant_is_distinct_and_reduces_without_correction(o)),
+    ("tc_constant", lambda o: pins.test_constant_state_is_preserved_bitwise(o, True)),
+    ("tc_lax_wendroff", lambda o: pins.test_one_dimensional_reduction_lax_wendroff(o, True)),
+    ("tc_limited_1d", lambda o: pins.test_one_dimensional_reduction_limited_scheme(o, "mc", True)),
+    ("tc_conservation", lambda o: pins.test_conservation_periodic(o, True)),
+    ("tc_symmetry", lambda o: pins.test_rotation_and_transpose_symmetry(o, True)),
+    ("tc_stability", lambda o: pins.test_von_neumann_stable_up_to_courant_one(o, True)),
 ]
 
 

@@ -116,10 +116,11 @@ def test_mc_branch_table(oracle_lib):
 # Whole-step invariants
 # --------------------------------------------------------------------------
 
-def test_constant_state_is_preserved_bitwise(oracle_lib):
+@pytest.mark.parametrize("tc", [False, True])
+def test_constant_state_is_preserved_bitwise(oracle_lib, tc):
     q = np.empty((3, 20, 28))
     q[0], q[1], q[2] = 1.25, -0.5, 0.75
-    out, cfl, _ = oracle_lib.step(q, 1 / 24, 1 / 16, 0.004, RHO, KB, "mc")
+    out, cfl, _ = oracle_lib.step(q, 1 / 24, 1 / 16, 0.004, RHO, KB, "mc", transverse_corr=tc)
     assert np.array_equal(out[:, 2:-2, 2:-2], q[:, 2:-2, 2:-2])
 
 
@@ -134,15 +135,17 @@ def _periodic_x(a):
     return np.roll(a, -1, axis=-1), np.roll(a, 1, axis=-1)
 
 
-def test_one_dimensional_reduction_lax_wendroff(oracle_lib):
+@pytest.mark.parametrize("tc", [False, True])
+def test_one_dimensional_reduction_lax_wendroff(oracle_lib, tc):
     """y-uniform data, phi = 1: the unsplit step is the textbook Lax-Wendroff
-    scheme Q - nu/2 Ahat (Q+ - Q-) + nu^2/2 Ahat^2 (Q+ - 2Q + Q-)."""
+    scheme Q - nu/2 Ahat (Q+ - Q-) + nu^2/2 Ahat^2 (Q+ - 2Q + Q-), with either
+    transverse solver (their terms cancel between the two y-edges)."""
     rng = np.random.default_rng(3)
     mx, my = 32, 6
     q = _y_uniform_state(mx, my, rng)
     oracle_lib.fill_bc(q, "periodic")
     dx, dy, dt = 1 / mx, 1 / my, 0.7 / (2 * mx)
-    out, _, _ = oracle_lib.step(q, dx, dy, dt, RHO, KB, "none")
+    out, _, _ = oracle_lib.step(q, dx, dy, dt, RHO, KB, "none", transverse_corr=tc)
     A, _ = acoustics_matrices(RHO, KB)
     Q = q[:, 2, 2:-2]
     Qp, Qm = _periodic_x(Q)
@@ -168,8 +171,9 @@ def test_one_dimensional_reduction_upwind(oracle_lib):
         np.testing.assert_allclose(out[:, 2 + j, 2:-2], ref, rtol=0, atol=1e-14)
 
 
+@pytest.mark.parametrize("tc", [False, True])
 @pytest.mark.parametrize("limiter", ["mc", "none", "zero"])
-def test_plane_wave_translates_exactly_at_courant_one(oracle_lib, limiter):
+def test_plane_wave_translates_exactly_at_courant_one(oracle_lib, limiter, tc):
     """A right-going simple wave (p' = Z u, v = 0) moves one cell per step at
     nu = 1, whatever the limiter: the correction weight (1 - nu) vanishes."""
     mx, my = 128, 4
@@ -181,13 +185,15 @@ def test_plane_wave_translates_exactly_at_courant_one(oracle_lib, limiter):
     q[1, 2:-2, 2:-2] = prof[None, :] / Z
     dx = 1.0 / mx
     dt = dx / c
-    res = oracle_lib.run(q, 100, dx, 1.0 / my, RHO, KB, limiter=limiter, bc="periodic", dt=dt)
+    res = oracle_lib.run(q, 100, dx, 1.0 / my, RHO, KB, limiter=limiter, bc="periodic", dt=dt,
+                         transverse_corr=tc)
     expect = np.roll(q[:, 2:-2, 2:-2], 100, axis=-1)
     err = np.abs(res["q"][:, 2:-2, 2:-2] - expect).max()
     assert err <= 1e-13, err
 
 
-def test_conservation_periodic(oracle_lib):
+@pytest.mark.parametrize("tc", [False, True])
+def test_conservation_periodic(oracle_lib, tc):
     n = 48
     spec, q = workloads.uniform_patch(n)
     # make the pulse reach the boundary: shift the centre off the middle
@@ -195,17 +201,19 @@ def test_conservation_periodic(oracle_lib):
     rng = np.random.default_rng(9)
     q[1:, 2:-2, 2:-2] = 0.1 * rng.normal(size=(2, n, n))
     s0 = oracle_lib.conservation_sums(oracle_lib.fill_bc(q.copy(), "periodic"), 1 / n, 1 / n)
-    res = oracle_lib.run(q, 500, 1 / n, 1 / n, RHO, KB, limiter="mc", bc="periodic", cfl_desired=0.9)
+    res = oracle_lib.run(q, 500, 1 / n, 1 / n, RHO, KB, limiter="mc", bc="periodic", cfl_desired=0.9,
+                         transverse_corr=tc)
     s1 = oracle_lib.conservation_sums(res["q"], 1 / n, 1 / n)
     scale = np.abs(q[:, 2:-2, 2:-2]).sum(axis=(1, 2)) / n**2
     assert np.all(np.abs(s1 - s0) <= 1e-13 * scale), (s0, s1)
 
 
-def test_rotation_and_transpose_symmetry(oracle_lib):
+@pytest.mark.parametrize("tc", [False, True])
+def test_rotation_and_transpose_symmetry(oracle_lib, tc):
     """Centred pulse on the 128^2 square, extrapolation BCs, 100 steps at CFL 0.9."""
     spec, q = workloads.uniform_patch(128)
     res = oracle_lib.run(q, 100, spec.dx, spec.dy, RHO, KB, limiter="mc", bc="extrap",
-                         cfl_desired=0.9)
+                         cfl_desired=0.9, transverse_corr=tc)
     p, u, v = (res["q"][m, 2:-2, 2:-2] for m in range(3))  # arrays [j, i]
     scale = np.abs(res["q"]).max()
     # transpose: p(i,j) = p(j,i), u(i,j) = v(j,i)
@@ -235,7 +243,8 @@ def _plane_wave_cell_average(n, kx, ky, Z, t, c):
 
 
 @pytest.mark.slow
-def test_second_order_convergence_oblique_plane_wave(oracle_lib):
+@pytest.mark.parametrize("tc", [False, True])
+def test_second_order_convergence_oblique_plane_wave(oracle_lib, tc):
     """phi = 1, periodic unit square, oblique smooth wave (kx, ky) = (1, 2),
     nu = 0.8, t = 0.25: errors fall by 4x per refinement.  The cross term is
     only second-order accurate with the transverse terms present, with the
@@ -250,7 +259,8 @@ def test_second_order_convergence_oblique_plane_wave(oracle_lib):
         dt = T / nsteps
         q = np.zeros((3, n + 4, n + 4))
         q[:, 2:-2, 2:-2] = _plane_wave_cell_average(n, kx, ky, Z, 0.0, c)
-        res = oracle_lib.run(q, nsteps, h, h, RHO, KB, limiter="none", bc="periodic", dt=dt)
+        res = oracle_lib.run(q, nsteps, h, h, RHO, KB, limiter="none", bc="periodic", dt=dt,
+                             transverse_corr=tc)
         ex = _plane_wave_cell_average(n, kx, ky, Z, T, c)
         d = res["q"][:, 2:-2, 2:-2] - ex
         errs1.append(np.abs(d).sum() * h * h)
@@ -317,8 +327,9 @@ def _scalar_tvd_step(w, nu, phi):
     return w - first - (np.roll(flux, -1) - flux)
 
 
+@pytest.mark.parametrize("tc", [False, True])
 @pytest.mark.parametrize("limiter", ["mc", "vanleer"])
-def test_one_dimensional_reduction_limited_scheme(oracle_lib, limiter):
+def test_one_dimensional_reduction_limited_scheme(oracle_lib, limiter, tc):
     """y-uniform data: each characteristic field of A (numpy eigenvectors)
     follows the scalar flux-limited scheme with the same limiter."""
     rng = np.random.default_rng(21)
@@ -327,7 +338,7 @@ def test_one_dimensional_reduction_limited_scheme(oracle_lib, limiter):
     q[:, 2:-2, 2 + 10:2 + 18] += 1.5  # a plateau gives both smooth and steep ratios
     oracle_lib.fill_bc(q, "periodic")
     dx, dy, dt = 1 / mx, 1 / my, 0.8 / (2 * mx)
-    out, _, _ = oracle_lib.step(q, dx, dy, dt, RHO, KB, limiter)
+    out, _, _ = oracle_lib.step(q, dx, dy, dt, RHO, KB, limiter, transverse_corr=tc)
     A, _ = acoustics_matrices(RHO, KB)
     lam, V = np.linalg.eig(A)
     lam, V = lam.real, V.real
@@ -338,3 +349,74 @@ def test_one_dimensional_reduction_limited_scheme(oracle_lib, limiter):
     ref = V @ W1
     for j in range(my):
         np.testing.assert_allclose(out[:, 2 + j, 2:-2], ref, rtol=0, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# The variant that also splits the second-order correction transversely
+# --------------------------------------------------------------------------
+
+def _step_matrix(oracle_lib, n, nu_x, nu_y, tc):
+    """Matrix of the phi = 1 step (a linear map) on a periodic n x n grid,
+    columns from unit inputs: the oracle is used as a black box."""
+    c = math.sqrt(KB / RHO)
+    dx = 1.0 / n
+    dt = nu_x * dx / c
+    dy = c * dt / nu_y
+    m = 3 * n * n
+    M = np.empty((m, m))
+    for k in range(m):
+        x = np.zeros(m)
+        x[k] = 1.0
+        q = np.zeros((3, n + 4, n + 4))
+        q[:, 2:-2, 2:-2] = x.reshape(3, n, n)
+        oracle_lib.fill_bc(q, "periodic")
+        out, _, _ = oracle_lib.step(q, dx, dy, dt, RHO, KB, "none", transverse_corr=tc,
+                                    parallel=False)
+        M[:, k] = out[:, 2:-2, 2:-2].ravel()
+    return M
+
+
+@pytest.mark.parametrize("tc", [False, True])
+def test_von_neumann_stable_up_to_courant_one(oracle_lib, tc):
+    """The unsplit method with transverse terms is stable for Courant numbers up
+    to one in each direction (Sec. 2.4 eq. (2.10) and the time-step rule of
+    Sec. 2.5 rely on it): on a periodic grid the spectral radius of the linear
+    phi = 1 step stays at most 1 (the constant mode gives exactly 1).  Moving the
+    correction the wrong way, or too much of it, into the split fluctuations
+    makes some mode grow."""
+    for nu_x, nu_y in [(0.8, 0.8), (1.0, 0.5), (0.9, 0.3), (0.5, 0.95)]:
+        M = _step_matrix(oracle_lib, 10, nu_x, nu_y, tc)
+        r = np.abs(np.linalg.eigvals(M)).max()
+        assert r <= 1.0 + 1e-12, (nu_x, nu_y, r)
+
+
+def test_transverse_correction_variant_is_distinct_and_reduces_without_correction(oracle_lib):
+    """The variant differs from the default only through the limited correction:
+    with phi = 0 there is none and the two steps agree bitwise; with a live
+    limiter they differ at the size of the transverse correction terms,
+    (c dt)^2 / (dx dy) times second differences, and so not at rounding level."""
+    spec, q = workloads.uniform_patch(48, xc=0.4, yc=0.55)
+    rng = np.random.default_rng(31)
+    q[1:, 2:-2, 2:-2] = 0.1 * rng.normal(size=(2, 48, 48))
+    oracle_lib.fill_bc(q, "extrap")
+    dt = 0.8 * spec.dx / 2.0
+    a, ca, _ = oracle_lib.step(q, spec.dx, spec.dy, dt, RHO, KB, "zero")
+    b, cb, _ = oracle_lib.step(q, spec.dx, spec.dy, dt, RHO, KB, "zero", transverse_corr=True)
+    assert np.array_equal(a, b) and ca == cb
+    a, _, _ = oracle_lib.step(q, spec.dx, spec.dy, dt, RHO, KB, "mc")
+    b, _, _ = oracle_lib.step(q, spec.dx, spec.dy, dt, RHO, KB, "mc", transverse_corr=True)
+    d = np.abs(a - b)[:, 2:-2, 2:-2].max()
+    assert d > 1e-4 * np.abs(q[:, 2:-2, 2:-2] - q[:, 2:-2, 2:-2].mean()).max(), d
+    # the two variants agree to second order: one step differs by O(h^3)
+    # relative to the O(h) change of the step itself
+    assert d < 0.2 * np.abs(a - q)[:, 2:-2, 2:-2].max(), d
+
+
+def test_transverse_correction_variant_rejects_masks(oracle_lib):
+    """The variant limits on the outer ghost rows too, which have no mask bytes."""
+    q = np.ones((3, 12, 12))
+    try:
+        oracle_lib.step(q, 0.1, 0.1, 0.01, RHO, KB, "mc", transverse_corr=True, record_masks=True)
+    except RuntimeError:
+        return
+    raise AssertionError("masks were accepted with the transverse-correction variant")
