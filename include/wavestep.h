@@ -247,6 +247,65 @@ int ws_time_step_kernel(ws_ctx *ctx, int32_t n_launches, int32_t per_patch,
 /* Index (0 = A, 1 = B) of the pool holding the current state. */
 int ws_current_pool(ws_ctx *ctx, int32_t *which);
 
+/* --------------------------------------------------------------------------
+ * Coarse-fine coupling: one composite coarse step of two levels with the
+ * conservation fix (Sec. 2.2 flow chart: advance, updating, conservation
+ * fix; Sec. 2.3 for the fix terms C1, C2, C3).
+ *
+ * The fine level's patches are nested in the coarse level's with refinement
+ * ratio r in space and time: fine patch k covers the ncx x ncy coarse cells
+ * from (ci0, cj0) of coarse patch coarse_patch, has r*ncx x r*ncy cells of
+ * size dx/r, and steps r times with dt/r per coarse step.  One composite step
+ * (ws_cf_step, all on the shared stream, no host synchronisation):
+ *   1. the coarse terms at every coarse-fine interface edge are taken from
+ *      the coarse state Q^n, then the coarse level steps with dt;
+ *   2. r times: the fine ghosts are filled from the coarse level at
+ *      t_n + k dt/r (linear in time between Q^n and Q^{n+1}, MC-limited
+ *      linear in space inside the coarse cell holding the ghost), the fine
+ *      terms at the fine patches' boundary edges are accumulated, and the
+ *      fine level steps with dt/r;
+ *   3. each covered coarse cell takes the mean of its r x r fine cells;
+ *   4. each coarse cell next to a fine patch replaces the coarse flux through
+ *      their shared edge by the mean of the fine fluxes through it over the r
+ *      fine steps; written in fluctuations this is C1 + C2 + C3 (C1 from the
+ *      Riemann problem between the coarse cell at t_n and the fine ghost, C2
+ *      from the fluctuations, C3 from F~ or G~; the coarse F~ enters with
+ *      weight dt/dx);
+ *   5. the coarse physical ghosts are refilled.
+ * Afterwards the composite totals (sum of q over coarse cells, covered ones
+ * holding fine means) change only by the fluxes through the coarse
+ * patch's physical boundary.
+ *
+ * Requirements (WS_EINVAL otherwise): both contexts have the same dtype,
+ * limiter (no WS_TRANSVERSE_CORR) and stream; fine patches have bc
+ * WS_BC_NONE, sizes divisible by r, cell sizes dx/r, dy/r and the coarse
+ * patch's material; each lies at least 2 coarse cells inside its coarse
+ * patch, and fine patches of one coarse patch are at least 3 coarse cells
+ * apart (their ghosts come from the coarse level only).
+ */
+typedef struct ws_cf ws_cf;
+typedef struct {
+  int32_t coarse_patch; /* index in the coarse context                       */
+  int32_t ci0, cj0;     /* coarse cell under the fine patch's interior (0, 0) */
+} ws_fine_place;
+
+/* Bytes of device workspace the coupling needs (placement table, one
+ * accumulator of 3 doubles per fine boundary edge, 3 doubles per coarse
+ * interface edge). */
+int ws_cf_layout(ws_ctx *fine, int32_t ratio, int64_t *bytes);
+/* places: one per fine patch.  workspace: caller-owned device buffer of at
+ * least ws_cf_layout bytes, kept until ws_cf_destroy.  Both contexts must
+ * outlive the coupling.  Synchronises the stream. */
+int ws_cf_init(ws_cf **out, ws_ctx *coarse, ws_ctx *fine, int32_t ratio,
+               const ws_fine_place *places, void *workspace, int64_t ws_bytes);
+/* One composite coarse step of size dt (steps 1-5 above).  Each level's
+ * current pool flips as in ws_step_level (the fine level's r times). */
+int ws_cf_step(ws_cf *cf, double dt);
+/* Fill the fine ghosts alone, at t_n + alpha (t_{n+1} - t_n) with t_n the
+ * coarse level's previous pool and t_{n+1} its current one, 0 <= alpha <= 1. */
+int ws_cf_fill_fine_ghosts(ws_cf *cf, double alpha);
+int ws_cf_destroy(ws_cf *cf);
+
 int ws_destroy(ws_ctx *ctx);
 const char *ws_last_error(void);
 

@@ -65,6 +65,11 @@ def load_lib(path):
     L.oracle_riemann_edge.restype = None
     L.oracle_split_vec.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp]
     L.oracle_split_vec.restype = None
+    L.oracle_step_terms.argtypes = [
+        dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+        ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp,
+    ]
+    L.oracle_step_terms.restype = ctypes.c_int
     if hasattr(L, "oracle_adjoint_step"):
         L.oracle_adjoint_step.argtypes = [
             dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -167,6 +172,23 @@ def step(q, dx, dy, dt, rho, K, limiter="mc", *, drop_zero_wave=False,
     if rc != 0:
         raise RuntimeError("oracle_step_ex failed")
     return out, cfl.value, masks
+
+
+def step_terms(q, dx, dy, dt, rho, K, limiter="mc", *, transverse_corr=False):
+    """The terms of eq. (2.3) at every edge of the interior cells, as one step
+    of q would use them: dict of arrays
+      Fx, amx, apx: (my, mx+1, 3) at x-edges (i-1/2, j)  (F~, A-dQ, A+dQ)
+      Gy, amy, apy: (my+1, mx, 3) at y-edges (i, j-1/2)  (G~, B-dQ, B+dQ)."""
+    mx, my = _check_state(q)
+    X = [np.zeros((my, mx + 1, 3)) for _ in range(3)]
+    Y = [np.zeros((my + 1, mx, 3)) for _ in range(3)]
+    rc = lib().oracle_step_terms(
+        _dptr(q), mx, my, float(dx), float(dy), float(dt), float(rho), float(K), LIM[limiter],
+        OPT_TRANSVERSE_CORR if transverse_corr else 0,
+        *[_dptr(a) for a in X], *[_dptr(a) for a in Y])
+    if rc != 0:
+        raise RuntimeError("oracle_step_terms failed")
+    return dict(Fx=X[0], amx=X[1], apx=X[2], Gy=Y[0], amy=Y[1], apy=Y[2])
 
 
 def step_patches(states, dxs, dys, dts, rhos, Ks, limiter="mc"):

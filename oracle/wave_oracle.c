@@ -258,10 +258,22 @@ void oracle_fill_bc(double *q, int mx, int my, int bc_kind) {
  * cfl_out     : max over edges of |s| dt/dx (x-edges) and |s| dt/dy (y-edges).
  * Returns 0, or -1 on bad sizes / allocation failure.
  */
-int oracle_step_ex(const double *q_in, double *q_out, int mx, int my,
-                   double dx, double dy, double dt, double rho, double K,
-                   int limiter, int options, const uint8_t *frozen,
-                   uint8_t *masks_out, double *cfl_out, int parallel) {
+/* Optional outputs of the step: the terms of eq. (2.3) at every edge of the
+ * interior cells, as the update uses them.
+ *   x-edges (i-1/2, j), j = 0..my-1, i = 0..mx: [my][mx+1][3]
+ *     Fx  = F~ (normal correction plus transverse contributions),
+ *     amx = A-dQ, apx = A+dQ;
+ *   y-edges (i, j-1/2), j = 0..my, i = 0..mx-1: [my+1][mx][3]
+ *     Gy = G~, amy = B-dQ, apy = B+dQ. */
+typedef struct {
+  double *Fx, *amx, *apx, *Gy, *amy, *apy;
+} edge_terms_t;
+
+static int step_core(const double *q_in, double *q_out, int mx, int my,
+                     double dx, double dy, double dt, double rho, double K,
+                     int limiter, int options, const uint8_t *frozen,
+                     uint8_t *masks_out, double *cfl_out, int parallel,
+                     const edge_terms_t *terms) {
   if (mx < 1 || my < 1 || !(dx > 0.0) || !(dy > 0.0)) return -1;
   const int drop_zero_wave = (options & OR_OPT_DROP_ZERO_WAVE) != 0;
   const int tcorr = (options & OR_OPT_TRANSVERSE_CORR) != 0;
@@ -461,6 +473,25 @@ int oracle_step_ex(const double *q_in, double *q_out, int mx, int my,
     free(w);
   }
 
+  if (terms) {
+    for (int j = 0; j < my; ++j)
+      for (int e = 0; e <= mx; ++e)
+        for (int m = 0; m < NM; ++m) {
+          const size_t o = ((size_t)j * (size_t)(mx + 1) + (size_t)e) * NM + (size_t)m;
+          terms->Fx[o] = Fc[FC(j, e) + m] + Fy_right[FY(j, e - 1) + m] + Fy_left[FY(j, e) + m];
+          terms->amx[o] = amdq_x[AX(j, e) + m];
+          terms->apx[o] = apdq_x[AX(j, e) + m];
+        }
+    for (int f = 0; f <= my; ++f)
+      for (int i = 0; i < mx; ++i)
+        for (int m = 0; m < NM; ++m) {
+          const size_t o = ((size_t)f * (size_t)mx + (size_t)i) * NM + (size_t)m;
+          terms->Gy[o] = Gc[GC(f, i) + m] + Gx_top[GX(f - 1, i) + m] + Gx_bot[GX(f, i) + m];
+          terms->amy[o] = amdq_y[AY(f, i) + m];
+          terms->apy[o] = apdq_y[AY(f, i) + m];
+        }
+  }
+
   /* ---- update, eq. (2.3) ---- */
   if (q_out != q_in) memcpy(q_out, q_in, sizeof(double) * NM * (size_t)(mx + 4) * (size_t)(my + 4));
 #pragma omp parallel for if (par) schedule(static)
@@ -500,6 +531,30 @@ int oracle_step_ex(const double *q_in, double *q_out, int mx, int my,
 done:
   free(amdq_x); free(apdq_x); free(amdq_y); free(apdq_y);
   free(Fc); free(Gc); free(Gx_top); free(Gx_bot); free(Fy_right); free(Fy_left);
+  return rc;
+}
+
+int oracle_step_ex(const double *q_in, double *q_out, int mx, int my,
+                   double dx, double dy, double dt, double rho, double K,
+                   int limiter, int options, const uint8_t *frozen,
+                   uint8_t *masks_out, double *cfl_out, int parallel) {
+  return step_core(q_in, q_out, mx, my, dx, dy, dt, rho, K, limiter, options, frozen,
+                   masks_out, cfl_out, parallel, NULL);
+}
+
+/* The edge terms of one step of q_in (layouts as in edge_terms_t); the new
+ * state itself is discarded. */
+int oracle_step_terms(const double *q_in, int mx, int my, double dx, double dy,
+                      double dt, double rho, double K, int limiter, int options,
+                      double *Fx, double *amx, double *apx, double *Gy,
+                      double *amy, double *apy) {
+  if (mx < 1 || my < 1) return -1;
+  double *tmp = malloc(sizeof(double) * NM * (size_t)(mx + 4) * (size_t)(my + 4));
+  if (!tmp) return -1;
+  const edge_terms_t t = {Fx, amx, apx, Gy, amy, apy};
+  const int rc = step_core(q_in, tmp, mx, my, dx, dy, dt, rho, K, limiter, options, NULL,
+                           NULL, NULL, 1, &t);
+  free(tmp);
   return rc;
 }
 

@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["ws_kernels.hip", "ws_adjoint.hip", "ws_api.hip"]
+SOURCES = ["ws_kernels.hip", "ws_adjoint.hip", "ws_amr.hip", "ws_api.hip"]
 LIB = os.path.join(HERE, "libwavestep.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

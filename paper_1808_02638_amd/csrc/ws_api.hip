@@ -235,6 +235,7 @@ struct ws_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_steps = 0, graph_start_pool = 0;
+  std::vector<InstRow> inst_host;  // (c, Z) per instance, as on the device
 
   CflSlots slots() {
     CflSlots c;
@@ -378,6 +379,7 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
     inst[k].c = std::sqrt(mats[k].K / mats[k].rho);
     inst[k].Z = mats[k].rho * inst[k].c;
   }
+  c->inst_host = inst;
   c->rows.resize(n_patches);
   int64_t mask_off = 0;
   for (int k = 0; k < n_patches; ++k) {
@@ -776,6 +778,201 @@ int ws_destroy(ws_ctx *c) {
   c->drop_graph();
   if (c->host_buf) (void)hipHostFree(c->host_buf);
   delete c;
+  return WS_OK;
+}
+
+}  // extern "C"
+
+// --------------------------------------------------------------------------
+// Coarse-fine coupling: one composite coarse step of two levels
+// --------------------------------------------------------------------------
+
+struct ws_cf {
+  ws_ctx *coarse = nullptr, *fine = nullptr;
+  int r = 1;
+  char *ws = nullptr;
+  int64_t off_place = 0, off_acc = 0, off_pc = 0;
+  int n_fine = 0;
+  int max_fedges = 0, max_cedges = 0, max_ring = 0, max_cover = 0;
+
+  CfArgs args() const {
+    CfArgs a{};
+    a.cpatch = coarse->d_patches();
+    a.fpatch = fine->d_patches();
+    a.cinst = reinterpret_cast<const InstRow *>(coarse->ws + coarse->L.inst);
+    a.finst = reinterpret_cast<const InstRow *>(fine->ws + fine->L.inst);
+    a.place = reinterpret_cast<const CfPlace *>(ws + off_place);
+    a.n_fine = n_fine;
+    a.r = r;
+    a.acc = reinterpret_cast<double *>(ws + off_acc);
+    a.pc = reinterpret_cast<double *>(ws + off_pc);
+    return a;
+  }
+};
+
+namespace {
+
+struct CfSizes {
+  int64_t place, acc, pc, total;
+  int64_t n_fedges, n_cedges;
+};
+
+CfSizes cf_sizes(const ws_ctx *fine, int r) {
+  CfSizes z{};
+  for (const ws_patch_desc &d : fine->desc) {
+    z.n_fedges += 2 * ((int64_t)d.mx + d.my);
+    z.n_cedges += 2 * ((int64_t)d.mx / r + d.my / r);
+  }
+  z.place = 0;
+  z.acc = round_up((int64_t)fine->n_patches * (int64_t)sizeof(CfPlace), 256);
+  z.pc = z.acc + round_up(24 * std::max<int64_t>(z.n_fedges, 1), 256);
+  z.total = z.pc + round_up(24 * std::max<int64_t>(z.n_cedges, 1), 256);
+  return z;
+}
+
+bool same_rel(double a, double b) { return std::fabs(a - b) <= 1e-12 * std::fabs(b); }
+
+}  // namespace
+
+extern "C" {
+
+int ws_cf_layout(ws_ctx *fine, int32_t ratio, int64_t *bytes) {
+  if (!fine || !bytes) return fail(WS_EINVAL, "NULL argument");
+  if (ratio < 1) return fail(WS_EINVAL, "refinement ratio must be >= 1");
+  *bytes = cf_sizes(fine, ratio).total;
+  return WS_OK;
+}
+
+int ws_cf_init(ws_cf **out, ws_ctx *coarse, ws_ctx *fine, int32_t ratio,
+               const ws_fine_place *places, void *workspace, int64_t ws_bytes) {
+  if (!out) return fail(WS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!coarse || !fine || !places || !workspace) return fail(WS_EINVAL, "NULL argument");
+  if (coarse == fine) return fail(WS_EINVAL, "the two levels must be different contexts");
+  if (ratio < 1) return fail(WS_EINVAL, "refinement ratio must be >= 1");
+  if (coarse->dtype != fine->dtype) return fail(WS_EINVAL, "the levels' dtypes differ");
+  if (coarse->limiter != fine->limiter) return fail(WS_EINVAL, "the levels' limiters differ");
+  if (coarse->limiter & WS_TRANSVERSE_CORR)
+    return fail(WS_EINVAL, "the coarse-fine coupling needs the default transverse variant");
+  if (coarse->stream != fine->stream) return fail(WS_EINVAL, "the levels must share one stream");
+  const CfSizes z = cf_sizes(fine, ratio);
+  if (ws_bytes < z.total)
+    return fail(WS_ENOMEM, "coupling workspace too small (%lld < %lld bytes)", (long long)ws_bytes,
+                (long long)z.total);
+  std::vector<CfPlace> pl(fine->n_patches);
+  int64_t fe = 0, ce = 0;
+  for (int k = 0; k < fine->n_patches; ++k) {
+    const ws_patch_desc &d = fine->desc[k];
+    const ws_fine_place &p = places[k];
+    if (p.coarse_patch < 0 || p.coarse_patch >= coarse->n_patches)
+      return fail(WS_EINVAL, "fine patch %d: coarse patch %d out of range", k, p.coarse_patch);
+    const ws_patch_desc &cd = coarse->desc[p.coarse_patch];
+    if (d.bc != WS_BC_NONE)
+      return fail(WS_EINVAL, "fine patch %d: its ghosts come from the coarse level (bc must be "
+                  "WS_BC_NONE)", k);
+    if (d.mx % ratio || d.my % ratio)
+      return fail(WS_EINVAL, "fine patch %d: %d x %d cells is not a whole number of coarse cells",
+                  k, d.mx, d.my);
+    if (!same_rel(d.dx * ratio, cd.dx) || !same_rel(d.dy * ratio, cd.dy))
+      return fail(WS_EINVAL, "fine patch %d: cell size times the ratio differs from the coarse", k);
+    const InstRow &fi = fine->inst_host[d.instance], &ci = coarse->inst_host[cd.instance];
+    if (fi.c != ci.c || fi.Z != ci.Z)
+      return fail(WS_EINVAL, "fine patch %d: material differs from its coarse patch's", k);
+    const int ncx = d.mx / ratio, ncy = d.my / ratio;
+    if (p.ci0 < 2 || p.cj0 < 2 || p.ci0 + ncx > cd.mx - 2 || p.cj0 + ncy > cd.my - 2)
+      return fail(WS_EINVAL, "fine patch %d must lie at least 2 coarse cells inside its coarse "
+                  "patch", k);
+    for (int o = 0; o < k; ++o) {
+      const ws_fine_place &q = places[o];
+      if (q.coarse_patch != p.coarse_patch) continue;
+      const int oncx = fine->desc[o].mx / ratio, oncy = fine->desc[o].my / ratio;
+      const int gx = std::max(q.ci0 - (p.ci0 + ncx), p.ci0 - (q.ci0 + oncx));
+      const int gy = std::max(q.cj0 - (p.cj0 + ncy), p.cj0 - (q.cj0 + oncy));
+      if (std::max(gx, gy) < 3)
+        return fail(WS_EINVAL, "fine patches %d and %d must be at least 3 coarse cells apart", o,
+                    k);
+    }
+    pl[k] = CfPlace{p.coarse_patch, p.ci0, p.cj0, ncx, ncy, (int32_t)fe, (int32_t)ce, 0};
+    fe += 2 * ((int64_t)d.mx + d.my);
+    ce += 2 * ((int64_t)ncx + ncy);
+  }
+  if (fe > INT32_MAX || ce > INT32_MAX) return fail(WS_EINVAL, "too many boundary edges");
+  ws_cf *cf = new ws_cf;
+  cf->coarse = coarse;
+  cf->fine = fine;
+  cf->r = ratio;
+  cf->ws = static_cast<char *>(workspace);
+  cf->off_place = z.place;
+  cf->off_acc = z.acc;
+  cf->off_pc = z.pc;
+  cf->n_fine = fine->n_patches;
+  for (int k = 0; k < fine->n_patches; ++k) {
+    const ws_patch_desc &d = fine->desc[k];
+    cf->max_fedges = std::max(cf->max_fedges, 2 * (d.mx + d.my));
+    cf->max_cedges = std::max(cf->max_cedges, 2 * (pl[k].ncx + pl[k].ncy));
+    cf->max_ring = std::max(cf->max_ring, 4 * (d.mx + 4) + 4 * d.my);
+    cf->max_cover = std::max(cf->max_cover, pl[k].ncx * pl[k].ncy);
+  }
+  if (hipMemcpyAsync(cf->ws + cf->off_place, pl.data(), pl.size() * sizeof(CfPlace),
+                     hipMemcpyHostToDevice, coarse->stream) != hipSuccess ||
+      hipStreamSynchronize(coarse->stream) != hipSuccess) {
+    delete cf;
+    return fail(WS_EHIP, "cannot upload the placement table");
+  }
+  *out = cf;
+  return WS_OK;
+}
+
+int ws_cf_fill_fine_ghosts(ws_cf *cf, double alpha) {
+  if (!cf) return fail(WS_EINVAL, "coupling is NULL");
+  if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(WS_EINVAL, "alpha must lie in [0, 1]");
+  ws_ctx *c = cf->coarse, *f = cf->fine;
+  CfArgs a = cf->args();
+  a.c_old = c->pool[1 - c->cur];
+  a.c_new = c->pool[c->cur];
+  a.f_cur = f->pool[f->cur];
+  HIPCHK(launch_cf_ghosts(c->dtype, a, alpha, cf->max_ring, c->stream));
+  return WS_OK;
+}
+
+int ws_cf_step(ws_cf *cf, double dt) {
+  if (!cf) return fail(WS_EINVAL, "coupling is NULL");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
+  ws_ctx *c = cf->coarse, *f = cf->fine;
+  const int r = cf->r;
+  const double dtf = dt / r;
+  CfArgs a = cf->args();
+  // coarse terms at the interfaces from Q_c^n, then the coarse step
+  HIPCHK(launch_cf_coarse_terms(c->dtype, c->limiter, a, c->pool[c->cur], dt, cf->max_cedges,
+                                c->stream));
+  {
+    StepArgs s = c->step_args(c->cur, dt, 0.0);
+    HIPCHK(launch_step(c->dtype, c->limiter, c->vars, s, c->grid, c->stream));
+    c->cur = 1 - c->cur;
+  }
+  a.c_old = c->pool[1 - c->cur];
+  a.c_new = c->pool[c->cur];
+  // r fine steps, each after its ghost fill and boundary terms
+  for (int k = 0; k < r; ++k) {
+    a.f_cur = f->pool[f->cur];
+    HIPCHK(launch_cf_ghosts(c->dtype, a, (double)k / r, cf->max_ring, c->stream));
+    HIPCHK(launch_cf_fine_terms(c->dtype, c->limiter, a, k, dtf, cf->max_fedges, c->stream));
+    StepArgs s = f->step_args(f->cur, dtf, 0.0);
+    HIPCHK(launch_step(f->dtype, f->limiter, f->vars, s, f->grid, f->stream));
+    f->cur = 1 - f->cur;
+  }
+  // updating and the conservation fix, then the coarse physical ghosts
+  a.f_cur = f->pool[f->cur];
+  HIPCHK(launch_cf_average_fix(c->dtype, a, dt, cf->max_cover, cf->max_cedges, c->stream));
+  HIPCHK(launch_fill_ghosts(c->dtype, c->d_patches(), c->n_patches, c->max_padded_cells,
+                            c->pool[c->cur], c->stream));
+  return WS_OK;
+}
+
+int ws_cf_destroy(ws_cf *cf) {
+  if (!cf) return WS_OK;
+  (void)hipStreamSynchronize(cf->coarse->stream);
+  delete cf;
   return WS_OK;
 }
 

@@ -114,4 +114,38 @@ hipError_t launch_gather(const PatchRow *patches, int patch, int comp, int n, co
 hipError_t launch_add_at(const PatchRow *patches, int patch, int comp, int n, const int32_t *ij,
                          const double *val, double *buf, hipStream_t s);
 
+// Coarse-fine coupling of two levels (defined in ws_amr.hip).  One row per
+// fine patch: where it sits in its coarse patch and where its edges' slots
+// start.  Fine boundary edges are numbered left (my), right (my), bottom
+// (mx), top (mx); the coarse interface edges the same way over ncy, ncx.
+struct CfPlace {
+  int32_t coarse;    // coarse patch index
+  int32_t ci0, cj0;  // coarse cell under fine interior cell (0, 0)
+  int32_t ncx, ncy;  // coarse cells covered
+  int32_t fedge0;    // first fine boundary edge (accumulator slots)
+  int32_t cedge0;    // first coarse interface edge
+  int32_t pad_;
+};
+
+struct CfArgs {
+  const PatchRow *cpatch, *fpatch;  // device patch tables of the coarse and fine level
+  const InstRow *cinst, *finst;
+  const CfPlace *place;             // [n_fine]
+  int32_t n_fine, r;
+  const void *c_old;  // coarse state at t_n
+  void *c_new;        // coarse state after the coarse step (updated in place)
+  void *f_cur;        // fine current state
+  double *acc;        // [fine edges][3] fine terms summed over the fine steps
+  double *pc;         // [coarse interface edges][3] coarse terms
+};
+
+hipError_t launch_cf_coarse_terms(int dtype, int limiter, const CfArgs &a, const void *qc,
+                                  double dt, int max_items, hipStream_t s);
+hipError_t launch_cf_ghosts(int dtype, const CfArgs &a, double alpha, int max_items,
+                            hipStream_t s);
+hipError_t launch_cf_fine_terms(int dtype, int limiter, const CfArgs &a, int step, double dt_fine,
+                                int max_items, hipStream_t s);
+hipError_t launch_cf_average_fix(int dtype, const CfArgs &a, double dt, int max_cover,
+                                 int max_cedges, hipStream_t s);
+
 }  // namespace ws

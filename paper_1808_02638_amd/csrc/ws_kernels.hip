@@ -44,28 +44,6 @@
 namespace ws {
 namespace {
 
-// --------------------------------------------------------------------------
-// Limiter on unscaled strengths: psi(a, a_up) = phi(a_up/a) a (the limiters
-// are positively homogeneous).  MC: minmod(2a, 2a_up, (a + a_up)/2), written
-// branch-free.
-// --------------------------------------------------------------------------
-template <typename T, int LIM>
-__device__ inline T limited(T a, T b) {
-  if constexpr (LIM == WS_LIM_NONE) {
-    return a;
-  } else if constexpr (LIM == WS_LIM_VANLEER) {
-    // van Leer, phi(theta) = (theta + |theta|)/(1 + |theta|) with theta = b/a:
-    // 0 unless a and b share a sign, then 2ab/(a + b)
-    const T ab = a * b;
-    return ab > T(0) ? (ab + ab) / (a + b) : T(0);
-  } else {
-    const T ta = a + a, tb = b + b, m = (a + b) * T(0.5);
-    const T lo = fmin(fmin(ta, tb), m);
-    const T hi = fmax(fmax(ta, tb), m);
-    return fmax(lo, T(0)) + fmin(hi, T(0));
-  }
-}
-
 // MC branch taken: 0 -> 0, 1 -> (a+b)/2, 2 -> 2a, 3 -> 2b; ties -> lowest.
 template <typename T>
 __device__ inline unsigned mc_branch(T a, T b) {
@@ -74,48 +52,6 @@ __device__ inline unsigned mc_branch(T a, T b) {
   const T m1 = fabs(a + b) * T(0.5), m2 = fabs(a) * T(2), m3 = fabs(b) * T(2);
   if (m1 <= m2 && m1 <= m3) return 1u;
   return (m2 <= m3) ? 2u : 3u;
-}
-
-// Strengths at an edge from the jumps of (p, normal velocity).
-template <typename T>
-__device__ inline T s1(T Z, T dp, T dn) { return fma(Z, dn, -dp); }
-template <typename T>
-__device__ inline T s2(T Z, T dp, T dn) { return fma(Z, dn, dp); }
-
-// F~ at an x-edge from the limited strengths of its two waves (l1 of wave -c,
-// l2 of wave +c): the normal correction plus the transverse waves A-+ split
-// from the y-terms of the cells left and right.
-template <typename T>
-__device__ inline void ftilde_l(const Coef<T> &k, T l1, T l2, T ys_left, T ys_right, T &Fp,
-                                T &Fu) {
-  const T Fcp = k.fx * (l2 - l1), Fcu = k.fxz * (l1 + l2);
-  Fp = Fcp - k.gy * (ys_left - ys_right);
-  Fu = Fcu - k.gyz * (ys_right + ys_left);
-}
-
-// G~ at a y-edge, the mirror image: transverse waves B-+ split from the
-// x-terms of the cells below (lo) and above (hi).
-template <typename T>
-__device__ inline void gtilde_l(const Coef<T> &k, T l1, T l2, T xs_lo, T xs_hi, T &Gp, T &Gv) {
-  const T Gcp = k.fy * (l2 - l1), Gcv = k.fyz * (l1 + l2);
-  Gp = Gcp - k.gx * (xs_lo - xs_hi);
-  Gv = Gcv - k.gxz * (xs_hi + xs_lo);
-}
-
-// F~ from the raw strengths (wave -c takes its upwind neighbour on the right,
-// wave +c on the left) and the y-fluctuations of the cells left and right.
-template <typename T, int LIM>
-__device__ inline void ftilde(const Coef<T> &k, T a1, T a2, T a1_right, T a2_left, T ys_left,
-                              T ys_right, T &Fp, T &Fu) {
-  ftilde_l<T>(k, limited<T, LIM>(a1, a1_right), limited<T, LIM>(a2, a2_left), ys_left, ys_right,
-              Fp, Fu);
-}
-
-// G~ from the raw strengths and the x-fluctuations of the cells below and above.
-template <typename T, int LIM>
-__device__ inline void gtilde(const Coef<T> &k, T b1, T b2, T b1_up, T b2_down, T xs_lo, T xs_hi,
-                              T &Gp, T &Gv) {
-  gtilde_l<T>(k, limited<T, LIM>(b1, b1_up), limited<T, LIM>(b2, b2_down), xs_lo, xs_hi, Gp, Gv);
 }
 
 // Transverse-correction variant: the split vectors are the fluctuations with

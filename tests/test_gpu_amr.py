@@ -1,0 +1,176 @@
+"""GPU parity of the two-level composite step (coarse step, r fine steps with
+ghosts from the coarse level, updating, conservation fix) against the
+oracle's composite step, through the ws_cf_* entry points of the C ABI.
+
+FP64 within a relative L-infinity of 1e-12 per component, FP32 within 1e-5;
+composite totals conserved to 1e-13 on a periodic coarse patch; with ratio 1
+the composite step equals the plain level step bitwise.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import FP32_TOL, FP64_TOL, rel_linf
+from oracle import amr as oamr
+import oracle.oracle as O
+
+pytestmark = pytest.mark.gpu
+
+RHO, KB, C0 = 1.0, 4.0, 2.0
+
+
+@pytest.fixture(scope="module")
+def ws():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1808_02638_amd as ws
+    return ws
+
+
+def smooth(X, Y):
+    r = np.hypot(X - 0.45, Y - 0.55)
+    p = 1.0 + 0.5 * np.exp(-((r / 0.12) ** 2))
+    return np.stack([p, 0.1 * np.sin(2 * np.pi * X), 0.1 * np.cos(2 * np.pi * Y)])
+
+
+def coarse_state(n, fn):
+    xc = (np.arange(-2, n + 2) + 0.5) / n
+    X, Y = np.meshgrid(xc, xc, indexing="xy")
+    return np.ascontiguousarray(fn(X, Y), dtype=np.float64)
+
+
+def build(ws, n, rects, r, bc, dtype=torch.float64, fn=smooth, limiter="mc"):
+    """Oracle start state and the two GPU levels holding it."""
+    qc = coarse_state(n, fn)
+    fines = oamr.init_fines(qc, rects, r, fn)
+    O.fill_bc(qc, bc)
+    coarse = ws.Level([dict(mx=n, my=n, dx=1 / n, dy=1 / n, bc=bc)], [(RHO, KB)], dtype=dtype,
+                      limiter=limiter)
+    fine = ws.Level([dict(mx=r * w, my=r * h, dx=1 / (n * r), dy=1 / (n * r)) for (_, _, w, h) in rects],
+                    [(RHO, KB)], dtype=dtype, limiter=limiter, stream=coarse.stream)
+    coarse.upload(0, qc)
+    for k, f in enumerate(fines):
+        fine.upload(k, f.q)
+    tl = ws.TwoLevel(coarse, fine, r, [(0, ci0, cj0) for (ci0, cj0, _, _) in rects])
+    return qc, fines, coarse, fine, tl
+
+
+RECTS = [(6, 8, 8, 10), (20, 5, 6, 6), (30, 30, 10, 8)]
+
+
+@pytest.mark.parametrize("bc", ["periodic", "extrap"])
+@pytest.mark.parametrize("r", [2, 4])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_composite_matches_oracle(ws, dtype, r, bc):
+    n, steps = 48, 8
+    dt = 0.8 / n / C0
+    qc, fines, coarse, fine, tl = build(ws, n, RECTS, r, bc, dtype)
+    q, fs = qc, fines
+    for _ in range(steps):
+        q, fs = oamr.two_level_step(q, fs, 1 / n, 1 / n, dt, RHO, KB, r, bc=bc)
+        tl.step(dt)
+    tol = FP64_TOL if dtype == torch.float64 else FP32_TOL
+    err = rel_linf(coarse.download(0), q)
+    print(f"two-level r={r} {bc} {dtype}: coarse rel Linf {err}")
+    assert err.max() <= tol, err
+    for k, f in enumerate(fs):
+        got = fine.download(k)
+        e = rel_linf(got[:, 2:-2, 2:-2], f.q[:, 2:-2, 2:-2])
+        assert e.max() <= tol, (k, e)
+    tl.close()
+    fine.close()
+    coarse.close()
+
+
+@pytest.mark.parametrize("r", [2, 4])
+def test_composite_conserves(ws, r):
+    """Periodic coarse 64^2, three fine patches, 60 composite steps at CFL
+    0.9: the coarse level's sums (covered cells hold the fine means) stay
+    constant to 1e-13."""
+    n = 64
+    rects = [(6, 8, 12, 10), (26, 5, 8, 8), (40, 36, 14, 12)]
+    _, _, coarse, fine, tl = build(ws, n, rects, r, "periodic")
+    s0 = coarse.conservation_sums()[0]
+    dt = 0.9 / n / C0
+    for _ in range(60):
+        tl.step(dt)
+    s1 = coarse.conservation_sums()[0]
+    scale = np.abs(s0).max()
+    print(f"two-level r={r} conservation drift {(s1 - s0) / scale}")
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * scale), (s0, s1)
+    tl.close()
+    fine.close()
+    coarse.close()
+
+
+def test_ratio_one_equals_level_step(ws):
+    n = 40
+    rects = [(5, 6, 12, 9), (22, 20, 14, 16)]
+    qc, _, coarse, fine, tl = build(ws, n, rects, 1, "extrap")
+    plain = ws.Level([dict(mx=n, my=n, dx=1 / n, dy=1 / n, bc="extrap")], [(RHO, KB)])
+    plain.upload(0, qc)
+    dt = 0.8 / n / C0
+    for _ in range(6):
+        tl.step(dt)
+        plain.step(dt, read_cfl=False)
+    ref = plain.download(0)
+    assert np.array_equal(coarse.download(0), ref)
+    for k, (ci0, cj0, w, h) in enumerate(rects):
+        got = fine.download(k)[:, 2:-2, 2:-2]
+        assert np.array_equal(got, ref[:, 2 + cj0:2 + cj0 + h, 2 + ci0:2 + ci0 + w])
+    for lev in (tl, fine, coarse, plain):
+        lev.close()
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_fine_ghost_fill_matches_oracle(ws, r):
+    """Both coarse pools hold the same state after an upload, so the fill at
+    any alpha is the spatial interpolation alone."""
+    n = 30
+    rects = [(4, 5, 7, 6), (16, 14, 9, 11)]
+    rng = np.random.default_rng(60 + r)
+    rough = lambda X, Y: np.stack([np.sin(7 * X) + 0.1 * rng.normal(size=X.shape),
+                                   np.cos(5 * Y) * X, X * Y + 0.2 * rng.normal(size=X.shape)])
+    qc, fines, coarse, fine, tl = build(ws, n, rects, r, "extrap", fn=rough)
+    tl.fill_fine_ghosts(0.3)
+    for k, f in enumerate(fines):
+        ref = f.q.copy()
+        oamr.fill_fine_ghosts(ref, f, qc, r)
+        got = fine.download(k)
+        scale = np.abs(ref).max()
+        assert np.abs(got - ref).max() <= 1e-15 * scale, k
+    for lev in (tl, fine, coarse):
+        lev.close()
+
+
+def test_invalid_layouts_are_refused(ws):
+    n = 32
+    coarse = ws.Level([dict(mx=n, my=n, dx=1 / n, dy=1 / n, bc="extrap")], [(RHO, KB)])
+
+    def fine_of(shapes, r=2, bc=None, mat=(RHO, KB), dx=None):
+        return ws.Level([dict(mx=w, my=h, dx=dx or 1 / (n * r), dy=dx or 1 / (n * r), bc=bc)
+                         for (w, h) in shapes], [mat], stream=coarse.stream)
+
+    cases = [
+        (fine_of([(8, 8)]), 2, [(0, 1, 5)]),                  # not 2 cells inside
+        (fine_of([(8, 8), (8, 8)]), 2, [(0, 4, 4), (0, 10, 4)]),  # 2 cells apart
+        (fine_of([(9, 8)]), 2, [(0, 5, 5)]),                  # not whole coarse cells
+        (fine_of([(8, 8)], bc="extrap"), 2, [(0, 5, 5)]),     # fine ghosts not frozen
+        (fine_of([(8, 8)], mat=(1.0, 9.0)), 2, [(0, 5, 5)]),  # another material
+        (fine_of([(8, 8)], dx=1 / (3 * n)), 2, [(0, 5, 5)]),  # wrong cell size
+        (fine_of([(8, 8)]), 2, [(1, 5, 5)]),                  # no such coarse patch
+    ]
+    for fine, r, places in cases:
+        with pytest.raises(ws.WaveStepError):
+            ws.TwoLevel(coarse, fine, r, places)
+        fine.close()
+    other = ws.Level([dict(mx=8, my=8, dx=1 / (2 * n), dy=1 / (2 * n))], [(RHO, KB)])
+    with pytest.raises(ValueError):
+        ws.TwoLevel(coarse, other, 2, [(0, 5, 5)])  # not on the coarse stream
+    other.close()
+    tc = ws.Level([dict(mx=8, my=8, dx=1 / (2 * n), dy=1 / (2 * n))], [(RHO, KB)],
+                  transverse_corr=True, stream=coarse.stream)
+    with pytest.raises(ws.WaveStepError):
+        ws.TwoLevel(coarse, tc, 2, [(0, 5, 5)])  # limiters differ
+    tc.close()
+    coarse.close()

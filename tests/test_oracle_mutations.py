@@ -141,3 +141,68 @@ def test_planted_mistake_is_caught(name, tmp_path):
     finally:
         oracle_mod._lib = saved
     assert caught is not None, f"planted mistake {name!r} passed every pin"
+
+
+# --------------------------------------------------------------------------
+# The two-level composite step (oracle/amr.py): mistakes planted in a copy of
+# the module, checked against the pins of test_oracle_amr
+# --------------------------------------------------------------------------
+
+import importlib.util  # noqa: E402
+import sys  # noqa: E402
+
+import oracle.amr as amr_src  # noqa: E402
+import test_oracle_amr as amr_pins  # noqa: E402
+
+AMR_MUTATIONS = {
+    # the factor printed in front of the coarse second-order term
+    "coarse_correction_quarter": (
+        'Pc = -Tc["apx"][fp.cj0 + J, e] + Tc["Fx"][fp.cj0 + J, e]',
+        'Pc = -Tc["apx"][fp.cj0 + J, e] + 0.25 * Tc["Fx"][fp.cj0 + J, e]'),
+    "left_fix_sign": ("qc[:, fp.cj0 + J + 2, fp.ci0 - 1 + 2] -= dt / dxc",
+                      "qc[:, fp.cj0 + J + 2, fp.ci0 - 1 + 2] += dt / dxc"),
+    "right_fine_fluctuation_side": ('- Tf["apx"][b, mxf] + Tf["Fx"][b, mxf]',
+                                    '+ Tf["amx"][b, mxf] + Tf["Fx"][b, mxf]'),
+    "c1_dropped_top": ('acc["top"][a] += _fsum(1, rho, K, out, g) - Tf["apy"][myf, a]',
+                       'acc["top"][a] += - Tf["apy"][myf, a]'),
+    "time_fraction": ("a = k / r", "a = (k + 1) / r"),
+    "average_weight": ("sum(axis=1) / (r * r)", "sum(axis=1) / (r * r + 1)"),
+    "slope_unlimited": ("return s * np.minimum(np.minimum(2.0 * np.abs(a), 2.0 * np.abs(b)), 0.5 * np.abs(a + b))",
+                        "return 0.5 * (a + b)"),
+    "ghost_cell_offset": ("X = fp.ci0 + (i + 0.5) / r", "X = fp.ci0 + (i + 1.0) / r"),
+}
+
+AMR_PIN_CALLS = [
+    ("interp_r2", lambda m: amr_pins.test_interpolation_conservative_linear_exact_and_bounded(2, m)),
+    ("interp_r3", lambda m: amr_pins.test_interpolation_conservative_linear_exact_and_bounded(3, m)),
+    ("mc_step", lambda m: amr_pins.test_mc_slope_bounds_a_step(m)),
+    ("constant", lambda m: amr_pins.test_constant_state_preserved(m)),
+    ("ratio_one", lambda m: amr_pins.test_ratio_one_equals_single_level_step(m)),
+    ("conserves_r2", lambda m: amr_pins.test_composite_conserves(2, m)),
+    ("symmetry", lambda m: amr_pins.test_symmetric_layout_gives_symmetric_result(m)),
+]
+
+
+@pytest.mark.parametrize("name", sorted(AMR_MUTATIONS))
+def test_planted_composite_mistake_is_caught(name, tmp_path):
+    orig, mutated = AMR_MUTATIONS[name]
+    src = open(amr_src.__file__).read()
+    assert src.count(orig) == 1, f"mutation anchor for {name} occurs {src.count(orig)} times"
+    src = src.replace(orig, mutated).replace("from . import oracle as O", "import oracle.oracle as O")
+    path = tmp_path / "amr_mutant.py"
+    path.write_text(src)
+    spec = importlib.util.spec_from_file_location("amr_mutant", path)
+    mod = importlib.util.module_from_spec(spec)
+    sys.modules["amr_mutant"] = mod  # dataclasses look their module up
+    try:
+        spec.loader.exec_module(mod)
+        caught = None
+        for pin_name, call in AMR_PIN_CALLS:
+            try:
+                call(mod)
+            except (AssertionError, ValueError, RuntimeError, FloatingPointError, IndexError):
+                caught = pin_name
+                break
+    finally:
+        del sys.modules["amr_mutant"]
+    assert caught is not None, f"planted mistake {name!r} passed every pin"
