@@ -258,6 +258,67 @@ def run_adjoint(ws, torch):
 PROFILE = os.path.join(ROOT, "profiles", "step_kernel_march_f64_2048sq.md")
 
 
+def run_two_level(ws, torch, steps=20, warmup=3, r=4, n=1024):
+    """Composite coarse steps of a 1024^2 coarse grid and 320 ratio-4 fine
+    patches of 128^2 cells over the ring's annulus (coarse step, r fine steps
+    with ghosts from the coarse level, updating, conservation fix), against
+    the same level steps without the coupling kernels."""
+    import numpy as np
+
+    import workloads
+
+    rects = workloads.two_level_layout(n)
+    dx = 1.0 / n
+    coarse = ws.Level([dict(mx=n, my=n, dx=dx, dy=dx, bc="extrap")], [(RHO, K_BULK)])
+    fine = ws.Level([dict(mx=r * w, my=r * h, dx=dx / r, dy=dx / r) for (_, _, w, h) in rects],
+                    [(RHO, K_BULK)], stream=coarse.stream)
+    coarse.upload(0, workloads.padded_state(n, n, 0.0, 0.0, dx, dx))
+    coarse.fill_ghosts()
+    for k, (ci0, cj0, w, h) in enumerate(rects):
+        fine.upload(k, workloads.padded_state(r * w, r * h, ci0 * dx, cj0 * dx, dx / r, dx / r))
+    tl = ws.TwoLevel(coarse, fine, r, [(0, ci0, cj0) for (ci0, cj0, _, _) in rects])
+    dt = 0.9 * dx / C_SOUND
+    stream = coarse.stream
+
+    def timed(fn, count):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(count):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / count
+
+    for _ in range(warmup):
+        tl.step(dt)
+    ms = timed(lambda: tl.step(dt), steps)
+
+    def levels_only():
+        coarse.step(dt, read_cfl=False)
+        for _ in range(r):
+            fine.step(dt / r, read_cfl=False)
+
+    ms_levels = timed(levels_only, steps)
+    q = coarse.download(0)
+    finite = bool(np.isfinite(q).all())
+    fine_cells = sum(r * w * r * h for (_, _, w, h) in rects)
+    updates = n * n + r * fine_cells
+    nbytes = (algorithmic_bytes([(n, n)], 8, True)
+              + r * algorithmic_bytes([(r * w, r * h) for (_, _, w, h) in rects], 8, False))
+    tl.close()
+    fine.close()
+    coarse.close()
+    return {"coarse": f"{n}x{n}", "ratio": r, "fine_patches": len(rects),
+            "fine_cells": fine_cells, "cell_updates_per_step": updates, "steps": steps,
+            "ms_per_composite_step": ms, "gcells": round(updates / (ms / 1e3) / 1e9, 3),
+            "levels_only_ms": ms_levels,
+            "coupling_overhead": round(ms / ms_levels - 1.0, 4),
+            "GBs": round(nbytes / (ms / 1e3) / 1e9, 1),
+            "frac": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "finite": finite}
+
+
 def measured_traffic(tiling, profile=PROFILE):
     """HBM bytes per launch of the FP64 step kernel from the committed counter
     summary, or None when the library has been rebuilt since the counters were
@@ -355,6 +416,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip FP32, AMR and CPU legs")
     ap.add_argument("--no-tune", action="store_true", help="time the default tiling")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--two-level-only", action="store_true",
+                    help="only run the two-level composite leg (for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -378,6 +441,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
+    if args.two_level_only:
+        print(json.dumps({"two_level_fp64": run_two_level(ws, torch)}), flush=True)
         return
     n, K = args.n, args.steps
     shapes = [(n, n)]
@@ -457,6 +523,7 @@ def main():
                                   "cache_free": copy_bandwidth(torch, 4 * bytes64)}
         line["ensemble_fp64"] = run_ensemble(ws, torch, args.ensemble_steps, tune=not args.no_tune)
         line["adjoint_fp64"] = run_adjoint(ws, torch)
+        line["two_level_fp64"] = run_two_level(ws, torch)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

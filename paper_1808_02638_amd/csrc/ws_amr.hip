@@ -55,8 +55,8 @@ __device__ inline T *cell_ptr(void *pool, const PatchRow &pr, int m, int i, int 
 }
 
 // Terms at x-edge (e - 1/2, j): A-dQ, A+dQ, F~ (3 components each).
-template <typename T, int LIM>
-__device__ inline void xedge_terms(const View<T> &q, const Coef<T> &k, int e, int j, T am[3],
+template <typename T, int LIM, class Q>
+__device__ inline void xedge_terms(const Q &q, const Coef<T> &k, int e, int j, T am[3],
                                    T ap[3], T F[3]) {
   const T Z = k.Z;
   const T a1 = s1(Z, q.P(e, j) - q.P(e - 1, j), q.U(e, j) - q.U(e - 1, j));
@@ -76,8 +76,8 @@ __device__ inline void xedge_terms(const View<T> &q, const Coef<T> &k, int e, in
 }
 
 // Terms at y-edge (i, f - 1/2): B-dQ, B+dQ, G~.
-template <typename T, int LIM>
-__device__ inline void yedge_terms(const View<T> &q, const Coef<T> &k, int i, int f, T bm[3],
+template <typename T, int LIM, class Q>
+__device__ inline void yedge_terms(const Q &q, const Coef<T> &k, int i, int f, T bm[3],
                                    T bp[3], T G[3]) {
   const T Z = k.Z;
   const T b1 = s1(Z, q.P(i, f) - q.P(i, f - 1), q.V(i, f) - q.V(i, f - 1));
@@ -183,52 +183,109 @@ __global__ __launch_bounds__(kThreads) void cf_ghosts_kernel(CfArgs a, double al
   }
 }
 
+// Columns e-2 .. e+1 of rows j0-1 .. j0+kStrip of one patch, staged in LDS
+// for the edges of a left or right side (a column of edges: their cells are
+// strided in memory, so the block reads the strip row by row instead).
+constexpr int kStrip = kThreads;  // edges per block
+template <typename T>
+struct Strip {
+  const T *s;  // [3][kStrip + 2][4]
+  int e, j0;
+  __device__ T at(int m, int i, int j) const {
+    return s[(m * (kStrip + 2) + (j - j0 + 1)) * 4 + (i - e + 2)];
+  }
+  __device__ T P(int i, int j) const { return at(0, i, j); }
+  __device__ T U(int i, int j) const { return at(1, i, j); }
+  __device__ T V(int i, int j) const { return at(2, i, j); }
+};
+
+// Blocks of one fine patch: ceil(my/kStrip) for each of the left and right
+// sides, then ceil(mx/kStrip) for each of the bottom and top sides.
+__device__ inline int cf_side_blocks(int mx, int my) {
+  return 2 * ((my + kStrip - 1) / kStrip) + 2 * ((mx + kStrip - 1) / kStrip);
+}
+
+// Fine terms of one boundary edge (ghost (gi, gj), coarse cell (oi, oj)
+// outside it) added to its accumulator slot.
+template <typename T, int LIM, class Q>
+__device__ inline void fine_edge(const CfArgs &a, const Q &q, const View<T> &co,
+                                 const Coef<T> &k, bool xdir, bool low, int e_or_i, int j_or_f,
+                                 int gi, int gj, int oi, int oj, int step, double *o) {
+  T m[3], pp[3], F[3];
+  if (xdir)
+    xedge_terms<T, LIM>(q, k, e_or_i, j_or_f, m, pp, F);
+  else
+    yedge_terms<T, LIM>(q, k, e_or_i, j_or_f, m, pp, F);
+  // C1: f(ghost) - f(Q_O^n), the fluctuation sum of the Riemann problem
+  // between the coarse cell and the fine ghost
+  const T dp = q.P(gi, gj) - co.P(oi, oj);
+  T c1[3];
+  if (xdir) {
+    const T du = q.U(gi, gj) - co.U(oi, oj);
+    const T w1 = s1(k.Z, dp, du), w2 = s2(k.Z, dp, du);
+    c1[0] = k.h * (w1 + w2), c1[1] = k.hz * (w2 - w1), c1[2] = T(0);
+  } else {
+    const T dv = q.V(gi, gj) - co.V(oi, oj);
+    const T w1 = s1(k.Z, dp, dv), w2 = s2(k.Z, dp, dv);
+    c1[0] = k.h * (w1 + w2), c1[1] = T(0), c1[2] = k.hz * (w2 - w1);
+  }
+  // the ghost is the edge's left (lower) state on the left (bottom) side
+  for (int c = 0; c < 3; ++c) {
+    const double v = (double)c1[c] + (low ? (double)m[c] : -(double)pp[c]) + (double)F[c];
+    o[c] = step == 0 ? v : o[c] + v;
+  }
+}
+
 template <typename T, int LIM>
 __global__ __launch_bounds__(kThreads) void cf_fine_terms_kernel(CfArgs a, int step,
                                                                  double dt_fine) {
+  __shared__ T strip[3 * (kStrip + 2) * 4];
   const CfPlace pl = a.place[blockIdx.y];
   const PatchRow fp = a.fpatch[blockIdx.y];
+  const int mx = fp.mx, my = fp.my, r = a.r;
+  int b = blockIdx.x;
+  const int nxb = (my + kStrip - 1) / kStrip, nyb = (mx + kStrip - 1) / kStrip;
+  if (b >= 2 * nxb + 2 * nyb) return;
   const PatchRow cp = a.cpatch[pl.coarse];
   const InstRow in = a.finst[fp.inst];
   const Coef<T> k = make_coef<T>(in.c, in.Z, dt_fine, fp.dx, fp.dy);
-  const View<T> q = view<T>(a.f_cur, fp);
   const View<T> co = view<T>(a.c_old, cp);
-  const int mx = fp.mx, my = fp.my, r = a.r;
-  const int n = 2 * (mx + my);
-  for (int e = blockIdx.x * kThreads + threadIdx.x; e < n; e += gridDim.x * kThreads) {
-    int side, idx;
-    side_of(e, mx, my, side, idx);
-    T m[3], pp[3], F[3];
-    int gi, gj, oi, oj;  // fine ghost next to the edge, coarse cell outside it
-    if (side < 2) {
-      const int edge = side == 0 ? 0 : mx;
-      xedge_terms<T, LIM>(q, k, edge, idx, m, pp, F);
-      gi = side == 0 ? -1 : mx, gj = idx;
-      oi = side == 0 ? pl.ci0 - 1 : pl.ci0 + pl.ncx, oj = pl.cj0 + idx / r;
-    } else {
-      const int edge = side == 2 ? 0 : my;
-      yedge_terms<T, LIM>(q, k, idx, edge, m, pp, F);
-      gi = idx, gj = side == 2 ? -1 : my;
-      oi = pl.ci0 + idx / r, oj = side == 2 ? pl.cj0 - 1 : pl.cj0 + pl.ncy;
+  const int t = threadIdx.x;
+  if (b < 2 * nxb) {
+    // left (e = 0) or right (e = mx) side, rows j0 .. j1-1
+    const bool left = b < nxb;
+    const int j0 = (left ? b : b - nxb) * kStrip, j1 = min(j0 + kStrip, my);
+    const int e = left ? 0 : mx;
+    const View<T> q = view<T>(a.f_cur, fp);
+    const int rows = j1 - j0 + 2;  // j0-1 .. j1
+    for (int x = t; x < 3 * rows * 4; x += kThreads) {
+      const int m = x / (rows * 4), rem = x % (rows * 4);
+      const int j = j0 - 1 + rem / 4, i = e - 2 + rem % 4;
+      const T v = m == 0 ? q.P(i, j) : m == 1 ? q.U(i, j) : q.V(i, j);
+      strip[(m * (kStrip + 2) + (j - j0 + 1)) * 4 + (i - e + 2)] = v;
     }
-    // C1: f(ghost) - f(Q_O^n), the fluctuation sum of the Riemann problem
-    // between the coarse cell and the fine ghost
-    const T dp = q.P(gi, gj) - co.P(oi, oj);
-    T c1[3];
-    if (side < 2) {
-      const T du = q.U(gi, gj) - co.U(oi, oj);
-      const T w1 = s1(k.Z, dp, du), w2 = s2(k.Z, dp, du);
-      c1[0] = k.h * (w1 + w2), c1[1] = k.hz * (w2 - w1), c1[2] = T(0);
-    } else {
-      const T dv = q.V(gi, gj) - co.V(oi, oj);
-      const T w1 = s1(k.Z, dp, dv), w2 = s2(k.Z, dp, dv);
-      c1[0] = k.h * (w1 + w2), c1[1] = T(0), c1[2] = k.hz * (w2 - w1);
+    __syncthreads();
+    const int j = j0 + t;
+    if (j < j1) {
+      const Strip<T> S{strip, e, j0};
+      const int oi = left ? pl.ci0 - 1 : pl.ci0 + pl.ncx, oj = pl.cj0 + j / r;
+      const int edge = left ? j : my + j;
+      fine_edge<T, LIM>(a, S, co, k, true, left, e, j, left ? -1 : mx, j, oi, oj, step,
+                        a.acc + 3 * ((int64_t)pl.fedge0 + edge));
     }
-    const bool low = side == 0 || side == 2;  // the ghost is the edge's left (lower) state
-    double *o = a.acc + 3 * ((int64_t)pl.fedge0 + e);
-    for (int c = 0; c < 3; ++c) {
-      const double v = (double)c1[c] + (low ? (double)m[c] : -(double)pp[c]) + (double)F[c];
-      o[c] = step == 0 ? v : o[c] + v;
+  } else {
+    // bottom (f = 0) or top (f = my) side, columns i0 .. i1-1: rows of
+    // cells, read directly (consecutive threads, consecutive columns)
+    b -= 2 * nxb;
+    const bool bottom = b < nyb;
+    const int i = (bottom ? b : b - nyb) * kStrip + t;
+    if (i < mx) {
+      const View<T> q = view<T>(a.f_cur, fp);
+      const int f = bottom ? 0 : my;
+      const int oi = pl.ci0 + i / r, oj = bottom ? pl.cj0 - 1 : pl.cj0 + pl.ncy;
+      const int edge = 2 * my + (bottom ? i : mx + i);
+      fine_edge<T, LIM>(a, q, co, k, false, bottom, i, f, i, bottom ? -1 : my, oi, oj, step,
+                        a.acc + 3 * ((int64_t)pl.fedge0 + edge));
     }
   }
 }
@@ -307,7 +364,7 @@ hipError_t coarse_terms_t(int limiter, const CfArgs &a, const void *qc, double d
 template <typename T>
 hipError_t fine_terms_t(int limiter, const CfArgs &a, int step, double dt_fine, int max_items,
                         hipStream_t s) {
-  const dim3 g = cf_grid(max_items, a.n_fine);
+  const dim3 g((unsigned)max(1, max_items), (unsigned)a.n_fine);
   switch (limiter) {
     case WS_LIM_NONE:
       hipLaunchKernelGGL((cf_fine_terms_kernel<T, WS_LIM_NONE>), g, dim3(kThreads), 0, s, a, step, dt_fine);

@@ -794,6 +794,7 @@ struct ws_cf {
   int64_t off_place = 0, off_acc = 0, off_pc = 0;
   int n_fine = 0;
   int max_fedges = 0, max_cedges = 0, max_ring = 0, max_cover = 0;
+  int max_side_blocks = 0;  // blocks of the fine-terms launch per fine patch
 
   CfArgs args() const {
     CfArgs a{};
@@ -912,6 +913,8 @@ int ws_cf_init(ws_cf **out, ws_ctx *coarse, ws_ctx *fine, int32_t ratio,
     cf->max_cedges = std::max(cf->max_cedges, 2 * (pl[k].ncx + pl[k].ncy));
     cf->max_ring = std::max(cf->max_ring, 4 * (d.mx + 4) + 4 * d.my);
     cf->max_cover = std::max(cf->max_cover, pl[k].ncx * pl[k].ncy);
+    cf->max_side_blocks = std::max(cf->max_side_blocks, 2 * ((d.my + kThreads - 1) / kThreads) +
+                                                           2 * ((d.mx + kThreads - 1) / kThreads));
   }
   if (hipMemcpyAsync(cf->ws + cf->off_place, pl.data(), pl.size() * sizeof(CfPlace),
                      hipMemcpyHostToDevice, coarse->stream) != hipSuccess ||
@@ -956,7 +959,7 @@ int ws_cf_step(ws_cf *cf, double dt) {
   for (int k = 0; k < r; ++k) {
     a.f_cur = f->pool[f->cur];
     HIPCHK(launch_cf_ghosts(c->dtype, a, (double)k / r, cf->max_ring, c->stream));
-    HIPCHK(launch_cf_fine_terms(c->dtype, c->limiter, a, k, dtf, cf->max_fedges, c->stream));
+    HIPCHK(launch_cf_fine_terms(c->dtype, c->limiter, a, k, dtf, cf->max_side_blocks, c->stream));
     StepArgs s = f->step_args(f->cur, dtf, 0.0);
     HIPCHK(launch_step(f->dtype, f->limiter, f->vars, s, f->grid, f->stream));
     f->cur = 1 - f->cur;

@@ -143,8 +143,9 @@ hipError_t launch_cf_coarse_terms(int dtype, int limiter, const CfArgs &a, const
                                   double dt, int max_items, hipStream_t s);
 hipError_t launch_cf_ghosts(int dtype, const CfArgs &a, double alpha, int max_items,
                             hipStream_t s);
+// max_blocks: the largest 2 ceil(my/256) + 2 ceil(mx/256) over the fine patches.
 hipError_t launch_cf_fine_terms(int dtype, int limiter, const CfArgs &a, int step, double dt_fine,
-                                int max_items, hipStream_t s);
+                                int max_blocks, hipStream_t s);
 hipError_t launch_cf_average_fix(int dtype, const CfArgs &a, double dt, int max_cover,
                                  int max_cedges, hipStream_t s);
 

@@ -1066,13 +1066,22 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void fill_ghosts_kernel(const PatchRow *patches, T *q) {
   const PatchRow pr = patches[blockIdx.y];
   if (pr.bc == WS_BC_NONE) return;
-  const int wx = pr.mx + 4, wy = pr.my + 4;
+  const int wx = pr.mx + 4;
   const int64_t org = pr.q_off + 2 * (int64_t)pr.ld + pr.col0;
   T *base = q + org;
-  for (int idx = blockIdx.x * kThreads + threadIdx.x; idx < wx * wy;
-       idx += gridDim.x * kThreads) {
-    const int i = idx % wx - 2, j = idx / wx - 2;
-    if (i >= 0 && i < pr.mx && j >= 0 && j < pr.my) continue;
+  // the ghost ring only: rows -2, -1, my, my+1 across the padded width, then
+  // columns -2, -1, mx, mx+1 of the interior rows
+  const int ring = 4 * wx + 4 * pr.my;
+  for (int g = blockIdx.x * kThreads + threadIdx.x; g < ring; g += gridDim.x * kThreads) {
+    int i, j;
+    if (g < 2 * wx) {
+      j = g / wx - 2, i = g % wx - 2;
+    } else if (g < 4 * wx) {
+      j = pr.my + (g - 2 * wx) / wx, i = (g - 2 * wx) % wx - 2;
+    } else {
+      const int h = g - 4 * wx, c = h % 4;
+      j = h / 4, i = c < 2 ? c - 2 : pr.mx + c - 2;
+    }
     int si, sj;
     if (pr.bc == WS_BC_PERIODIC) {
       si = (i + pr.mx) % pr.mx;

@@ -174,3 +174,70 @@ def test_invalid_layouts_are_refused(ws):
         ws.TwoLevel(coarse, tc, 2, [(0, 5, 5)])  # limiters differ
     tc.close()
     coarse.close()
+
+
+def _full_layout(ws, bc):
+    import workloads
+    n, r = 1024, 4
+    rects = workloads.two_level_layout(n)
+    dx = 1.0 / n
+    qc = workloads.padded_state(n, n, 0.0, 0.0, dx, dx)
+    O.fill_bc(qc, bc)
+    fq = [workloads.padded_state(r * w, r * h, ci0 * dx, cj0 * dx, dx / r, dx / r)
+          for (ci0, cj0, w, h) in rects]
+    coarse = ws.Level([dict(mx=n, my=n, dx=dx, dy=dx, bc=bc)], [(RHO, KB)])
+    fine = ws.Level([dict(mx=r * w, my=r * h, dx=dx / r, dy=dx / r) for (_, _, w, h) in rects],
+                    [(RHO, KB)], stream=coarse.stream)
+    coarse.upload(0, qc)
+    for k, q in enumerate(fq):
+        fine.upload(k, q)
+    tl = ws.TwoLevel(coarse, fine, r, [(0, ci0, cj0) for (ci0, cj0, _, _) in rects])
+    return n, r, rects, qc, fq, coarse, fine, tl
+
+
+def test_full_size_layout_sampled_against_oracle(ws):
+    """The benchmark's layout (1024^2 coarse, 320 ratio-4 fine patches of
+    128^2): one composite step on the GPU; the oracle steps the same coarse
+    state with three of the fine patches.  Fine patches are 3 coarse cells
+    apart, so within one step a patch and the coarse cells it covers or
+    borders depend on no other patch: those cells, the three fine states and
+    every coarse cell at least 3 cells from all patches must agree."""
+    n, r, rects, qc, fq, coarse, fine, tl = _full_layout(ws, "extrap")
+    dt = 0.9 / n / C0
+    tl.step(dt)
+    got_c = coarse.download(0)
+    picks = [0, len(rects) // 2, len(rects) - 1]
+    fines = [oamr.FinePatch(*rects[k], fq[k]) for k in picks]
+    ref_c, ref_f = oamr.two_level_step(qc, fines, 1 / n, 1 / n, dt, RHO, KB, r, bc="extrap")
+    scale = np.abs(ref_c).reshape(3, -1).max(axis=1)
+    for k, f in zip(picks, ref_f):
+        ci0, cj0, w, h = rects[k]
+        blk = (slice(None), slice(2 + cj0 - 1, 2 + cj0 + h + 1), slice(2 + ci0 - 1, 2 + ci0 + w + 1))
+        err = (np.abs(got_c[blk] - ref_c[blk]).reshape(3, -1).max(axis=1)) / scale
+        assert err.max() <= FP64_TOL, (k, err)
+        e = rel_linf(fine.download(k)[:, 2:-2, 2:-2], f.q[:, 2:-2, 2:-2])
+        assert e.max() <= FP64_TOL, (k, e)
+    far = np.ones((n, n), bool)
+    for (ci0, cj0, w, h) in rects:
+        far[max(cj0 - 3, 0):cj0 + h + 3, max(ci0 - 3, 0):ci0 + w + 3] = False
+    d = np.abs(got_c[:, 2:-2, 2:-2] - ref_c[:, 2:-2, 2:-2])[:, far]
+    assert (d.max(axis=1) / scale).max() <= FP64_TOL
+    for lev in (tl, fine, coarse):
+        lev.close()
+
+
+def test_full_size_layout_conserves_periodic(ws):
+    """The benchmark's layout with a periodic coarse patch: the covered coarse
+    cells start as point values, not fine means, so the totals are compared
+    from the end of the first composite step on, over 8 more steps."""
+    n, r, rects, qc, fq, coarse, fine, tl = _full_layout(ws, "periodic")
+    tl.step(0.9 / n / C0)
+    s1 = coarse.conservation_sums()[0]
+    for _ in range(8):
+        tl.step(0.9 / n / C0)
+    s2 = coarse.conservation_sums()[0]
+    scale = np.abs(s1).max()
+    print(f"full-size two-level conservation drift {(s2 - s1) / scale}")
+    assert np.all(np.abs(s2 - s1) <= 1e-13 * scale), (s1, s2)
+    for lev in (tl, fine, coarse):
+        lev.close()

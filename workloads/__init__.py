@@ -18,5 +18,6 @@ from .generators import (  # noqa: F401
     padded_state,
     plane_wave_state,
     radial_pulse,
+    two_level_layout,
     uniform_patch,
 )

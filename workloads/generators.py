@@ -9,7 +9,9 @@ synthetic stand-ins for the paper's AMR run:
 * ``uniform_patch(2048)`` -- one 2048x2048 grid, 500 steps at CFL 0.9;
 * ``amr_level_batch()``   -- ~3000 patches on 3 levels (ratio 4) over the ring;
 * ``ensemble()``          -- 64 independent problems of uneven sizes;
-* ``adjoint_setup()``     -- 512x512, fixed dt, 16 receivers, shifted target.
+* ``adjoint_setup()``     -- 512x512, fixed dt, 16 receivers, shifted target;
+* ``two_level_layout()``  -- a 1024x1024 coarse grid and ratio-4 fine patches
+  over the ring's annulus, for the composite step with the conservation fix.
 
 A patch state is a C-contiguous float64 array (3, my+4, mx+4): components
 (p, u, v), two ghost layers on each side, x fastest.
@@ -239,3 +241,20 @@ def adjoint_setup(seed=18085, n=512, steps=200, courant=0.8, c=2.0, n_receivers=
     dt = courant * (1.0 / n) / c
     return AdjointSetup(n, steps, dt, rec, (0.5 + float(off[0]), 0.5 + float(off[1])),
                         checkpoint_every)
+
+
+def two_level_layout(n=1024, size=32, gap=3, r_lo=0.15, r_hi=0.35):
+    """Fine patches of size x size coarse cells on a pitch of size + gap over
+    the n x n coarse grid of the unit square, kept where any of the patch's
+    coarse-cell centres lies in the annulus r_lo <= r <= r_hi around the
+    ring's centre (0.5, 0.5).  Returns a list of (ci0, cj0, ncx, ncy)."""
+    pitch = size + gap
+    rects = []
+    for cj0 in range(2, n - size - 1, pitch):
+        for ci0 in range(2, n - size - 1, pitch):
+            xs = (ci0 + np.arange(size) + 0.5) / n - 0.5
+            ys = (cj0 + np.arange(size) + 0.5) / n - 0.5
+            rr = np.hypot(xs[None, :], ys[:, None])
+            if np.any((rr >= r_lo) & (rr <= r_hi)):
+                rects.append((ci0, cj0, size, size))
+    return rects
