@@ -2,23 +2,27 @@
 // it: the pieces of one composite coarse step that are not the level step
 // itself (paper Sec. 2.2 flow chart; Sec. 2.3 updating and conservation fix).
 //
-//   cf_coarse_terms: before the coarse step, the coarse terms at every
-//     coarse-fine interface edge from Q_c^n, P_c = A-dQ + F~ (fine patch on
-//     the edge's right) or -A+dQ + F~ (fine patch on its left), y alike;
-//   cf_ghosts: the fine ghosts at t_n + alpha dt from the coarse level, linear
-//     in time between Q_c^n and Q_c^{n+1} and MC-limited linear in space
-//     inside the coarse cell that holds the ghost;
-//   cf_fine_terms: before fine step k, the fine terms at the patch's boundary
-//     edges, accumulated over the r fine steps: f(ghost) - f(Q_O^n) (the
-//     Riemann fluctuation sum between the coarse cell O outside the edge and
-//     the fine ghost next to it, C1) plus A-dQ^ + F~^ (left side) or
-//     -A+dQ^ + F~^ (right side), y alike;
-//   cf_average: each covered coarse cell takes the mean of its r x r fine
-//     cells (updating);
-//   cf_fix: each coarse cell O next to a fine patch replaces the coarse flux
-//     through their shared edge by the mean of the fine fluxes:
-//     O -= dt/dx ((1/r^2) sum acc - P_c) when the patch is on O's right,
-//     O += dt/dx ((1/r^2) sum acc - P_c) when it is on O's left (y alike).
+//   cf_fine_step (before fine step k, after the coarse step):
+//     - the fine ghosts at t_n + k dt/r from the coarse level, linear in time
+//       between Q_c^n and Q_c^{n+1} and MC-limited linear in space inside the
+//       coarse cell that holds the ghost;
+//     - the fine terms at the patch's boundary edges, accumulated over the r
+//       fine steps: f(ghost) - f(Q_O^n) (the Riemann fluctuation sum between
+//       the coarse cell O outside the edge and the fine ghost next to it, C1)
+//       plus A-dQ^ + F~^ (left side) or -A+dQ^ + F~^ (right side), y alike;
+//     - for k = 0, the coarse terms at every coarse-fine interface edge from
+//       Q_c^n (still in the coarse pool the step read), P_c = A-dQ + F~ (fine
+//       patch on the edge's right) or -A+dQ + F~ (fine patch on its left);
+//   cf_finish (after the fine steps):
+//     - updating: each covered coarse cell takes the mean of its r x r fine
+//       cells;
+//     - the fix: each coarse cell O next to a fine patch replaces the coarse
+//       flux through their shared edge by the mean of the fine fluxes,
+//       O -= dt/dx ((1/r^2) sum acc - P_c) when the patch is on O's right,
+//       O += dt/dx ((1/r^2) sum acc - P_c) when it is on O's left (y alike).
+// A composite step is thus the coarse step, r pairs (cf_fine_step, fine
+// step), cf_finish and the coarse ghost ring: few launches, as every small
+// launch carries a fixed cost of a few microseconds.
 // Edge terms use the closed forms of the level step (A-dQ = (c/2 a1,
 // -c/(2Z) a1, 0), A+dQ = (c/2 a2, c/(2Z) a2, 0) with the unscaled strengths
 // a1 = Z du - dp, a2 = Z du + dp; F~ and G~ as the step forms them).
@@ -104,34 +108,22 @@ __device__ inline void side_of(int e, int mx, int my, int &side, int &idx) {
   else { side = 3; idx = e - 2 * my - mx; }
 }
 
+// Coarse terms of interface edge e of one fine patch (numbered left, right
+// over ncy, bottom, top over ncx) from the coarse state before the coarse
+// step.
 template <typename T, int LIM>
-__global__ __launch_bounds__(kThreads) void cf_coarse_terms_kernel(CfArgs a, const void *qc,
-                                                                   double dt) {
-  const CfPlace pl = a.place[blockIdx.y];
-  const PatchRow cp = a.cpatch[pl.coarse];
-  const InstRow in = a.cinst[cp.inst];
-  const Coef<T> k = make_coef<T>(in.c, in.Z, dt, cp.dx, cp.dy);
-  const View<T> q = view<T>(qc, cp);
-  const int n = 2 * (pl.ncx + pl.ncy);
-  for (int e = blockIdx.x * kThreads + threadIdx.x; e < n; e += gridDim.x * kThreads) {
-    int side, idx;
-    side_of(e, pl.ncx, pl.ncy, side, idx);
-    T m[3], pp[3], F[3];
-    double out[3];
-    if (side < 2) {
-      const int edge = side == 0 ? pl.ci0 : pl.ci0 + pl.ncx;
-      xedge_terms<T, LIM>(q, k, edge, pl.cj0 + idx, m, pp, F);
-      for (int c = 0; c < 3; ++c)
-        out[c] = side == 0 ? (double)m[c] + (double)F[c] : -(double)pp[c] + (double)F[c];
-    } else {
-      const int edge = side == 2 ? pl.cj0 : pl.cj0 + pl.ncy;
-      yedge_terms<T, LIM>(q, k, pl.ci0 + idx, edge, m, pp, F);
-      for (int c = 0; c < 3; ++c)
-        out[c] = side == 2 ? (double)m[c] + (double)F[c] : -(double)pp[c] + (double)F[c];
-    }
-    double *o = a.pc + 3 * ((int64_t)pl.cedge0 + e);
-    o[0] = out[0], o[1] = out[1], o[2] = out[2];
-  }
+__device__ inline void coarse_edge(const CfArgs &a, const CfPlace &pl, const View<T> &q,
+                                   const Coef<T> &k, int e) {
+  int side, idx;
+  side_of(e, pl.ncx, pl.ncy, side, idx);
+  T m[3], pp[3], F[3];
+  if (side < 2)
+    xedge_terms<T, LIM>(q, k, side == 0 ? pl.ci0 : pl.ci0 + pl.ncx, pl.cj0 + idx, m, pp, F);
+  else
+    yedge_terms<T, LIM>(q, k, pl.ci0 + idx, side == 2 ? pl.cj0 : pl.cj0 + pl.ncy, m, pp, F);
+  const bool low = side == 0 || side == 2;  // the fine patch is on the edge's right (upper) side
+  double *o = a.pc + 3 * ((int64_t)pl.cedge0 + e);
+  for (int c = 0; c < 3; ++c) o[c] = (low ? (double)m[c] : -(double)pp[c]) + (double)F[c];
 }
 
 // MC-limited slope from the one-sided differences.
@@ -142,15 +134,61 @@ __device__ inline T mc_slope(T l, T r) {
   return s * fmin(fmin(T(2) * fabs(l), T(2) * fabs(r)), T(0.5) * fabs(l + r));
 }
 
+// Fine ghost values from the coarse level at t_n + alpha dt: linear in time
+// between the two coarse states, then MC-limited linear in space inside the
+// coarse cell holding the ghost.  Every caller evaluates a ghost with this
+// one expression, so a ghost computed twice has the same bits.
+template <typename T>
+struct GhostSrc {
+  View<T> qo, qn;
+  T al, bl;
+  int ci0, cj0, r;
+  __device__ T q(int m, int ci, int cj) const {
+    const T vo = m == 0 ? qo.P(ci, cj) : m == 1 ? qo.U(ci, cj) : qo.V(ci, cj);
+    const T vn = m == 0 ? qn.P(ci, cj) : m == 1 ? qn.U(ci, cj) : qn.V(ci, cj);
+    return bl * vo + al * vn;
+  }
+  // All three components of fine cell (i, j): the cell's coarse position is
+  // worked out once and the 30 coarse loads are issued together.
+  __device__ void value3(int i, int j, T out[3]) const {
+    const double X = ci0 + (i + 0.5) / r, Y = cj0 + (j + 0.5) / r;
+    const int ci = (int)floor(X), cj = (int)floor(Y);
+    const T xi = (T)(X - (ci + 0.5)), eta = (T)(Y - (cj + 0.5));
+    T c[3][5];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      c[m][0] = q(m, ci, cj);
+      c[m][1] = q(m, ci - 1, cj);
+      c[m][2] = q(m, ci + 1, cj);
+      c[m][3] = q(m, ci, cj - 1);
+      c[m][4] = q(m, ci, cj + 1);
+    }
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const T q0 = c[m][0];
+      const T sx = mc_slope(q0 - c[m][1], c[m][2] - q0);
+      const T sy = mc_slope(q0 - c[m][3], c[m][4] - q0);
+      out[m] = q0 + xi * sx + eta * sy;
+    }
+  }
+};
+
+template <typename T>
+__device__ inline GhostSrc<T> ghost_src(const CfArgs &a, const CfPlace &pl, const PatchRow &cp,
+                                        double alpha) {
+  return GhostSrc<T>{view<T>(a.c_old, cp), view<T>(a.c_new, cp), (T)alpha, (T)(1.0 - alpha),
+                     pl.ci0, pl.cj0, a.r};
+}
+
+// The whole ghost ring of each fine patch (used alone by ws_cf_fill_fine_ghosts).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void cf_ghosts_kernel(CfArgs a, double alpha) {
   const CfPlace pl = a.place[blockIdx.y];
   const PatchRow fp = a.fpatch[blockIdx.y];
   const PatchRow cp = a.cpatch[pl.coarse];
-  const View<T> qo = view<T>(a.c_old, cp), qn = view<T>(a.c_new, cp);
-  const int mx = fp.mx, my = fp.my, r = a.r;
+  const GhostSrc<T> G = ghost_src<T>(a, pl, cp, alpha);
+  const int mx = fp.mx, my = fp.my;
   const int ring = 4 * (mx + 4) + 4 * my;
-  const T al = (T)alpha, bl = (T)(1.0 - alpha);
   for (int g = blockIdx.x * kThreads + threadIdx.x; g < ring; g += gridDim.x * kThreads) {
     int i, j;
     if (g < 2 * (mx + 4)) {  // rows -2, -1
@@ -164,32 +202,21 @@ __global__ __launch_bounds__(kThreads) void cf_ghosts_kernel(CfArgs a, double al
       const int c = h % 4;
       i = c < 2 ? c - 2 : mx + c - 2;
     }
-    // fine centre in coarse index units, its coarse cell and offset
-    const double X = pl.ci0 + (i + 0.5) / r, Y = pl.cj0 + (j + 0.5) / r;
-    const int ci = (int)floor(X), cj = (int)floor(Y);
-    const T xi = (T)(X - (ci + 0.5)), eta = (T)(Y - (cj + 0.5));
-    for (int m = 0; m < 3; ++m) {
-      auto at = [&](int di, int dj) {
-        const View<T> &o = qo;
-        const T vo = m == 0 ? o.P(ci + di, cj + dj) : m == 1 ? o.U(ci + di, cj + dj) : o.V(ci + di, cj + dj);
-        const T vn = m == 0 ? qn.P(ci + di, cj + dj) : m == 1 ? qn.U(ci + di, cj + dj) : qn.V(ci + di, cj + dj);
-        return bl * vo + al * vn;
-      };
-      const T q0 = at(0, 0);
-      const T sx = mc_slope(q0 - at(-1, 0), at(1, 0) - q0);
-      const T sy = mc_slope(q0 - at(0, -1), at(0, 1) - q0);
-      *cell_ptr<T>(a.f_cur, fp, m, i, j) = q0 + xi * sx + eta * sy;
-    }
+    T v[3];
+    G.value3(i, j, v);
+    for (int m = 0; m < 3; ++m) *cell_ptr<T>(a.f_cur, fp, m, i, j) = v[m];
   }
 }
 
-// Columns e-2 .. e+1 of rows j0-1 .. j0+kStrip of one patch, staged in LDS
-// for the edges of a left or right side (a column of edges: their cells are
-// strided in memory, so the block reads the strip row by row instead).
+// A strip of a fine patch staged in LDS for the edges of one side: for a
+// left or right side the columns e-2 .. e+1 of rows j0-1 .. j0+kStrip (the
+// cells of a column of edges are strided in memory); for a bottom or top side
+// the rows f-2 .. f+1 of columns i0-1 .. i0+kStrip.  Ghost cells are
+// evaluated from the coarse level, interior cells read from the fine state.
 constexpr int kStrip = kThreads;  // edges per block
 template <typename T>
-struct Strip {
-  const T *s;  // [3][kStrip + 2][4]
+struct StripX {
+  const T *s;  // [3][kStrip + 2][4]: row-major in (row, column)
   int e, j0;
   __device__ T at(int m, int i, int j) const {
     return s[(m * (kStrip + 2) + (j - j0 + 1)) * 4 + (i - e + 2)];
@@ -198,19 +225,24 @@ struct Strip {
   __device__ T U(int i, int j) const { return at(1, i, j); }
   __device__ T V(int i, int j) const { return at(2, i, j); }
 };
-
-// Blocks of one fine patch: ceil(my/kStrip) for each of the left and right
-// sides, then ceil(mx/kStrip) for each of the bottom and top sides.
-__device__ inline int cf_side_blocks(int mx, int my) {
-  return 2 * ((my + kStrip - 1) / kStrip) + 2 * ((mx + kStrip - 1) / kStrip);
-}
+template <typename T>
+struct StripY {
+  const T *s;  // [3][kStrip + 2][4]: column-major in (column, row)
+  int i0, f;
+  __device__ T at(int m, int i, int j) const {
+    return s[(m * (kStrip + 2) + (i - i0 + 1)) * 4 + (j - f + 2)];
+  }
+  __device__ T P(int i, int j) const { return at(0, i, j); }
+  __device__ T U(int i, int j) const { return at(1, i, j); }
+  __device__ T V(int i, int j) const { return at(2, i, j); }
+};
 
 // Fine terms of one boundary edge (ghost (gi, gj), coarse cell (oi, oj)
 // outside it) added to its accumulator slot.
 template <typename T, int LIM, class Q>
-__device__ inline void fine_edge(const CfArgs &a, const Q &q, const View<T> &co,
-                                 const Coef<T> &k, bool xdir, bool low, int e_or_i, int j_or_f,
-                                 int gi, int gj, int oi, int oj, int step, double *o) {
+__device__ inline void fine_edge(const Q &q, const View<T> &co, const Coef<T> &k, bool xdir,
+                                 bool low, int e_or_i, int j_or_f, int gi, int gj, int oi, int oj,
+                                 int step, double *o) {
   T m[3], pp[3], F[3];
   if (xdir)
     xedge_terms<T, LIM>(q, k, e_or_i, j_or_f, m, pp, F);
@@ -236,107 +268,172 @@ __device__ inline void fine_edge(const CfArgs &a, const Q &q, const View<T> &co,
   }
 }
 
+// Blocks per fine patch of the fine-step kernel: ceil(my/kStrip) for each of
+// the left and right sides, ceil(mx/kStrip) for each of the bottom and top
+// sides, and (first fine step only) ceil(2 (ncx + ncy)/kThreads) for the
+// coarse interface edges.
+__host__ __device__ inline int cf_step_blocks(int mx, int my, int ncx, int ncy, bool coarse) {
+  return 2 * ((my + kStrip - 1) / kStrip) + 2 * ((mx + kStrip - 1) / kStrip) +
+         (coarse ? (2 * (ncx + ncy) + kThreads - 1) / kThreads : 0);
+}
+
+// Before fine step k: the fine ghost ring at t_n + k dt/r (each block writes
+// the ghosts of its side's range), the fine terms at every boundary edge, and
+// for k = 0 the coarse interface terms from the coarse state at t_n.
 template <typename T, int LIM>
-__global__ __launch_bounds__(kThreads) void cf_fine_terms_kernel(CfArgs a, int step,
-                                                                 double dt_fine) {
+__global__ __launch_bounds__(kThreads) void cf_fine_step_kernel(CfArgs a, int step,
+                                                                double dt_fine, double dt) {
   __shared__ T strip[3 * (kStrip + 2) * 4];
   const CfPlace pl = a.place[blockIdx.y];
   const PatchRow fp = a.fpatch[blockIdx.y];
   const int mx = fp.mx, my = fp.my, r = a.r;
-  int b = blockIdx.x;
   const int nxb = (my + kStrip - 1) / kStrip, nyb = (mx + kStrip - 1) / kStrip;
-  if (b >= 2 * nxb + 2 * nyb) return;
+  int b = blockIdx.x;
+  if (b >= cf_step_blocks(mx, my, pl.ncx, pl.ncy, step == 0)) return;
   const PatchRow cp = a.cpatch[pl.coarse];
-  const InstRow in = a.finst[fp.inst];
-  const Coef<T> k = make_coef<T>(in.c, in.Z, dt_fine, fp.dx, fp.dy);
   const View<T> co = view<T>(a.c_old, cp);
   const int t = threadIdx.x;
+  if (b >= 2 * nxb + 2 * nyb) {
+    // coarse interface edges, from the coarse state before its step
+    const InstRow ic = a.cinst[cp.inst];
+    const Coef<T> kc = make_coef<T>(ic.c, ic.Z, dt, cp.dx, cp.dy);
+    const int e = (b - 2 * nxb - 2 * nyb) * kThreads + t;
+    if (e < 2 * (pl.ncx + pl.ncy)) coarse_edge<T, LIM>(a, pl, co, kc, e);
+    return;
+  }
+  const InstRow in = a.finst[fp.inst];
+  const Coef<T> k = make_coef<T>(in.c, in.Z, dt_fine, fp.dx, fp.dy);
+  const View<T> q = view<T>(a.f_cur, fp);
+  const GhostSrc<T> G = ghost_src<T>(a, pl, cp, (double)step / r);
+  // all three components of fine cell (i, j): a ghost from the coarse level,
+  // an interior cell from the fine state
+  auto fine3 = [&](int i, int j, T v[3]) {
+    if (i < 0 || i >= mx || j < 0 || j >= my) {
+      G.value3(i, j, v);
+    } else {
+      v[0] = q.P(i, j), v[1] = q.U(i, j), v[2] = q.V(i, j);
+    }
+  };
   if (b < 2 * nxb) {
     // left (e = 0) or right (e = mx) side, rows j0 .. j1-1
     const bool left = b < nxb;
     const int j0 = (left ? b : b - nxb) * kStrip, j1 = min(j0 + kStrip, my);
     const int e = left ? 0 : mx;
-    const View<T> q = view<T>(a.f_cur, fp);
+    // the ghosts this block owns: the side's two ghost columns of its rows
+    for (int x = t; x < 2 * (j1 - j0); x += kThreads) {
+      const int j = j0 + x / 2, i = left ? x % 2 - 2 : mx + x % 2;
+      T v[3];
+      G.value3(i, j, v);
+      for (int m = 0; m < 3; ++m) *cell_ptr<T>(a.f_cur, fp, m, i, j) = v[m];
+    }
     const int rows = j1 - j0 + 2;  // j0-1 .. j1
-    for (int x = t; x < 3 * rows * 4; x += kThreads) {
-      const int m = x / (rows * 4), rem = x % (rows * 4);
-      const int j = j0 - 1 + rem / 4, i = e - 2 + rem % 4;
-      const T v = m == 0 ? q.P(i, j) : m == 1 ? q.U(i, j) : q.V(i, j);
-      strip[(m * (kStrip + 2) + (j - j0 + 1)) * 4 + (i - e + 2)] = v;
+    for (int x = t; x < rows * 4; x += kThreads) {
+      const int j = j0 - 1 + x / 4, i = e - 2 + x % 4;
+      T v[3];
+      fine3(i, j, v);
+      for (int m = 0; m < 3; ++m) strip[(m * (kStrip + 2) + (j - j0 + 1)) * 4 + (i - e + 2)] = v[m];
     }
     __syncthreads();
     const int j = j0 + t;
     if (j < j1) {
-      const Strip<T> S{strip, e, j0};
+      const StripX<T> S{strip, e, j0};
       const int oi = left ? pl.ci0 - 1 : pl.ci0 + pl.ncx, oj = pl.cj0 + j / r;
-      const int edge = left ? j : my + j;
-      fine_edge<T, LIM>(a, S, co, k, true, left, e, j, left ? -1 : mx, j, oi, oj, step,
-                        a.acc + 3 * ((int64_t)pl.fedge0 + edge));
+      fine_edge<T, LIM>(S, co, k, true, left, e, j, left ? -1 : mx, j, oi, oj, step,
+                        a.acc + 3 * ((int64_t)pl.fedge0 + (left ? j : my + j)));
     }
   } else {
-    // bottom (f = 0) or top (f = my) side, columns i0 .. i1-1: rows of
-    // cells, read directly (consecutive threads, consecutive columns)
+    // bottom (f = 0) or top (f = my) side, columns i0 .. i1-1
     b -= 2 * nxb;
     const bool bottom = b < nyb;
-    const int i = (bottom ? b : b - nyb) * kStrip + t;
-    if (i < mx) {
-      const View<T> q = view<T>(a.f_cur, fp);
-      const int f = bottom ? 0 : my;
+    const int c = bottom ? b : b - nyb;
+    const int i0 = c * kStrip, i1 = min(i0 + kStrip, mx);
+    const int f = bottom ? 0 : my;
+    // the ghosts this block owns: the side's two ghost rows over its columns,
+    // and the corner columns for the first and last block of the side
+    const int lo = c == 0 ? -2 : i0, hi = i1 == mx ? mx + 2 : i1;
+    for (int x = t; x < 2 * (hi - lo); x += kThreads) {
+      const int i = lo + x % (hi - lo), j = bottom ? x / (hi - lo) - 2 : my + x / (hi - lo);
+      T v[3];
+      G.value3(i, j, v);
+      for (int m = 0; m < 3; ++m) *cell_ptr<T>(a.f_cur, fp, m, i, j) = v[m];
+    }
+    const int cols = i1 - i0 + 2;  // i0-1 .. i1
+    for (int x = t; x < cols * 4; x += kThreads) {
+      const int j = f - 2 + x / cols, i = i0 - 1 + x % cols;  // consecutive columns
+      T v[3];
+      fine3(i, j, v);
+      for (int m = 0; m < 3; ++m) strip[(m * (kStrip + 2) + (i - i0 + 1)) * 4 + (j - f + 2)] = v[m];
+    }
+    __syncthreads();
+    const int i = i0 + t;
+    if (i < i1) {
+      const StripY<T> S{strip, i0, f};
       const int oi = pl.ci0 + i / r, oj = bottom ? pl.cj0 - 1 : pl.cj0 + pl.ncy;
-      const int edge = 2 * my + (bottom ? i : mx + i);
-      fine_edge<T, LIM>(a, q, co, k, false, bottom, i, f, i, bottom ? -1 : my, oi, oj, step,
-                        a.acc + 3 * ((int64_t)pl.fedge0 + edge));
+      fine_edge<T, LIM>(S, co, k, false, bottom, i, f, i, bottom ? -1 : my, oi, oj, step,
+                        a.acc + 3 * ((int64_t)pl.fedge0 + 2 * my + (bottom ? i : mx + i)));
     }
   }
 }
 
+// After the fine steps: updating (each covered coarse cell takes the mean of
+// its r x r fine cells) and the conservation fix of the coarse cells around
+// the patch (disjoint cells, one launch).
+__host__ __device__ inline int cf_finish_blocks(int ncx, int ncy) {
+  return (ncx * ncy + kThreads - 1) / kThreads + (2 * (ncx + ncy) + kThreads - 1) / kThreads;
+}
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void cf_average_kernel(CfArgs a) {
+__global__ __launch_bounds__(kThreads) void cf_finish_kernel(CfArgs a, double dt) {
   const CfPlace pl = a.place[blockIdx.y];
-  const PatchRow fp = a.fpatch[blockIdx.y];
+  const int b = blockIdx.x, na = (pl.ncx * pl.ncy + kThreads - 1) / kThreads;
+  if (b >= cf_finish_blocks(pl.ncx, pl.ncy)) return;
   const PatchRow cp = a.cpatch[pl.coarse];
-  const int r = a.r, n = pl.ncx * pl.ncy;
-  const View<T> f = view<T>(a.f_cur, fp);
-  for (int c = blockIdx.x * kThreads + threadIdx.x; c < n; c += gridDim.x * kThreads) {
-    const int I = c % pl.ncx, J = c / pl.ncx;
+  const int r = a.r;
+  if (b < na) {
+    const PatchRow fp = a.fpatch[blockIdx.y];
+    const View<T> f = view<T>(a.f_cur, fp);
+    const int cidx = b * kThreads + threadIdx.x;
+    if (cidx >= pl.ncx * pl.ncy) return;
+    const int I = cidx % pl.ncx, J = cidx / pl.ncx;
+    // row by row, the row's loads issued together (up to 4 cells at a time)
     double s[3] = {0.0, 0.0, 0.0};
-    for (int b = 0; b < r; ++b)
-      for (int aa = 0; aa < r; ++aa) {
-        const int i = I * r + aa, j = J * r + b;
-        s[0] += (double)f.P(i, j);
-        s[1] += (double)f.U(i, j);
-        s[2] += (double)f.V(i, j);
+    for (int bb = 0; bb < r; ++bb) {
+      const int j = J * r + bb;
+      for (int a0 = 0; a0 < r; a0 += 4) {
+        T v[3][4];
+#pragma unroll
+        for (int aa = 0; aa < 4; ++aa) {
+          const int i = I * r + min(a0 + aa, r - 1);
+          v[0][aa] = f.P(i, j), v[1][aa] = f.U(i, j), v[2][aa] = f.V(i, j);
+        }
+        for (int aa = 0; aa < 4 && a0 + aa < r; ++aa)
+          for (int m = 0; m < 3; ++m) s[m] += (double)v[m][aa];
       }
+    }
     for (int m = 0; m < 3; ++m)
       *cell_ptr<T>(a.c_new, cp, m, pl.ci0 + I, pl.cj0 + J) = (T)(s[m] / (double)(r * r));
+    return;
   }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void cf_fix_kernel(CfArgs a, double dt) {
-  const CfPlace pl = a.place[blockIdx.y];
-  const PatchRow cp = a.cpatch[pl.coarse];
-  const int r = a.r, n = 2 * (pl.ncx + pl.ncy);
+  const int e = (b - na) * kThreads + threadIdx.x;
+  if (e >= 2 * (pl.ncx + pl.ncy)) return;
   const int mxf = pl.ncx * r, myf = pl.ncy * r;
   const double w = 1.0 / (double)(r * r);
-  for (int e = blockIdx.x * kThreads + threadIdx.x; e < n; e += gridDim.x * kThreads) {
-    int side, idx;
-    side_of(e, pl.ncx, pl.ncy, side, idx);
-    // the r fine edges on this coarse edge, in the fine edge numbering
-    int f0, oi, oj;
-    double h;
-    if (side == 0) f0 = idx * r, oi = pl.ci0 - 1, oj = pl.cj0 + idx, h = -dt / cp.dx;
-    else if (side == 1) f0 = myf + idx * r, oi = pl.ci0 + pl.ncx, oj = pl.cj0 + idx, h = dt / cp.dx;
-    else if (side == 2) f0 = 2 * myf + idx * r, oi = pl.ci0 + idx, oj = pl.cj0 - 1, h = -dt / cp.dy;
-    else f0 = 2 * myf + mxf + idx * r, oi = pl.ci0 + idx, oj = pl.cj0 + pl.ncy, h = dt / cp.dy;
-    const double *acc = a.acc + 3 * ((int64_t)pl.fedge0 + f0);
-    const double *pc = a.pc + 3 * ((int64_t)pl.cedge0 + e);
-    for (int m = 0; m < 3; ++m) {
-      double s = 0.0;
-      for (int b = 0; b < r; ++b) s += acc[3 * b + m];
-      T *o = cell_ptr<T>(a.c_new, cp, m, oi, oj);
-      *o = (T)((double)*o + h * (w * s - pc[m]));
-    }
+  int side, idx;
+  side_of(e, pl.ncx, pl.ncy, side, idx);
+  // the r fine edges on this coarse edge, in the fine edge numbering
+  int f0, oi, oj;
+  double h;
+  if (side == 0) f0 = idx * r, oi = pl.ci0 - 1, oj = pl.cj0 + idx, h = -dt / cp.dx;
+  else if (side == 1) f0 = myf + idx * r, oi = pl.ci0 + pl.ncx, oj = pl.cj0 + idx, h = dt / cp.dx;
+  else if (side == 2) f0 = 2 * myf + idx * r, oi = pl.ci0 + idx, oj = pl.cj0 - 1, h = -dt / cp.dy;
+  else f0 = 2 * myf + mxf + idx * r, oi = pl.ci0 + idx, oj = pl.cj0 + pl.ncy, h = dt / cp.dy;
+  const double *acc = a.acc + 3 * ((int64_t)pl.fedge0 + f0);
+  const double *pc = a.pc + 3 * ((int64_t)pl.cedge0 + e);
+  for (int m = 0; m < 3; ++m) {
+    double s = 0.0;
+    for (int bb = 0; bb < r; ++bb) s += acc[3 * bb + m];
+    T *o = cell_ptr<T>(a.c_new, cp, m, oi, oj);
+    *o = (T)((double)*o + h * (w * s - pc[m]));
   }
 }
 
@@ -345,46 +442,26 @@ inline dim3 cf_grid(int max_items, int n) {
 }
 
 template <typename T>
-hipError_t coarse_terms_t(int limiter, const CfArgs &a, const void *qc, double dt, int max_items,
-                          hipStream_t s) {
-  const dim3 g = cf_grid(max_items, a.n_fine);
+hipError_t fine_step_t(int limiter, const CfArgs &a, int step, double dt_fine, double dt,
+                       int max_blocks, hipStream_t s) {
+  const dim3 g((unsigned)max(1, max_blocks), (unsigned)a.n_fine);
   switch (limiter) {
     case WS_LIM_NONE:
-      hipLaunchKernelGGL((cf_coarse_terms_kernel<T, WS_LIM_NONE>), g, dim3(kThreads), 0, s, a, qc, dt);
+      hipLaunchKernelGGL((cf_fine_step_kernel<T, WS_LIM_NONE>), g, dim3(kThreads), 0, s, a, step,
+                         dt_fine, dt);
       break;
     case WS_LIM_VANLEER:
-      hipLaunchKernelGGL((cf_coarse_terms_kernel<T, WS_LIM_VANLEER>), g, dim3(kThreads), 0, s, a, qc, dt);
+      hipLaunchKernelGGL((cf_fine_step_kernel<T, WS_LIM_VANLEER>), g, dim3(kThreads), 0, s, a,
+                         step, dt_fine, dt);
       break;
     default:
-      hipLaunchKernelGGL((cf_coarse_terms_kernel<T, WS_LIM_MC>), g, dim3(kThreads), 0, s, a, qc, dt);
-  }
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t fine_terms_t(int limiter, const CfArgs &a, int step, double dt_fine, int max_items,
-                        hipStream_t s) {
-  const dim3 g((unsigned)max(1, max_items), (unsigned)a.n_fine);
-  switch (limiter) {
-    case WS_LIM_NONE:
-      hipLaunchKernelGGL((cf_fine_terms_kernel<T, WS_LIM_NONE>), g, dim3(kThreads), 0, s, a, step, dt_fine);
-      break;
-    case WS_LIM_VANLEER:
-      hipLaunchKernelGGL((cf_fine_terms_kernel<T, WS_LIM_VANLEER>), g, dim3(kThreads), 0, s, a, step, dt_fine);
-      break;
-    default:
-      hipLaunchKernelGGL((cf_fine_terms_kernel<T, WS_LIM_MC>), g, dim3(kThreads), 0, s, a, step, dt_fine);
+      hipLaunchKernelGGL((cf_fine_step_kernel<T, WS_LIM_MC>), g, dim3(kThreads), 0, s, a, step,
+                         dt_fine, dt);
   }
   return hipGetLastError();
 }
 
 }  // namespace
-
-hipError_t launch_cf_coarse_terms(int dtype, int limiter, const CfArgs &a, const void *qc,
-                                  double dt, int max_items, hipStream_t s) {
-  return dtype == WS_F32 ? coarse_terms_t<float>(limiter, a, qc, dt, max_items, s)
-                         : coarse_terms_t<double>(limiter, a, qc, dt, max_items, s);
-}
 
 hipError_t launch_cf_ghosts(int dtype, const CfArgs &a, double alpha, int max_items,
                             hipStream_t s) {
@@ -396,22 +473,25 @@ hipError_t launch_cf_ghosts(int dtype, const CfArgs &a, double alpha, int max_it
   return hipGetLastError();
 }
 
-hipError_t launch_cf_fine_terms(int dtype, int limiter, const CfArgs &a, int step, double dt_fine,
-                                int max_items, hipStream_t s) {
-  return dtype == WS_F32 ? fine_terms_t<float>(limiter, a, step, dt_fine, max_items, s)
-                         : fine_terms_t<double>(limiter, a, step, dt_fine, max_items, s);
+hipError_t launch_cf_fine_step(int dtype, int limiter, const CfArgs &a, int step, double dt_fine,
+                               double dt, int max_blocks, hipStream_t s) {
+  return dtype == WS_F32 ? fine_step_t<float>(limiter, a, step, dt_fine, dt, max_blocks, s)
+                         : fine_step_t<double>(limiter, a, step, dt_fine, dt, max_blocks, s);
 }
 
-hipError_t launch_cf_average_fix(int dtype, const CfArgs &a, double dt, int max_cover,
-                                 int max_cedges, hipStream_t s) {
-  const dim3 ga = cf_grid(max_cover, a.n_fine), gf = cf_grid(max_cedges, a.n_fine);
-  if (dtype == WS_F32) {
-    hipLaunchKernelGGL(cf_average_kernel<float>, ga, dim3(kThreads), 0, s, a);
-    hipLaunchKernelGGL(cf_fix_kernel<float>, gf, dim3(kThreads), 0, s, a, dt);
-  } else {
-    hipLaunchKernelGGL(cf_average_kernel<double>, ga, dim3(kThreads), 0, s, a);
-    hipLaunchKernelGGL(cf_fix_kernel<double>, gf, dim3(kThreads), 0, s, a, dt);
-  }
+int cf_step_blocks_host(int mx, int my, int ncx, int ncy, bool coarse) {
+  return cf_step_blocks(mx, my, ncx, ncy, coarse);
+}
+
+int cf_finish_blocks_host(int ncx, int ncy) { return cf_finish_blocks(ncx, ncy); }
+
+hipError_t launch_cf_finish(int dtype, const CfArgs &a, double dt, int max_blocks,
+                            hipStream_t s) {
+  const dim3 g((unsigned)max(1, max_blocks), (unsigned)a.n_fine);
+  if (dtype == WS_F32)
+    hipLaunchKernelGGL(cf_finish_kernel<float>, g, dim3(kThreads), 0, s, a, dt);
+  else
+    hipLaunchKernelGGL(cf_finish_kernel<double>, g, dim3(kThreads), 0, s, a, dt);
   return hipGetLastError();
 }
 

@@ -793,8 +793,8 @@ struct ws_cf {
   char *ws = nullptr;
   int64_t off_place = 0, off_acc = 0, off_pc = 0;
   int n_fine = 0;
-  int max_fedges = 0, max_cedges = 0, max_ring = 0, max_cover = 0;
-  int max_side_blocks = 0;  // blocks of the fine-terms launch per fine patch
+  int max_ring = 0;
+  int max_step_blocks = 0, max_finish_blocks = 0;  // blocks per fine patch of the two launches
 
   CfArgs args() const {
     CfArgs a{};
@@ -909,12 +909,11 @@ int ws_cf_init(ws_cf **out, ws_ctx *coarse, ws_ctx *fine, int32_t ratio,
   cf->n_fine = fine->n_patches;
   for (int k = 0; k < fine->n_patches; ++k) {
     const ws_patch_desc &d = fine->desc[k];
-    cf->max_fedges = std::max(cf->max_fedges, 2 * (d.mx + d.my));
-    cf->max_cedges = std::max(cf->max_cedges, 2 * (pl[k].ncx + pl[k].ncy));
     cf->max_ring = std::max(cf->max_ring, 4 * (d.mx + 4) + 4 * d.my);
-    cf->max_cover = std::max(cf->max_cover, pl[k].ncx * pl[k].ncy);
-    cf->max_side_blocks = std::max(cf->max_side_blocks, 2 * ((d.my + kThreads - 1) / kThreads) +
-                                                           2 * ((d.mx + kThreads - 1) / kThreads));
+    cf->max_step_blocks =
+        std::max(cf->max_step_blocks, cf_step_blocks_host(d.mx, d.my, pl[k].ncx, pl[k].ncy, true));
+    cf->max_finish_blocks =
+        std::max(cf->max_finish_blocks, cf_finish_blocks_host(pl[k].ncx, pl[k].ncy));
   }
   if (hipMemcpyAsync(cf->ws + cf->off_place, pl.data(), pl.size() * sizeof(CfPlace),
                      hipMemcpyHostToDevice, coarse->stream) != hipSuccess ||
@@ -945,9 +944,7 @@ int ws_cf_step(ws_cf *cf, double dt) {
   const int r = cf->r;
   const double dtf = dt / r;
   CfArgs a = cf->args();
-  // coarse terms at the interfaces from Q_c^n, then the coarse step
-  HIPCHK(launch_cf_coarse_terms(c->dtype, c->limiter, a, c->pool[c->cur], dt, cf->max_cedges,
-                                c->stream));
+  // the coarse step; Q_c^n stays in the pool it read
   {
     StepArgs s = c->step_args(c->cur, dt, 0.0);
     HIPCHK(launch_step(c->dtype, c->limiter, c->vars, s, c->grid, c->stream));
@@ -955,18 +952,19 @@ int ws_cf_step(ws_cf *cf, double dt) {
   }
   a.c_old = c->pool[1 - c->cur];
   a.c_new = c->pool[c->cur];
-  // r fine steps, each after its ghost fill and boundary terms
+  // r fine steps, each after its ghost ring and boundary terms (the first
+  // launch also takes the coarse interface terms from Q_c^n)
   for (int k = 0; k < r; ++k) {
     a.f_cur = f->pool[f->cur];
-    HIPCHK(launch_cf_ghosts(c->dtype, a, (double)k / r, cf->max_ring, c->stream));
-    HIPCHK(launch_cf_fine_terms(c->dtype, c->limiter, a, k, dtf, cf->max_side_blocks, c->stream));
+    HIPCHK(launch_cf_fine_step(c->dtype, c->limiter, a, k, dtf, dt, cf->max_step_blocks,
+                               c->stream));
     StepArgs s = f->step_args(f->cur, dtf, 0.0);
     HIPCHK(launch_step(f->dtype, f->limiter, f->vars, s, f->grid, f->stream));
     f->cur = 1 - f->cur;
   }
   // updating and the conservation fix, then the coarse physical ghosts
   a.f_cur = f->pool[f->cur];
-  HIPCHK(launch_cf_average_fix(c->dtype, a, dt, cf->max_cover, cf->max_cedges, c->stream));
+  HIPCHK(launch_cf_finish(c->dtype, a, dt, cf->max_finish_blocks, c->stream));
   HIPCHK(launch_fill_ghosts(c->dtype, c->d_patches(), c->n_patches, c->max_padded_cells,
                             c->pool[c->cur], c->stream));
   return WS_OK;

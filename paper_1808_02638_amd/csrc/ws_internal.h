@@ -139,14 +139,15 @@ struct CfArgs {
   double *pc;         // [coarse interface edges][3] coarse terms
 };
 
-hipError_t launch_cf_coarse_terms(int dtype, int limiter, const CfArgs &a, const void *qc,
-                                  double dt, int max_items, hipStream_t s);
 hipError_t launch_cf_ghosts(int dtype, const CfArgs &a, double alpha, int max_items,
                             hipStream_t s);
-// max_blocks: the largest 2 ceil(my/256) + 2 ceil(mx/256) over the fine patches.
-hipError_t launch_cf_fine_terms(int dtype, int limiter, const CfArgs &a, int step, double dt_fine,
-                                int max_blocks, hipStream_t s);
-hipError_t launch_cf_average_fix(int dtype, const CfArgs &a, double dt, int max_cover,
-                                 int max_cedges, hipStream_t s);
+// Before fine step `step` (ghost ring, fine terms; coarse terms when step is 0).
+hipError_t launch_cf_fine_step(int dtype, int limiter, const CfArgs &a, int step, double dt_fine,
+                               double dt, int max_blocks, hipStream_t s);
+// Updating and the conservation fix.
+hipError_t launch_cf_finish(int dtype, const CfArgs &a, double dt, int max_blocks, hipStream_t s);
+// Blocks per fine patch of the two launches.
+int cf_step_blocks_host(int mx, int my, int ncx, int ncy, bool coarse);
+int cf_finish_blocks_host(int ncx, int ncy);
 
 }  // namespace ws
