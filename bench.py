@@ -319,6 +319,62 @@ def run_two_level(ws, torch, steps=20, warmup=3, r=4, n=1024):
             "frac": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "finite": finite}
 
 
+def run_three_level(ws, torch, steps=10, warmup=2, r=4, n=512):
+    """Composite steps of three levels: 512^2, 94 ratio-4 level-1 patches of
+    128^2 over the annulus, 374 ratio-4 level-2 patches of 128^2 inside them
+    near the ring (level 2 takes 16 steps per level-0 step)."""
+    import numpy as np
+
+    import workloads
+
+    l1, l2 = workloads.three_level_layout(n)
+    dx0, dx1, dx2 = 1.0 / n, 1.0 / (n * r), 1.0 / (n * r * r)
+    lev0 = ws.Level([dict(mx=n, my=n, dx=dx0, dy=dx0, bc="extrap")], [(RHO, K_BULK)])
+    lev1 = ws.Level([dict(mx=r * w, my=r * h, dx=dx1, dy=dx1) for (_, _, w, h) in l1],
+                    [(RHO, K_BULK)], stream=lev0.stream)
+    lev2 = ws.Level([dict(mx=r * w, my=r * h, dx=dx2, dy=dx2) for (_, _, _, w, h) in l2],
+                    [(RHO, K_BULK)], stream=lev0.stream)
+    lev0.upload(0, workloads.padded_state(n, n, 0.0, 0.0, dx0, dx0))
+    lev0.fill_ghosts()
+    for k, (ci0, cj0, w, h) in enumerate(l1):
+        lev1.upload(k, workloads.padded_state(r * w, r * h, ci0 * dx0, cj0 * dx0, dx1, dx1))
+    for k, (p, a0, b0, w, h) in enumerate(l2):
+        x0, y0 = l1[p][0] * dx0 + a0 * dx1, l1[p][1] * dx0 + b0 * dx1
+        lev2.upload(k, workloads.padded_state(r * w, r * h, x0, y0, dx2, dx2))
+    hier = ws.Hierarchy([lev0, lev1, lev2], r,
+                        [[(0, ci0, cj0) for (ci0, cj0, _, _) in l1],
+                         [(p, a0, b0) for (p, a0, b0, _, _) in l2]])
+    dt = 0.9 * dx0 / C_SOUND
+    stream = lev0.stream
+    for _ in range(warmup):
+        hier.step(dt)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        hier.step(dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    finite = bool(np.isfinite(lev0.download(0)).all())
+    c1 = sum(r * w * r * h for (_, _, w, h) in l1)
+    c2 = sum(r * w * r * h for (_, _, _, w, h) in l2)
+    updates = n * n + r * c1 + r * r * c2
+    nbytes = (algorithmic_bytes([(n, n)], 8, True)
+              + r * algorithmic_bytes([(r * w, r * h) for (_, _, w, h) in l1], 8, False)
+              + r * r * algorithmic_bytes([(r * w, r * h) for (_, _, _, w, h) in l2], 8, False))
+    hier.close()
+    for lev in (lev2, lev1, lev0):
+        lev.close()
+    return {"levels": [f"{n}x{n}", f"{len(l1)} patches, {c1} cells",
+                       f"{len(l2)} patches, {c2} cells"], "ratio": r, "steps": steps,
+            "cell_updates_per_step": updates, "ms_per_composite_step": ms,
+            "gcells": round(updates / (ms / 1e3) / 1e9, 3),
+            "GBs": round(nbytes / (ms / 1e3) / 1e9, 1),
+            "frac": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "finite": finite}
+
+
 def measured_traffic(tiling, profile=PROFILE):
     """HBM bytes per launch of the FP64 step kernel from the committed counter
     summary, or None when the library has been rebuilt since the counters were
@@ -416,8 +472,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip FP32, AMR and CPU legs")
     ap.add_argument("--no-tune", action="store_true", help="time the default tiling")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--two-level-only", action="store_true",
-                    help="only run the two-level composite leg (for profiling)")
+    ap.add_argument("--levels-only", action="store_true",
+                    help="only run the two- and three-level composite legs (for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     args = ap.parse_args()
@@ -442,8 +498,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
         return
-    if args.two_level_only:
-        print(json.dumps({"two_level_fp64": run_two_level(ws, torch)}), flush=True)
+    if args.levels_only:
+        print(json.dumps({"two_level_fp64": run_two_level(ws, torch),
+                          "three_level_fp64": run_three_level(ws, torch)}), flush=True)
         return
     n, K = args.n, args.steps
     shapes = [(n, n)]
@@ -524,6 +581,7 @@ def main():
         line["ensemble_fp64"] = run_ensemble(ws, torch, args.ensemble_steps, tune=not args.no_tune)
         line["adjoint_fp64"] = run_adjoint(ws, torch)
         line["two_level_fp64"] = run_two_level(ws, torch)
+        line["three_level_fp64"] = run_three_level(ws, torch)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

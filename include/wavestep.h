@@ -301,6 +301,13 @@ int ws_cf_init(ws_cf **out, ws_ctx *coarse, ws_ctx *fine, int32_t ratio,
 /* One composite coarse step of size dt (steps 1-5 above).  Each level's
  * current pool flips as in ws_step_level (the fine level's r times). */
 int ws_cf_step(ws_cf *cf, double dt);
+/* Nest couplings for more than two levels: inner couples outer's fine level
+ * (as its coarse level) with a finer one.  ws_cf_step(outer) then runs, in
+ * place of each plain fine step, ws_cf_step(inner) with dt/r: the fine level's
+ * step, its own fine steps, their updating and fix (the recursion of the
+ * Sec. 2.2 flow chart).  inner NULL removes the nesting.  Both couplings must
+ * outlive the nesting. */
+int ws_cf_nest(ws_cf *outer, ws_cf *inner);
 /* Fill the fine ghosts alone, at t_n + alpha (t_{n+1} - t_n) with t_n the
  * coarse level's previous pool and t_{n+1} its current one, 0 <= alpha <= 1. */
 int ws_cf_fill_fine_ghosts(ws_cf *cf, double alpha);

@@ -54,6 +54,7 @@ class FinePatch:
     ncx: int
     ncy: int
     q: np.ndarray  # padded fine state (3, r*ncy+4, r*ncx+4)
+    parent: int = 0  # index of the patch of the next coarser level it lies in
 
 
 def check_layout(mxc, myc, fines, r):
@@ -226,3 +227,59 @@ def init_fines(qc, fines_rect, r, fn):
         average_down(qc, fp, q, r)
         out.append(fp)
     return out
+
+
+def multi_level_step(q0, levels, dx0, dy0, dt, rho, K, r, limiter="mc", bc="periodic"):
+    """One composite step of a hierarchy: level 0 is the single padded patch
+    q0 (ghosts filled); levels[l-1] lists the FinePatch objects of level l,
+    each nested (ratio r) in patch `parent` of level l-1, with coordinates in
+    its parent's cells.  Level l advances r^l steps of dt / r^l: every step of
+    a level is its step followed, r times, by its children's ghost fill from
+    it (between its old and new state), their boundary terms and their own
+    composite step; then updating and the fix of the level's cells around its
+    children (the recursion of the paper's flow chart, Sec. 2.2).  Returns the
+    new level-0 state and the new levels."""
+    states = [[q0.copy()]] + [[p.q.copy() for p in lv] for lv in levels]
+    geo = [None] + [list(lv) for lv in levels]
+    for l in range(1, len(geo)):
+        by_parent = {}
+        for p in geo[l]:
+            by_parent.setdefault(p.parent, []).append(p)
+        for k, ps in by_parent.items():
+            P = states[l - 1][k]
+            check_layout(P.shape[2] - 4, P.shape[1] - 4, [FinePatch(p.ci0, p.cj0, p.ncx, p.ncy,
+                                                                   p.q) for p in ps], r)
+
+    def advance(l, dt_l, dx, dy):
+        old = states[l]
+        Tc = [O.step_terms(q, dx, dy, dt_l, rho, K, limiter) for q in old]
+        new = [O.step(q, dx, dy, dt_l, rho, K, limiter)[0] for q in old]
+        if l == 0:
+            O.fill_bc(new[0], bc)
+        kids = geo[l + 1] if l + 1 < len(geo) else []
+        if kids:
+            accs = []
+            for p in kids:
+                myf, mxf = p.ncy * r, p.ncx * r
+                accs.append({"left": np.zeros((myf, 3)), "right": np.zeros((myf, 3)),
+                             "bottom": np.zeros((mxf, 3)), "top": np.zeros((mxf, 3))})
+            for k in range(r):
+                a = k / r
+                for c, p in enumerate(kids):
+                    qf = states[l + 1][c]
+                    Qt = (1.0 - a) * old[p.parent] + a * new[p.parent]
+                    fill_fine_ghosts(qf, p, Qt, r)
+                    Tf = O.step_terms(qf, dx / r, dy / r, dt_l / r, rho, K, limiter)
+                    accumulate_fine(accs[c], p, qf, Tf, old[p.parent], r, rho, K)
+                advance(l + 1, dt_l / r, dx / r, dy / r)
+            for c, p in enumerate(kids):
+                average_down(new[p.parent], p, states[l + 1][c], r)
+                apply_fix(new[p.parent], p, accs[c], Tc[p.parent], dt_l, dx, dy, r)
+            if l == 0:
+                O.fill_bc(new[0], bc)
+        states[l] = new
+
+    advance(0, dt, dx0, dy0)
+    out = [[FinePatch(p.ci0, p.cj0, p.ncx, p.ncy, q, p.parent) for p, q in zip(geo[l], states[l])]
+           for l in range(1, len(geo))]
+    return states[0][0], out

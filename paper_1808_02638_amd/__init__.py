@@ -9,4 +9,4 @@ PyTorch for device memory and streams only.
 from ._lib import WaveStepError  # noqa: F401
 from .level import Level  # noqa: F401
 from .adjoint import AcousticsAdjoint  # noqa: F401
-from .amr import TwoLevel  # noqa: F401
+from .amr import Hierarchy, TwoLevel  # noqa: F401

@@ -27,7 +27,8 @@ EXPORTS = (
     "ws_capture_steps", "ws_graph_launch", "ws_read_dt_cfl", "ws_read_patch_cfl",
     "ws_conservation_sums", "ws_mask_bytes", "ws_patch_layout", "ws_step_record_masks",
     "ws_adjoint_step", "ws_gather", "ws_add_at", "ws_time_step_kernel", "ws_current_pool",
-    "ws_cf_layout", "ws_cf_init", "ws_cf_step", "ws_cf_fill_fine_ghosts", "ws_cf_destroy",
+    "ws_cf_layout", "ws_cf_init", "ws_cf_step", "ws_cf_nest", "ws_cf_fill_fine_ghosts",
+    "ws_cf_destroy",
     "ws_destroy", "ws_last_error",
 )
 
@@ -99,6 +100,7 @@ def lib():
         "ws_cf_layout": [vp, i32, P(i64)],
         "ws_cf_init": [P(vp), vp, vp, i32, P(FinePlace), vp, i64],
         "ws_cf_step": [vp, dbl],
+        "ws_cf_nest": [vp, vp],
         "ws_cf_fill_fine_ghosts": [vp, dbl],
         "ws_cf_destroy": [vp],
         "ws_destroy": [vp],

@@ -1,5 +1,6 @@
-"""Two levels coupled for the composite coarse step with the conservation
-fix: a thin binding of the ``ws_cf_*`` entry points of the C ABI.
+"""Levels coupled for the composite coarse step with the conservation fix:
+a thin binding of the ``ws_cf_*`` entry points of the C ABI (``TwoLevel``
+for one coarse-fine pair, ``Hierarchy`` for more levels).
 
 The coarse ``Level`` and the fine ``Level`` (patches nested in the coarse ones,
 ``bc=None``, created on the coarse level's stream) stay usable on their own;
@@ -62,3 +63,31 @@ class TwoLevel:
             self.close()
         except Exception:
             pass
+
+
+class Hierarchy:
+    """Levels 0..L coupled pairwise and nested: levels[l+1]'s patches lie in
+    levels[l]'s (ratio ratios[l]); places[l] lists, per patch of level l+1,
+    (parent patch in level l, ci0, cj0).  Every level must be created on
+    levels[0]'s stream.  ``step(dt)`` advances level 0 by dt and level l by
+    r^l steps of dt / r^l, with the updating and the fix at every pair."""
+
+    def __init__(self, levels: Sequence[Level], ratios, places: Sequence):
+        if len(levels) < 2:
+            raise ValueError("a hierarchy needs at least two levels")
+        if isinstance(ratios, int):
+            ratios = [ratios] * (len(levels) - 1)
+        if len(ratios) != len(levels) - 1 or len(places) != len(levels) - 1:
+            raise ValueError("one ratio and one place list per coupled pair")
+        self.levels = list(levels)
+        self.pairs = [TwoLevel(levels[l], levels[l + 1], ratios[l], places[l])
+                      for l in range(len(levels) - 1)]
+        for outer, inner in zip(self.pairs, self.pairs[1:]):
+            C.check(C.lib().ws_cf_nest(outer._cf, inner._cf))
+
+    def step(self, dt: float):
+        self.pairs[0].step(dt)
+
+    def close(self):
+        for p in self.pairs:
+            p.close()

@@ -789,6 +789,7 @@ int ws_destroy(ws_ctx *c) {
 
 struct ws_cf {
   ws_ctx *coarse = nullptr, *fine = nullptr;
+  ws_cf *inner = nullptr;  // coupling of the fine level with the next finer one
   int r = 1;
   char *ws = nullptr;
   int64_t off_place = 0, off_acc = 0, off_pc = 0;
@@ -958,15 +959,35 @@ int ws_cf_step(ws_cf *cf, double dt) {
     a.f_cur = f->pool[f->cur];
     HIPCHK(launch_cf_fine_step(c->dtype, c->limiter, a, k, dtf, dt, cf->max_step_blocks,
                                c->stream));
-    StepArgs s = f->step_args(f->cur, dtf, 0.0);
-    HIPCHK(launch_step(f->dtype, f->limiter, f->vars, s, f->grid, f->stream));
-    f->cur = 1 - f->cur;
+    if (cf->inner) {
+      // the fine level's own composite step (its step, its finer levels,
+      // their updating and fix)
+      if (int rc = ws_cf_step(cf->inner, dtf)) return rc;
+    } else {
+      StepArgs s = f->step_args(f->cur, dtf, 0.0);
+      HIPCHK(launch_step(f->dtype, f->limiter, f->vars, s, f->grid, f->stream));
+      f->cur = 1 - f->cur;
+    }
   }
   // updating and the conservation fix, then the coarse physical ghosts
   a.f_cur = f->pool[f->cur];
   HIPCHK(launch_cf_finish(c->dtype, a, dt, cf->max_finish_blocks, c->stream));
   HIPCHK(launch_fill_ghosts(c->dtype, c->d_patches(), c->n_patches, c->max_padded_cells,
                             c->pool[c->cur], c->stream));
+  return WS_OK;
+}
+
+int ws_cf_nest(ws_cf *outer, ws_cf *inner) {
+  if (!outer) return fail(WS_EINVAL, "coupling is NULL");
+  if (!inner) {
+    outer->inner = nullptr;
+    return WS_OK;
+  }
+  if (inner->coarse != outer->fine)
+    return fail(WS_EINVAL, "the inner coupling's coarse level must be the outer one's fine level");
+  for (ws_cf *c = inner; c; c = c->inner)
+    if (c == outer) return fail(WS_EINVAL, "nesting would form a cycle");
+  outer->inner = inner;
   return WS_OK;
 }
 

@@ -241,3 +241,99 @@ def test_full_size_layout_conserves_periodic(ws):
     assert np.all(np.abs(s2 - s1) <= 1e-13 * scale), (s1, s2)
     for lev in (tl, fine, coarse):
         lev.close()
+
+
+# --------------------------------------------------------------------------
+# Three levels (nested couplings)
+# --------------------------------------------------------------------------
+
+L1_RECTS = [(4, 4, 10, 12), (19, 6, 8, 8)]
+L2_PLACES = [(0, (2, 2, 3, 3)), (1, (2, 2, 4, 3)), (0, (2, 8, 4, 2))]
+
+
+def build3(ws, n, r, bc, dtype=torch.float64, fn=smooth):
+    """Oracle start state (level 1 and 2 means written into their parents) and
+    the three GPU levels holding it."""
+    qc = coarse_state(n, fn)
+    l1 = oamr.init_fines(qc, L1_RECTS, r, fn)
+    l2 = []
+    dx1 = 1.0 / (n * r)
+    for parent, (ci0, cj0, ncx, ncy) in L2_PLACES:
+        P = l1[parent]
+        x0, y0 = P.ci0 / n + ci0 * dx1, P.cj0 / n + cj0 * dx1
+        x = x0 + (np.arange(-2, r * ncx + 2) + 0.5) * dx1 / r
+        y = y0 + (np.arange(-2, r * ncy + 2) + 0.5) * dx1 / r
+        X, Y = np.meshgrid(x, y, indexing="xy")
+        q = np.ascontiguousarray(fn(X, Y), dtype=np.float64)
+        fp = oamr.FinePatch(ci0, cj0, ncx, ncy, q, parent)
+        oamr.average_down(P.q, fp, q, r)
+        l2.append(fp)
+    for P in l1:
+        oamr.average_down(qc, P, P.q, r)
+    O.fill_bc(qc, bc)
+    lev0 = ws.Level([dict(mx=n, my=n, dx=1 / n, dy=1 / n, bc=bc)], [(RHO, KB)], dtype=dtype)
+    lev1 = ws.Level([dict(mx=r * w, my=r * h, dx=dx1, dy=dx1) for (_, _, w, h) in L1_RECTS],
+                    [(RHO, KB)], dtype=dtype, stream=lev0.stream)
+    lev2 = ws.Level([dict(mx=r * p[1][2], my=r * p[1][3], dx=dx1 / r, dy=dx1 / r) for p in L2_PLACES],
+                    [(RHO, KB)], dtype=dtype, stream=lev0.stream)
+    lev0.upload(0, qc)
+    for k, P in enumerate(l1):
+        lev1.upload(k, P.q)
+    for k, P in enumerate(l2):
+        lev2.upload(k, P.q)
+    h = ws.Hierarchy([lev0, lev1, lev2], r,
+                     [[(0, ci0, cj0) for (ci0, cj0, _, _) in L1_RECTS],
+                      [(parent, rc[0], rc[1]) for parent, rc in L2_PLACES]])
+    return qc, [l1, l2], (lev0, lev1, lev2), h
+
+
+@pytest.mark.parametrize("bc", ["periodic", "extrap"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_three_levels_match_oracle(ws, dtype, bc):
+    n, r = 32, 2
+    qc, levels, levs, h = build3(ws, n, r, bc, dtype)
+    dt = 0.8 / n / C0
+    q, lv = qc, levels
+    for _ in range(4):
+        q, lv = oamr.multi_level_step(q, lv, 1 / n, 1 / n, dt, RHO, KB, r, bc=bc)
+        h.step(dt)
+    tol = FP64_TOL if dtype == torch.float64 else FP32_TOL
+    err = rel_linf(levs[0].download(0), q)
+    print(f"three levels {bc} {dtype}: level-0 rel Linf {err}")
+    assert err.max() <= tol, err
+    for l in (1, 2):
+        for k, P in enumerate(lv[l - 1]):
+            e = rel_linf(levs[l].download(k)[:, 2:-2, 2:-2], P.q[:, 2:-2, 2:-2])
+            assert e.max() <= tol, (l, k, e)
+    h.close()
+    for lev in levs:
+        lev.close()
+
+
+def test_three_levels_conserve(ws):
+    n, r = 32, 2
+    _, _, levs, h = build3(ws, n, r, "periodic")
+    s0 = levs[0].conservation_sums()[0]
+    for _ in range(30):
+        h.step(0.9 / n / C0)
+    s1 = levs[0].conservation_sums()[0]
+    scale = np.abs(s0).max()
+    print(f"three levels conservation drift {(s1 - s0) / scale}")
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * scale), (s0, s1)
+    h.close()
+    for lev in levs:
+        lev.close()
+
+
+def test_nesting_is_checked(ws):
+    n, r = 32, 2
+    _, _, levs, h = build3(ws, n, r, "extrap")
+    outer, inner = h.pairs
+    L = ws._lib.lib()
+    with pytest.raises(ws.WaveStepError):
+        ws._lib.check(L.ws_cf_nest(inner._cf, outer._cf))  # levels do not chain
+    with pytest.raises(ws.WaveStepError):
+        ws._lib.check(L.ws_cf_nest(outer._cf, outer._cf))
+    h.close()
+    for lev in levs:
+        lev.close()

@@ -152,3 +152,79 @@ def test_layout_checks(mod=amr_mod):
              mod.FinePatch(9, 3, 4, 4, np.zeros((3, 12, 12)))]
     with pytest.raises(ValueError):
         mod.check_layout(20, 20, close, 2)
+
+
+# --------------------------------------------------------------------------
+# Three levels: the recursion of the composite step
+# --------------------------------------------------------------------------
+
+def three_levels(mod, n, r, fn=smooth):
+    """Level 0: n^2; level 1: two patches; level 2: patches nested in them."""
+    qc = coarse_state(n, fn)
+    l1 = mod.init_fines(qc, [(4, 4, 10, 12), (19, 6, 8, 8)], r, fn)
+    # level-2 patches in level-1 cells: fine states from fn at their centres
+    l2 = []
+    for parent, (ci0, cj0, ncx, ncy) in [(0, (2, 2, 3, 3)), (1, (2, 2, 4, 3)), (0, (2, 8, 4, 2))]:
+        P = l1[parent]
+        dx1 = 1.0 / (n * r)
+        x0 = P.ci0 / n + ci0 * dx1
+        y0 = P.cj0 / n + cj0 * dx1
+        x = x0 + (np.arange(-2, r * ncx + 2) + 0.5) * dx1 / r
+        y = y0 + (np.arange(-2, r * ncy + 2) + 0.5) * dx1 / r
+        X, Y = np.meshgrid(x, y, indexing="xy")
+        q = np.ascontiguousarray(fn(X, Y), dtype=np.float64)
+        fp = mod.FinePatch(ci0, cj0, ncx, ncy, q, parent)
+        mod.average_down(P.q, fp, q, r)
+        l2.append(fp)
+    for P in l1:  # level-1 cells covered by level 2 changed: refresh level 0
+        mod.average_down(qc, P, P.q, r)
+    for P in l1:
+        P.parent = 0
+    return qc, [l1, l2]
+
+
+def test_three_levels_conserve(mod=amr_mod):
+    n, r = 32, 2
+    qc, levels = three_levels(mod, n, r)
+    O.fill_bc(qc, "periodic")
+    s0 = mod.composite_sums(qc, 1 / n, 1 / n)
+    q, lv = qc, levels
+    dt = 0.8 / n / 2.0
+    for _ in range(4):
+        q, lv = mod.multi_level_step(q, lv, 1 / n, 1 / n, dt, RHO, KB, r, bc="periodic")
+    s1 = mod.composite_sums(q, 1 / n, 1 / n)
+    scale = np.abs(s0).max()
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * scale), (s1 - s0) / scale
+    # the finest level moved
+    assert np.abs(lv[1][0].q - levels[1][0].q).max() > 1e-4
+
+
+def test_one_level_recursion_equals_two_level_step(mod=amr_mod):
+    n, r = 32, 2
+    rects = [(6, 8, 8, 10), (20, 5, 6, 6)]
+    qc = coarse_state(n, smooth)
+    fines = mod.init_fines(qc, rects, r, smooth)
+    O.fill_bc(qc, "extrap")
+    dt = 0.8 / n / 2.0
+    a, fa = mod.two_level_step(qc, fines, 1 / n, 1 / n, dt, RHO, KB, r, bc="extrap")
+    b, lb = mod.multi_level_step(qc, [fines], 1 / n, 1 / n, dt, RHO, KB, r, bc="extrap")
+    assert np.array_equal(a, b)
+    for x, y in zip(fa, lb[0]):
+        assert np.array_equal(x.q, y.q)
+
+
+def test_three_levels_ratio_one_equal_single_level(mod=amr_mod):
+    n, r = 32, 1
+    qc, levels = three_levels(mod, n, r)
+    O.fill_bc(qc, "extrap")
+    p = qc.copy()
+    q, lv = qc, levels
+    dt = 0.8 / n / 2.0
+    for _ in range(3):
+        q, lv = mod.multi_level_step(q, lv, 1 / n, 1 / n, dt, RHO, KB, r, bc="extrap")
+        p, _, _ = O.step(p, 1 / n, 1 / n, dt, RHO, KB, "mc")
+        O.fill_bc(p, "extrap")
+    assert np.array_equal(q, p)
+    for P in lv[0]:
+        assert np.array_equal(P.q[:, 2:-2, 2:-2],
+                              p[:, 2 + P.cj0:2 + P.cj0 + P.ncy, 2 + P.ci0:2 + P.ci0 + P.ncx])

@@ -18,6 +18,7 @@ from .generators import (  # noqa: F401
     padded_state,
     plane_wave_state,
     radial_pulse,
+    three_level_layout,
     two_level_layout,
     uniform_patch,
 )

@@ -11,7 +11,9 @@ synthetic stand-ins for the paper's AMR run:
 * ``ensemble()``          -- 64 independent problems of uneven sizes;
 * ``adjoint_setup()``     -- 512x512, fixed dt, 16 receivers, shifted target;
 * ``two_level_layout()``  -- a 1024x1024 coarse grid and ratio-4 fine patches
-  over the ring's annulus, for the composite step with the conservation fix.
+  over the ring's annulus, for the composite step with the conservation fix;
+* ``three_level_layout()`` -- 512x512, ratio-4 level-1 patches over the
+  annulus and ratio-4 level-2 patches inside them near the ring.
 
 A patch state is a C-contiguous float64 array (3, my+4, mx+4): components
 (p, u, v), two ghost layers on each side, x fastest.
@@ -243,8 +245,9 @@ def adjoint_setup(seed=18085, n=512, steps=200, courant=0.8, c=2.0, n_receivers=
                         checkpoint_every)
 
 
-def two_level_layout(n=1024, size=32, gap=3, r_lo=0.15, r_hi=0.35):
-    """Fine patches of size x size coarse cells on a pitch of size + gap over
+def two_level_layout(n=1024, size=30, gap=3, r_lo=0.15, r_hi=0.35):
+    """Fine patches of size x size coarse cells (at ratio 4, 120 x 120 fine
+    cells: two 60-column MARCH segments) on a pitch of size + gap over
     the n x n coarse grid of the unit square, kept where any of the patch's
     coarse-cell centres lies in the annulus r_lo <= r <= r_hi around the
     ring's centre (0.5, 0.5).  Returns a list of (ci0, cj0, ncx, ncy)."""
@@ -258,3 +261,24 @@ def two_level_layout(n=1024, size=32, gap=3, r_lo=0.15, r_hi=0.35):
             if np.any((rr >= r_lo) & (rr <= r_hi)):
                 rects.append((ci0, cj0, size, size))
     return rects
+
+
+def three_level_layout(n=512, size=30, gap=3, r=4, r_lo=0.15, r_hi=0.35, r2_lo=0.2, r2_hi=0.3):
+    """Level 1: ``two_level_layout(n, size, gap, r_lo, r_hi)``.  Level 2: in
+    each level-1 patch (r*size cells a side), patches of size x size level-1
+    cells on a pitch of size + gap starting 2 cells in, kept where any of their
+    level-1 cell centres lies in r2_lo <= r <= r2_hi.  Returns (level-1 rects,
+    level-2 places (parent, ci0, cj0, ncx, ncy))."""
+    l1 = two_level_layout(n, size, gap, r_lo, r_hi)
+    dx1 = 1.0 / (n * r)
+    l2 = []
+    m = r * size
+    for k, (ci0, cj0, _, _) in enumerate(l1):
+        for b0 in range(2, m - size - 1, size + gap):
+            for a0 in range(2, m - size - 1, size + gap):
+                xs = ci0 / n + (a0 + np.arange(size) + 0.5) * dx1 - 0.5
+                ys = cj0 / n + (b0 + np.arange(size) + 0.5) * dx1 - 0.5
+                rr = np.hypot(xs[None, :], ys[:, None])
+                if np.any((rr >= r2_lo) & (rr <= r2_hi)):
+                    l2.append((k, a0, b0, size, size))
+    return l1, l2
