@@ -258,9 +258,9 @@ def run_adjoint(ws, torch):
 PROFILE = os.path.join(ROOT, "profiles", "step_kernel_march_f64_2048sq.md")
 
 
-def run_two_level(ws, torch, steps=20, warmup=3, r=4, n=1024):
-    """Composite coarse steps of a 1024^2 coarse grid and 320 ratio-4 fine
-    patches of 128^2 cells over the ring's annulus (coarse step, r fine steps
+def run_two_level(ws, torch, steps=20, warmup=3, r=4, n=1024, tune=True):
+    """Composite coarse steps of a 1024^2 coarse grid and 364 ratio-4 fine
+    patches of 120^2 cells over the ring's annulus (coarse step, r fine steps
     with ghosts from the coarse level, updating, conservation fix), against
     the same level steps without the coupling kernels."""
     import numpy as np
@@ -279,6 +279,10 @@ def run_two_level(ws, torch, steps=20, warmup=3, r=4, n=1024):
     tl = ws.TwoLevel(coarse, fine, r, [(0, ci0, cj0) for (ci0, cj0, _, _) in rects])
     dt = 0.9 * dx / C_SOUND
     stream = coarse.stream
+    if tune:
+        from paper_1808_02638_amd.autotune import autotune
+        for lev in (coarse, fine):
+            autotune(lev)  # timing only: the state is restored and results do not change
 
     def timed(fn, count):
         e0 = torch.cuda.Event(enable_timing=True)
@@ -301,6 +305,7 @@ def run_two_level(ws, torch, steps=20, warmup=3, r=4, n=1024):
             fine.step(dt / r, read_cfl=False)
 
     ms_levels = timed(levels_only, steps)
+    tilings = [lev.get_tiling() for lev in (coarse, fine)]
     q = coarse.download(0)
     finite = bool(np.isfinite(q).all())
     fine_cells = sum(r * w * r * h for (_, _, w, h) in rects)
@@ -315,13 +320,15 @@ def run_two_level(ws, torch, steps=20, warmup=3, r=4, n=1024):
             "ms_per_composite_step": ms, "gcells": round(updates / (ms / 1e3) / 1e9, 3),
             "levels_only_ms": ms_levels,
             "coupling_overhead": round(ms / ms_levels - 1.0, 4),
+            "tilings": [{"variant": t[0][0], "tile_w": int(t[1][0]), "tile_h": int(t[2][0]),
+                         "wg_per_cu": t[3]} for t in tilings],
             "GBs": round(nbytes / (ms / 1e3) / 1e9, 1),
             "frac": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "finite": finite}
 
 
-def run_three_level(ws, torch, steps=10, warmup=2, r=4, n=512):
-    """Composite steps of three levels: 512^2, 94 ratio-4 level-1 patches of
-    128^2 over the annulus, 374 ratio-4 level-2 patches of 128^2 inside them
+def run_three_level(ws, torch, steps=10, warmup=2, r=4, n=512, tune=True):
+    """Composite steps of three levels: 512^2, 103 ratio-4 level-1 patches of
+    120^2 over the annulus, 409 ratio-4 level-2 patches of 120^2 inside them
     near the ring (level 2 takes 16 steps per level-0 step)."""
     import numpy as np
 
@@ -346,6 +353,10 @@ def run_three_level(ws, torch, steps=10, warmup=2, r=4, n=512):
                          [(p, a0, b0) for (p, a0, b0, _, _) in l2]])
     dt = 0.9 * dx0 / C_SOUND
     stream = lev0.stream
+    if tune:
+        from paper_1808_02638_amd.autotune import autotune
+        for lev in (lev0, lev1, lev2):
+            autotune(lev)
     for _ in range(warmup):
         hier.step(dt)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -499,8 +510,9 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
         return
     if args.levels_only:
-        print(json.dumps({"two_level_fp64": run_two_level(ws, torch),
-                          "three_level_fp64": run_three_level(ws, torch)}), flush=True)
+        print(json.dumps({"two_level_fp64": run_two_level(ws, torch, tune=not args.no_tune),
+                          "three_level_fp64": run_three_level(ws, torch, tune=not args.no_tune)}),
+              flush=True)
         return
     n, K = args.n, args.steps
     shapes = [(n, n)]
@@ -580,8 +592,8 @@ def main():
                                   "cache_free": copy_bandwidth(torch, 4 * bytes64)}
         line["ensemble_fp64"] = run_ensemble(ws, torch, args.ensemble_steps, tune=not args.no_tune)
         line["adjoint_fp64"] = run_adjoint(ws, torch)
-        line["two_level_fp64"] = run_two_level(ws, torch)
-        line["three_level_fp64"] = run_three_level(ws, torch)
+        line["two_level_fp64"] = run_two_level(ws, torch, tune=not args.no_tune)
+        line["three_level_fp64"] = run_three_level(ws, torch, tune=not args.no_tune)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

@@ -196,8 +196,8 @@ def _full_layout(ws, bc):
 
 
 def test_full_size_layout_sampled_against_oracle(ws):
-    """The benchmark's layout (1024^2 coarse, 320 ratio-4 fine patches of
-    128^2): one composite step on the GPU; the oracle steps the same coarse
+    """The benchmark's layout (1024^2 coarse, 364 ratio-4 fine patches of
+    120^2): one composite step on the GPU; the oracle steps the same coarse
     state with three of the fine patches.  Fine patches are 3 coarse cells
     apart, so within one step a patch and the coarse cells it covers or
     borders depend on no other patch: those cells, the three fine states and

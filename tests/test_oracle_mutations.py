@@ -165,7 +165,13 @@ AMR_MUTATIONS = {
                                     '+ Tf["amx"][b, mxf] + Tf["Fx"][b, mxf]'),
     "c1_dropped_top": ('acc["top"][a] += _fsum(1, rho, K, out, g) - Tf["apy"][myf, a]',
                        'acc["top"][a] += - Tf["apy"][myf, a]'),
-    "time_fraction": ("a = k / r", "a = (k + 1) / r"),
+    "time_fraction": ("a = k / r\n            Qt = (1.0 - a) * qc + a * qc1",
+                      "a = (k + 1) / r\n            Qt = (1.0 - a) * qc + a * qc1"),
+    # the recursion of several levels
+    "recursion_time_ends_swapped": ("Qt = (1.0 - a) * old[p.parent] + a * new[p.parent]",
+                                    "Qt = (1.0 - a) * new[p.parent] + a * old[p.parent]"),
+    "recursion_fix_skipped": ("apply_fix(new[p.parent], p, accs[c], Tc[p.parent], dt_l, dx, dy, r)",
+                              "pass"),
     "average_weight": ("sum(axis=1) / (r * r)", "sum(axis=1) / (r * r + 1)"),
     "slope_unlimited": ("return s * np.minimum(np.minimum(2.0 * np.abs(a), 2.0 * np.abs(b)), 0.5 * np.abs(a + b))",
                         "return 0.5 * (a + b)"),
@@ -180,6 +186,9 @@ AMR_PIN_CALLS = [
     ("ratio_one", lambda m: amr_pins.test_ratio_one_equals_single_level_step(m)),
     ("conserves_r2", lambda m: amr_pins.test_composite_conserves(2, m)),
     ("symmetry", lambda m: amr_pins.test_symmetric_layout_gives_symmetric_result(m)),
+    ("one_level_recursion", lambda m: amr_pins.test_one_level_recursion_equals_two_level_step(m)),
+    ("three_ratio_one", lambda m: amr_pins.test_three_levels_ratio_one_equal_single_level(m)),
+    ("three_conserve", lambda m: amr_pins.test_three_levels_conserve(m)),
 ]
 
 
