@@ -65,6 +65,11 @@ def load_lib(path):
     L.oracle_riemann_edge.restype = None
     L.oracle_split_vec.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, dp, dp, dp]
     L.oracle_split_vec.restype = None
+    L.oracle_step_var.argtypes = [
+        dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+        dp, dp, ctypes.c_int, dp,
+    ]
+    L.oracle_step_var.restype = ctypes.c_int
     L.oracle_step_terms.argtypes = [
         dp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
         ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, dp, dp, dp, dp, dp, dp,
@@ -172,6 +177,37 @@ def step(q, dx, dy, dt, rho, K, limiter="mc", *, drop_zero_wave=False,
     if rc != 0:
         raise RuntimeError("oracle_step_ex failed")
     return out, cfl.value, masks
+
+
+def step_var(q, dx, dy, dt, rho, K, limiter="mc"):
+    """One step in a heterogeneous medium: rho, K padded (my+4, mx+4) arrays
+    (ghost cells included).  Returns (q_new, cfl)."""
+    mx, my = _check_state(q)
+    rho = np.ascontiguousarray(rho, np.float64)
+    K = np.ascontiguousarray(K, np.float64)
+    if rho.shape != (my + 4, mx + 4) or K.shape != rho.shape:
+        raise ValueError("rho and K must have the padded shape (my+4, mx+4)")
+    out = np.empty_like(q)
+    cfl = ctypes.c_double(0.0)
+    rc = lib().oracle_step_var(_dptr(q), _dptr(out), mx, my, float(dx), float(dy), float(dt),
+                               _dptr(rho), _dptr(K), LIM[limiter], ctypes.byref(cfl))
+    if rc != 0:
+        raise RuntimeError("oracle_step_var failed")
+    return out, cfl.value
+
+
+def run_var(q0, nsteps, dx, dy, rho, K, dt, *, limiter="mc", bc="extrap"):
+    """nsteps heterogeneous steps of fixed dt; ghosts refilled after each."""
+    q = np.array(q0, dtype=np.float64, order="C", copy=True)
+    if bc is not None:
+        fill_bc(q, bc)
+    cfls = []
+    for _ in range(nsteps):
+        q, cfl = step_var(q, dx, dy, dt, rho, K, limiter)
+        if bc is not None:
+            fill_bc(q, bc)
+        cfls.append(cfl)
+    return {"q": q, "cfls": np.array(cfls)}
 
 
 def step_terms(q, dx, dy, dt, rho, K, limiter="mc", *, transverse_corr=False):

@@ -584,6 +584,246 @@ int oracle_step_patches(int n, const double *q_in, double *q_out,
 }
 
 /* ---------------------------------------------------------------------- */
+/* One step in a heterogeneous medium (rho, K per cell)                    */
+/* ---------------------------------------------------------------------- */
+/*
+ * The same unsplit step, eq. (2.3), for q_t + A(x,y) q_x + B(x,y) q_y = 0
+ * with A, B of Sec. 4.1 eq. (4.2) taken cell by cell (rho, K: padded
+ * [my+4][mx+4] like one plane of q; c = sqrt(K/rho), Z = rho c).
+ *
+ * Normal solve at the edge between cells l and r (x: A; y: B with v): the
+ * jump is split into a left-going wave along (-Z_l, 1, 0) with speed -c_l
+ * and a right-going wave along (Z_r, 1, 0) with speed +c_r (plus the
+ * speed-0 tangential wave), i.e. strengths
+ *   a1 = (-dp + Z_r du)/(Z_l + Z_r),  a2 = (dp + Z_l du)/(Z_l + Z_r),
+ * A-dQ = -c_l W1, A+dQ = +c_r W2 (the wave decomposition of the jump in the
+ * eigenvectors of the two cells).  Limiter as in the constant medium, on the
+ * wave vectors (theta = W_upwind . W / W . W).  Transverse solve of a
+ * fluctuation a entering cell m: the part going down is the down-going wave
+ * of the Riemann problem between the cell below (b) and m,
+ *   B-a = -c_b beta (-Z_b, 0, 1), beta = (-a_p + Z_m a_v)/(Z_b + Z_m),
+ * the part going up the up-going wave between m and the cell above (t),
+ *   B+a = +c_t beta (Z_t, 0, 1), beta = (a_p + Z_m a_v)/(Z_m + Z_t);
+ * mirror images in x.  Courant number: max over the edges of interior cells
+ * of max(c_l, c_r) dt/dx (x) and max(c_b, c_t) dt/dy (y).
+ */
+#define VIX(i, j) ((size_t)((j) + 2) * (size_t)(mx + 4) + (size_t)((i) + 2))
+
+/* dir 0: x (normal velocity u = component 1), 1: y (v = component 2) */
+static void riemann_var(int dir, double Zl, double cl, double Zr, double cr,
+                        const double ql[NM], const double qr[NM], double W[2][NM],
+                        double s[2], double am[NM], double ap[NM]) {
+  const int n = dir == 0 ? 1 : 2;
+  const double dp = qr[0] - ql[0], dn = qr[n] - ql[n];
+  const double a1 = (-dp + Zr * dn) / (Zl + Zr);
+  const double a2 = (dp + Zl * dn) / (Zl + Zr);
+  for (int m = 0; m < NM; ++m) W[0][m] = W[1][m] = 0.0;
+  W[0][0] = -Zl * a1;
+  W[0][n] = a1;
+  W[1][0] = Zr * a2;
+  W[1][n] = a2;
+  s[0] = -cl;
+  s[1] = cr;
+  for (int m = 0; m < NM; ++m) {
+    am[m] = s[0] * W[0][m];
+    ap[m] = s[1] * W[1][m];
+  }
+}
+
+/* split a (entering cell m) by the other direction's waves: down (left)
+ * with the cell below (left) b, up (right) with the cell above (right) t */
+static void split_var(int dir, const double a[NM], double Zb, double cb, double Zm,
+                      double Zt, double ct, double minus[NM], double plus[NM]) {
+  const int n = dir == 0 ? 1 : 2; /* the normal velocity of the split direction */
+  const double bd = (-a[0] + Zm * a[n]) / (Zb + Zm);
+  const double bu = (a[0] + Zm * a[n]) / (Zm + Zt);
+  for (int m = 0; m < NM; ++m) minus[m] = plus[m] = 0.0;
+  minus[0] = -cb * bd * (-Zb);
+  minus[n] = -cb * bd;
+  plus[0] = ct * bu * Zt;
+  plus[n] = ct * bu;
+}
+
+int oracle_step_var(const double *q_in, double *q_out, int mx, int my, double dx, double dy,
+                    double dt, const double *rho, const double *K, int limiter,
+                    double *cfl_out) {
+  if (mx < 1 || my < 1 || !(dx > 0.0) || !(dy > 0.0) || !rho || !K) return -1;
+  const double dtdx = dt / dx, dtdy = dt / dy;
+  const size_t np = (size_t)(mx + 4) * (size_t)(my + 4);
+  double *Zc = malloc(sizeof(double) * np), *cc = malloc(sizeof(double) * np);
+  const size_t nxe = (size_t)(my + 2) * (size_t)(mx + 1);
+  const size_t nye = (size_t)(my + 1) * (size_t)(mx + 2);
+  double *amdq_x = calloc(nxe * NM, sizeof(double)), *apdq_x = calloc(nxe * NM, sizeof(double));
+  double *amdq_y = calloc(nye * NM, sizeof(double)), *apdq_y = calloc(nye * NM, sizeof(double));
+  double *Fc = calloc((size_t)my * (mx + 1) * NM, sizeof(double));
+  double *Gc = calloc((size_t)(my + 1) * mx * NM, sizeof(double));
+  double *Gx_top = calloc((size_t)(my + 2) * mx * NM, sizeof(double));
+  double *Gx_bot = calloc((size_t)(my + 2) * mx * NM, sizeof(double));
+  double *Fy_right = calloc((size_t)my * (mx + 2) * NM, sizeof(double));
+  double *Fy_left = calloc((size_t)my * (mx + 2) * NM, sizeof(double));
+  int rc = 0;
+  if (!Zc || !cc || !amdq_x || !apdq_x || !amdq_y || !apdq_y || !Fc || !Gc || !Gx_top ||
+      !Gx_bot || !Fy_right || !Fy_left) {
+    rc = -1;
+    goto done;
+  }
+  for (size_t k = 0; k < np; ++k) {
+    if (!(rho[k] > 0.0) || !(K[k] > 0.0)) {
+      rc = -1;
+      goto done;
+    }
+    cc[k] = sqrt(K[k] / rho[k]);
+    Zc[k] = rho[k] * cc[k];
+  }
+#define AX(j, e) (((size_t)((j) + 1) * (size_t)(mx + 1) + (size_t)(e)) * NM)
+#define AY(f, i) (((size_t)(f) * (size_t)(mx + 2) + (size_t)((i) + 1)) * NM)
+#define FC(j, e) (((size_t)(j) * (size_t)(mx + 1) + (size_t)(e)) * NM)
+#define GC(f, i) (((size_t)(f) * (size_t)mx + (size_t)(i)) * NM)
+#define GX(j, i) (((size_t)((j) + 1) * (size_t)mx + (size_t)(i)) * NM)
+#define FY(j, i) (((size_t)(j) * (size_t)(mx + 2) + (size_t)((i) + 1)) * NM)
+
+  /* ---- x-direction: rows j = -1..my ---- */
+  for (int j = -1; j <= my; ++j) {
+    double(*W)[2][NM] = malloc(sizeof(double[2][NM]) * (size_t)(mx + 3));
+    for (int e = -1; e <= mx + 1; ++e) {
+      double ql[NM], qr[NM], am[NM], ap[NM], s[2];
+      for (int m = 0; m < NM; ++m) {
+        ql[m] = q_in[QIX(m, e - 1, j)];
+        qr[m] = q_in[QIX(m, e, j)];
+      }
+      riemann_var(0, Zc[VIX(e - 1, j)], cc[VIX(e - 1, j)], Zc[VIX(e, j)], cc[VIX(e, j)], ql, qr,
+                  W[e + 1], s, am, ap);
+      if (e >= 0 && e <= mx)
+        for (int m = 0; m < NM; ++m) {
+          amdq_x[AX(j, e) + m] = am[m];
+          apdq_x[AX(j, e) + m] = ap[m];
+        }
+    }
+    if (j >= 0 && j < my)
+      for (int e = 0; e <= mx; ++e) {
+        const double sp[2] = {-cc[VIX(e - 1, j)], cc[VIX(e, j)]};
+        for (int p = 0; p < 2; ++p) {
+          const int up = p == 0 ? e + 1 : e - 1; /* wave 0 goes left, wave 1 right */
+          double wl[NM];
+          limit_wave(limiter, W[e + 1][p], W[up + 1][p], -1, wl, NULL);
+          const double coef = 0.5 * fabs(sp[p]) * (1.0 - dtdx * fabs(sp[p]));
+          for (int m = 0; m < NM; ++m) Fc[FC(j, e) + m] += coef * wl[m];
+        }
+      }
+    /* transverse: A+dQ at edge e enters cell e, A-dQ enters cell e-1 */
+    for (int e = 0; e <= mx; ++e) {
+      double bm[NM], bp[NM];
+      if (e <= mx - 1) {
+        split_var(1, &apdq_x[AX(j, e)], Zc[VIX(e, j - 1)], cc[VIX(e, j - 1)], Zc[VIX(e, j)],
+                  Zc[VIX(e, j + 1)], cc[VIX(e, j + 1)], bm, bp);
+        for (int m = 0; m < NM; ++m) {
+          Gx_top[GX(j, e) + m] -= 0.5 * dtdx * bp[m];
+          Gx_bot[GX(j, e) + m] -= 0.5 * dtdx * bm[m];
+        }
+      }
+      if (e >= 1) {
+        split_var(1, &amdq_x[AX(j, e)], Zc[VIX(e - 1, j - 1)], cc[VIX(e - 1, j - 1)],
+                  Zc[VIX(e - 1, j)], Zc[VIX(e - 1, j + 1)], cc[VIX(e - 1, j + 1)], bm, bp);
+        for (int m = 0; m < NM; ++m) {
+          Gx_top[GX(j, e - 1) + m] -= 0.5 * dtdx * bp[m];
+          Gx_bot[GX(j, e - 1) + m] -= 0.5 * dtdx * bm[m];
+        }
+      }
+    }
+    free(W);
+  }
+
+  /* ---- y-direction: columns i = -1..mx ---- */
+  for (int i = -1; i <= mx; ++i) {
+    double(*W)[2][NM] = malloc(sizeof(double[2][NM]) * (size_t)(my + 3));
+    for (int f = -1; f <= my + 1; ++f) {
+      double ql[NM], qr[NM], bm[NM], bp[NM], s[2];
+      for (int m = 0; m < NM; ++m) {
+        ql[m] = q_in[QIX(m, i, f - 1)];
+        qr[m] = q_in[QIX(m, i, f)];
+      }
+      riemann_var(1, Zc[VIX(i, f - 1)], cc[VIX(i, f - 1)], Zc[VIX(i, f)], cc[VIX(i, f)], ql, qr,
+                  W[f + 1], s, bm, bp);
+      if (f >= 0 && f <= my)
+        for (int m = 0; m < NM; ++m) {
+          amdq_y[AY(f, i) + m] = bm[m];
+          apdq_y[AY(f, i) + m] = bp[m];
+        }
+    }
+    if (i >= 0 && i < mx)
+      for (int f = 0; f <= my; ++f) {
+        const double sp[2] = {-cc[VIX(i, f - 1)], cc[VIX(i, f)]};
+        for (int p = 0; p < 2; ++p) {
+          const int up = p == 0 ? f + 1 : f - 1;
+          double wl[NM];
+          limit_wave(limiter, W[f + 1][p], W[up + 1][p], -1, wl, NULL);
+          const double coef = 0.5 * fabs(sp[p]) * (1.0 - dtdy * fabs(sp[p]));
+          for (int m = 0; m < NM; ++m) Gc[GC(f, i) + m] += coef * wl[m];
+        }
+      }
+    for (int f = 0; f <= my; ++f) {
+      double am[NM], ap[NM];
+      if (f <= my - 1) { /* B+dQ at edge f enters cell (i, f) */
+        split_var(0, &apdq_y[AY(f, i)], Zc[VIX(i - 1, f)], cc[VIX(i - 1, f)], Zc[VIX(i, f)],
+                  Zc[VIX(i + 1, f)], cc[VIX(i + 1, f)], am, ap);
+        for (int m = 0; m < NM; ++m) {
+          Fy_right[FY(f, i) + m] -= 0.5 * dtdy * ap[m];
+          Fy_left[FY(f, i) + m] -= 0.5 * dtdy * am[m];
+        }
+      }
+      if (f >= 1) { /* B-dQ at edge f enters cell (i, f-1) */
+        split_var(0, &amdq_y[AY(f, i)], Zc[VIX(i - 1, f - 1)], cc[VIX(i - 1, f - 1)],
+                  Zc[VIX(i, f - 1)], Zc[VIX(i + 1, f - 1)], cc[VIX(i + 1, f - 1)], am, ap);
+        for (int m = 0; m < NM; ++m) {
+          Fy_right[FY(f - 1, i) + m] -= 0.5 * dtdy * ap[m];
+          Fy_left[FY(f - 1, i) + m] -= 0.5 * dtdy * am[m];
+        }
+      }
+    }
+    free(W);
+  }
+
+  /* ---- update, eq. (2.3) ---- */
+  if (q_out != q_in) memcpy(q_out, q_in, sizeof(double) * NM * np);
+  for (int j = 0; j < my; ++j)
+    for (int i = 0; i < mx; ++i)
+      for (int m = 0; m < NM; ++m) {
+        const double FL = Fc[FC(j, i) + m] + Fy_right[FY(j, i - 1) + m] + Fy_left[FY(j, i) + m];
+        const double FR = Fc[FC(j, i + 1) + m] + Fy_right[FY(j, i) + m] + Fy_left[FY(j, i + 1) + m];
+        const double GB = Gc[GC(j, i) + m] + Gx_top[GX(j - 1, i) + m] + Gx_bot[GX(j, i) + m];
+        const double GT = Gc[GC(j + 1, i) + m] + Gx_top[GX(j, i) + m] + Gx_bot[GX(j + 1, i) + m];
+        const double fluct_x = apdq_x[AX(j, i) + m] + amdq_x[AX(j, i + 1) + m];
+        const double fluct_y = apdq_y[AY(j, i) + m] + amdq_y[AY(j + 1, i) + m];
+        q_out[QIX(m, i, j)] = q_in[QIX(m, i, j)] - dtdx * fluct_x - dtdy * fluct_y -
+                              dtdx * (FR - FL) - dtdy * (GT - GB);
+      }
+
+  /* ---- Courant number over the edges of interior cells ---- */
+  if (cfl_out) {
+    double cfl = 0.0;
+    for (int j = 0; j < my; ++j)
+      for (int e = 0; e <= mx; ++e)
+        cfl = fmax(cfl, fmax(cc[VIX(e - 1, j)], cc[VIX(e, j)]) * dtdx);
+    for (int f = 0; f <= my; ++f)
+      for (int i = 0; i < mx; ++i)
+        cfl = fmax(cfl, fmax(cc[VIX(i, f - 1)], cc[VIX(i, f)]) * dtdy);
+    *cfl_out = cfl;
+  }
+#undef AX
+#undef AY
+#undef FC
+#undef GC
+#undef GX
+#undef FY
+done:
+  free(Zc); free(cc);
+  free(amdq_x); free(apdq_x); free(amdq_y); free(apdq_y);
+  free(Fc); free(Gc); free(Gx_top); free(Gx_bot); free(Fy_right); free(Fy_left);
+  return rc;
+}
+#undef VIX
+
+/* ---------------------------------------------------------------------- */
 /* Exported single-edge hooks, used by the oracle's own pin tests          */
 /* ---------------------------------------------------------------------- */
 /* Riemann solve at one edge in direction dir (0: x with A, 1: y with B).

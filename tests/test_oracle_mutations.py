@@ -215,3 +215,51 @@ def test_planted_composite_mistake_is_caught(name, tmp_path):
     finally:
         del sys.modules["amr_mutant"]
     assert caught is not None, f"planted mistake {name!r} passed every pin"
+
+
+# --------------------------------------------------------------------------
+# The heterogeneous-medium step: mistakes planted in the C source, checked
+# against the pins of test_oracle_var
+# --------------------------------------------------------------------------
+
+import test_oracle_var as var_pins  # noqa: E402
+
+VAR_MUTATIONS = {
+    "strength_impedance": ("const double a1 = (-dp + Zr * dn) / (Zl + Zr);",
+                           "const double a1 = (-dp + Zl * dn) / (Zl + Zr);"),
+    "left_wave_speed": ("s[0] = -cl;", "s[0] = -cr;"),
+    "transverse_own_impedance": ("const double bd = (-a[0] + Zm * a[n]) / (Zb + Zm);",
+                                 "const double bd = (-a[0] + Zm * a[n]) / (Zm + Zm);"),
+    "transverse_speed": ("minus[0] = -cb * bd * (-Zb);\n  minus[n] = -cb * bd;",
+                         "minus[0] = -ct * bd * (-Zb);\n  minus[n] = -ct * bd;"),
+    "cfl_smaller_speed": ("cfl = fmax(cfl, fmax(cc[VIX(e - 1, j)], cc[VIX(e, j)]) * dtdx);",
+                          "cfl = fmax(cfl, fmin(cc[VIX(e - 1, j)], cc[VIX(e, j)]) * dtdx);"),
+}
+
+VAR_PIN_CALLS = [
+    ("uniform", lambda L: var_pins.test_uniform_medium_is_the_constant_coefficient_step("mc", L)),
+    ("interface_x", lambda L: var_pins.test_interface_riemann_problem_first_step_is_exact(0, L)),
+    ("interface_y", lambda L: var_pins.test_interface_riemann_problem_first_step_is_exact(1, L)),
+    ("cfl", lambda L: var_pins.test_courant_number_is_the_largest_edge_speed(L)),
+    ("transpose", lambda L: var_pins.test_transpose_symmetry(L)),
+    ("energy", lambda L: var_pins.test_mc_step_dissipates_energy_on_a_rough_medium(L)),
+]
+
+
+@pytest.mark.parametrize("name", sorted(VAR_MUTATIONS))
+def test_planted_medium_mistake_is_caught(name, tmp_path):
+    orig, mutated = VAR_MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(orig) == 1, f"mutation anchor for {name} occurs {src.count(orig)} times"
+    mpath = tmp_path / "mutant.c"
+    mpath.write_text(src.replace(orig, mutated))
+    so = oracle_mod.build(str(mpath), str(tmp_path / "libmutant.so"))
+    L = oracle_mod.load_lib(so)
+    caught = None
+    for pin_name, call in VAR_PIN_CALLS:
+        try:
+            call(L)
+        except (AssertionError, ValueError, RuntimeError, FloatingPointError):
+            caught = pin_name
+            break
+    assert caught is not None, f"planted mistake {name!r} passed every pin"
