@@ -128,6 +128,23 @@ int ws_get_tiling(ws_ctx *ctx, int32_t *variant, int32_t *tile_w, int32_t *tile_
 int ws_set_tiling(ws_ctx *ctx, const int32_t *variant, const int32_t *tile_w,
                   const int32_t *tile_h, int32_t wg_per_cu);
 
+/* Heterogeneous medium (the paper's extension to variable coefficients):
+ * rho and K per cell instead of per instance.  medium: caller-owned device
+ * buffer of at least pool_bytes (it holds c and Z per cell, laid out like
+ * the q pools), kept until ws_destroy.  Attaching switches every patch to
+ * DIRECT tiles (MARCH tiles are refused afterwards); the step then uses the
+ * normal solver for two media (waves along (-Z_l, 1, 0) with speed -c_l and
+ * (Z_r, 1, 0) with +c_r), limits on wave vectors, splits transversely with
+ * the impedances of the neighbouring cells, and reduces the Courant number
+ * max over edges of max(c_l, c_r) dt/dx from the cells (the instance's
+ * material is then unused; the instance still owns the dt slot).  Not with
+ * WS_TRANSVERSE_CORR, branch recording, the adjoint or the coarse-fine
+ * coupling.  Synchronises the stream. */
+int ws_attach_medium(ws_ctx *ctx, void *medium, int64_t bytes);
+/* rho, K: host arrays [my+4][mx+4] (ghost cells included: the step reads the
+ * medium of ghost cells next to the patch), finite and > 0.  Synchronises. */
+int ws_upload_medium(ws_ctx *ctx, int32_t patch, const double *rho, const double *K);
+
 /* Copy one patch, host layout, into BOTH pools (ghosts included).  src may be
  * a host or a device pointer.  Synchronises the stream. */
 int ws_upload_patch(ws_ctx *ctx, int32_t patch, const void *src);

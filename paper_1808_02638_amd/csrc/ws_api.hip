@@ -236,6 +236,9 @@ struct ws_ctx {
   hipGraphExec_t gexec = nullptr;
   int graph_steps = 0, graph_start_pool = 0;
   std::vector<InstRow> inst_host;  // (c, Z) per instance, as on the device
+  void *medium = nullptr;          // per-cell (c, Z) planes, laid out like a q pool
+  // limiter code of the kernel launchers (the medium selects its own kernel)
+  int lim_code() const { return limiter | (medium ? kMediumFlag : 0); }
 
   CflSlots slots() {
     CflSlots c;
@@ -267,6 +270,7 @@ struct ws_ctx {
     a.cfl_desired = cfl_desired;
     a.retire = reinterpret_cast<unsigned int *>(ws + L.retire);
     a.masks = nullptr;
+    a.medium = medium;
     return a;
   }
 
@@ -294,7 +298,7 @@ struct ws_ctx {
     if ((int64_t)tiles.size() > L.max_tiles) return fail(WS_EINVAL, "tile list overflow");
     vars = 0;
     for (const PatchRow &r : rows) vars |= (r.variant == kMarch) ? 2 : 1;
-    if (step_occupancy(dtype, limiter, vars, &occupancy) != 0 || occupancy < 1) occupancy = 1;
+    if (step_occupancy(dtype, lim_code(), vars, &occupancy) != 0 || occupancy < 1) occupancy = 1;
     wg_per_cu = wg_override > 0 ? wg_override : occupancy;
     HIPCHK(hipMemcpyAsync(ws + L.patches, rows.data(), rows.size() * sizeof(PatchRow),
                           hipMemcpyHostToDevice, stream));
@@ -439,6 +443,8 @@ int ws_set_tiling(ws_ctx *c, const int32_t *variant, const int32_t *tile_w,
                     tile_h[k]);
       if (v == kMarch && c->rows[k].bc == WS_BC_PERIODIC)
         return fail(WS_EINVAL, "patch %d: periodic patches take DIRECT tiles only", k);
+      if (v == kMarch && c->medium)
+        return fail(WS_EINVAL, "patch %d: a heterogeneous medium takes DIRECT tiles only", k);
       if (v == kMarch && !march_fits(c->rows[k].plane, c->dtype))
         return fail(WS_EINVAL, "patch %d: too large for MARCH tiles (32-bit offsets)", k);
     }
@@ -452,6 +458,52 @@ int ws_set_tiling(ws_ctx *c, const int32_t *variant, const int32_t *tile_w,
   if (wg_per_cu > 0) c->wg_override = wg_per_cu;
   c->drop_graph();
   return c->build_tiles();
+}
+
+int ws_attach_medium(ws_ctx *c, void *medium, int64_t bytes) {
+  if (!c || !medium) return fail(WS_EINVAL, "NULL argument");
+  if (bytes < c->pool_bytes)
+    return fail(WS_ENOMEM, "medium buffer too small (%lld < %lld bytes)", (long long)bytes,
+                (long long)c->pool_bytes);
+  if (c->limiter & WS_TRANSVERSE_CORR)
+    return fail(WS_EINVAL, "a heterogeneous medium needs the default transverse variant");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->medium = medium;
+  // DIRECT tiles (the default DIRECT shape of each patch)
+  for (int k = 0; k < c->n_patches; ++k) {
+    PatchRow &r = c->rows[k];
+    default_tile(r.mx, r.my, WS_BC_PERIODIC, c->n_cu, &r.variant, &r.tw, &r.th);
+  }
+  c->drop_graph();
+  return c->build_tiles();
+}
+
+int ws_upload_medium(ws_ctx *c, int32_t patch, const double *rho, const double *K) {
+  if (!c || !rho || !K) return fail(WS_EINVAL, "NULL argument");
+  if (!c->medium) return fail(WS_ESTATE, "no medium attached");
+  if (patch < 0 || patch >= c->n_patches) return fail(WS_EINVAL, "patch %d out of range", patch);
+  const PatchRow &r = c->rows[patch];
+  const size_t w = (size_t)r.mx + 4, h = (size_t)r.my + 4, n = w * h;
+  const bool f32 = c->dtype == WS_F32;
+  const size_t es = f32 ? 4 : 8;
+  std::vector<char> host(2 * n * es);
+  for (size_t x = 0; x < n; ++x) {
+    if (!(rho[x] > 0.0) || !(K[x] > 0.0) || !std::isfinite(rho[x]) || !std::isfinite(K[x]))
+      return fail(WS_EINVAL, "patch %d: rho and K must be finite and > 0 (cell %zu)", patch, x);
+    const double cs = std::sqrt(K[x] / rho[x]), Z = rho[x] * cs;
+    if (f32) {
+      reinterpret_cast<float *>(host.data())[x] = (float)cs;
+      reinterpret_cast<float *>(host.data())[n + x] = (float)Z;
+    } else {
+      reinterpret_cast<double *>(host.data())[x] = cs;
+      reinterpret_cast<double *>(host.data())[n + x] = Z;
+    }
+  }
+  const int64_t first = r.q_off + r.col0 - 2;  // padded (i=-2, j=-2) of plane 0
+  HIPCHK(hipMemcpy2DAsync(reinterpret_cast<char *>(c->medium) + first * es, r.ld * es,
+                          host.data(), w * es, w * es, 2 * h, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return WS_OK;
 }
 
 int ws_get_tiling(ws_ctx *c, int32_t *variant, int32_t *tile_w, int32_t *tile_h,
@@ -516,7 +568,7 @@ int ws_step_level(ws_ctx *c, double dt, double *cfl_out) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
   // one persistent launch; its last workgroup also files the Courant numbers
   StepArgs a = c->step_args(c->cur, dt, 0.0);
-  HIPCHK(launch_step(c->dtype, c->limiter, c->vars, a, c->grid, c->stream));
+  HIPCHK(launch_step(c->dtype, c->lim_code(), c->vars, a, c->grid, c->stream));
   c->cur = 1 - c->cur;
   return read_level_cfl(c, cfl_out);
 }
@@ -529,7 +581,7 @@ int ws_step_level_per_patch(ws_ctx *c, double dt, double *cfl_out) {
   a.persistent = 0;
   for (int k : c->order) {  // largest patch first
     a.tile_base = c->rows[k].tile_begin;
-    HIPCHK(launch_step(c->dtype, c->limiter, c->vars, a, c->rows[k].n_tiles, c->stream));
+    HIPCHK(launch_step(c->dtype, c->lim_code(), c->vars, a, c->rows[k].n_tiles, c->stream));
   }
   HIPCHK(launch_finish_step(c->slots(), 0.0, c->stream));
   c->cur = 1 - c->cur;
@@ -553,7 +605,7 @@ int ws_set_dt(ws_ctx *c, const double *dt_per_instance) {
 
 static int enqueue_auto(ws_ctx *c, int src, double cfl_desired) {
   StepArgs a = c->step_args(src, 0.0, cfl_desired);
-  HIPCHK(launch_step(c->dtype, c->limiter, c->vars, a, c->grid, c->stream));
+  HIPCHK(launch_step(c->dtype, c->lim_code(), c->vars, a, c->grid, c->stream));
   return WS_OK;
 }
 
@@ -659,13 +711,13 @@ int ws_time_step_kernel(ws_ctx *c, int32_t n_launches, int32_t per_patch, double
       a.persistent = 0;
       for (int k : c->order) {
         a.tile_base = c->rows[k].tile_begin;
-        e = launch_step(c->dtype, c->limiter, c->vars, a, c->rows[k].n_tiles, c->stream);
+        e = launch_step(c->dtype, c->lim_code(), c->vars, a, c->rows[k].n_tiles, c->stream);
         if (e != hipSuccess) break;
       }
       // per-patch launches leave their Courant numbers in the accumulators
       if (e == hipSuccess) e = launch_finish_step(c->slots(), 0.0, c->stream);
     } else if (e == hipSuccess) {
-      e = launch_step(c->dtype, c->limiter, c->vars, a, c->grid, c->stream);
+      e = launch_step(c->dtype, c->lim_code(), c->vars, a, c->grid, c->stream);
     }
     if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], c->stream);
     c->cur = 1 - c->cur;
@@ -703,12 +755,13 @@ int ws_patch_layout(ws_ctx *c, int32_t patch, int64_t *offset, int64_t *ld, int6
 int ws_step_record_masks(ws_ctx *c, double dt, void *masks_dev, double *cfl_out) {
   if (!c) return fail(WS_EINVAL, "ctx is NULL");
   if (!masks_dev) return fail(WS_EINVAL, "masks buffer is NULL");
-  if (c->limiter != WS_LIM_MC)
-    return fail(WS_EINVAL, "branches exist for the MC limiter of the default variant only");
+  if (c->limiter != WS_LIM_MC || c->medium)
+    return fail(WS_EINVAL,
+                "branches exist for the MC limiter of the default variant in a homogeneous medium");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
   StepArgs a = c->step_args(c->cur, dt, 0.0);
   a.masks = reinterpret_cast<uint8_t *>(masks_dev);
-  HIPCHK(launch_step(c->dtype, c->limiter, c->vars, a, c->grid, c->stream));
+  HIPCHK(launch_step(c->dtype, c->lim_code(), c->vars, a, c->grid, c->stream));
   c->cur = 1 - c->cur;
   return read_level_cfl(c, cfl_out);
 }
@@ -722,8 +775,9 @@ static int check_adjoint_ctx(ws_ctx *c) {
 int ws_adjoint_step(ws_ctx *c, double dt, const void *masks_dev, const void *lam_in,
                     void *lam_out) {
   if (int rc = check_adjoint_ctx(c)) return rc;
-  if (c->limiter != WS_LIM_MC)
-    return fail(WS_EINVAL, "the adjoint needs the MC limiter of the default variant");
+  if (c->limiter != WS_LIM_MC || c->medium)
+    return fail(WS_EINVAL,
+                "the adjoint needs the MC limiter of the default variant in a homogeneous medium");
   if (!masks_dev || !lam_in || !lam_out) return fail(WS_EINVAL, "NULL buffer");
   if (lam_in == lam_out) return fail(WS_EINVAL, "lam_in and lam_out must be distinct buffers");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
@@ -857,6 +911,8 @@ int ws_cf_init(ws_cf **out, ws_ctx *coarse, ws_ctx *fine, int32_t ratio,
   if (coarse->limiter & WS_TRANSVERSE_CORR)
     return fail(WS_EINVAL, "the coarse-fine coupling needs the default transverse variant");
   if (coarse->stream != fine->stream) return fail(WS_EINVAL, "the levels must share one stream");
+  if (coarse->medium || fine->medium)
+    return fail(WS_EINVAL, "the coarse-fine coupling needs homogeneous media");
   const CfSizes z = cf_sizes(fine, ratio);
   if (ws_bytes < z.total)
     return fail(WS_ENOMEM, "coupling workspace too small (%lld < %lld bytes)", (long long)ws_bytes,
@@ -948,7 +1004,7 @@ int ws_cf_step(ws_cf *cf, double dt) {
   // the coarse step; Q_c^n stays in the pool it read
   {
     StepArgs s = c->step_args(c->cur, dt, 0.0);
-    HIPCHK(launch_step(c->dtype, c->limiter, c->vars, s, c->grid, c->stream));
+    HIPCHK(launch_step(c->dtype, c->lim_code(), c->vars, s, c->grid, c->stream));
     c->cur = 1 - c->cur;
   }
   a.c_old = c->pool[1 - c->cur];
@@ -965,7 +1021,7 @@ int ws_cf_step(ws_cf *cf, double dt) {
       if (int rc = ws_cf_step(cf->inner, dtf)) return rc;
     } else {
       StepArgs s = f->step_args(f->cur, dtf, 0.0);
-      HIPCHK(launch_step(f->dtype, f->limiter, f->vars, s, f->grid, f->stream));
+      HIPCHK(launch_step(f->dtype, f->lim_code(), f->vars, s, f->grid, f->stream));
       f->cur = 1 - f->cur;
     }
   }

@@ -80,7 +80,12 @@ struct StepArgs {
   CflSlots slots;
   unsigned int *retire;  // (kGroups + 1) counters, kLine apart
   uint8_t *masks;        // nullptr unless the branches are recorded
+  const void *medium;    // nullptr, or per-cell (c, Z) planes laid out like a q pool
 };
+
+// Bit OR-ed into the limiter code of the kernel launchers when the level has a
+// heterogeneous medium (DIRECT tiles only).
+constexpr int kMediumFlag = 0x10000;
 
 // Kernel launchers (defined in ws_kernels.hip).
 // vars: bit 0 -> DIRECT tiles present, bit 1 -> MARCH tiles present.

@@ -254,6 +254,150 @@ __device__ __attribute__((always_inline)) inline void cell_update_tc(const Plane
   update<T>(k, p0, u0, v0, xs0, xd0, ys0, yd0, FLp, FLu, FRp, FRu, GBp, GBv, GTp, GTv, pn, un, vn);
 }
 
+// --------------------------------------------------------------------------
+// Heterogeneous medium: c and Z per cell (planes 0 and 1 of the medium pool)
+// --------------------------------------------------------------------------
+// Normal solve at the edge between cells l and r: strengths of the wave
+// along (-Z_l, 1, 0) (speed -c_l) and of the wave along (Z_r, 1, 0) (speed
+// +c_r), a1 = (Z_r dn - dp)/(Z_l + Z_r), a2 = (dp + Z_l dn)/(Z_l + Z_r); the
+// fluctuations A-dQ = (c_l Z_l a1, -c_l a1), A+dQ = (c_r Z_r a2, c_r a2).
+// The limiter compares wave vectors, W_up . W / W . W: for wave 1 at edge
+// (l, r) the upwind wave lies at edge (r, rr) along (-Z_r, 1, 0), so the
+// limited strength is psi(a1, a1' (Z_r Z_l + 1)/(Z_l^2 + 1)); mirror for
+// wave 2.  The correction at the edge is
+//   Fc = 1/2 c_l (1 - c_l dt/dx) a1~ (-Z_l, 1, 0) + 1/2 c_r (1 - c_r dt/dx) a2~ (Z_r, 1, 0).
+// A cell's fluctuations (X_p, X_u) = (c Z xs, c xd); split by B with the
+// cells below (b) and above (t), B-X = c_b X_p/(Z_b + Z) (-Z_b, 0, 1) and
+// B+X = c_t X_p/(Z + Z_t) (Z_t, 0, 1): the G~ of the edge (b, t) gets
+//   -dt/(2dx) (c_t Z_t X_p(b) - c_b Z_b X_p(t), c_t X_p(b) + c_b X_p(t)) / (Z_b + Z_t)
+// (p and v), sharing the edge's 1/(Z_b + Z_t); F~ alike.
+template <typename T>
+__device__ inline void var_strengths(T Zl, T Zr, T dp, T dn, T &a1, T &a2, T &iz) {
+  iz = T(1) / (Zl + Zr);
+  a1 = (Zr * dn - dp) * iz;
+  a2 = (dp + Zl * dn) * iz;
+}
+
+// Limited strengths at the edge (l, r) given the upwind strengths a1u (edge
+// (r, rr)) and a2u (edge (ll, l)) and the per-cell 1/(Z^2 + 1) of l and r.
+template <typename T, int LIM>
+__device__ inline void var_limited(T a1, T a2, T a1u, T a2u, T Zl, T Zr, T wl, T wr, T &l1,
+                                   T &l2) {
+  const T zz = Zl * Zr + T(1);
+  l1 = limited<T, LIM>(a1, a1u * (zz * wl));
+  l2 = limited<T, LIM>(a2, a2u * (zz * wr));
+}
+
+// Normal correction (p, normal velocity) at an edge.
+template <typename T>
+__device__ inline void var_corr(T cl, T Zl, T cr, T Zr, T l1, T l2, T dtdx, T &Fp, T &Fn) {
+  const T gl = T(0.5) * cl * (T(1) - cl * dtdx), gr = T(0.5) * cr * (T(1) - cr * dtdx);
+  Fp = gr * Zr * l2 - gl * Zl * l1;
+  Fn = gl * l1 + gr * l2;
+}
+
+// DIRECT update of cell (i, j) in a heterogeneous medium (13-point footprint
+// of q and of (c, Z)); cfl receives the largest |s| dt/dx over its four edges.
+template <typename T, int LIM>
+__device__ inline void cell_update_var(const Planes<T> &q, const Planes<T> &md, int i, int j,
+                                       const Coef<T> &k, T &pn, T &un, T &vn, T &cfl) {
+  const T dtdx = k.dtdx, dtdy = k.dtdy;
+  // row j, cells i-2 .. i+2; x-edges e = 0..3 are i-3/2 .. i+3/2
+  T P[5], U[5], Cx[5], Zx[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    P[d] = q.P(i + d - 2, j), U[d] = q.U(i + d - 2, j);
+    Cx[d] = md.P(i + d - 2, j), Zx[d] = md.U(i + d - 2, j);
+  }
+  T a1[4], a2[4], izx[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    var_strengths(Zx[e], Zx[e + 1], P[e + 1] - P[e], U[e + 1] - U[e], a1[e], a2[e], izx[e]);
+  // column i, cells j-2 .. j+2; y-edges f = 0..3 are j-3/2 .. j+3/2
+  T Q[5], V[5], Cy[5], Zy[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    Q[d] = q.P(i, j + d - 2), V[d] = q.V(i, j + d - 2);
+    Cy[d] = md.P(i, j + d - 2), Zy[d] = md.U(i, j + d - 2);
+  }
+  T b1[4], b2[4], izy[4];
+#pragma unroll
+  for (int f = 0; f < 4; ++f)
+    var_strengths(Zy[f], Zy[f + 1], Q[f + 1] - Q[f], V[f + 1] - V[f], b1[f], b2[f], izy[f]);
+  // 1/(Z^2 + 1) of the cells next to the cell's edges
+  const T w0 = T(1) / (Zx[2] * Zx[2] + T(1));
+  const T wxl = T(1) / (Zx[1] * Zx[1] + T(1)), wxr = T(1) / (Zx[3] * Zx[3] + T(1));
+  const T wyb = T(1) / (Zy[1] * Zy[1] + T(1)), wyt = T(1) / (Zy[3] * Zy[3] + T(1));
+
+  // x-fluctuation p-part of the cells below and above (rows j-1, j+1)
+  auto xp_row = [&](int jj) {
+    const T pl = q.P(i - 1, jj), p0 = q.P(i, jj), pr = q.P(i + 1, jj);
+    const T ul = q.U(i - 1, jj), u0 = q.U(i, jj), ur = q.U(i + 1, jj);
+    const T Zl = md.U(i - 1, jj), Z0 = md.U(i, jj), Zr = md.U(i + 1, jj), c0 = md.P(i, jj);
+    T s1l, s2l, izl, s1r, s2r, izr;
+    var_strengths(Zl, Z0, p0 - pl, u0 - ul, s1l, s2l, izl);
+    var_strengths(Z0, Zr, pr - p0, ur - u0, s1r, s2r, izr);
+    return c0 * Z0 * (s2l + s1r);
+  };
+  // y-fluctuation p-part of the cells left and right (columns i-1, i+1)
+  auto yp_col = [&](int ii) {
+    const T pb = q.P(ii, j - 1), p0 = q.P(ii, j), pt = q.P(ii, j + 1);
+    const T vb = q.V(ii, j - 1), v0 = q.V(ii, j), vt = q.V(ii, j + 1);
+    const T Zb = md.U(ii, j - 1), Z0 = md.U(ii, j), Zt = md.U(ii, j + 1), c0 = md.P(ii, j);
+    T s1b, s2b, izb, s1t, s2t, izt;
+    var_strengths(Zb, Z0, p0 - pb, v0 - vb, s1b, s2b, izb);
+    var_strengths(Z0, Zt, pt - p0, vt - v0, s1t, s2t, izt);
+    return c0 * Z0 * (s2b + s1t);
+  };
+  const T c0 = Cx[2], Z0 = Zx[2];
+  const T xs0 = a2[1] + a1[2], xd0 = a2[1] - a1[2];
+  const T ys0 = b2[1] + b1[2], yd0 = b2[1] - b1[2];
+  const T Xp0 = c0 * Z0 * xs0, Yp0 = c0 * Z0 * ys0;
+  const T Xpb = xp_row(j - 1), Xpt = xp_row(j + 1);
+  const T Ypl = yp_col(i - 1), Ypr = yp_col(i + 1);
+
+  // F~ at x-edges i-1/2 (cells 1, 2) and i+1/2 (cells 2, 3)
+  T FLp, FLu, FRp, FRu;
+  {
+    T l1, l2;
+    var_limited<T, LIM>(a1[1], a2[1], a1[2], a2[0], Zx[1], Zx[2], wxl, w0, l1, l2);
+    var_corr(Cx[1], Zx[1], Cx[2], Zx[2], l1, l2, dtdx, FLp, FLu);
+    const T h = T(0.5) * dtdy * izx[1];
+    FLp -= h * (Cx[2] * Zx[2] * Ypl - Cx[1] * Zx[1] * Yp0);
+    FLu -= h * (Cx[2] * Ypl + Cx[1] * Yp0);
+  }
+  {
+    T l1, l2;
+    var_limited<T, LIM>(a1[2], a2[2], a1[3], a2[1], Zx[2], Zx[3], w0, wxr, l1, l2);
+    var_corr(Cx[2], Zx[2], Cx[3], Zx[3], l1, l2, dtdx, FRp, FRu);
+    const T h = T(0.5) * dtdy * izx[2];
+    FRp -= h * (Cx[3] * Zx[3] * Yp0 - Cx[2] * Zx[2] * Ypr);
+    FRu -= h * (Cx[3] * Yp0 + Cx[2] * Ypr);
+  }
+  // G~ at y-edges j-1/2 (cells 1, 2) and j+1/2 (cells 2, 3)
+  T GBp, GBv, GTp, GTv;
+  {
+    T l1, l2;
+    var_limited<T, LIM>(b1[1], b2[1], b1[2], b2[0], Zy[1], Zy[2], wyb, w0, l1, l2);
+    var_corr(Cy[1], Zy[1], Cy[2], Zy[2], l1, l2, dtdy, GBp, GBv);
+    const T h = T(0.5) * dtdx * izy[1];
+    GBp -= h * (Cy[2] * Zy[2] * Xpb - Cy[1] * Zy[1] * Xp0);
+    GBv -= h * (Cy[2] * Xpb + Cy[1] * Xp0);
+  }
+  {
+    T l1, l2;
+    var_limited<T, LIM>(b1[2], b2[2], b1[3], b2[1], Zy[2], Zy[3], w0, wyt, l1, l2);
+    var_corr(Cy[2], Zy[2], Cy[3], Zy[3], l1, l2, dtdy, GTp, GTv);
+    const T h = T(0.5) * dtdx * izy[2];
+    GTp -= h * (Cy[3] * Zy[3] * Xp0 - Cy[2] * Zy[2] * Xpt);
+    GTv -= h * (Cy[3] * Xp0 + Cy[2] * Xpt);
+  }
+  pn = P[2] - dtdx * (Xp0 + (FRp - FLp)) - dtdy * (Yp0 + (GTp - GBp));
+  un = U[2] - dtdx * (c0 * xd0 + (FRu - FLu));
+  vn = V[2] - dtdy * (c0 * yd0 + (GTv - GBv));
+  cfl = fmax(fmax(fmax(Cx[1], Cx[2]), Cx[3]) * dtdx, fmax(fmax(Cy[1], Cy[2]), Cy[3]) * dtdy);
+}
+
 // Store a new cell value and, on physical boundaries, its ghost images.  Up
 // to 5 column and 5 row positions (the cell and its images); the loops are
 // fully unrolled so everything stays in registers.
@@ -849,7 +993,7 @@ __device__ inline double wave_max(double v) {
 // Courant number.  No barrier: wavefronts take units independently.
 // VARS: bit 0 -> DIRECT tiles may occur, bit 1 -> MARCH tiles may occur.
 // TC: the transverse-correction variant (never with MASKS).
-template <typename T, int LIM, bool MASKS, int VARS, bool TC>
+template <typename T, int LIM, bool MASKS, int VARS, bool TC, bool VAR = false>
 __device__ __attribute__((always_inline)) inline double do_unit(const StepArgs &a, int t, int q) {
   const TileEntry te = uniform_row(a.tiles[t]);
   const PatchRow pr = uniform_row(a.patches[te.patch]);
@@ -893,6 +1037,21 @@ __device__ __attribute__((always_inline)) inline double do_unit(const StepArgs &
     const int j0 = te.ty * pr.th + ly * rows_per_thread;
     const int j1 = min(j0 + rows_per_thread, pr.my);
     const Planes<T> q{qi, qi + pr.plane, qi + 2 * pr.plane, pr.ld};
+    if constexpr (VAR) {
+      // heterogeneous medium: the tile's Courant number is reduced from its cells
+      const T *mi = reinterpret_cast<const T *>(a.medium) + org;
+      const Planes<T> md{mi, mi + pr.plane, mi + 2 * pr.plane, pr.ld};
+      T cfl = T(0);
+      if (i < pr.mx && j0 < j1) {
+        for (int j = j0; j < j1; ++j) {
+          T pn, un, vn, cj;
+          cell_update_var<T, LIM>(q, md, i, j, k, pn, un, vn, cj);
+          cfl = fmax(cfl, cj);
+          store<T>(qo, pr.plane, pr.ld, i, j, pr.mx, pr.my, pr.bc, pn, un, vn);
+        }
+      }
+      return wave_max((double)cfl);
+    }
     if (i < pr.mx && j0 < j1) {
       for (int j = j0; j < j1; ++j) {
         T pn, un, vn;
@@ -996,7 +1155,18 @@ __device__ inline void file_tile(const StepArgs &a, int group, CflRun &run, int 
 // round-robin (largest patches first), with no atomics; the four wavefronts
 // of a workgroup work the four quarters of its tile independently.  With a
 // grid of one workgroup per tile the hardware dispatcher balances the load.
-template <typename T, int LIM, bool MASKS, int VARS, bool TC>
+// Heterogeneous medium: the four wavefronts' Courant numbers of a tile.
+__device__ inline double tile_max(double m, int lane, int wave) {
+  __shared__ double s_m[kThreads / 64];
+  if (lane == 0) s_m[wave] = m;
+  __syncthreads();
+  double r = s_m[0];
+  for (int w = 1; w < kThreads / 64; ++w) r = fmax(r, s_m[w]);
+  __syncthreads();
+  return r;
+}
+
+template <typename T, int LIM, bool MASKS, int VARS, bool TC, bool VAR = false>
 __device__ __attribute__((always_inline)) inline void step_body(const StepArgs &a) {
   CflRun run;  // meaningful in lane 0 of each wavefront
   const int lane = (int)threadIdx.x & 63;
@@ -1004,7 +1174,8 @@ __device__ __attribute__((always_inline)) inline void step_body(const StepArgs &
   if (!a.persistent) {
     const int t = a.tile_base + (int)blockIdx.x;
     if (t < a.n_tiles) {
-      const double m = do_unit<T, LIM, MASKS, VARS, TC>(a, t, wave);
+      double m = do_unit<T, LIM, MASKS, VARS, TC, VAR>(a, t, wave);
+      if constexpr (VAR) m = tile_max(m, lane, wave);
       if (lane == 0) {
         file_tile(a, 0, run, t, m);
         flush_cfl(a, 0, run);
@@ -1019,7 +1190,8 @@ __device__ __attribute__((always_inline)) inline void step_body(const StepArgs &
   const int beg = (int)((int64_t)a.n_tiles * x / groups);
   const int end = (int)((int64_t)a.n_tiles * (x + 1) / groups);
   for (int t = beg + y; t < end; t += in_group) {
-    const double m = do_unit<T, LIM, MASKS, VARS, TC>(a, t, wave);
+    double m = do_unit<T, LIM, MASKS, VARS, TC, VAR>(a, t, wave);
+    if constexpr (VAR) m = tile_max(m, lane, wave);
     if (lane == 0 && wave == 0) file_tile(a, x, run, t, m);
   }
   // Retire: the workgroup's values are filed (and waited for) before its
@@ -1051,6 +1223,12 @@ __device__ __attribute__((always_inline)) inline void step_body(const StepArgs &
 template <typename T, int LIM, bool MASKS, int VARS, bool TC>
 __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a) {
   step_body<T, LIM, MASKS, VARS, TC>(a);
+}
+
+// Heterogeneous media: DIRECT tiles only.
+template <typename T, int LIM>
+__global__ __launch_bounds__(kThreads) void step_kernel_var(StepArgs a) {
+  step_body<T, LIM, false, 1, false, true>(a);
 }
 
 // MARCH-only levels: a kernel of their own, free of the DIRECT path's registers.
@@ -1232,9 +1410,29 @@ hipError_t launch_step_m(bool tc, int vars, const StepArgs &a, int grid, hipStre
   return launch_step_v<T, LIM, false, false>(vars, a, grid, s);
 }
 
-// limiter: WS_LIM_*, optionally with WS_TRANSVERSE_CORR.
+template <typename T>
+hipError_t launch_step_var(int lim, const StepArgs &a, int grid, hipStream_t s) {
+  if (a.masks) return hipErrorInvalidValue;
+  switch (lim) {
+    case WS_LIM_NONE:
+      hipLaunchKernelGGL((step_kernel_var<T, WS_LIM_NONE>), dim3(grid), dim3(kThreads), 0, s, a);
+      break;
+    case WS_LIM_VANLEER:
+      hipLaunchKernelGGL((step_kernel_var<T, WS_LIM_VANLEER>), dim3(grid), dim3(kThreads), 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((step_kernel_var<T, WS_LIM_MC>), dim3(grid), dim3(kThreads), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+// limiter: WS_LIM_*, optionally with WS_TRANSVERSE_CORR or kMediumFlag.
 template <typename T>
 hipError_t launch_step_l(int limiter, int vars, const StepArgs &a, int grid, hipStream_t s) {
+  if (limiter & kMediumFlag) {
+    if (vars != 1 || !a.medium || (limiter & WS_TRANSVERSE_CORR)) return hipErrorInvalidValue;
+    return launch_step_var<T>(limiter & 0xff, a, grid, s);
+  }
   const bool tc = (limiter & WS_TRANSVERSE_CORR) != 0;
   switch (limiter & ~WS_TRANSVERSE_CORR) {
     case WS_LIM_NONE: return launch_step_m<T, WS_LIM_NONE>(tc, vars, a, grid, s);
@@ -1279,6 +1477,23 @@ hipError_t launch_step(int dtype, int limiter, int vars, const StepArgs &a, int 
 
 template <typename T>
 int occupancy_l(int limiter, int vars, int *wg_per_cu) {
+  if (limiter & kMediumFlag) {
+    hipError_t e;
+    switch (limiter & 0xff) {
+      case WS_LIM_NONE:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, step_kernel_var<T, WS_LIM_NONE>,
+                                                         kThreads, 0);
+        break;
+      case WS_LIM_VANLEER:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            wg_per_cu, step_kernel_var<T, WS_LIM_VANLEER>, kThreads, 0);
+        break;
+      default:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, step_kernel_var<T, WS_LIM_MC>,
+                                                         kThreads, 0);
+    }
+    return e == hipSuccess ? 0 : -1;
+  }
   const bool tc = (limiter & WS_TRANSVERSE_CORR) != 0;
   switch (limiter & ~WS_TRANSVERSE_CORR) {
     case WS_LIM_NONE: return occupancy_t<T, WS_LIM_NONE>(tc, vars, wg_per_cu);

@@ -86,6 +86,26 @@ class Level:
             ctypes.c_void_p(self.stream.cuda_stream)))
         self._ctx = ctx
 
+    # ------------------------------------------------------------ medium
+    def set_medium(self, k: int, rho, K) -> None:
+        """Heterogeneous medium of patch k: rho, K as (my+4, mx+4) arrays (ghost
+        cells included).  The first call attaches a medium buffer to the level
+        (every patch then takes DIRECT tiles); patches never given a medium
+        keep whatever the buffer holds, so give every patch one."""
+        mx, my = self.shapes[k]
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        K = np.ascontiguousarray(K, dtype=np.float64)
+        if rho.shape != (my + 4, mx + 4) or K.shape != rho.shape:
+            raise ValueError(f"patch {k}: rho and K must have shape {(my + 4, mx + 4)}")
+        if getattr(self, "medium", None) is None:
+            self.medium = torch.empty(self.pool_bytes, dtype=torch.uint8, device=self.device)
+            torch.cuda.synchronize(self.device)
+            C.check(self._L.ws_attach_medium(self._ctx, ctypes.c_void_p(self.medium.data_ptr()),
+                                             self.pool_bytes))
+        dp = ctypes.POINTER(ctypes.c_double)
+        C.check(self._L.ws_upload_medium(self._ctx, k, rho.ctypes.data_as(dp),
+                                         K.ctypes.data_as(dp)))
+
     # ------------------------------------------------------------------ data
     def upload(self, k: int, q) -> None:
         """Patch k's state in host layout (3, my+4, mx+4): a numpy array, or a
