@@ -109,7 +109,12 @@ PIN_CALLS = [
 
 
 # anchors that occur in both the forward step and the adjoint: which occurrence
-OCCURRENCE = {"correction_weight_sign": (0, 2), "adjoint_correction_weight": (1, 2)}
+# (the heterogeneous-medium step repeats some lines of the homogeneous one, which
+# comes first in the file: the mistakes are planted in the homogeneous step)
+OCCURRENCE = {"correction_weight_sign": (0, 2), "adjoint_correction_weight": (1, 2),
+              "transverse_factor": (0, 2), "transverse_swapped_parts": (0, 2),
+              "y_transverse_swapped_parts": (0, 2), "dropped_transverse_term": (0, 2),
+              "flux_difference_sign": (0, 2), "y_fluctuation_edges_swapped": (0, 2)}
 
 
 def _plant(src, name):
