@@ -100,6 +100,59 @@ def run_uniform(ws, torch, n, steps, warmup, dtype, kernel_launches, tune=True, 
                 kernel_ms=kernel_ms, tiling=tiling)
 
 
+def run_medium(ws, torch, n=2048, steps=200, warmup=10, tune=True):
+    """The 2048^2 FP64 pulse in a heterogeneous medium (three layers, +-10%
+    cell perturbation): DIRECT tiles of the variable-coefficient kernel,
+    CFL 0.9 from the device reduction over the cells, steps in one hipGraph."""
+    import numpy as np
+
+    import workloads
+
+    dx = 1.0 / n
+    rho, K = workloads.layered_medium(n, n)
+    lev = ws.Level([dict(mx=n, my=n, dx=dx, dy=dx, bc="extrap")], [(RHO, K_BULK)])
+    lev.set_medium(0, rho, K)
+    q0 = workloads.padded_state(n, n, 0.0, 0.0, dx, dx)
+    dt0 = 0.9 * dx / float(np.sqrt(K / rho).max())
+
+    def reset():
+        lev.upload(0, q0)
+        lev.fill_ghosts()
+        lev.set_dt([dt0])
+
+    reset()
+    if tune:
+        from paper_1808_02638_amd.autotune import autotune
+        autotune(lev)
+    var, tw, th, wg, grid = lev.get_tiling()
+    reset()
+    for _ in range(warmup):
+        lev.step_auto(0.9)
+    reset()
+    lev.capture(steps, 0.9)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(lev.stream)
+    lev.graph_launch()
+    e1.record(lev.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    _dt, cfl_last, cfl_max = lev.read_dt_cfl()
+    finite = bool(np.isfinite(lev.download(0)).all())
+    lev.close()
+    padded = (n + 4) * (n + 4)
+    nbytes = algorithmic_bytes([(n, n)], 8, True) + 2 * 8 * padded  # plus c, Z read once
+    kms = ms / steps
+    return {"grid": f"{n}x{n}", "steps": steps, "value": round(n * n * steps / (ms / 1e3) / 1e9, 3),
+            "kernel_ms": kms, "bytes_per_launch": nbytes,
+            "kernel_GBs": round(nbytes / (kms / 1e3) / 1e9, 1),
+            "frac": round(nbytes / (kms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "tiling": {"variant": var[0], "tile_w": int(tw[0]), "tile_h": int(th[0]),
+                       "wg_per_cu": wg},
+            "cfl_max": float(cfl_max[0]), "finite": finite}
+
+
 def run_amr(ws, torch, dtype, level_steps, tune=True):
     import workloads
 
@@ -483,6 +536,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip FP32, AMR and CPU legs")
     ap.add_argument("--no-tune", action="store_true", help="time the default tiling")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--medium-only", action="store_true",
+                    help="only run the heterogeneous-medium leg (for profiling)")
     ap.add_argument("--levels-only", action="store_true",
                     help="only run the two- and three-level composite legs (for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -508,6 +563,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": args.copy_probe}), flush=True)
+        return
+    if args.medium_only:
+        print(json.dumps({"medium_fp64": run_medium(ws, torch, tune=not args.no_tune)}),
+              flush=True)
         return
     if args.levels_only:
         print(json.dumps({"two_level_fp64": run_two_level(ws, torch, tune=not args.no_tune),
@@ -592,6 +651,7 @@ def main():
                                   "cache_free": copy_bandwidth(torch, 4 * bytes64)}
         line["ensemble_fp64"] = run_ensemble(ws, torch, args.ensemble_steps, tune=not args.no_tune)
         line["adjoint_fp64"] = run_adjoint(ws, torch)
+        line["medium_fp64"] = run_medium(ws, torch, tune=not args.no_tune)
         line["two_level_fp64"] = run_two_level(ws, torch, tune=not args.no_tune)
         line["three_level_fp64"] = run_three_level(ws, torch, tune=not args.no_tune)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)

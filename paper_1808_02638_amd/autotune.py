@@ -44,7 +44,8 @@ def size_classes(level):
 
 
 def candidates(mx, my, periodic):
-    """Tilings worth timing for patches of about mx x my cells."""
+    """Tilings worth timing for patches of about mx x my cells (DIRECT only when
+    ``periodic``: periodic patches and heterogeneous media)."""
     out = []
     for tw in (8, 16, 32, 64, 128):
         if tw > 2 * mx and tw > 8:
@@ -73,6 +74,7 @@ def _key(level):
     hist = sorted({(mx, my, str(level.bcs[k])) for k, (mx, my) in enumerate(level.shapes)})
     h = hashlib.sha1(json.dumps([hist, len(level.shapes)]).encode()).hexdigest()[:16]
     lim = level.limiter + ("+tc" if getattr(level, "transverse_corr", False) else "")
+    lim += "+medium" if getattr(level, "medium", None) is not None else ""
     return f"{arch}|{_library_version()}|{level.dtype}|{lim}|{h}"
 
 
@@ -131,7 +133,7 @@ def autotune(level, *, launches=40, use_cache=True, cache_path=None, verbose=Fal
         idx = classes[c]
         mx = int(np.median([level.shapes[k][0] for k in idx]))
         my = int(np.median([level.shapes[k][1] for k in idx]))
-        for cand in candidates(mx, my, c[2]):
+        for cand in candidates(mx, my, c[2] or getattr(level, "medium", None) is not None):
             if cand == choice[c]:
                 continue
             trial = dict(choice)

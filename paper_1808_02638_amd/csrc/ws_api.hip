@@ -486,22 +486,25 @@ int ws_upload_medium(ws_ctx *c, int32_t patch, const double *rho, const double *
   const size_t w = (size_t)r.mx + 4, h = (size_t)r.my + 4, n = w * h;
   const bool f32 = c->dtype == WS_F32;
   const size_t es = f32 ? 4 : 8;
-  std::vector<char> host(2 * n * es);
+  std::vector<char> host(3 * n * es);
   for (size_t x = 0; x < n; ++x) {
     if (!(rho[x] > 0.0) || !(K[x] > 0.0) || !std::isfinite(rho[x]) || !std::isfinite(K[x]))
       return fail(WS_EINVAL, "patch %d: rho and K must be finite and > 0 (cell %zu)", patch, x);
     const double cs = std::sqrt(K[x] / rho[x]), Z = rho[x] * cs;
     if (f32) {
+      const float Zf = (float)Z;
       reinterpret_cast<float *>(host.data())[x] = (float)cs;
-      reinterpret_cast<float *>(host.data())[n + x] = (float)Z;
+      reinterpret_cast<float *>(host.data())[n + x] = Zf;
+      reinterpret_cast<float *>(host.data())[2 * n + x] = 1.0f / (Zf * Zf + 1.0f);
     } else {
       reinterpret_cast<double *>(host.data())[x] = cs;
       reinterpret_cast<double *>(host.data())[n + x] = Z;
+      reinterpret_cast<double *>(host.data())[2 * n + x] = 1.0 / (Z * Z + 1.0);
     }
   }
   const int64_t first = r.q_off + r.col0 - 2;  // padded (i=-2, j=-2) of plane 0
   HIPCHK(hipMemcpy2DAsync(reinterpret_cast<char *>(c->medium) + first * es, r.ld * es,
-                          host.data(), w * es, w * es, 2 * h, hipMemcpyHostToDevice, c->stream));
+                          host.data(), w * es, w * es, 3 * h, hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   return WS_OK;
 }

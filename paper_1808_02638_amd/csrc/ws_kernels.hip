@@ -255,7 +255,8 @@ __device__ __attribute__((always_inline)) inline void cell_update_tc(const Plane
 }
 
 // --------------------------------------------------------------------------
-// Heterogeneous medium: c and Z per cell (planes 0 and 1 of the medium pool)
+// Heterogeneous medium: c, Z and 1/(Z^2 + 1) per cell (planes 0, 1, 2 of the
+// medium pool)
 // --------------------------------------------------------------------------
 // Normal solve at the edge between cells l and r: strengths of the wave
 // along (-Z_l, 1, 0) (speed -c_l) and of the wave along (Z_r, 1, 0) (speed
@@ -296,40 +297,73 @@ __device__ inline void var_corr(T cl, T Zl, T cr, T Zr, T l1, T l2, T dtdx, T &F
   Fn = gl * l1 + gr * l2;
 }
 
+// One direction of a cell's update in a heterogeneous medium, from the five
+// cells of its row (or column) around it: the normal corrections at its two
+// edges (p and normal velocity), the fluctuation sums xs, xd, and the edge
+// coefficients the transverse terms need.
+template <typename T>
+struct VarLine {
+  T Fl_p, Fl_n, Fr_p, Fr_n;  // normal corrections at the low and high edge
+  T xs, xd;                  // fluctuation sums of the cell
+  T izl, izr;                // 1/(Z_l + Z) and 1/(Z + Z_r) of the two edges
+  T cl, zl, c0, z0, cr, zr;  // c and Z of the cell and its two neighbours
+};
+
+template <typename T, int LIM>
+__device__ inline VarLine<T> var_line(const T P[5], const T N[5], const T C[5], const T Zc[5],
+                                      T wl, T w0, T wr, T dtdx) {
+  T a1[4], a2[4], iz[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    var_strengths(Zc[e], Zc[e + 1], P[e + 1] - P[e], N[e + 1] - N[e], a1[e], a2[e], iz[e]);
+  VarLine<T> L;
+  T l1, l2;
+  var_limited<T, LIM>(a1[1], a2[1], a1[2], a2[0], Zc[1], Zc[2], wl, w0, l1, l2);
+  var_corr(C[1], Zc[1], C[2], Zc[2], l1, l2, dtdx, L.Fl_p, L.Fl_n);
+  var_limited<T, LIM>(a1[2], a2[2], a1[3], a2[1], Zc[2], Zc[3], w0, wr, l1, l2);
+  var_corr(C[2], Zc[2], C[3], Zc[3], l1, l2, dtdx, L.Fr_p, L.Fr_n);
+  L.xs = a2[1] + a1[2];
+  L.xd = a2[1] - a1[2];
+  L.izl = iz[1], L.izr = iz[2];
+  L.cl = C[1], L.zl = Zc[1], L.c0 = C[2], L.z0 = Zc[2], L.cr = C[3], L.zr = Zc[3];
+  return L;
+}
+
 // DIRECT update of cell (i, j) in a heterogeneous medium (13-point footprint
-// of q and of (c, Z)); cfl receives the largest |s| dt/dx over its four edges.
+// of q and of the medium), taken in stages behind scheduling barriers so that
+// only a few values stay live between them; cfl receives the largest
+// |s| dt/dx over its four edges.
 template <typename T, int LIM>
 __device__ inline void cell_update_var(const Planes<T> &q, const Planes<T> &md, int i, int j,
                                        const Coef<T> &k, T &pn, T &un, T &vn, T &cfl) {
   const T dtdx = k.dtdx, dtdy = k.dtdy;
-  // row j, cells i-2 .. i+2; x-edges e = 0..3 are i-3/2 .. i+3/2
-  T P[5], U[5], Cx[5], Zx[5];
+  const T w0 = md.V(i, j);
+  // row j: x-direction
+  VarLine<T> X;
+  {
+    T P[5], U[5], C[5], Z[5];
 #pragma unroll
-  for (int d = 0; d < 5; ++d) {
-    P[d] = q.P(i + d - 2, j), U[d] = q.U(i + d - 2, j);
-    Cx[d] = md.P(i + d - 2, j), Zx[d] = md.U(i + d - 2, j);
+    for (int d = 0; d < 5; ++d) {
+      P[d] = q.P(i + d - 2, j), U[d] = q.U(i + d - 2, j);
+      C[d] = md.P(i + d - 2, j), Z[d] = md.U(i + d - 2, j);
+    }
+    X = var_line<T, LIM>(P, U, C, Z, md.V(i - 1, j), w0, md.V(i + 1, j), dtdx);
   }
-  T a1[4], a2[4], izx[4];
+  __builtin_amdgcn_sched_barrier(0);
+  // column i: y-direction
+  VarLine<T> Y;
+  {
+    T P[5], V[5], C[5], Z[5];
 #pragma unroll
-  for (int e = 0; e < 4; ++e)
-    var_strengths(Zx[e], Zx[e + 1], P[e + 1] - P[e], U[e + 1] - U[e], a1[e], a2[e], izx[e]);
-  // column i, cells j-2 .. j+2; y-edges f = 0..3 are j-3/2 .. j+3/2
-  T Q[5], V[5], Cy[5], Zy[5];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) {
-    Q[d] = q.P(i, j + d - 2), V[d] = q.V(i, j + d - 2);
-    Cy[d] = md.P(i, j + d - 2), Zy[d] = md.U(i, j + d - 2);
+    for (int d = 0; d < 5; ++d) {
+      P[d] = q.P(i, j + d - 2), V[d] = q.V(i, j + d - 2);
+      C[d] = md.P(i, j + d - 2), Z[d] = md.U(i, j + d - 2);
+    }
+    Y = var_line<T, LIM>(P, V, C, Z, md.V(i, j - 1), w0, md.V(i, j + 1), dtdy);
   }
-  T b1[4], b2[4], izy[4];
-#pragma unroll
-  for (int f = 0; f < 4; ++f)
-    var_strengths(Zy[f], Zy[f + 1], Q[f + 1] - Q[f], V[f + 1] - V[f], b1[f], b2[f], izy[f]);
-  // 1/(Z^2 + 1) of the cells next to the cell's edges
-  const T w0 = T(1) / (Zx[2] * Zx[2] + T(1));
-  const T wxl = T(1) / (Zx[1] * Zx[1] + T(1)), wxr = T(1) / (Zx[3] * Zx[3] + T(1));
-  const T wyb = T(1) / (Zy[1] * Zy[1] + T(1)), wyt = T(1) / (Zy[3] * Zy[3] + T(1));
-
-  // x-fluctuation p-part of the cells below and above (rows j-1, j+1)
+  __builtin_amdgcn_sched_barrier(0);
+  // x-fluctuation p-part of the cells below and above, y-fluctuation p-part
+  // of the cells left and right
   auto xp_row = [&](int jj) {
     const T pl = q.P(i - 1, jj), p0 = q.P(i, jj), pr = q.P(i + 1, jj);
     const T ul = q.U(i - 1, jj), u0 = q.U(i, jj), ur = q.U(i + 1, jj);
@@ -339,7 +373,6 @@ __device__ inline void cell_update_var(const Planes<T> &q, const Planes<T> &md, 
     var_strengths(Z0, Zr, pr - p0, ur - u0, s1r, s2r, izr);
     return c0 * Z0 * (s2l + s1r);
   };
-  // y-fluctuation p-part of the cells left and right (columns i-1, i+1)
   auto yp_col = [&](int ii) {
     const T pb = q.P(ii, j - 1), p0 = q.P(ii, j), pt = q.P(ii, j + 1);
     const T vb = q.V(ii, j - 1), v0 = q.V(ii, j), vt = q.V(ii, j + 1);
@@ -349,53 +382,31 @@ __device__ inline void cell_update_var(const Planes<T> &q, const Planes<T> &md, 
     var_strengths(Z0, Zt, pt - p0, vt - v0, s1t, s2t, izt);
     return c0 * Z0 * (s2b + s1t);
   };
-  const T c0 = Cx[2], Z0 = Zx[2];
-  const T xs0 = a2[1] + a1[2], xd0 = a2[1] - a1[2];
-  const T ys0 = b2[1] + b1[2], yd0 = b2[1] - b1[2];
-  const T Xp0 = c0 * Z0 * xs0, Yp0 = c0 * Z0 * ys0;
   const T Xpb = xp_row(j - 1), Xpt = xp_row(j + 1);
+  __builtin_amdgcn_sched_barrier(0);
   const T Ypl = yp_col(i - 1), Ypr = yp_col(i + 1);
-
-  // F~ at x-edges i-1/2 (cells 1, 2) and i+1/2 (cells 2, 3)
-  T FLp, FLu, FRp, FRu;
-  {
-    T l1, l2;
-    var_limited<T, LIM>(a1[1], a2[1], a1[2], a2[0], Zx[1], Zx[2], wxl, w0, l1, l2);
-    var_corr(Cx[1], Zx[1], Cx[2], Zx[2], l1, l2, dtdx, FLp, FLu);
-    const T h = T(0.5) * dtdy * izx[1];
-    FLp -= h * (Cx[2] * Zx[2] * Ypl - Cx[1] * Zx[1] * Yp0);
-    FLu -= h * (Cx[2] * Ypl + Cx[1] * Yp0);
-  }
-  {
-    T l1, l2;
-    var_limited<T, LIM>(a1[2], a2[2], a1[3], a2[1], Zx[2], Zx[3], w0, wxr, l1, l2);
-    var_corr(Cx[2], Zx[2], Cx[3], Zx[3], l1, l2, dtdx, FRp, FRu);
-    const T h = T(0.5) * dtdy * izx[2];
-    FRp -= h * (Cx[3] * Zx[3] * Yp0 - Cx[2] * Zx[2] * Ypr);
-    FRu -= h * (Cx[3] * Yp0 + Cx[2] * Ypr);
-  }
-  // G~ at y-edges j-1/2 (cells 1, 2) and j+1/2 (cells 2, 3)
-  T GBp, GBv, GTp, GTv;
-  {
-    T l1, l2;
-    var_limited<T, LIM>(b1[1], b2[1], b1[2], b2[0], Zy[1], Zy[2], wyb, w0, l1, l2);
-    var_corr(Cy[1], Zy[1], Cy[2], Zy[2], l1, l2, dtdy, GBp, GBv);
-    const T h = T(0.5) * dtdx * izy[1];
-    GBp -= h * (Cy[2] * Zy[2] * Xpb - Cy[1] * Zy[1] * Xp0);
-    GBv -= h * (Cy[2] * Xpb + Cy[1] * Xp0);
-  }
-  {
-    T l1, l2;
-    var_limited<T, LIM>(b1[2], b2[2], b1[3], b2[1], Zy[2], Zy[3], w0, wyt, l1, l2);
-    var_corr(Cy[2], Zy[2], Cy[3], Zy[3], l1, l2, dtdy, GTp, GTv);
-    const T h = T(0.5) * dtdx * izy[2];
-    GTp -= h * (Cy[3] * Zy[3] * Xp0 - Cy[2] * Zy[2] * Xpt);
-    GTv -= h * (Cy[3] * Xp0 + Cy[2] * Xpt);
-  }
-  pn = P[2] - dtdx * (Xp0 + (FRp - FLp)) - dtdy * (Yp0 + (GTp - GBp));
-  un = U[2] - dtdx * (c0 * xd0 + (FRu - FLu));
-  vn = V[2] - dtdy * (c0 * yd0 + (GTv - GBv));
-  cfl = fmax(fmax(fmax(Cx[1], Cx[2]), Cx[3]) * dtdx, fmax(fmax(Cy[1], Cy[2]), Cy[3]) * dtdy);
+  __builtin_amdgcn_sched_barrier(0);
+  const T c0 = X.c0, Z0 = X.z0;
+  const T Xp0 = c0 * Z0 * X.xs, Yp0 = c0 * Z0 * Y.xs;
+  // F~ at x-edges i-1/2 and i+1/2: normal correction and transverse waves
+  // from the y-fluctuations of the cells on either side
+  T h = T(0.5) * dtdy * X.izl;
+  const T FLp = X.Fl_p - h * (X.c0 * X.z0 * Ypl - X.cl * X.zl * Yp0);
+  const T FLu = X.Fl_n - h * (X.c0 * Ypl + X.cl * Yp0);
+  h = T(0.5) * dtdy * X.izr;
+  const T FRp = X.Fr_p - h * (X.cr * X.zr * Yp0 - X.c0 * X.z0 * Ypr);
+  const T FRu = X.Fr_n - h * (X.cr * Yp0 + X.c0 * Ypr);
+  // G~ at y-edges j-1/2 and j+1/2
+  h = T(0.5) * dtdx * Y.izl;
+  const T GBp = Y.Fl_p - h * (Y.c0 * Y.z0 * Xpb - Y.cl * Y.zl * Xp0);
+  const T GBv = Y.Fl_n - h * (Y.c0 * Xpb + Y.cl * Xp0);
+  h = T(0.5) * dtdx * Y.izr;
+  const T GTp = Y.Fr_p - h * (Y.cr * Y.zr * Xp0 - Y.c0 * Y.z0 * Xpt);
+  const T GTv = Y.Fr_n - h * (Y.cr * Xp0 + Y.c0 * Xpt);
+  pn = q.P(i, j) - dtdx * (Xp0 + (FRp - FLp)) - dtdy * (Yp0 + (GTp - GBp));
+  un = q.U(i, j) - dtdx * (c0 * X.xd + (FRu - FLu));
+  vn = q.V(i, j) - dtdy * (c0 * Y.xd + (GTv - GBv));
+  cfl = fmax(fmax(fmax(X.cl, X.c0), X.cr) * dtdx, fmax(fmax(Y.cl, Y.c0), Y.cr) * dtdy);
 }
 
 // Store a new cell value and, on physical boundaries, its ghost images.  Up

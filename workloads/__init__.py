@@ -14,6 +14,7 @@ from .generators import (  # noqa: F401
     adjoint_setup,
     amr_level_batch,
     ensemble,
+    layered_medium,
     padded_centres,
     padded_state,
     plane_wave_state,

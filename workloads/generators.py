@@ -13,7 +13,10 @@ synthetic stand-ins for the paper's AMR run:
 * ``two_level_layout()``  -- a 1024x1024 coarse grid and ratio-4 fine patches
   over the ring's annulus, for the composite step with the conservation fix;
 * ``three_level_layout()`` -- 512x512, ratio-4 level-1 patches over the
-  annulus and ratio-4 level-2 patches inside them near the ring.
+  annulus and ratio-4 level-2 patches inside them near the ring;
+* ``layered_medium()``    -- per-cell rho, K of a heterogeneous medium (two
+  slanted interfaces and a seeded +-10% perturbation) for the variable-
+  coefficient step.
 
 A patch state is a C-contiguous float64 array (3, my+4, mx+4): components
 (p, u, v), two ghost layers on each side, x fastest.
@@ -282,3 +285,18 @@ def three_level_layout(n=512, size=30, gap=3, r=4, r_lo=0.15, r_hi=0.35, r2_lo=0
                 if np.any((rr >= r2_lo) & (rr <= r2_hi)):
                     l2.append((k, a0, b0, size, size))
     return l1, l2
+
+
+def layered_medium(mx, my, seed=18086):
+    """rho and K per padded cell of the unit square: three layers separated by
+    the lines x + 0.3 y = 0.45 and x - 0.2 y = 0.75 (impedances 2, 3 and 1.2;
+    sound speeds 2, 1.2 and 3), each cell perturbed by a factor U(0.9, 1.1)
+    in rho and in K.  Returns (rho, K), each (my+4, mx+4)."""
+    rng = np.random.default_rng(seed)
+    X, Y = padded_centres(mx, my, 0.0, 0.0, 1.0 / mx, 1.0 / my)
+    layer = (X + 0.3 * Y > 0.45).astype(int) + (X - 0.2 * Y > 0.75).astype(int)
+    rho = np.choose(layer, [1.0, 2.5, 0.4])
+    K = np.choose(layer, [4.0, 3.6, 3.6])
+    rho = rho * rng.uniform(0.9, 1.1, size=rho.shape)
+    K = K * rng.uniform(0.9, 1.1, size=K.shape)
+    return np.ascontiguousarray(rho), np.ascontiguousarray(K)
