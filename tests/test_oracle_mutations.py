@@ -237,6 +237,11 @@ VAR_MUTATIONS = {
                                  "const double bd = (-a[0] + Zm * a[n]) / (Zm + Zm);"),
     "transverse_speed": ("minus[0] = -cb * bd * (-Zb);\n  minus[n] = -cb * bd;",
                          "minus[0] = -ct * bd * (-Zb);\n  minus[n] = -ct * bd;"),
+    "transverse_cells_swapped_in_x": (
+        "split_var(1, &apdq_x[AX(j, e)], Zc[VIX(e, j - 1)], cc[VIX(e, j - 1)], Zc[VIX(e, j)],\n"
+        "                  Zc[VIX(e, j + 1)], cc[VIX(e, j + 1)], bm, bp);",
+        "split_var(1, &apdq_x[AX(j, e)], Zc[VIX(e, j + 1)], cc[VIX(e, j + 1)], Zc[VIX(e, j)],\n"
+        "                  Zc[VIX(e, j - 1)], cc[VIX(e, j - 1)], bm, bp);"),
     "cfl_smaller_speed": ("cfl = fmax(cfl, fmax(cc[VIX(e - 1, j)], cc[VIX(e, j)]) * dtdx);",
                           "cfl = fmax(cfl, fmin(cc[VIX(e - 1, j)], cc[VIX(e, j)]) * dtdx);"),
 }
