@@ -31,10 +31,17 @@ edge of the coarse step.  The other three sides are the mirror images.  The
 coarse F~_c enters with weight dt/dx (the printed 1/4 in front of it would
 not conserve; the conservation pin decides).
 
+Same-level ghosts: fine patches of one coarse patch may touch (they must not
+overlap).  A fine ghost cell that lies in a sibling patch takes the sibling's
+value at the same fine step (all fine patches advance in lockstep), every
+other ghost comes from the coarse level as in step 2; a coarse cell covered by
+a sibling takes no fix (updating sets it), and a coarse cell bordered by
+several fine patches takes the fix of each.
+
 Layout: states are padded (3, my+4, mx+4) arrays as in the C oracle.  A fine
 patch covers coarse cells [ci0, ci0+ncx) x [cj0, cj0+ncy), so it has
 r*ncx x r*ncy cells of size dx/r; patches lie at least 2 coarse cells inside
-the coarse patch and at least 3 coarse cells apart.
+the coarse patch and do not overlap.
 """
 
 from __future__ import annotations
@@ -73,8 +80,13 @@ def check_layout(mxc, myc, fines, r):
             fa, fb = fines[a], fines[b]
             gap_x = max(fb.ci0 - (fa.ci0 + fa.ncx), fa.ci0 - (fb.ci0 + fb.ncx))
             gap_y = max(fb.cj0 - (fa.cj0 + fa.ncy), fa.cj0 - (fb.cj0 + fb.ncy))
-            if max(gap_x, gap_y) < 3:
-                raise ValueError("fine patches must be at least 3 coarse cells apart")
+            if max(gap_x, gap_y) < 0:
+                raise ValueError("fine patches must not overlap")
+
+
+def covered_cells(fines):
+    """The coarse cells (ci, cj) that some fine patch covers."""
+    return {(f.ci0 + I, f.cj0 + J) for f in fines for I in range(f.ncx) for J in range(f.ncy)}
 
 
 def mc_slope(a, b):
@@ -95,12 +107,25 @@ def interp_cell(Qt, ci, cj, xi, eta):
     return q0 + xi * sx + eta * sy
 
 
-def fill_fine_ghosts(qf, fp, Qt, r):
-    """Every ghost cell of the fine patch from the coarse state Qt."""
+def fill_fine_ghosts(qf, fp, Qt, r, siblings=()):
+    """Every ghost cell of the fine patch: from the sibling that holds it, if
+    one does, else from the coarse state Qt.  siblings: (FinePatch, current
+    padded state) pairs of the other fine patches of the same coarse patch."""
     myf, mxf = qf.shape[1] - 4, qf.shape[2] - 4
     for j in range(-2, myf + 2):
         for i in range(-2, mxf + 2):
             if 0 <= i < mxf and 0 <= j < myf:
+                continue
+            # global fine index of the ghost, and the sibling that holds it
+            gi, gj = r * fp.ci0 + i, r * fp.cj0 + j
+            src = None
+            for sp, sq in siblings:
+                si, sj = gi - r * sp.ci0, gj - r * sp.cj0
+                if 0 <= si < r * sp.ncx and 0 <= sj < r * sp.ncy:
+                    src = sq[:, sj + 2, si + 2]
+                    break
+            if src is not None:
+                qf[:, j + 2, i + 2] = src
                 continue
             X = fp.ci0 + (i + 0.5) / r  # fine centre in coarse index units
             Y = fp.cj0 + (j + 0.5) / r
@@ -146,25 +171,30 @@ def accumulate_fine(acc, fp, qf, Tf, qc_n, r, rho, K):
         acc["top"][a] += _fsum(1, rho, K, out, g) - Tf["apy"][myf, a] + Tf["Gy"][myf, a]
 
 
-def apply_fix(qc, fp, acc, Tc, dt, dxc, dyc, r):
-    """Conservation fix of the coarse cells around one fine patch."""
+def apply_fix(qc, fp, acc, Tc, dt, dxc, dyc, r, covered=frozenset()):
+    """Conservation fix of the coarse cells around one fine patch; an out
+    cell in `covered` (covered by a sibling, so set by updating) is skipped."""
     w = 1.0 / (r * r)
     for J in range(fp.ncy):
         rows = slice(J * r, (J + 1) * r)
         e = fp.ci0  # left side: the out cell's right edge
-        Pc = Tc["amx"][fp.cj0 + J, e] + Tc["Fx"][fp.cj0 + J, e]
-        qc[:, fp.cj0 + J + 2, fp.ci0 - 1 + 2] -= dt / dxc * (w * acc["left"][rows].sum(axis=0) - Pc)
+        if (e - 1, fp.cj0 + J) not in covered:
+            Pc = Tc["amx"][fp.cj0 + J, e] + Tc["Fx"][fp.cj0 + J, e]
+            qc[:, fp.cj0 + J + 2, fp.ci0 - 1 + 2] -= dt / dxc * (w * acc["left"][rows].sum(axis=0) - Pc)
         e = fp.ci0 + fp.ncx  # right side: the out cell's left edge
-        Pc = -Tc["apx"][fp.cj0 + J, e] + Tc["Fx"][fp.cj0 + J, e]
-        qc[:, fp.cj0 + J + 2, e + 2] += dt / dxc * (w * acc["right"][rows].sum(axis=0) - Pc)
+        if (e, fp.cj0 + J) not in covered:
+            Pc = -Tc["apx"][fp.cj0 + J, e] + Tc["Fx"][fp.cj0 + J, e]
+            qc[:, fp.cj0 + J + 2, e + 2] += dt / dxc * (w * acc["right"][rows].sum(axis=0) - Pc)
     for I in range(fp.ncx):
         cols = slice(I * r, (I + 1) * r)
         f = fp.cj0  # bottom side: the out cell's top edge
-        Pc = Tc["amy"][f, fp.ci0 + I] + Tc["Gy"][f, fp.ci0 + I]
-        qc[:, fp.cj0 - 1 + 2, fp.ci0 + I + 2] -= dt / dyc * (w * acc["bottom"][cols].sum(axis=0) - Pc)
+        if (fp.ci0 + I, f - 1) not in covered:
+            Pc = Tc["amy"][f, fp.ci0 + I] + Tc["Gy"][f, fp.ci0 + I]
+            qc[:, fp.cj0 - 1 + 2, fp.ci0 + I + 2] -= dt / dyc * (w * acc["bottom"][cols].sum(axis=0) - Pc)
         f = fp.cj0 + fp.ncy  # top side: the out cell's bottom edge
-        Pc = -Tc["apy"][f, fp.ci0 + I] + Tc["Gy"][f, fp.ci0 + I]
-        qc[:, f + 2, fp.ci0 + I + 2] += dt / dyc * (w * acc["top"][cols].sum(axis=0) - Pc)
+        if (fp.ci0 + I, f) not in covered:
+            Pc = -Tc["apy"][f, fp.ci0 + I] + Tc["Gy"][f, fp.ci0 + I]
+            qc[:, f + 2, fp.ci0 + I + 2] += dt / dyc * (w * acc["top"][cols].sum(axis=0) - Pc)
 
 
 def two_level_step(qc, fines, dxc, dyc, dt, rho, K, r, limiter="mc", bc="periodic", fix=True):
@@ -178,27 +208,30 @@ def two_level_step(qc, fines, dxc, dyc, dt, rho, K, r, limiter="mc", bc="periodi
     Tc = O.step_terms(qc, dxc, dyc, dt, rho, K, limiter)
     qc1, _, _ = O.step(qc, dxc, dyc, dt, rho, K, limiter)
     O.fill_bc(qc1, bc)
-    new_q, accs = [], []
+    new_q = [fp.q.copy() for fp in fines]
+    accs = []
     for fp in fines:
-        qf = fp.q.copy()
-        myf, mxf = qf.shape[1] - 4, qf.shape[2] - 4
-        acc = {"left": np.zeros((myf, 3)), "right": np.zeros((myf, 3)),
-               "bottom": np.zeros((mxf, 3)), "top": np.zeros((mxf, 3))}
-        for k in range(r):
-            a = k / r
-            Qt = (1.0 - a) * qc + a * qc1
-            fill_fine_ghosts(qf, fp, Qt, r)
-            Tf = O.step_terms(qf, dxf, dyf, dtf, rho, K, limiter)
-            accumulate_fine(acc, fp, qf, Tf, qc, r, rho, K)
-            qf, _, _ = O.step(qf, dxf, dyf, dtf, rho, K, limiter)
-        new_q.append(qf)
-        accs.append(acc)
+        myf, mxf = r * fp.ncy, r * fp.ncx
+        accs.append({"left": np.zeros((myf, 3)), "right": np.zeros((myf, 3)),
+                     "bottom": np.zeros((mxf, 3)), "top": np.zeros((mxf, 3))})
+    for k in range(r):
+        # every fine patch's ghosts (siblings at step k), then every patch's step
+        a = k / r
+        Qt = (1.0 - a) * qc + a * qc1
+        for c, fp in enumerate(fines):
+            sibs = [(fines[d], new_q[d]) for d in range(len(fines)) if d != c]
+            fill_fine_ghosts(new_q[c], fp, Qt, r, sibs)
+        for c, fp in enumerate(fines):
+            Tf = O.step_terms(new_q[c], dxf, dyf, dtf, rho, K, limiter)
+            accumulate_fine(accs[c], fp, new_q[c], Tf, qc, r, rho, K)
+            new_q[c] = O.step(new_q[c], dxf, dyf, dtf, rho, K, limiter)[0]
     qc2 = qc1.copy()
     for fp, qf in zip(fines, new_q):
         average_down(qc2, fp, qf, r)
     if fix:
+        cov = covered_cells(fines)
         for fp, acc in zip(fines, accs):
-            apply_fix(qc2, fp, acc, Tc, dt, dxc, dyc, r)
+            apply_fix(qc2, fp, acc, Tc, dt, dxc, dyc, r, cov)
     O.fill_bc(qc2, bc)
     return qc2, [FinePatch(fp.ci0, fp.cj0, fp.ncx, fp.ncy, q) for fp, q in zip(fines, new_q)]
 
@@ -268,13 +301,19 @@ def multi_level_step(q0, levels, dx0, dy0, dt, rho, K, r, limiter="mc", bc="peri
                 for c, p in enumerate(kids):
                     qf = states[l + 1][c]
                     Qt = (1.0 - a) * old[p.parent] + a * new[p.parent]
-                    fill_fine_ghosts(qf, p, Qt, r)
+                    sibs = [(s, states[l + 1][d]) for d, s in enumerate(kids)
+                            if d != c and s.parent == p.parent]
+                    fill_fine_ghosts(qf, p, Qt, r, sibs)
+                for c, p in enumerate(kids):
+                    qf = states[l + 1][c]
                     Tf = O.step_terms(qf, dx / r, dy / r, dt_l / r, rho, K, limiter)
                     accumulate_fine(accs[c], p, qf, Tf, old[p.parent], r, rho, K)
                 advance(l + 1, dt_l / r, dx / r, dy / r)
             for c, p in enumerate(kids):
                 average_down(new[p.parent], p, states[l + 1][c], r)
-                apply_fix(new[p.parent], p, accs[c], Tc[p.parent], dt_l, dx, dy, r)
+            for c, p in enumerate(kids):
+                cov = covered_cells([s for s in kids if s.parent == p.parent])
+                apply_fix(new[p.parent], p, accs[c], Tc[p.parent], dt_l, dx, dy, r, cov)
             if l == 0:
                 O.fill_bc(new[0], bc)
         states[l] = new

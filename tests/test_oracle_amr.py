@@ -148,10 +148,10 @@ def test_layout_checks(mod=amr_mod):
     bad = [mod.FinePatch(1, 5, 4, 4, np.zeros((3, 12, 12)))]
     with pytest.raises(ValueError):
         mod.check_layout(20, 20, bad, 2)
-    close = [mod.FinePatch(3, 3, 4, 4, np.zeros((3, 12, 12))),
-             mod.FinePatch(9, 3, 4, 4, np.zeros((3, 12, 12)))]
+    overlapping = [mod.FinePatch(3, 3, 4, 4, np.zeros((3, 12, 12))),
+                   mod.FinePatch(6, 3, 4, 4, np.zeros((3, 12, 12)))]
     with pytest.raises(ValueError):
-        mod.check_layout(20, 20, close, 2)
+        mod.check_layout(20, 20, overlapping, 2)
 
 
 # --------------------------------------------------------------------------
@@ -228,3 +228,95 @@ def test_three_levels_ratio_one_equal_single_level(mod=amr_mod):
     for P in lv[0]:
         assert np.array_equal(P.q[:, 2:-2, 2:-2],
                               p[:, 2 + P.cj0:2 + P.cj0 + P.ncy, 2 + P.ci0:2 + P.ci0 + P.ncx])
+
+
+# --------------------------------------------------------------------------
+# Touching fine patches: same-level ghosts and the fix at covered cells
+# --------------------------------------------------------------------------
+
+def _composite_steps(mod, driver, n, rects, r, steps, bc="extrap"):
+    qc = coarse_state(n, smooth)
+    fines = mod.init_fines(qc, rects, r, smooth)
+    O.fill_bc(qc, bc)
+    dt = 0.8 / n / 2.0
+    q, fs = qc, fines
+    for _ in range(steps):
+        if driver == "two":
+            q, fs = mod.two_level_step(q, fs, 1 / n, 1 / n, dt, RHO, KB, r, bc=bc)
+        else:
+            q, lv = mod.multi_level_step(q, [fs], 1 / n, 1 / n, dt, RHO, KB, r, bc=bc)
+            fs = lv[0]
+    return q, fs
+
+
+def _assemble(fs, r):
+    """The fine interiors of patches that tile a rectangle, as one array."""
+    i0 = min(f.ci0 for f in fs)
+    j0 = min(f.cj0 for f in fs)
+    i1 = max(f.ci0 + f.ncx for f in fs)
+    j1 = max(f.cj0 + f.ncy for f in fs)
+    out = np.full((3, r * (j1 - j0), r * (i1 - i0)), np.nan)
+    for f in fs:
+        a, b = r * (f.ci0 - i0), r * (f.cj0 - j0)
+        out[:, b:b + r * f.ncy, a:a + r * f.ncx] = f.q[:, 2:-2, 2:-2]
+    return out
+
+
+SPLITS = {
+    "x": [(6, 7, 4, 8), (10, 7, 5, 8)],
+    "y": [(6, 7, 9, 3), (6, 10, 9, 5)],
+    "quadrants": [(6, 7, 4, 3), (10, 7, 5, 3), (6, 10, 4, 5), (10, 10, 5, 5)],
+}
+
+
+@pytest.mark.parametrize("driver", ["two", "multi"])
+@pytest.mark.parametrize("split", sorted(SPLITS))
+@pytest.mark.parametrize("r", [2, 3])
+def test_split_patch_equals_whole_patch(r, split, driver, mod=amr_mod):
+    """A fine patch cut into touching pieces gives the composite of the whole
+    patch: the pieces see each other's cells as ghosts (the quadrants also at
+    the corners), the cut edges carry no fix, and the covered coarse cells
+    take the means of their fine cells."""
+    n = 24
+    whole = [(6, 7, 9, 8)]
+    qa, fa = _composite_steps(mod, driver, n, whole, r, 3)
+    qb, fb = _composite_steps(mod, driver, n, SPLITS[split], r, 3)
+    scale = np.abs(qa).max()
+    assert np.abs(qa - qb).max() <= 1e-13 * scale, np.abs(qa - qb).max()
+    fw, fs = _assemble(fa, r), _assemble(fb, r)
+    assert not np.isnan(fs).any()
+    assert np.abs(fw - fs).max() <= 1e-13 * scale, np.abs(fw - fs).max()
+
+
+TOUCHING = [(4, 4, 5, 6), (9, 4, 4, 6), (14, 4, 4, 6), (4, 10, 3, 4)]
+# (9, 4) touches (4, 4) on its right; coarse column 13 lies between (9, 4) and
+# (14, 4), so its cells border two patches; cell (7, 10) borders (4, 4) below
+# and (4, 10) on its left (a concave corner).
+
+
+@pytest.mark.parametrize("r", [2, 4])
+def test_touching_patches_conserve(r, mod=amr_mod):
+    _, _, _, _, s0, s1 = run_composite(mod, 24, TOUCHING, r, 6)
+    scale = np.abs(s0).max()
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * scale), (s1 - s0) / scale
+
+
+def test_covered_cells_hold_the_means_of_their_fine_cells(mod=amr_mod):
+    r = 2
+    for driver in ("two", "multi"):
+        q, fs = _composite_steps(mod, driver, 24, TOUCHING, r, 2, bc="periodic")
+        scale = np.abs(q).max()
+        for f in fs:
+            blk = f.q[:, 2:-2, 2:-2].reshape(3, f.ncy, r, f.ncx, r).mean(axis=(2, 4))
+            cov = q[:, 2 + f.cj0:2 + f.cj0 + f.ncy, 2 + f.ci0:2 + f.ci0 + f.ncx]
+            assert np.abs(cov - blk).max() <= 1e-14 * scale, (driver, np.abs(cov - blk).max())
+
+
+def test_touching_layout_accepted_overlap_refused(mod=amr_mod):
+    z = lambda ncx, ncy: np.zeros((3, 2 * ncy + 4, 2 * ncx + 4))
+    mod.check_layout(20, 20, [mod.FinePatch(3, 3, 4, 4, z(4, 4)),
+                              mod.FinePatch(7, 3, 4, 4, z(4, 4)),
+                              mod.FinePatch(11, 7, 2, 2, z(2, 2))], 2)
+    with pytest.raises(ValueError):
+        mod.check_layout(20, 20, [mod.FinePatch(3, 3, 4, 4, z(4, 4)),
+                                  mod.FinePatch(6, 6, 4, 4, z(4, 4))], 2)

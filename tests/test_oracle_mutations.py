@@ -170,13 +170,29 @@ AMR_MUTATIONS = {
                                     '+ Tf["amx"][b, mxf] + Tf["Fx"][b, mxf]'),
     "c1_dropped_top": ('acc["top"][a] += _fsum(1, rho, K, out, g) - Tf["apy"][myf, a]',
                        'acc["top"][a] += - Tf["apy"][myf, a]'),
-    "time_fraction": ("a = k / r\n            Qt = (1.0 - a) * qc + a * qc1",
-                      "a = (k + 1) / r\n            Qt = (1.0 - a) * qc + a * qc1"),
+    "time_fraction": ("a = k / r\n        Qt = (1.0 - a) * qc + a * qc1",
+                      "a = (k + 1) / r\n        Qt = (1.0 - a) * qc + a * qc1"),
     # the recursion of several levels
     "recursion_time_ends_swapped": ("Qt = (1.0 - a) * old[p.parent] + a * new[p.parent]",
                                     "Qt = (1.0 - a) * new[p.parent] + a * old[p.parent]"),
-    "recursion_fix_skipped": ("apply_fix(new[p.parent], p, accs[c], Tc[p.parent], dt_l, dx, dy, r)",
+    "recursion_fix_skipped": ("apply_fix(new[p.parent], p, accs[c], Tc[p.parent], dt_l, dx, dy, r, cov)",
                               "pass"),
+    # same-level ghosts and the fix next to touching fine patches
+    "sibling_ghosts_from_coarse": ("fill_fine_ghosts(new_q[c], fp, Qt, r, sibs)",
+                                   "fill_fine_ghosts(new_q[c], fp, Qt, r)"),
+    "recursion_sibling_ghosts_from_coarse": ("fill_fine_ghosts(qf, p, Qt, r, sibs)",
+                                             "fill_fine_ghosts(qf, p, Qt, r)"),
+    "sibling_index_offset": ("si, sj = gi - r * sp.ci0, gj - r * sp.cj0",
+                             "si, sj = gi - r * sp.ci0, gj - r * sp.cj0 - 1"),
+    "sibling_one_step_ahead": (
+        "sibs = [(fines[d], new_q[d]) for d in range(len(fines)) if d != c]",
+        "sibs = [(fines[d], O.step(new_q[d], dxf, dyf, dtf, rho, K, limiter)[0])"
+        " for d in range(len(fines)) if d != c]"),
+    "fix_on_covered_cells": ("apply_fix(qc2, fp, acc, Tc, dt, dxc, dyc, r, cov)",
+                             "apply_fix(qc2, fp, acc, Tc, dt, dxc, dyc, r)"),
+    "recursion_fix_on_covered_cells": (
+        "apply_fix(new[p.parent], p, accs[c], Tc[p.parent], dt_l, dx, dy, r, cov)",
+        "apply_fix(new[p.parent], p, accs[c], Tc[p.parent], dt_l, dx, dy, r)"),
     "average_weight": ("sum(axis=1) / (r * r)", "sum(axis=1) / (r * r + 1)"),
     "slope_unlimited": ("return s * np.minimum(np.minimum(2.0 * np.abs(a), 2.0 * np.abs(b)), 0.5 * np.abs(a + b))",
                         "return 0.5 * (a + b)"),
@@ -194,6 +210,11 @@ AMR_PIN_CALLS = [
     ("one_level_recursion", lambda m: amr_pins.test_one_level_recursion_equals_two_level_step(m)),
     ("three_ratio_one", lambda m: amr_pins.test_three_levels_ratio_one_equal_single_level(m)),
     ("three_conserve", lambda m: amr_pins.test_three_levels_conserve(m)),
+    ("split_two_x", lambda m: amr_pins.test_split_patch_equals_whole_patch(2, "x", "two", m)),
+    ("split_multi_quadrants",
+     lambda m: amr_pins.test_split_patch_equals_whole_patch(3, "quadrants", "multi", m)),
+    ("touching_conserve", lambda m: amr_pins.test_touching_patches_conserve(2, m)),
+    ("covered_means", lambda m: amr_pins.test_covered_cells_hold_the_means_of_their_fine_cells(m)),
 ]
 
 
