@@ -276,14 +276,17 @@ int ws_current_pool(ws_ctx *ctx, int32_t *which);
  * (ws_cf_step, all on the shared stream, no host synchronisation):
  *   1. the coarse terms at every coarse-fine interface edge are taken from
  *      the coarse state Q^n, then the coarse level steps with dt;
- *   2. r times: the fine ghosts are filled from the coarse level at
- *      t_n + k dt/r (linear in time between Q^n and Q^{n+1}, MC-limited
+ *   2. r times: the fine ghosts are filled (a ghost inside a sibling fine
+ *      patch of the same coarse patch copies the sibling's cell at the same
+ *      fine step; every other ghost comes from the coarse level at
+ *      t_n + k dt/r, linear in time between Q^n and Q^{n+1}, MC-limited
  *      linear in space inside the coarse cell holding the ghost), the fine
  *      terms at the fine patches' boundary edges are accumulated, and the
  *      fine level steps with dt/r;
  *   3. each covered coarse cell takes the mean of its r x r fine cells;
- *   4. each coarse cell next to a fine patch replaces the coarse flux through
- *      their shared edge by the mean of the fine fluxes through it over the r
+ *   4. each coarse cell next to a fine patch and covered by none (it may
+ *      border several) replaces the coarse flux through each shared edge by
+ *      the mean of the fine fluxes through it over the r
  *      fine steps; written in fluctuations this is C1 + C2 + C3 (C1 from the
  *      Riemann problem between the coarse cell at t_n and the fine ghost, C2
  *      from the fluctuations, C3 from F~ or G~; the coarse F~ enters with
@@ -297,8 +300,8 @@ int ws_current_pool(ws_ctx *ctx, int32_t *which);
  * limiter (no WS_TRANSVERSE_CORR) and stream; fine patches have bc
  * WS_BC_NONE, sizes divisible by r, cell sizes dx/r, dy/r and the coarse
  * patch's material; each lies at least 2 coarse cells inside its coarse
- * patch, and fine patches of one coarse patch are at least 3 coarse cells
- * apart (their ghosts come from the coarse level only).
+ * patch, and fine patches of one coarse patch do not overlap (they may
+ * touch).
  */
 typedef struct ws_cf ws_cf;
 typedef struct {
@@ -308,7 +311,8 @@ typedef struct {
 
 /* Bytes of device workspace the coupling needs (placement table, one
  * accumulator of 3 doubles per fine boundary edge, 3 doubles per coarse
- * interface edge). */
+ * interface edge, the sibling copy rectangles and the fix list, both sized
+ * for any layout of these patches). */
 int ws_cf_layout(ws_ctx *fine, int32_t ratio, int64_t *bytes);
 /* places: one per fine patch.  workspace: caller-owned device buffer of at
  * least ws_cf_layout bytes, kept until ws_cf_destroy.  Both contexts must

@@ -3,9 +3,11 @@
 // itself (paper Sec. 2.2 flow chart; Sec. 2.3 updating and conservation fix).
 //
 //   cf_fine_step (before fine step k, after the coarse step):
-//     - the fine ghosts at t_n + k dt/r from the coarse level, linear in time
-//       between Q_c^n and Q_c^{n+1} and MC-limited linear in space inside the
-//       coarse cell that holds the ghost;
+//     - the fine ghosts: a ghost inside a sibling fine patch (fine patches of
+//       one coarse patch may touch) copies the sibling's cell at the same
+//       fine step; every other one comes from the coarse level at
+//       t_n + k dt/r, linear in time between Q_c^n and Q_c^{n+1} and
+//       MC-limited linear in space inside the coarse cell that holds it;
 //     - the fine terms at the patch's boundary edges, accumulated over the r
 //       fine steps: f(ghost) - f(Q_O^n) (the Riemann fluctuation sum between
 //       the coarse cell O outside the edge and the fine ghost next to it, C1)
@@ -16,10 +18,13 @@
 //   cf_finish (after the fine steps):
 //     - updating: each covered coarse cell takes the mean of its r x r fine
 //       cells;
-//     - the fix: each coarse cell O next to a fine patch replaces the coarse
-//       flux through their shared edge by the mean of the fine fluxes,
-//       O -= dt/dx ((1/r^2) sum acc - P_c) when the patch is on O's right,
-//       O += dt/dx ((1/r^2) sum acc - P_c) when it is on O's left (y alike).
+//     - the fix: each coarse cell O next to a fine patch (and covered by
+//       none) replaces the coarse flux through their shared edge by the mean
+//       of the fine fluxes, O -= dt/dx ((1/r^2) sum acc - P_c) when the patch
+//       is on O's right, O += dt/dx ((1/r^2) sum acc - P_c) when it is on O's
+//       left (y alike); a cell bordering several patches takes each fix, all
+//       in one thread (a gathered list built at set-up), so no two threads
+//       update one cell.
 // A composite step is thus the coarse step, r pairs (cf_fine_step, fine
 // step), cf_finish and the coarse ghost ring: few launches, as every small
 // launch carries a fixed cost of a few microseconds.
@@ -101,7 +106,7 @@ __device__ inline void yedge_terms(const Q &q, const Coef<T> &k, int i, int f, T
 
 // Side of a fine patch an edge index falls on: edges are numbered left
 // (my of them), right (my), bottom (mx), top (mx).
-__device__ inline void side_of(int e, int mx, int my, int &side, int &idx) {
+__host__ __device__ inline void side_of(int e, int mx, int my, int &side, int &idx) {
   if (e < my) { side = 0; idx = e; }
   else if (e < 2 * my) { side = 1; idx = e - my; }
   else if (e < 2 * my + mx) { side = 2; idx = e - 2 * my; }
@@ -180,13 +185,44 @@ __device__ inline GhostSrc<T> ghost_src(const CfArgs &a, const CfPlace &pl, cons
                      pl.ci0, pl.cj0, a.r};
 }
 
+// A fine ghost from the sibling that holds it, if one does (its current
+// state: all fine patches are at the same fine step), else from the coarse
+// level.  Siblings' interiors are read while ghosts are written: disjoint.
+template <typename T>
+struct FineGhost {
+  GhostSrc<T> G;
+  const CfCopy *cp;
+  int n;
+  const PatchRow *fpatch;
+  const void *f_cur;
+  __device__ void value3(int i, int j, T out[3]) const {
+    for (int c = 0; c < n; ++c) {
+      const CfCopy k = cp[c];
+      if (i >= k.i0 && i < k.i1 && j >= k.j0 && j < k.j1) {
+        const View<T> s = view<T>(f_cur, fpatch[k.src]);
+        out[0] = s.P(i + k.di, j + k.dj), out[1] = s.U(i + k.di, j + k.dj),
+        out[2] = s.V(i + k.di, j + k.dj);
+        return;
+      }
+    }
+    G.value3(i, j, out);
+  }
+};
+
+template <typename T>
+__device__ inline FineGhost<T> fine_ghost(const CfArgs &a, const CfPlace &pl, const PatchRow &cp,
+                                          double alpha) {
+  return FineGhost<T>{ghost_src<T>(a, pl, cp, alpha), a.copy + pl.copy0, pl.ncopy, a.fpatch,
+                      a.f_cur};
+}
+
 // The whole ghost ring of each fine patch (used alone by ws_cf_fill_fine_ghosts).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void cf_ghosts_kernel(CfArgs a, double alpha) {
   const CfPlace pl = a.place[blockIdx.y];
   const PatchRow fp = a.fpatch[blockIdx.y];
   const PatchRow cp = a.cpatch[pl.coarse];
-  const GhostSrc<T> G = ghost_src<T>(a, pl, cp, alpha);
+  const FineGhost<T> G = fine_ghost<T>(a, pl, cp, alpha);
   const int mx = fp.mx, my = fp.my;
   const int ring = 4 * (mx + 4) + 4 * my;
   for (int g = blockIdx.x * kThreads + threadIdx.x; g < ring; g += gridDim.x * kThreads) {
@@ -304,9 +340,9 @@ __global__ __launch_bounds__(kThreads) void cf_fine_step_kernel(CfArgs a, int st
   const InstRow in = a.finst[fp.inst];
   const Coef<T> k = make_coef<T>(in.c, in.Z, dt_fine, fp.dx, fp.dy);
   const View<T> q = view<T>(a.f_cur, fp);
-  const GhostSrc<T> G = ghost_src<T>(a, pl, cp, (double)step / r);
-  // all three components of fine cell (i, j): a ghost from the coarse level,
-  // an interior cell from the fine state
+  const FineGhost<T> G = fine_ghost<T>(a, pl, cp, (double)step / r);
+  // all three components of fine cell (i, j): a ghost from a sibling or the
+  // coarse level, an interior cell from the fine state
   auto fine3 = [&](int i, int j, T v[3]) {
     if (i < 0 || i >= mx || j < 0 || j >= my) {
       G.value3(i, j, v);
@@ -376,65 +412,76 @@ __global__ __launch_bounds__(kThreads) void cf_fine_step_kernel(CfArgs a, int st
 }
 
 // After the fine steps: updating (each covered coarse cell takes the mean of
-// its r x r fine cells) and the conservation fix of the coarse cells around
-// the patch (disjoint cells, one launch).
+// its r x r fine cells; grid row p < n_fine, patch p) and the conservation
+// fix (grid row n_fine, one thread per cell of the fix list).  The two write
+// disjoint coarse cells (fix cells are covered by no fine patch).
 __host__ __device__ inline int cf_finish_blocks(int ncx, int ncy) {
-  return (ncx * ncy + kThreads - 1) / kThreads + (2 * (ncx + ncy) + kThreads - 1) / kThreads;
+  return (ncx * ncy + kThreads - 1) / kThreads;
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void cf_finish_kernel(CfArgs a, double dt) {
-  const CfPlace pl = a.place[blockIdx.y];
-  const int b = blockIdx.x, na = (pl.ncx * pl.ncy + kThreads - 1) / kThreads;
-  if (b >= cf_finish_blocks(pl.ncx, pl.ncy)) return;
-  const PatchRow cp = a.cpatch[pl.coarse];
   const int r = a.r;
-  if (b < na) {
-    const PatchRow fp = a.fpatch[blockIdx.y];
-    const View<T> f = view<T>(a.f_cur, fp);
-    const int cidx = b * kThreads + threadIdx.x;
-    if (cidx >= pl.ncx * pl.ncy) return;
-    const int I = cidx % pl.ncx, J = cidx / pl.ncx;
-    // row by row, the row's loads issued together (up to 4 cells at a time)
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int bb = 0; bb < r; ++bb) {
-      const int j = J * r + bb;
-      for (int a0 = 0; a0 < r; a0 += 4) {
-        T v[3][4];
-#pragma unroll
-        for (int aa = 0; aa < 4; ++aa) {
-          const int i = I * r + min(a0 + aa, r - 1);
-          v[0][aa] = f.P(i, j), v[1][aa] = f.U(i, j), v[2][aa] = f.V(i, j);
+  if ((int)blockIdx.y == a.n_fine) {
+    const double w = 1.0 / (double)(r * r);
+    for (int x = blockIdx.x * kThreads + threadIdx.x; x < a.n_fix; x += gridDim.x * kThreads) {
+      const CfFix fx = a.fix[x];
+      const PatchRow cp = a.cpatch[fx.coarse];
+      double v[3];
+      for (int m = 0; m < 3; ++m) v[m] = (double)*cell_ptr<T>(a.c_new, cp, m, fx.oi, fx.oj);
+      for (int c = 0; c < fx.n; ++c) {
+        const CfPlace pl = a.place[fx.patch[c]];
+        const int e = fx.edge[c], mxf = pl.ncx * r, myf = pl.ncy * r;
+        int side, idx;
+        side_of(e, pl.ncx, pl.ncy, side, idx);
+        // the r fine edges on this coarse edge, in the fine edge numbering;
+        // the patch on the cell's right (top) takes -, on its left (bottom) +
+        const int f0 = side == 0 ? idx * r
+                       : side == 1 ? myf + idx * r
+                       : side == 2 ? 2 * myf + idx * r
+                                   : 2 * myf + mxf + idx * r;
+        const double h = side == 0   ? -dt / cp.dx
+                         : side == 1 ? dt / cp.dx
+                         : side == 2 ? -dt / cp.dy
+                                     : dt / cp.dy;
+        const double *acc = a.acc + 3 * ((int64_t)pl.fedge0 + f0);
+        const double *pc = a.pc + 3 * ((int64_t)pl.cedge0 + e);
+        for (int m = 0; m < 3; ++m) {
+          double s = 0.0;
+          for (int bb = 0; bb < r; ++bb) s += acc[3 * bb + m];
+          v[m] = v[m] + h * (w * s - pc[m]);
         }
-        for (int aa = 0; aa < 4 && a0 + aa < r; ++aa)
-          for (int m = 0; m < 3; ++m) s[m] += (double)v[m][aa];
       }
+      for (int m = 0; m < 3; ++m) *cell_ptr<T>(a.c_new, cp, m, fx.oi, fx.oj) = (T)v[m];
     }
-    for (int m = 0; m < 3; ++m)
-      *cell_ptr<T>(a.c_new, cp, m, pl.ci0 + I, pl.cj0 + J) = (T)(s[m] / (double)(r * r));
     return;
   }
-  const int e = (b - na) * kThreads + threadIdx.x;
-  if (e >= 2 * (pl.ncx + pl.ncy)) return;
-  const int mxf = pl.ncx * r, myf = pl.ncy * r;
-  const double w = 1.0 / (double)(r * r);
-  int side, idx;
-  side_of(e, pl.ncx, pl.ncy, side, idx);
-  // the r fine edges on this coarse edge, in the fine edge numbering
-  int f0, oi, oj;
-  double h;
-  if (side == 0) f0 = idx * r, oi = pl.ci0 - 1, oj = pl.cj0 + idx, h = -dt / cp.dx;
-  else if (side == 1) f0 = myf + idx * r, oi = pl.ci0 + pl.ncx, oj = pl.cj0 + idx, h = dt / cp.dx;
-  else if (side == 2) f0 = 2 * myf + idx * r, oi = pl.ci0 + idx, oj = pl.cj0 - 1, h = -dt / cp.dy;
-  else f0 = 2 * myf + mxf + idx * r, oi = pl.ci0 + idx, oj = pl.cj0 + pl.ncy, h = dt / cp.dy;
-  const double *acc = a.acc + 3 * ((int64_t)pl.fedge0 + f0);
-  const double *pc = a.pc + 3 * ((int64_t)pl.cedge0 + e);
-  for (int m = 0; m < 3; ++m) {
-    double s = 0.0;
-    for (int bb = 0; bb < r; ++bb) s += acc[3 * bb + m];
-    T *o = cell_ptr<T>(a.c_new, cp, m, oi, oj);
-    *o = (T)((double)*o + h * (w * s - pc[m]));
+  const CfPlace pl = a.place[blockIdx.y];
+  const int b = blockIdx.x;
+  if (b >= cf_finish_blocks(pl.ncx, pl.ncy)) return;
+  const PatchRow cp = a.cpatch[pl.coarse];
+  const PatchRow fp = a.fpatch[blockIdx.y];
+  const View<T> f = view<T>(a.f_cur, fp);
+  const int cidx = b * kThreads + threadIdx.x;
+  if (cidx >= pl.ncx * pl.ncy) return;
+  const int I = cidx % pl.ncx, J = cidx / pl.ncx;
+  // row by row, the row's loads issued together (up to 4 cells at a time)
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int bb = 0; bb < r; ++bb) {
+    const int j = J * r + bb;
+    for (int a0 = 0; a0 < r; a0 += 4) {
+      T v[3][4];
+#pragma unroll
+      for (int aa = 0; aa < 4; ++aa) {
+        const int i = I * r + min(a0 + aa, r - 1);
+        v[0][aa] = f.P(i, j), v[1][aa] = f.U(i, j), v[2][aa] = f.V(i, j);
+      }
+      for (int aa = 0; aa < 4 && a0 + aa < r; ++aa)
+        for (int m = 0; m < 3; ++m) s[m] += (double)v[m][aa];
+    }
   }
+  for (int m = 0; m < 3; ++m)
+    *cell_ptr<T>(a.c_new, cp, m, pl.ci0 + I, pl.cj0 + J) = (T)(s[m] / (double)(r * r));
 }
 
 inline dim3 cf_grid(int max_items, int n) {
@@ -485,9 +532,19 @@ int cf_step_blocks_host(int mx, int my, int ncx, int ncy, bool coarse) {
 
 int cf_finish_blocks_host(int ncx, int ncy) { return cf_finish_blocks(ncx, ncy); }
 
+void cf_out_cell_host(const CfPlace &pl, int e, int &oi, int &oj) {
+  int side, idx;
+  side_of(e, pl.ncx, pl.ncy, side, idx);
+  if (side == 0) oi = pl.ci0 - 1, oj = pl.cj0 + idx;
+  else if (side == 1) oi = pl.ci0 + pl.ncx, oj = pl.cj0 + idx;
+  else if (side == 2) oi = pl.ci0 + idx, oj = pl.cj0 - 1;
+  else oi = pl.ci0 + idx, oj = pl.cj0 + pl.ncy;
+}
+
 hipError_t launch_cf_finish(int dtype, const CfArgs &a, double dt, int max_blocks,
                             hipStream_t s) {
-  const dim3 g((unsigned)max(1, max_blocks), (unsigned)a.n_fine);
+  const int fix_blocks = min(64, (a.n_fix + kThreads - 1) / kThreads);
+  const dim3 g((unsigned)max(1, max(max_blocks, fix_blocks)), (unsigned)a.n_fine + 1);
   if (dtype == WS_F32)
     hipLaunchKernelGGL(cf_finish_kernel<float>, g, dim3(kThreads), 0, s, a, dt);
   else

@@ -17,8 +17,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/wavestep.h"
@@ -849,8 +851,8 @@ struct ws_cf {
   ws_cf *inner = nullptr;  // coupling of the fine level with the next finer one
   int r = 1;
   char *ws = nullptr;
-  int64_t off_place = 0, off_acc = 0, off_pc = 0;
-  int n_fine = 0;
+  int64_t off_place = 0, off_acc = 0, off_pc = 0, off_copy = 0, off_fix = 0;
+  int n_fine = 0, n_fix = 0;
   int max_ring = 0;
   int max_step_blocks = 0, max_finish_blocks = 0;  // blocks per fine patch of the two launches
 
@@ -865,6 +867,9 @@ struct ws_cf {
     a.r = r;
     a.acc = reinterpret_cast<double *>(ws + off_acc);
     a.pc = reinterpret_cast<double *>(ws + off_pc);
+    a.copy = reinterpret_cast<const CfCopy *>(ws + off_copy);
+    a.fix = reinterpret_cast<const CfFix *>(ws + off_fix);
+    a.n_fix = n_fix;
     return a;
   }
 };
@@ -872,20 +877,29 @@ struct ws_cf {
 namespace {
 
 struct CfSizes {
-  int64_t place, acc, pc, total;
-  int64_t n_fedges, n_cedges;
+  int64_t place, acc, pc, copy, fix, total;
+  int64_t n_fedges, n_cedges, max_copies;
 };
 
+// The copy list's bound: a sibling whose interior meets a fine patch's ghost
+// ring covers a coarse cell of the ring of coarse cells (width 2) around the
+// patch, and siblings do not overlap, so there are at most 4 (ncx + ncy) + 16
+// of them (and at most n_fine - 1).  The fix list has at most one cell per
+// coarse interface edge.
 CfSizes cf_sizes(const ws_ctx *fine, int r) {
   CfSizes z{};
   for (const ws_patch_desc &d : fine->desc) {
+    const int64_t ncx = d.mx / r, ncy = d.my / r;
     z.n_fedges += 2 * ((int64_t)d.mx + d.my);
-    z.n_cedges += 2 * ((int64_t)d.mx / r + d.my / r);
+    z.n_cedges += 2 * (ncx + ncy);
+    z.max_copies += std::min<int64_t>(fine->n_patches - 1, 4 * (ncx + ncy) + 16);
   }
   z.place = 0;
   z.acc = round_up((int64_t)fine->n_patches * (int64_t)sizeof(CfPlace), 256);
   z.pc = z.acc + round_up(24 * std::max<int64_t>(z.n_fedges, 1), 256);
-  z.total = z.pc + round_up(24 * std::max<int64_t>(z.n_cedges, 1), 256);
+  z.copy = z.pc + round_up(24 * std::max<int64_t>(z.n_cedges, 1), 256);
+  z.fix = z.copy + round_up((int64_t)sizeof(CfCopy) * std::max<int64_t>(z.max_copies, 1), 256);
+  z.total = z.fix + round_up((int64_t)sizeof(CfFix) * std::max<int64_t>(z.n_cedges, 1), 256);
   return z;
 }
 
@@ -949,15 +963,68 @@ int ws_cf_init(ws_cf **out, ws_ctx *coarse, ws_ctx *fine, int32_t ratio,
       const int oncx = fine->desc[o].mx / ratio, oncy = fine->desc[o].my / ratio;
       const int gx = std::max(q.ci0 - (p.ci0 + ncx), p.ci0 - (q.ci0 + oncx));
       const int gy = std::max(q.cj0 - (p.cj0 + ncy), p.cj0 - (q.cj0 + oncy));
-      if (std::max(gx, gy) < 3)
-        return fail(WS_EINVAL, "fine patches %d and %d must be at least 3 coarse cells apart", o,
-                    k);
+      if (std::max(gx, gy) < 0)
+        return fail(WS_EINVAL, "fine patches %d and %d overlap", o, k);
     }
-    pl[k] = CfPlace{p.coarse_patch, p.ci0, p.cj0, ncx, ncy, (int32_t)fe, (int32_t)ce, 0};
+    pl[k] = CfPlace{p.coarse_patch, p.ci0, p.cj0, ncx, ncy, (int32_t)fe, (int32_t)ce, 0, 0, 0};
     fe += 2 * ((int64_t)d.mx + d.my);
     ce += 2 * ((int64_t)ncx + ncy);
   }
   if (fe > INT32_MAX || ce > INT32_MAX) return fail(WS_EINVAL, "too many boundary edges");
+  // sibling copy rectangles: the part of each sibling's interior inside the
+  // patch's ghost ring, in the patch's fine coordinates
+  std::vector<CfCopy> copies;
+  for (int k = 0; k < fine->n_patches; ++k) {
+    pl[k].copy0 = (int32_t)copies.size();
+    const int mx = fine->desc[k].mx, my = fine->desc[k].my;
+    for (int o = 0; o < fine->n_patches; ++o) {
+      if (o == k || pl[o].coarse != pl[k].coarse) continue;
+      const int di = ratio * (pl[k].ci0 - pl[o].ci0), dj = ratio * (pl[k].cj0 - pl[o].cj0);
+      // sibling o's interior in k's coordinates: [-di, -di + mx_o) x [-dj, -dj + my_o)
+      const int i0 = std::max(-2, -di), i1 = std::min(mx + 2, -di + fine->desc[o].mx);
+      const int j0 = std::max(-2, -dj), j1 = std::min(my + 2, -dj + fine->desc[o].my);
+      if (i0 < i1 && j0 < j1) copies.push_back(CfCopy{o, i0, i1, j0, j1, di, dj, 0});
+    }
+    pl[k].ncopy = (int32_t)copies.size() - pl[k].copy0;
+  }
+  if ((int64_t)copies.size() > z.max_copies)
+    return fail(WS_EINVAL, "internal: %zu sibling copies exceed the bound %lld", copies.size(),
+                (long long)z.max_copies);
+  // the fix list: every coarse cell outside the fine patches that borders one,
+  // with its (patch, interface edge) pairs in patch order
+  std::vector<CfFix> fixes;
+  {
+    std::map<std::tuple<int, int, int>, int> at;  // (coarse patch, oi, oj) -> fix index
+    std::map<int, std::vector<char>> cover;       // coarse patch -> covered cells
+    for (int k = 0; k < fine->n_patches; ++k) {
+      const ws_patch_desc &cd = coarse->desc[pl[k].coarse];
+      std::vector<char> &cv = cover[pl[k].coarse];
+      if (cv.empty()) cv.assign((size_t)cd.mx * cd.my, 0);
+      for (int J = 0; J < pl[k].ncy; ++J)
+        for (int I = 0; I < pl[k].ncx; ++I)
+          cv[(size_t)(pl[k].cj0 + J) * cd.mx + pl[k].ci0 + I] = 1;
+    }
+    for (int k = 0; k < fine->n_patches; ++k) {
+      const int mxc = coarse->desc[pl[k].coarse].mx;
+      const std::vector<char> &cv = cover[pl[k].coarse];
+      for (int e = 0; e < 2 * (pl[k].ncx + pl[k].ncy); ++e) {
+        int oi, oj;
+        cf_out_cell_host(pl[k], e, oi, oj);
+        if (cv[(size_t)oj * mxc + oi]) continue;  // covered by a sibling: updating sets it
+        auto key = std::make_tuple(pl[k].coarse, oi, oj);
+        auto it = at.find(key);
+        if (it == at.end()) {
+          it = at.emplace(key, (int)fixes.size()).first;
+          CfFix f{};
+          f.coarse = pl[k].coarse, f.oi = oi, f.oj = oj, f.n = 0;
+          fixes.push_back(f);
+        }
+        CfFix &f = fixes[it->second];
+        if (f.n >= 4) return fail(WS_EINVAL, "internal: a coarse cell borders over 4 patches");
+        f.patch[f.n] = k, f.edge[f.n] = e, ++f.n;
+      }
+    }
+  }
   ws_cf *cf = new ws_cf;
   cf->coarse = coarse;
   cf->fine = fine;
@@ -966,7 +1033,10 @@ int ws_cf_init(ws_cf **out, ws_ctx *coarse, ws_ctx *fine, int32_t ratio,
   cf->off_place = z.place;
   cf->off_acc = z.acc;
   cf->off_pc = z.pc;
+  cf->off_copy = z.copy;
+  cf->off_fix = z.fix;
   cf->n_fine = fine->n_patches;
+  cf->n_fix = (int)fixes.size();
   for (int k = 0; k < fine->n_patches; ++k) {
     const ws_patch_desc &d = fine->desc[k];
     cf->max_ring = std::max(cf->max_ring, 4 * (d.mx + 4) + 4 * d.my);
@@ -977,6 +1047,12 @@ int ws_cf_init(ws_cf **out, ws_ctx *coarse, ws_ctx *fine, int32_t ratio,
   }
   if (hipMemcpyAsync(cf->ws + cf->off_place, pl.data(), pl.size() * sizeof(CfPlace),
                      hipMemcpyHostToDevice, coarse->stream) != hipSuccess ||
+      (!copies.empty() &&
+       hipMemcpyAsync(cf->ws + cf->off_copy, copies.data(), copies.size() * sizeof(CfCopy),
+                      hipMemcpyHostToDevice, coarse->stream) != hipSuccess) ||
+      (!fixes.empty() &&
+       hipMemcpyAsync(cf->ws + cf->off_fix, fixes.data(), fixes.size() * sizeof(CfFix),
+                      hipMemcpyHostToDevice, coarse->stream) != hipSuccess) ||
       hipStreamSynchronize(coarse->stream) != hipSuccess) {
     delete cf;
     return fail(WS_EHIP, "cannot upload the placement table");

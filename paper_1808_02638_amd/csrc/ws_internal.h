@@ -129,7 +129,26 @@ struct CfPlace {
   int32_t ncx, ncy;  // coarse cells covered
   int32_t fedge0;    // first fine boundary edge (accumulator slots)
   int32_t cedge0;    // first coarse interface edge
+  int32_t copy0;     // first of this patch's sibling copy rectangles
+  int32_t ncopy;     // how many
   int32_t pad_;
+};
+
+// Ghost cells (i, j) of a fine patch with i0 <= i < i1, j0 <= j < j1 lie in
+// the interior of sibling fine patch `src`, at (i + di, j + dj) there.
+struct CfCopy {
+  int32_t src;
+  int32_t i0, i1, j0, j1;
+  int32_t di, dj;
+  int32_t pad_;
+};
+
+// A coarse cell outside every fine patch that borders n (1..4) of them: the
+// fix of each (fine patch, interface edge) pair, applied in this order.
+struct CfFix {
+  int32_t coarse, oi, oj, n;
+  int32_t patch[4];
+  int32_t edge[4];
 };
 
 struct CfArgs {
@@ -142,6 +161,9 @@ struct CfArgs {
   void *f_cur;        // fine current state
   double *acc;        // [fine edges][3] fine terms summed over the fine steps
   double *pc;         // [coarse interface edges][3] coarse terms
+  const CfCopy *copy; // sibling copy rectangles, CfPlace::copy0 .. + ncopy per fine patch
+  const CfFix *fix;   // [n_fix] the coarse cells that take the fix
+  int32_t n_fix, pad_;
 };
 
 hipError_t launch_cf_ghosts(int dtype, const CfArgs &a, double alpha, int max_items,
@@ -149,10 +171,14 @@ hipError_t launch_cf_ghosts(int dtype, const CfArgs &a, double alpha, int max_it
 // Before fine step `step` (ghost ring, fine terms; coarse terms when step is 0).
 hipError_t launch_cf_fine_step(int dtype, int limiter, const CfArgs &a, int step, double dt_fine,
                                double dt, int max_blocks, hipStream_t s);
-// Updating and the conservation fix.
+// Updating and the conservation fix (grid rows 0 .. n_fine-1 average the fine
+// patches down, row n_fine applies the fix list).
 hipError_t launch_cf_finish(int dtype, const CfArgs &a, double dt, int max_blocks, hipStream_t s);
 // Blocks per fine patch of the two launches.
 int cf_step_blocks_host(int mx, int my, int ncx, int ncy, bool coarse);
 int cf_finish_blocks_host(int ncx, int ncy);
+// The coarse cell outside interface edge e of a fine patch (edges numbered
+// left, right over ncy, then bottom, top over ncx).
+void cf_out_cell_host(const CfPlace &pl, int e, int &oi, int &oj);
 
 }  // namespace ws

@@ -153,7 +153,7 @@ def test_invalid_layouts_are_refused(ws):
 
     cases = [
         (fine_of([(8, 8)]), 2, [(0, 1, 5)]),                  # not 2 cells inside
-        (fine_of([(8, 8), (8, 8)]), 2, [(0, 4, 4), (0, 10, 4)]),  # 2 cells apart
+        (fine_of([(8, 8), (8, 8)]), 2, [(0, 4, 4), (0, 7, 5)]),  # overlapping
         (fine_of([(9, 8)]), 2, [(0, 5, 5)]),                  # not whole coarse cells
         (fine_of([(8, 8)], bc="extrap"), 2, [(0, 5, 5)]),     # fine ghosts not frozen
         (fine_of([(8, 8)], mat=(1.0, 9.0)), 2, [(0, 5, 5)]),  # another material
@@ -251,9 +251,10 @@ L1_RECTS = [(4, 4, 10, 12), (19, 6, 8, 8)]
 L2_PLACES = [(0, (2, 2, 3, 3)), (1, (2, 2, 4, 3)), (0, (2, 8, 4, 2))]
 
 
-def build3(ws, n, r, bc, dtype=torch.float64, fn=smooth):
+def build3(ws, n, r, bc, dtype=torch.float64, fn=smooth, l1_rects=L1_RECTS, l2_places=L2_PLACES):
     """Oracle start state (level 1 and 2 means written into their parents) and
     the three GPU levels holding it."""
+    L1_RECTS, L2_PLACES = l1_rects, l2_places
     qc = coarse_state(n, fn)
     l1 = oamr.init_fines(qc, L1_RECTS, r, fn)
     l2 = []
@@ -334,6 +335,114 @@ def test_nesting_is_checked(ws):
         ws._lib.check(L.ws_cf_nest(inner._cf, outer._cf))  # levels do not chain
     with pytest.raises(ws.WaveStepError):
         ws._lib.check(L.ws_cf_nest(outer._cf, outer._cf))
+    h.close()
+    for lev in levs:
+        lev.close()
+
+
+# --------------------------------------------------------------------------
+# Touching fine patches: ghosts from siblings, the fix gathered per coarse cell
+# --------------------------------------------------------------------------
+
+# B touches A on its right; coarse column 17 lies between B and C (its cells
+# border both); D touches A's top, E touches D's right and A's and B's tops
+# (concave corners whose coarse cells border two patches); F stands alone.
+TOUCHING = [(6, 6, 6, 8), (12, 6, 5, 8), (18, 6, 5, 8), (6, 14, 4, 5), (10, 14, 6, 3),
+            (26, 20, 6, 6)]
+
+
+@pytest.mark.parametrize("r", [2, 3])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_touching_patches_match_oracle(ws, dtype, r):
+    n, steps = 40, 6
+    dt = 0.8 / n / C0
+    qc, fines, coarse, fine, tl = build(ws, n, TOUCHING, r, "periodic", dtype)
+    q, fs = qc, fines
+    for _ in range(steps):
+        q, fs = oamr.two_level_step(q, fs, 1 / n, 1 / n, dt, RHO, KB, r, bc="periodic")
+        tl.step(dt)
+    tol = FP64_TOL if dtype == torch.float64 else FP32_TOL
+    err = rel_linf(coarse.download(0), q)
+    print(f"touching r={r} {dtype}: coarse rel Linf {err}")
+    assert err.max() <= tol, err
+    for k, f in enumerate(fs):
+        e = rel_linf(fine.download(k)[:, 2:-2, 2:-2], f.q[:, 2:-2, 2:-2])
+        assert e.max() <= tol, (k, e)
+    for lev in (tl, fine, coarse):
+        lev.close()
+
+
+@pytest.mark.parametrize("r", [2, 4])
+def test_touching_patches_conserve(ws, r):
+    n = 40
+    _, _, coarse, fine, tl = build(ws, n, TOUCHING, r, "periodic")
+    s0 = coarse.conservation_sums()[0]
+    for _ in range(40):
+        tl.step(0.9 / n / C0)
+    s1 = coarse.conservation_sums()[0]
+    scale = np.abs(s0).max()
+    print(f"touching r={r} conservation drift {(s1 - s0) / scale}")
+    assert np.all(np.abs(s1 - s0) <= 1e-13 * scale), (s0, s1)
+    for lev in (tl, fine, coarse):
+        lev.close()
+
+
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_sibling_ghost_fill_matches_oracle(ws, r):
+    """Ghosts inside a sibling hold the sibling's cell bitwise, the others the
+    coarse interpolation (both coarse pools hold the uploaded state)."""
+    n = 40
+    rng = np.random.default_rng(80 + r)
+    rough = lambda X, Y: np.stack([np.sin(7 * X) + 0.1 * rng.normal(size=X.shape),
+                                   np.cos(5 * Y) * X, X * Y + 0.2 * rng.normal(size=X.shape)])
+    qc, fines, coarse, fine, tl = build(ws, n, TOUCHING, r, "extrap", fn=rough)
+    tl.fill_fine_ghosts(0.3)
+    for k, f in enumerate(fines):
+        ref = f.q.copy()
+        sibs = [(g, g.q) for d, g in enumerate(fines) if d != k]
+        oamr.fill_fine_ghosts(ref, f, qc, r, sibs)
+        got = fine.download(k)
+        scale = np.abs(ref).max()
+        assert np.abs(got - ref).max() <= 1e-15 * scale, k
+        # the copied ghosts are exact
+        gi = r * f.ci0 + np.arange(-2, r * f.ncx + 2)[None, :]
+        gj = r * f.cj0 + np.arange(-2, r * f.ncy + 2)[:, None]
+        for g in (x for d, x in enumerate(fines) if d != k):
+            inside = ((gi >= r * g.ci0) & (gi < r * (g.ci0 + g.ncx)) &
+                      (gj >= r * g.cj0) & (gj < r * (g.cj0 + g.ncy)))
+            assert np.array_equal(got[:, inside], ref[:, inside]), (k, "copy")
+    for lev in (tl, fine, coarse):
+        lev.close()
+
+
+L1_TOUCH = [(4, 4, 10, 12), (14, 4, 8, 8), (14, 12, 6, 4)]
+L2_TOUCH = [(0, (2, 2, 3, 3)), (0, (5, 2, 4, 3)), (0, (2, 5, 3, 2)), (1, (2, 2, 4, 3)),
+            (1, (6, 2, 3, 5))]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_three_levels_touching_match_oracle_and_conserve(ws, dtype):
+    n, r = 32, 2
+    qc, levels, levs, h = build3(ws, n, r, "periodic", dtype, l1_rects=L1_TOUCH,
+                                 l2_places=L2_TOUCH)
+    s0 = levs[0].conservation_sums()[0]
+    dt = 0.8 / n / C0
+    q, lv = qc, levels
+    for _ in range(4):
+        q, lv = oamr.multi_level_step(q, lv, 1 / n, 1 / n, dt, RHO, KB, r, bc="periodic")
+        h.step(dt)
+    tol = FP64_TOL if dtype == torch.float64 else FP32_TOL
+    err = rel_linf(levs[0].download(0), q)
+    print(f"three levels touching {dtype}: level-0 rel Linf {err}")
+    assert err.max() <= tol, err
+    for l in (1, 2):
+        for k, P in enumerate(lv[l - 1]):
+            e = rel_linf(levs[l].download(k)[:, 2:-2, 2:-2], P.q[:, 2:-2, 2:-2])
+            assert e.max() <= tol, (l, k, e)
+    if dtype == torch.float64:
+        s1 = levs[0].conservation_sums()[0]
+        scale = np.abs(s0).max()
+        assert np.all(np.abs(s1 - s0) <= 1e-13 * scale), (s0, s1)
     h.close()
     for lev in levs:
         lev.close()
