@@ -294,3 +294,48 @@ def test_planted_medium_mistake_is_caught(name, tmp_path):
             caught = pin_name
             break
     assert caught is not None, f"planted mistake {name!r} passed every pin"
+
+
+# --------------------------------------------------------------------------
+# The ghost exchange of a tiled level (oracle/tiled.py): mistakes planted in a
+# copy of the module, checked against the pins of test_oracle_tiled
+# --------------------------------------------------------------------------
+
+import oracle.tiled as tiled_src  # noqa: E402
+import test_oracle_tiled as tiled_pins  # noqa: E402
+
+TILED_MUTATIONS = {
+    "wrap_off_by_one": ("gx = gx % DX if periodic[0]", "gx = (gx + 1) % DX if periodic[0]"),
+    "clamp_short": ("min(max(gy, 0), DY - 1)", "min(max(gy, 0), DY - 2)"),
+    "directions_swapped": ("gy = gy % DY if periodic[1]", "gy = gy % DY if periodic[0]"),
+    "source_origin_x": ("qs[o][:, sy - oy + 2, sx - ox + 2]", "qs[o][:, sy - oy + 2, sx + 2]"),
+    "own_patch_only": ("o = own[sy, sx]", "o = k"),
+}
+
+TILED_PIN_CALLS = [
+    (f"numpy_pad_{p}", lambda m, p=p: tiled_pins.test_single_patch_exchange_is_numpy_padding(p, m))
+    for p in [(True, True), (False, False), (True, False), (False, True)]
+] + [
+    (f"tiled_{t}_{p}", lambda m, t=t, p=p: tiled_pins.test_tiled_steps_equal_the_single_patch_step(t, p, m))
+    for t in sorted(tiled_pins.TILINGS) for p in [(True, True), (False, False), (True, False)]
+]
+
+
+@pytest.mark.parametrize("name", sorted(TILED_MUTATIONS))
+def test_planted_exchange_mistake_is_caught(name, tmp_path):
+    orig, mutated = TILED_MUTATIONS[name]
+    src = open(tiled_src.__file__).read()
+    assert src.count(orig) == 1, f"mutation anchor for {name} occurs {src.count(orig)} times"
+    path = tmp_path / "tiled_mutant.py"
+    path.write_text(src.replace(orig, mutated))
+    spec = importlib.util.spec_from_file_location("tiled_mutant", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    caught = None
+    for pin_name, call in TILED_PIN_CALLS:
+        try:
+            call(mod)
+        except (AssertionError, ValueError, IndexError):
+            caught = pin_name
+            break
+    assert caught is not None, f"planted mistake {name!r} passed every pin"
