@@ -153,6 +153,62 @@ def run_medium(ws, torch, n=2048, steps=200, warmup=10, tune=True):
             "cfl_max": float(cfl_max[0]), "finite": finite}
 
 
+def run_tiled(ws, torch, n=2048, tiles=4, steps=200, warmup=10, tune=True):
+    """The 2048^2 FP64 pulse with extrapolating sides cut into tiles x tiles
+    patches that exchange ghosts after every step (a tiled coarsest level);
+    CFL 0.9 from the device reduction, steps in one hipGraph.  Compared with
+    the single-patch leg this prices the exchange."""
+    import numpy as np
+
+    import workloads
+
+    dx = 1.0 / n
+    w = n // tiles
+    shapes = [(w, w)] * (tiles * tiles)
+    origins = [(w * a, w * b) for b in range(tiles) for a in range(tiles)]
+    lev = ws.Level([dict(mx=w, my=w, dx=dx, dy=dx) for _ in shapes], [(RHO, K_BULK)])
+    lev.link(origins, (n, n), (False, False))
+    q0 = workloads.padded_state(n, n, 0.0, 0.0, dx, dx)
+    parts = [np.ascontiguousarray(q0[:, y0:y0 + w + 4, x0:x0 + w + 4]) for (x0, y0) in origins]
+    dt0 = 0.9 * dx / C_SOUND
+
+    def reset():
+        for k, q in enumerate(parts):
+            lev.upload(k, q)
+        lev.fill_ghosts()
+        lev.set_dt([dt0])
+
+    reset()
+    if tune:
+        from paper_1808_02638_amd.autotune import autotune
+        autotune(lev)
+    var, tw, th, wg, grid = lev.get_tiling()
+    reset()
+    for _ in range(warmup):
+        lev.step_auto(0.9)
+    reset()
+    lev.capture(steps, 0.9)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(lev.stream)
+    lev.graph_launch()
+    e1.record(lev.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    _dt, _cl, cfl_max = lev.read_dt_cfl()
+    finite = all(bool(np.isfinite(lev.download(k)).all()) for k in range(len(shapes)))
+    lev.close()
+    ghosts = len(shapes) * (4 * (w + 4) + 4 * w)
+    return {"domain": f"{n}x{n}", "tiles": f"{tiles}x{tiles} of {w}x{w}", "steps": steps,
+            "value": round(n * n * steps / (ms / 1e3) / 1e9, 3),
+            "us_per_step": round(ms / steps * 1e3, 2),
+            "exchange_bytes_per_step": ghosts * (2 * 3 * 8 + 12),
+            "tiling": {"variant": var[0], "tile_w": int(tw[0]), "tile_h": int(th[0]),
+                       "wg_per_cu": wg},
+            "cfl_max": float(cfl_max[0]), "finite": finite}
+
+
 def run_amr(ws, torch, dtype, level_steps, tune=True):
     import workloads
 
@@ -538,6 +594,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--medium-only", action="store_true",
                     help="only run the heterogeneous-medium leg (for profiling)")
+    ap.add_argument("--tiled-only", action="store_true",
+                    help="only run the tiled-level leg (for profiling)")
     ap.add_argument("--levels-only", action="store_true",
                     help="only run the two- and three-level composite legs (for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -567,6 +625,9 @@ def main():
     if args.medium_only:
         print(json.dumps({"medium_fp64": run_medium(ws, torch, tune=not args.no_tune)}),
               flush=True)
+        return
+    if args.tiled_only:
+        print(json.dumps({"tiled_fp64": run_tiled(ws, torch, tune=not args.no_tune)}), flush=True)
         return
     if args.levels_only:
         print(json.dumps({"two_level_fp64": run_two_level(ws, torch, tune=not args.no_tune),
@@ -652,6 +713,7 @@ def main():
         line["ensemble_fp64"] = run_ensemble(ws, torch, args.ensemble_steps, tune=not args.no_tune)
         line["adjoint_fp64"] = run_adjoint(ws, torch)
         line["medium_fp64"] = run_medium(ws, torch, tune=not args.no_tune)
+        line["tiled_fp64"] = run_tiled(ws, torch, tune=not args.no_tune)
         line["two_level_fp64"] = run_two_level(ws, torch, tune=not args.no_tune)
         line["three_level_fp64"] = run_three_level(ws, torch, tune=not args.no_tune)
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)

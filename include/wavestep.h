@@ -154,8 +154,37 @@ int ws_upload_patch(ws_ctx *ctx, int32_t patch, const void *src);
 int ws_download_patch(ws_ctx *ctx, int32_t patch, void *dst);
 
 /* Rewrite the physical-boundary ghosts of the current state from its interior
- * (patches with bc != WS_BC_NONE).  Asynchronous. */
+ * (patches with bc != WS_BC_NONE); on a tiled level (ws_link_level) every
+ * ghost from the exchange instead.  Asynchronous. */
 int ws_fill_ghosts(ws_ctx *ctx);
+
+/* --------------------------------------------------------------------------
+ * Tiled level: the level's patches tile one rectangular domain and exchange
+ * ghosts (the ghost-cell rules of Sec. 2.2 at the coarsest level).  A ghost
+ * outside the domain is mapped into it by the physical condition of its
+ * direction (periodic: the global index wraps; otherwise zero-order
+ * extrapolation: it is clamped to the domain's edge cell), then copied from
+ * the interior cell of the patch holding that domain cell (possibly the patch
+ * itself).  Once linked, every step call (ws_step_level,
+ * ws_step_level_per_patch, ws_step_auto and captured graphs) runs the
+ * exchange on the new state right after the step, and ws_fill_ghosts runs it
+ * on the current one; a cut of the domain into tiles then steps exactly like
+ * the domain as one patch.  ws_step_record_masks, ws_adjoint_step and use as
+ * the fine level of a coupling refuse a tiled level.
+ *
+ * Bytes of the link buffer: 8 per patch (ring offsets) and 12 per ghost cell
+ * (source patch and cell), each part rounded up to 256. */
+int ws_link_layout(ws_ctx *ctx, int64_t *bytes);
+/* origins: 2 per patch, global cell (x0, y0) of its interior cell (0, 0).
+ * The patches must cover [0, domain_mx) x [0, domain_my) exactly, without
+ * overlap, have bc WS_BC_NONE, one instance and one cell size.  periodic:
+ * bit 0 for x, bit 1 for y.  buffer: caller-owned device memory of at least
+ * ws_link_layout bytes, kept for the context's lifetime; the table is built on
+ * the host and uploaded (synchronises the stream).  Drops a captured graph.
+ * WS_EINVAL on a layout that does not tile the domain, WS_ENOMEM on a short
+ * buffer. */
+int ws_link_level(ws_ctx *ctx, const int32_t *origins, int32_t domain_mx, int32_t domain_my,
+                  int32_t periodic, void *buffer, int64_t bytes);
 
 /* One step of every patch with the same dt, in ONE persistent launch over the
  * level's tile list.  Writes the other pool's interior (and physical ghosts),

@@ -27,7 +27,7 @@ EXPORTS = (
     "ws_capture_steps", "ws_graph_launch", "ws_read_dt_cfl", "ws_read_patch_cfl",
     "ws_conservation_sums", "ws_mask_bytes", "ws_patch_layout", "ws_step_record_masks",
     "ws_adjoint_step", "ws_gather", "ws_add_at", "ws_time_step_kernel", "ws_current_pool",
-    "ws_attach_medium", "ws_upload_medium",
+    "ws_attach_medium", "ws_upload_medium", "ws_link_layout", "ws_link_level",
     "ws_cf_layout", "ws_cf_init", "ws_cf_step", "ws_cf_nest", "ws_cf_fill_fine_ghosts",
     "ws_cf_destroy",
     "ws_destroy", "ws_last_error",
@@ -100,6 +100,8 @@ def lib():
         "ws_current_pool": [vp, P(i32)],
         "ws_attach_medium": [vp, vp, i64],
         "ws_upload_medium": [vp, i32, P(dbl), P(dbl)],
+        "ws_link_layout": [vp, P(i64)],
+        "ws_link_level": [vp, P(i32), i32, i32, i32, vp, i64],
         "ws_cf_layout": [vp, i32, P(i64)],
         "ws_cf_init": [P(vp), vp, vp, i32, P(FinePlace), vp, i64],
         "ws_cf_step": [vp, dbl],

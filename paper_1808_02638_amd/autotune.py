@@ -114,6 +114,12 @@ def autotune(level, *, launches=40, use_cache=True, cache_path=None, verbose=Fal
             return {"classes": choice, "wg_per_cu": ent["wg_per_cu"], "ms": ent["ms"],
                     "cached": True}
 
+    # The timed steps run with the level's device dt: give it a stable one
+    # for the duration (an unset dt steps garbage, whose timings mislead and
+    # whose values need not even be finite), and keep the state to restore.
+    dt_saved = level.read_dt_cfl()[0]
+    dt_safe = level.stable_dt(0.5)
+    level.set_dt(dt_safe)
     saved = [p.clone() for p in level.pools]
     torch.cuda.synchronize(level.device)
 
@@ -157,6 +163,7 @@ def autotune(level, *, launches=40, use_cache=True, cache_path=None, verbose=Fal
     for p, s in zip(level.pools, saved):
         p.copy_(s)
     torch.cuda.synchronize(level.device)
+    level.set_dt([d if np.isfinite(d) and d > 0 else s for d, s in zip(dt_saved, dt_safe)])
     if use_cache:
         cache[key] = {"classes": {json.dumps(list(c)): list(v) for c, v in choice.items()},
                       "wg_per_cu": wg, "ms": best}

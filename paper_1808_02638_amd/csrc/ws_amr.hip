@@ -412,19 +412,21 @@ __global__ __launch_bounds__(kThreads) void cf_fine_step_kernel(CfArgs a, int st
 }
 
 // After the fine steps: updating (each covered coarse cell takes the mean of
-// its r x r fine cells; grid row p < n_fine, patch p) and the conservation
-// fix (grid row n_fine, one thread per cell of the fix list).  The two write
-// disjoint coarse cells (fix cells are covered by no fine patch).
+// its r x r fine cells; blocks p * nav .. p * nav + nav - 1 for fine patch p)
+// and the conservation fix (the blocks after those, one thread per cell of
+// the fix list).  The two write disjoint coarse cells (fix cells are covered
+// by no fine patch).
 __host__ __device__ inline int cf_finish_blocks(int ncx, int ncy) {
   return (ncx * ncy + kThreads - 1) / kThreads;
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void cf_finish_kernel(CfArgs a, double dt) {
+__global__ __launch_bounds__(kThreads) void cf_finish_kernel(CfArgs a, double dt, int nav) {
   const int r = a.r;
-  if ((int)blockIdx.y == a.n_fine) {
+  if ((int)blockIdx.x >= nav * a.n_fine) {
     const double w = 1.0 / (double)(r * r);
-    for (int x = blockIdx.x * kThreads + threadIdx.x; x < a.n_fix; x += gridDim.x * kThreads) {
+    const int x = ((int)blockIdx.x - nav * a.n_fine) * kThreads + (int)threadIdx.x;
+    if (x < a.n_fix) {
       const CfFix fx = a.fix[x];
       const PatchRow cp = a.cpatch[fx.coarse];
       double v[3];
@@ -456,11 +458,11 @@ __global__ __launch_bounds__(kThreads) void cf_finish_kernel(CfArgs a, double dt
     }
     return;
   }
-  const CfPlace pl = a.place[blockIdx.y];
-  const int b = blockIdx.x;
+  const int patch = (int)blockIdx.x / nav, b = (int)blockIdx.x % nav;
+  const CfPlace pl = a.place[patch];
   if (b >= cf_finish_blocks(pl.ncx, pl.ncy)) return;
   const PatchRow cp = a.cpatch[pl.coarse];
-  const PatchRow fp = a.fpatch[blockIdx.y];
+  const PatchRow fp = a.fpatch[patch];
   const View<T> f = view<T>(a.f_cur, fp);
   const int cidx = b * kThreads + threadIdx.x;
   if (cidx >= pl.ncx * pl.ncy) return;
@@ -543,12 +545,14 @@ void cf_out_cell_host(const CfPlace &pl, int e, int &oi, int &oj) {
 
 hipError_t launch_cf_finish(int dtype, const CfArgs &a, double dt, int max_blocks,
                             hipStream_t s) {
-  const int fix_blocks = min(64, (a.n_fix + kThreads - 1) / kThreads);
-  const dim3 g((unsigned)max(1, max(max_blocks, fix_blocks)), (unsigned)a.n_fine + 1);
+  const int nav = max(1, max_blocks);
+  const int64_t blocks = (int64_t)nav * a.n_fine + (a.n_fix + kThreads - 1) / kThreads;
+  if (blocks < 1) return hipSuccess;
+  const dim3 g((unsigned)blocks);
   if (dtype == WS_F32)
-    hipLaunchKernelGGL(cf_finish_kernel<float>, g, dim3(kThreads), 0, s, a, dt);
+    hipLaunchKernelGGL(cf_finish_kernel<float>, g, dim3(kThreads), 0, s, a, dt, nav);
   else
-    hipLaunchKernelGGL(cf_finish_kernel<double>, g, dim3(kThreads), 0, s, a, dt);
+    hipLaunchKernelGGL(cf_finish_kernel<double>, g, dim3(kThreads), 0, s, a, dt, nav);
   return hipGetLastError();
 }
 

@@ -49,6 +49,7 @@ int fail(int code, const char *fmt, ...) {
   } while (0)
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+bool same_rel(double a, double b) { return std::fabs(a - b) <= 1e-12 * std::fabs(b); }
 
 constexpr int kTileWidths[] = {8, 16, 32, 64, 128, 256};
 
@@ -239,6 +240,10 @@ struct ws_ctx {
   int graph_steps = 0, graph_start_pool = 0;
   std::vector<InstRow> inst_host;  // (c, Z) per instance, as on the device
   void *medium = nullptr;          // per-cell (c, Z) planes, laid out like a q pool
+  // tiled level: per-patch ghost-ring offsets and the ghost source table
+  const int64_t *link_ring0 = nullptr;
+  const int32_t *link_src = nullptr;
+  int link_max_ring = 0;
   // limiter code of the kernel launchers (the medium selects its own kernel)
   int lim_code() const { return limiter | (medium ? kMediumFlag : 0); }
 
@@ -511,6 +516,84 @@ int ws_upload_medium(ws_ctx *c, int32_t patch, const double *rho, const double *
   return WS_OK;
 }
 
+int ws_link_layout(ws_ctx *c, int64_t *bytes) {
+  if (!c || !bytes) return fail(WS_EINVAL, "NULL argument");
+  int64_t ghosts = 0;
+  for (const PatchRow &r : c->rows) ghosts += ring_size(r.mx, r.my);
+  *bytes = round_up(8 * (int64_t)std::max(c->n_patches, 1), 256) + round_up(12 * ghosts, 256);
+  return WS_OK;
+}
+
+int ws_link_level(ws_ctx *c, const int32_t *origins, int32_t domain_mx, int32_t domain_my,
+                  int32_t periodic, void *buffer, int64_t bytes) {
+  if (!c || !origins || !buffer) return fail(WS_EINVAL, "NULL argument");
+  if (domain_mx < 1 || domain_my < 1 || c->n_patches < 1) return fail(WS_EINVAL, "empty domain");
+  if (periodic & ~3) return fail(WS_EINVAL, "periodic takes bits 0 (x) and 1 (y) only");
+  int64_t need = 0;
+  ws_link_layout(c, &need);
+  if (bytes < need)
+    return fail(WS_ENOMEM, "link buffer too small (%lld < %lld bytes)", (long long)bytes,
+                (long long)need);
+  const PatchRow &r0 = c->rows[0];
+  for (int k = 0; k < c->n_patches; ++k) {
+    const PatchRow &r = c->rows[k];
+    if (r.bc != WS_BC_NONE)
+      return fail(WS_EINVAL, "patch %d: a tiled level's ghosts come from the exchange (bc must "
+                  "be WS_BC_NONE)", k);
+    if (r.inst != r0.inst) return fail(WS_EINVAL, "patch %d: another instance than patch 0", k);
+    if (!same_rel(r.dx, r0.dx) || !same_rel(r.dy, r0.dy))
+      return fail(WS_EINVAL, "patch %d: another cell size than patch 0", k);
+  }
+  // the patch holding each domain cell; the patches must tile the domain
+  const int64_t DX = domain_mx, DY = domain_my;
+  std::vector<int32_t> own((size_t)(DX * DY), -1);
+  for (int k = 0; k < c->n_patches; ++k) {
+    const int x0 = origins[2 * k], y0 = origins[2 * k + 1], mx = c->rows[k].mx, my = c->rows[k].my;
+    if (x0 < 0 || y0 < 0 || x0 + mx > DX || y0 + my > DY)
+      return fail(WS_EINVAL, "patch %d does not lie in the domain", k);
+    for (int j = 0; j < my; ++j)
+      for (int i = 0; i < mx; ++i) {
+        int32_t &o = own[(size_t)((y0 + j) * DX + x0 + i)];
+        if (o >= 0) return fail(WS_EINVAL, "patches %d and %d overlap", o, k);
+        o = k;
+      }
+  }
+  for (int64_t x = 0; x < DX * DY; ++x)
+    if (own[(size_t)x] < 0) return fail(WS_EINVAL, "the patches do not cover the domain");
+  // each ghost: mapped into the domain by the physical condition of its
+  // direction (wrap or clamp), then the interior cell of the holding patch
+  std::vector<int64_t> ring0(c->n_patches);
+  std::vector<int32_t> src;
+  for (int k = 0; k < c->n_patches; ++k) {
+    const int mx = c->rows[k].mx, my = c->rows[k].my, n = ring_size(mx, my);
+    ring0[k] = (int64_t)src.size() / 3;
+    for (int g = 0; g < n; ++g) {
+      int i, j;
+      ring_cell(g, mx, my, i, j);
+      int64_t gx = origins[2 * k] + i, gy = origins[2 * k + 1] + j;
+      gx = (periodic & 1) ? ((gx % DX) + DX) % DX : std::min<int64_t>(std::max<int64_t>(gx, 0), DX - 1);
+      gy = (periodic & 2) ? ((gy % DY) + DY) % DY : std::min<int64_t>(std::max<int64_t>(gy, 0), DY - 1);
+      const int32_t o = own[(size_t)(gy * DX + gx)];
+      src.push_back(o);
+      src.push_back((int32_t)(gx - origins[2 * o]));
+      src.push_back((int32_t)(gy - origins[2 * o + 1]));
+    }
+  }
+  char *b = static_cast<char *>(buffer);
+  const int64_t off_src = round_up(8 * (int64_t)std::max(c->n_patches, 1), 256);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpyAsync(b, ring0.data(), 8 * ring0.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(b + off_src, src.data(), 4 * src.size(), hipMemcpyHostToDevice,
+                        c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  c->link_ring0 = reinterpret_cast<const int64_t *>(b);
+  c->link_src = reinterpret_cast<const int32_t *>(b + off_src);
+  c->link_max_ring = 0;
+  for (const PatchRow &r : c->rows) c->link_max_ring = std::max(c->link_max_ring, ring_size(r.mx, r.my));
+  c->drop_graph();
+  return WS_OK;
+}
+
 int ws_get_tiling(ws_ctx *c, int32_t *variant, int32_t *tile_w, int32_t *tile_h,
                   int32_t *wg_per_cu, int32_t *grid) {
   if (!c) return fail(WS_EINVAL, "ctx is NULL");
@@ -555,8 +638,22 @@ int ws_download_patch(ws_ctx *c, int32_t patch, void *dst) {
 
 int ws_fill_ghosts(ws_ctx *c) {
   if (!c) return fail(WS_EINVAL, "ctx is NULL");
-  HIPCHK(launch_fill_ghosts(c->dtype, c->d_patches(), c->n_patches, c->max_padded_cells,
-                            c->pool[c->cur], c->stream));
+  if (c->link_src)
+    HIPCHK(launch_link_ghosts(c->dtype, c->d_patches(), c->n_patches, c->link_max_ring,
+                              c->link_ring0, c->link_src, c->pool[c->cur], c->stream));
+  else
+    HIPCHK(launch_fill_ghosts(c->dtype, c->d_patches(), c->n_patches, c->max_padded_cells,
+                              c->pool[c->cur], c->stream));
+  return WS_OK;
+}
+
+// After a step that wrote pool `dst`: a tiled level's ghosts from the
+// neighbouring patches (the step itself writes the physical ghosts of
+// periodic and extrapolating patches).
+static int link_after_step(ws_ctx *c, int dst) {
+  if (c->link_src)
+    HIPCHK(launch_link_ghosts(c->dtype, c->d_patches(), c->n_patches, c->link_max_ring,
+                              c->link_ring0, c->link_src, c->pool[dst], c->stream));
   return WS_OK;
 }
 
@@ -574,6 +671,7 @@ int ws_step_level(ws_ctx *c, double dt, double *cfl_out) {
   // one persistent launch; its last workgroup also files the Courant numbers
   StepArgs a = c->step_args(c->cur, dt, 0.0);
   HIPCHK(launch_step(c->dtype, c->lim_code(), c->vars, a, c->grid, c->stream));
+  if (int rc = link_after_step(c, 1 - c->cur)) return rc;
   c->cur = 1 - c->cur;
   return read_level_cfl(c, cfl_out);
 }
@@ -589,6 +687,7 @@ int ws_step_level_per_patch(ws_ctx *c, double dt, double *cfl_out) {
     HIPCHK(launch_step(c->dtype, c->lim_code(), c->vars, a, c->rows[k].n_tiles, c->stream));
   }
   HIPCHK(launch_finish_step(c->slots(), 0.0, c->stream));
+  if (int rc = link_after_step(c, 1 - c->cur)) return rc;
   c->cur = 1 - c->cur;
   return read_level_cfl(c, cfl_out);
 }
@@ -611,7 +710,7 @@ int ws_set_dt(ws_ctx *c, const double *dt_per_instance) {
 static int enqueue_auto(ws_ctx *c, int src, double cfl_desired) {
   StepArgs a = c->step_args(src, 0.0, cfl_desired);
   HIPCHK(launch_step(c->dtype, c->lim_code(), c->vars, a, c->grid, c->stream));
-  return WS_OK;
+  return link_after_step(c, 1 - src);
 }
 
 int ws_step_auto(ws_ctx *c, double cfl_desired) {
@@ -763,6 +862,8 @@ int ws_step_record_masks(ws_ctx *c, double dt, void *masks_dev, double *cfl_out)
   if (c->limiter != WS_LIM_MC || c->medium)
     return fail(WS_EINVAL,
                 "branches exist for the MC limiter of the default variant in a homogeneous medium");
+  if (c->link_src)
+    return fail(WS_EINVAL, "branch recording (for the adjoint) does not take a tiled level");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
   StepArgs a = c->step_args(c->cur, dt, 0.0);
   a.masks = reinterpret_cast<uint8_t *>(masks_dev);
@@ -783,6 +884,7 @@ int ws_adjoint_step(ws_ctx *c, double dt, const void *masks_dev, const void *lam
   if (c->limiter != WS_LIM_MC || c->medium)
     return fail(WS_EINVAL,
                 "the adjoint needs the MC limiter of the default variant in a homogeneous medium");
+  if (c->link_src) return fail(WS_EINVAL, "the adjoint does not take a tiled level");
   if (!masks_dev || !lam_in || !lam_out) return fail(WS_EINVAL, "NULL buffer");
   if (lam_in == lam_out) return fail(WS_EINVAL, "lam_in and lam_out must be distinct buffers");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
@@ -903,8 +1005,6 @@ CfSizes cf_sizes(const ws_ctx *fine, int r) {
   return z;
 }
 
-bool same_rel(double a, double b) { return std::fabs(a - b) <= 1e-12 * std::fabs(b); }
-
 }  // namespace
 
 extern "C" {
@@ -930,6 +1030,8 @@ int ws_cf_init(ws_cf **out, ws_ctx *coarse, ws_ctx *fine, int32_t ratio,
   if (coarse->stream != fine->stream) return fail(WS_EINVAL, "the levels must share one stream");
   if (coarse->medium || fine->medium)
     return fail(WS_EINVAL, "the coarse-fine coupling needs homogeneous media");
+  if (fine->link_src)
+    return fail(WS_EINVAL, "the fine level's ghosts come from the coarse level (it is tiled)");
   const CfSizes z = cf_sizes(fine, ratio);
   if (ws_bytes < z.total)
     return fail(WS_ENOMEM, "coupling workspace too small (%lld < %lld bytes)", (long long)ws_bytes,
@@ -1107,9 +1209,7 @@ int ws_cf_step(ws_cf *cf, double dt) {
   // updating and the conservation fix, then the coarse physical ghosts
   a.f_cur = f->pool[f->cur];
   HIPCHK(launch_cf_finish(c->dtype, a, dt, cf->max_finish_blocks, c->stream));
-  HIPCHK(launch_fill_ghosts(c->dtype, c->d_patches(), c->n_patches, c->max_padded_cells,
-                            c->pool[c->cur], c->stream));
-  return WS_OK;
+  return ws_fill_ghosts(c);
 }
 
 int ws_cf_nest(ws_cf *outer, ws_cf *inner) {

@@ -91,6 +91,29 @@ constexpr int kMediumFlag = 0x10000;
 // vars: bit 0 -> DIRECT tiles present, bit 1 -> MARCH tiles present.
 hipError_t launch_step(int dtype, int limiter, int vars, const StepArgs &a, int grid,
                        hipStream_t s);
+// The ghost ring of an mx x my patch in one numbering, shared by the kernels
+// that walk it and the host tables indexed by it: rows -2, -1 across the
+// padded width, rows my, my+1, then columns -2, -1, mx, mx+1 of the interior
+// rows.
+__host__ __device__ inline int ring_size(int mx, int my) { return 4 * (mx + 4) + 4 * my; }
+__host__ __device__ inline void ring_cell(int g, int mx, int my, int &i, int &j) {
+  const int wx = mx + 4;
+  if (g < 2 * wx) {
+    j = g / wx - 2, i = g % wx - 2;
+  } else if (g < 4 * wx) {
+    j = my + (g - 2 * wx) / wx, i = (g - 2 * wx) % wx - 2;
+  } else {
+    const int h = g - 4 * wx, c = h % 4;
+    j = h / 4, i = c < 2 ? c - 2 : mx + c - 2;
+  }
+}
+
+// Ghosts of a level whose patches tile a domain: ghost g of patch p takes
+// the value of interior cell (src[3 e + 1], src[3 e + 2]) of patch
+// src[3 e], e = ring0[p] + g.
+hipError_t launch_link_ghosts(int dtype, const PatchRow *patches, int n_patches, int max_ring,
+                              const int64_t *ring0, const int32_t *src, void *q, hipStream_t s);
+
 hipError_t launch_fill_ghosts(int dtype, const PatchRow *patches, int n_patches,
                               int max_padded_cells, void *q, hipStream_t s);
 // dt[k] = value for every instance.

@@ -1255,22 +1255,13 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void fill_ghosts_kernel(const PatchRow *patches, T *q) {
   const PatchRow pr = patches[blockIdx.y];
   if (pr.bc == WS_BC_NONE) return;
-  const int wx = pr.mx + 4;
   const int64_t org = pr.q_off + 2 * (int64_t)pr.ld + pr.col0;
   T *base = q + org;
-  // the ghost ring only: rows -2, -1, my, my+1 across the padded width, then
-  // columns -2, -1, mx, mx+1 of the interior rows
-  const int ring = 4 * wx + 4 * pr.my;
+  // the ghost ring only
+  const int ring = ring_size(pr.mx, pr.my);
   for (int g = blockIdx.x * kThreads + threadIdx.x; g < ring; g += gridDim.x * kThreads) {
     int i, j;
-    if (g < 2 * wx) {
-      j = g / wx - 2, i = g % wx - 2;
-    } else if (g < 4 * wx) {
-      j = pr.my + (g - 2 * wx) / wx, i = (g - 2 * wx) % wx - 2;
-    } else {
-      const int h = g - 4 * wx, c = h % 4;
-      j = h / 4, i = c < 2 ? c - 2 : pr.mx + c - 2;
-    }
+    ring_cell(g, pr.mx, pr.my, i, j);
     int si, sj;
     if (pr.bc == WS_BC_PERIODIC) {
       si = (i + pr.mx) % pr.mx;
@@ -1281,6 +1272,33 @@ __global__ __launch_bounds__(kThreads) void fill_ghosts_kernel(const PatchRow *p
     }
     const int64_t d = (int64_t)j * pr.ld + i, s = (int64_t)sj * pr.ld + si;
     for (int m = 0; m < 3; ++m) base[m * pr.plane + d] = base[m * pr.plane + s];
+  }
+}
+
+// Ghosts of the patches of a tiled level, each copied from the interior cell
+// of the patch (possibly itself) that its host-built table names (Sec. 2.2:
+// copied from the patch of the same level holding it, after the physical
+// condition has mapped a ghost outside the domain into it).  Writes ghosts,
+// reads interiors: no cell is both.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void link_ghosts_kernel(const PatchRow *patches,
+                                                               const int64_t *ring0,
+                                                               const int32_t *src, T *q) {
+  const PatchRow pr = patches[blockIdx.y];
+  const int ring = ring_size(pr.mx, pr.my);
+  const int32_t *tab = src + 3 * ring0[blockIdx.y];
+  T *dst = q + pr.q_off + 2 * (int64_t)pr.ld + pr.col0;
+  for (int g = blockIdx.x * kThreads + threadIdx.x; g < ring; g += gridDim.x * kThreads) {
+    int i, j;
+    ring_cell(g, pr.mx, pr.my, i, j);
+    const PatchRow sr = patches[tab[3 * g]];
+    const T *s = q + sr.q_off + 2 * (int64_t)sr.ld + sr.col0 + (int64_t)tab[3 * g + 2] * sr.ld +
+                 tab[3 * g + 1];
+    const int64_t d = (int64_t)j * pr.ld + i;
+    const T a = s[0], b = s[sr.plane], c = s[2 * sr.plane];
+    dst[d] = a;
+    dst[pr.plane + d] = b;
+    dst[2 * pr.plane + d] = c;
   }
 }
 
@@ -1529,6 +1547,20 @@ hipError_t launch_fill_ghosts(int dtype, const PatchRow *patches, int n_patches,
   else
     hipLaunchKernelGGL(fill_ghosts_kernel<double>, grid, dim3(kThreads), 0, s, patches,
                        reinterpret_cast<double *>(q));
+  return hipGetLastError();
+}
+
+hipError_t launch_link_ghosts(int dtype, const PatchRow *patches, int n_patches, int max_ring,
+                              const int64_t *ring0, const int32_t *src, void *q, hipStream_t s) {
+  if (n_patches <= 0) return hipSuccess;
+  const dim3 grid((unsigned)max(1, min(64, (max_ring + kThreads - 1) / kThreads)),
+                  (unsigned)n_patches);
+  if (dtype == WS_F32)
+    hipLaunchKernelGGL(link_ghosts_kernel<float>, grid, dim3(kThreads), 0, s, patches, ring0, src,
+                       reinterpret_cast<float *>(q));
+  else
+    hipLaunchKernelGGL(link_ghosts_kernel<double>, grid, dim3(kThreads), 0, s, patches, ring0,
+                       src, reinterpret_cast<double *>(q));
   return hipGetLastError();
 }
 

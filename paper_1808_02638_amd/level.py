@@ -65,6 +65,12 @@ class Level:
         mats = (C.Material * self.n_inst)()
         for k, (rho, K) in enumerate(materials):
             mats[k].rho, mats[k].K = float(rho), float(K)
+        # per patch: instance, cell sizes and the largest sound speed (for a
+        # stable dt where none has been set, e.g. while timing tilings)
+        self.instances = [int(descs[k].instance) for k in range(self.n)]
+        self.cell_sizes = [(float(descs[k].dx), float(descs[k].dy)) for k in range(self.n)]
+        self._cmax = [float(np.sqrt(float(materials[i][1]) / float(materials[i][0])))
+                      for i in self.instances]
         code = C.WS_F64 if dtype == torch.float64 else C.WS_F32
         pool_b, ws_b = ctypes.c_int64(0), ctypes.c_int64(0)
         C.check(self._L.ws_layout(descs, self.n, self.n_inst, code, ctypes.byref(pool_b),
@@ -105,6 +111,25 @@ class Level:
         dp = ctypes.POINTER(ctypes.c_double)
         C.check(self._L.ws_upload_medium(self._ctx, k, rho.ctypes.data_as(dp),
                                          K.ctypes.data_as(dp)))
+        self._cmax[k] = float(np.sqrt(K / rho).max())
+
+    def link(self, origins, domain, periodic=(True, True)) -> None:
+        """Make the level a tiled domain: patch k's interior cell (0, 0) sits at
+        global cell origins[k] = (x0, y0) of a domain of domain = (DX, DY)
+        cells, which the patches cover exactly; periodic per direction.  From
+        now on every step refreshes the ghosts from the neighbouring patches
+        (and the domain's physical condition), and fill_ghosts does too."""
+        if len(origins) != self.n:
+            raise ValueError("one origin per patch")
+        org = np.ascontiguousarray(np.asarray(origins, dtype=np.int32).reshape(self.n, 2))
+        nbytes = ctypes.c_int64(0)
+        C.check(self._L.ws_link_layout(self._ctx, ctypes.byref(nbytes)))
+        self.links = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize(self.device)
+        bits = (1 if periodic[0] else 0) | (2 if periodic[1] else 0)
+        C.check(self._L.ws_link_level(self._ctx, org.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      int(domain[0]), int(domain[1]), bits,
+                                      ctypes.c_void_p(self.links.data_ptr()), nbytes.value))
 
     # ------------------------------------------------------------------ data
     def upload(self, k: int, q) -> None:
@@ -148,6 +173,15 @@ class Level:
         cfl = ctypes.c_double(0.0)
         C.check(self._L.ws_step_level_per_patch(self._ctx, float(dt), ctypes.byref(cfl)))
         return cfl.value
+
+    def stable_dt(self, cfl: float = 0.5) -> list:
+        """Per instance, cfl times the smallest min(dx, dy) / c over its patches
+        (c the largest sound speed of the patch's medium)."""
+        dts = [float("inf")] * self.n_inst
+        for k in range(self.n):
+            i = self.instances[k]
+            dts[i] = min(dts[i], cfl * min(self.cell_sizes[k]) / self._cmax[k])
+        return [d if np.isfinite(d) else 1.0 for d in dts]
 
     def set_dt(self, dts: Iterable[float]) -> None:
         arr = (ctypes.c_double * self.n_inst)(*[float(v) for v in dts])

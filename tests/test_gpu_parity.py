@@ -371,6 +371,32 @@ def test_autotune_restores_state_and_keeps_results(ws, tmp_path):
         assert np.array_equal(a, b)
 
 
+def test_autotune_times_with_a_stable_dt_and_restores_the_levels_dt(ws, tmp_path):
+    """On a level whose device dt was never set, the tuner's timed steps run
+    with a stable dt (their state stays finite, so the restore is exact and
+    the timings are of real data); a dt that was set comes back unchanged."""
+    from paper_1808_02638_amd.autotune import autotune
+
+    shapes = [(120, 120)] * 6
+    lev = ws.Level([dict(mx=mx, my=my, dx=1 / 480, dy=1 / 480) for mx, my in shapes], [(RHO, KB)])
+    rng = np.random.default_rng(5)
+    states = [1.0 + 0.1 * rng.normal(size=(3, my + 4, mx + 4)) for mx, my in shapes]
+    for k, q in enumerate(states):
+        lev.upload(k, q)
+    autotune(lev, launches=4, use_cache=False)
+    dt_after = lev.read_dt_cfl()[0]
+    assert np.isfinite(dt_after).all() and (dt_after > 0).all()
+    for k, q in enumerate(states):
+        assert np.array_equal(lev.download(k), q)
+    for _ in range(3):
+        lev.step(0.9 / 480 / 2.0, read_cfl=False)
+    assert all(np.isfinite(lev.download(k)).all() for k in range(len(shapes)))
+    lev.set_dt([1.25e-4])
+    autotune(lev, launches=4, use_cache=False)
+    assert lev.read_dt_cfl()[0][0] == 1.25e-4
+    lev.close()
+
+
 def test_ensemble_full_size_graph(ws, oracle_lib):
     """The 64-instance ensemble (sides 128-512, K in [1, 9], rho in [0.5, 2]),
     autotuned, 200 steps as one graph with per-instance FP64 Courant numbers:
