@@ -139,7 +139,8 @@ int ws_set_tiling(ws_ctx *ctx, const int32_t *variant, const int32_t *tile_w,
  * max over edges of max(c_l, c_r) dt/dx from the cells (the instance's
  * material is then unused; the instance still owns the dt slot).  Not with
  * WS_TRANSVERSE_CORR, branch recording, the adjoint or the coarse-fine
- * coupling.  Synchronises the stream. */
+ * coupling; WS_EINVAL for a patch whose three planes span 4 GiB or more.
+ * Synchronises the stream. */
 int ws_attach_medium(ws_ctx *ctx, void *medium, int64_t bytes);
 /* rho, K: host arrays [my+4][mx+4] (ghost cells included: the step reads the
  * medium of ghost cells next to the patch), finite and > 0.  Synchronises. */

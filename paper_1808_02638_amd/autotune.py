@@ -43,15 +43,18 @@ def size_classes(level):
     return dict(cls)
 
 
-def candidates(mx, my, periodic):
+def candidates(mx, my, periodic, medium=False):
     """Tilings worth timing for patches of about mx x my cells (DIRECT only when
-    ``periodic``: periodic patches and heterogeneous media)."""
+    ``periodic``: periodic patches and heterogeneous media).  A heterogeneous
+    medium's DIRECT threads march up their column, so taller runs of rows per
+    thread are tried too."""
     out = []
+    rows = (1, 2, 4, 8, 16, 32, 64) if medium else (1, 2, 4, 8)
     for tw in (8, 16, 32, 64, 128):
         if tw > 2 * mx and tw > 8:
             continue
         nty = 256 // tw
-        for r in (1, 2, 4, 8):
+        for r in rows:
             if nty * r > 2 * my and r > 1:
                 continue
             out.append((DIRECT, tw, nty * r))
@@ -139,7 +142,8 @@ def autotune(level, *, launches=40, use_cache=True, cache_path=None, verbose=Fal
         idx = classes[c]
         mx = int(np.median([level.shapes[k][0] for k in idx]))
         my = int(np.median([level.shapes[k][1] for k in idx]))
-        for cand in candidates(mx, my, c[2] or getattr(level, "medium", None) is not None):
+        medium = getattr(level, "medium", None) is not None
+        for cand in candidates(mx, my, c[2] or medium, medium):
             if cand == choice[c]:
                 continue
             trial = dict(choice)

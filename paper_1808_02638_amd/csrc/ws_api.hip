@@ -474,6 +474,12 @@ int ws_attach_medium(ws_ctx *c, void *medium, int64_t bytes) {
                 (long long)c->pool_bytes);
   if (c->limiter & WS_TRANSVERSE_CORR)
     return fail(WS_EINVAL, "a heterogeneous medium needs the default transverse variant");
+  // the medium kernel addresses a patch's three planes with 32-bit offsets
+  const int64_t es = c->dtype == WS_F32 ? 4 : 8;
+  for (int k = 0; k < c->n_patches; ++k)
+    if (3 * c->rows[k].plane * es >= ((int64_t)1 << 32))
+      return fail(WS_EINVAL, "patch %d: its three planes span 4 GiB or more (too large for a "
+                  "heterogeneous medium)", k);
   HIPCHK(hipStreamSynchronize(c->stream));
   c->medium = medium;
   // DIRECT tiles (the default DIRECT shape of each patch)

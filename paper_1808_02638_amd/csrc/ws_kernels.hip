@@ -89,6 +89,24 @@ struct Planes {
   __device__ T V(int i, int j) const { return v[(int64_t)j * ld + i]; }
 };
 
+// The same planes read through unsigned 32-bit byte offsets from a
+// wave-uniform base at padded cell (-2, -2) of plane 0: each load takes the
+// scalar base and one 32-bit vector offset instead of a 64-bit address of its
+// own.  The three planes of a patch must span less than 4 GiB.
+template <typename T>
+struct Planes32 {
+  const char *b;
+  uint32_t ld, plb;  // row stride (elements), plane stride (bytes)
+  __device__ uint32_t off(int i, int j) const {
+    return ((uint32_t)(j + 2) * ld + (uint32_t)(i + 2)) * (uint32_t)sizeof(T);
+  }
+  __device__ T P(int i, int j) const { return *reinterpret_cast<const T *>(b + off(i, j)); }
+  __device__ T U(int i, int j) const { return *reinterpret_cast<const T *>(b + plb + off(i, j)); }
+  __device__ T V(int i, int j) const {
+    return *reinterpret_cast<const T *>(b + 2 * plb + off(i, j));
+  }
+};
+
 struct CellMasks {
   unsigned own;    // bits of the cell's left x-edge (0-3) and bottom y-edge (4-7)
   unsigned right;  // bits 0-3 of the right x-edge (stored at cell i+1)
@@ -272,9 +290,24 @@ __device__ __attribute__((always_inline)) inline void cell_update_tc(const Plane
 // B+X = c_t X_p/(Z + Z_t) (Z_t, 0, 1): the G~ of the edge (b, t) gets
 //   -dt/(2dx) (c_t Z_t X_p(b) - c_b Z_b X_p(t), c_t X_p(b) + c_b X_p(t)) / (Z_b + Z_t)
 // (p and v), sharing the edge's 1/(Z_b + Z_t); F~ alike.
+// 1/x for x > 0 of moderate size (a sum of two impedances): the hardware
+// reciprocal refined by Newton's iteration r <- r + r (1 - x r), twice in FP64
+// (each step doubles the correct bits), once in FP32.
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 template <typename T>
 __device__ inline void var_strengths(T Zl, T Zr, T dp, T dn, T &a1, T &a2, T &iz) {
-  iz = T(1) / (Zl + Zr);
+  iz = recip(Zl + Zr);
   a1 = (Zr * dn - dp) * iz;
   a2 = (dp + Zl * dn) * iz;
 }
@@ -309,13 +342,12 @@ struct VarLine {
   T cl, zl, c0, z0, cr, zr;  // c and Z of the cell and its two neighbours
 };
 
+// The line from its four edges' strengths (edge e between cells e and e+1 of
+// the five), so a caller that carries edges along a column can reuse them.
 template <typename T, int LIM>
-__device__ inline VarLine<T> var_line(const T P[5], const T N[5], const T C[5], const T Zc[5],
-                                      T wl, T w0, T wr, T dtdx) {
-  T a1[4], a2[4], iz[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e)
-    var_strengths(Zc[e], Zc[e + 1], P[e + 1] - P[e], N[e + 1] - N[e], a1[e], a2[e], iz[e]);
+__device__ inline VarLine<T> var_line_edges(const T a1[4], const T a2[4], const T iz[4],
+                                            const T C[5], const T Zc[5], T wl, T w0, T wr,
+                                            T dtdx) {
   VarLine<T> L;
   T l1, l2;
   var_limited<T, LIM>(a1[1], a2[1], a1[2], a2[0], Zc[1], Zc[2], wl, w0, l1, l2);
@@ -329,12 +361,52 @@ __device__ inline VarLine<T> var_line(const T P[5], const T N[5], const T C[5], 
   return L;
 }
 
+template <typename T, int LIM>
+__device__ inline VarLine<T> var_line(const T P[5], const T N[5], const T C[5], const T Zc[5],
+                                      T wl, T w0, T wr, T dtdx) {
+  T a1[4], a2[4], iz[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    var_strengths(Zc[e], Zc[e + 1], P[e + 1] - P[e], N[e + 1] - N[e], a1[e], a2[e], iz[e]);
+  return var_line_edges<T, LIM>(a1, a2, iz, C, Zc, wl, w0, wr, dtdx);
+}
+
+// The cell's update from its two lines and the p-parts of the neighbours'
+// fluctuations: X-fluctuations of the cells below and above (Xpb, Xpt) and
+// Y-fluctuations of the cells left and right (Ypl, Ypr), each c Z times the
+// neighbour's own fluctuation sum.  F~ at x-edges i-1/2 and i+1/2 take the
+// normal correction and the transverse waves from the y-fluctuations of the
+// cells on either side; G~ alike.
+template <typename T>
+__device__ inline void var_combine(const VarLine<T> &X, const VarLine<T> &Y, T Xpb, T Xpt, T Ypl,
+                                   T Ypr, T p0, T u0, T v0, T dtdx, T dtdy, T &pn, T &un, T &vn,
+                                   T &cfl) {
+  const T c0 = X.c0, Z0 = X.z0;
+  const T Xp0 = c0 * Z0 * X.xs, Yp0 = c0 * Z0 * Y.xs;
+  T h = T(0.5) * dtdy * X.izl;
+  const T FLp = X.Fl_p - h * (X.c0 * X.z0 * Ypl - X.cl * X.zl * Yp0);
+  const T FLu = X.Fl_n - h * (X.c0 * Ypl + X.cl * Yp0);
+  h = T(0.5) * dtdy * X.izr;
+  const T FRp = X.Fr_p - h * (X.cr * X.zr * Yp0 - X.c0 * X.z0 * Ypr);
+  const T FRu = X.Fr_n - h * (X.cr * Yp0 + X.c0 * Ypr);
+  h = T(0.5) * dtdx * Y.izl;
+  const T GBp = Y.Fl_p - h * (Y.c0 * Y.z0 * Xpb - Y.cl * Y.zl * Xp0);
+  const T GBv = Y.Fl_n - h * (Y.c0 * Xpb + Y.cl * Xp0);
+  h = T(0.5) * dtdx * Y.izr;
+  const T GTp = Y.Fr_p - h * (Y.cr * Y.zr * Xp0 - Y.c0 * Y.z0 * Xpt);
+  const T GTv = Y.Fr_n - h * (Y.cr * Xp0 + Y.c0 * Xpt);
+  pn = p0 - dtdx * (Xp0 + (FRp - FLp)) - dtdy * (Yp0 + (GTp - GBp));
+  un = u0 - dtdx * (c0 * X.xd + (FRu - FLu));
+  vn = v0 - dtdy * (c0 * Y.xd + (GTv - GBv));
+  cfl = fmax(fmax(fmax(X.cl, X.c0), X.cr) * dtdx, fmax(fmax(Y.cl, Y.c0), Y.cr) * dtdy);
+}
+
 // DIRECT update of cell (i, j) in a heterogeneous medium (13-point footprint
 // of q and of the medium), taken in stages behind scheduling barriers so that
 // only a few values stay live between them; cfl receives the largest
 // |s| dt/dx over its four edges.
 template <typename T, int LIM>
-__device__ inline void cell_update_var(const Planes<T> &q, const Planes<T> &md, int i, int j,
+__device__ inline void cell_update_var(const Planes32<T> &q, const Planes32<T> &md, int i, int j,
                                        const Coef<T> &k, T &pn, T &un, T &vn, T &cfl) {
   const T dtdx = k.dtdx, dtdy = k.dtdy;
   const T w0 = md.V(i, j);
@@ -386,27 +458,8 @@ __device__ inline void cell_update_var(const Planes<T> &q, const Planes<T> &md, 
   __builtin_amdgcn_sched_barrier(0);
   const T Ypl = yp_col(i - 1), Ypr = yp_col(i + 1);
   __builtin_amdgcn_sched_barrier(0);
-  const T c0 = X.c0, Z0 = X.z0;
-  const T Xp0 = c0 * Z0 * X.xs, Yp0 = c0 * Z0 * Y.xs;
-  // F~ at x-edges i-1/2 and i+1/2: normal correction and transverse waves
-  // from the y-fluctuations of the cells on either side
-  T h = T(0.5) * dtdy * X.izl;
-  const T FLp = X.Fl_p - h * (X.c0 * X.z0 * Ypl - X.cl * X.zl * Yp0);
-  const T FLu = X.Fl_n - h * (X.c0 * Ypl + X.cl * Yp0);
-  h = T(0.5) * dtdy * X.izr;
-  const T FRp = X.Fr_p - h * (X.cr * X.zr * Yp0 - X.c0 * X.z0 * Ypr);
-  const T FRu = X.Fr_n - h * (X.cr * Yp0 + X.c0 * Ypr);
-  // G~ at y-edges j-1/2 and j+1/2
-  h = T(0.5) * dtdx * Y.izl;
-  const T GBp = Y.Fl_p - h * (Y.c0 * Y.z0 * Xpb - Y.cl * Y.zl * Xp0);
-  const T GBv = Y.Fl_n - h * (Y.c0 * Xpb + Y.cl * Xp0);
-  h = T(0.5) * dtdx * Y.izr;
-  const T GTp = Y.Fr_p - h * (Y.cr * Y.zr * Xp0 - Y.c0 * Y.z0 * Xpt);
-  const T GTv = Y.Fr_n - h * (Y.cr * Xp0 + Y.c0 * Xpt);
-  pn = q.P(i, j) - dtdx * (Xp0 + (FRp - FLp)) - dtdy * (Yp0 + (GTp - GBp));
-  un = q.U(i, j) - dtdx * (c0 * X.xd + (FRu - FLu));
-  vn = q.V(i, j) - dtdy * (c0 * Y.xd + (GTv - GBv));
-  cfl = fmax(fmax(fmax(X.cl, X.c0), X.cr) * dtdx, fmax(fmax(Y.cl, Y.c0), Y.cr) * dtdy);
+  var_combine(X, Y, Xpb, Xpt, Ypl, Ypr, q.P(i, j), q.U(i, j), q.V(i, j), dtdx, dtdy, pn, un, vn,
+              cfl);
 }
 
 // Store a new cell value and, on physical boundaries, its ghost images.  Up
@@ -453,6 +506,105 @@ __device__ inline void store(T *qo, int64_t plane, int64_t ld, int i, int j, int
     qo[plane + o] = un;
     qo[2 * plane + o] = vn;
   }
+}
+
+// Heterogeneous medium, one column i marched up over rows [j0, j1): the
+// quantities of cell_update_var, each formed by the same expression from the
+// same inputs (so every cell's result is bitwise that of cell_update_var),
+// with what neighbouring rows share carried in registers: the column's
+// five-row window (p, v, c, Z, 1/(Z^2 + 1)), the four y-edges along it, the
+// x-line of the next row (computed one row ahead, it also gives that row's
+// x-fluctuation), the x-fluctuation of the row below, and the lower y-edge of
+// the neighbouring columns.  Per row: one row of loads and seven edge solves
+// instead of sixteen.  Returns the largest Courant number of the cells.
+template <typename T, int LIM>
+__device__ inline T march_col_var(const Planes32<T> &q, const Planes32<T> &md, int i, int j0,
+                                  int j1, const Coef<T> &k, T *qo, const PatchRow &pr) {
+  const T dtdx = k.dtdx, dtdy = k.dtdy;
+  // the column's window, rows j-2 .. j+2
+  T Pc[5], Vc[5], Cc[5], Zc[5], Wc[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    Pc[d] = q.P(i, j0 + d - 2), Vc[d] = q.V(i, j0 + d - 2);
+    Cc[d] = md.P(i, j0 + d - 2), Zc[d] = md.U(i, j0 + d - 2), Wc[d] = md.V(i, j0 + d - 2);
+  }
+  // y-edge e between window rows e and e+1
+  T b1[4], b2[4], bz[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    var_strengths(Zc[e], Zc[e + 1], Pc[e + 1] - Pc[e], Vc[e + 1] - Vc[e], b1[e], b2[e], bz[e]);
+  // x-line of row jj (centre values from the window), with p and u of the
+  // centre and p of the cells left and right
+  auto xline = [&](int jj, T pc, T cc, T zc, T wc, T &uc, T &pl, T &pr_) {
+    T P[5], U[5], C[5], Z[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      if (d == 2) continue;
+      P[d] = q.P(i + d - 2, jj), U[d] = q.U(i + d - 2, jj);
+      C[d] = md.P(i + d - 2, jj), Z[d] = md.U(i + d - 2, jj);
+    }
+    P[2] = pc, U[2] = q.U(i, jj), C[2] = cc, Z[2] = zc;
+    uc = U[2], pl = P[1], pr_ = P[3];
+    return var_line<T, LIM>(P, U, C, Z, md.V(i - 1, jj), wc, md.V(i + 1, jj), dtdx);
+  };
+  T u0, pl0, pr0;
+  VarLine<T> XL = xline(j0, Pc[2], Cc[2], Zc[2], Wc[2], u0, pl0, pr0);
+  // x-fluctuation p-part of row j0-1
+  T Xpb;
+  {
+    const int jj = j0 - 1;
+    const T pl = q.P(i - 1, jj), p0 = Pc[1], pr_ = q.P(i + 1, jj);
+    const T ul = q.U(i - 1, jj), uu = q.U(i, jj), ur = q.U(i + 1, jj);
+    const T Zl = md.U(i - 1, jj), Z0 = Zc[1], Zr = md.U(i + 1, jj), c0 = Cc[1];
+    T s1l, s2l, izl, s1r, s2r, izr;
+    var_strengths(Zl, Z0, p0 - pl, uu - ul, s1l, s2l, izl);
+    var_strengths(Z0, Zr, pr_ - p0, ur - uu, s1r, s2r, izr);
+    Xpb = c0 * Z0 * (s2l + s1r);
+  }
+  // the neighbouring columns at row j: p, v, Z there and a2 of their y-edge j-1/2
+  T Pl = pl0, Vl = q.V(i - 1, j0), Pr = pr0, Vr = q.V(i + 1, j0), s2bl, s2br;
+  {
+    T s1, iz;
+    var_strengths(md.U(i - 1, j0 - 1), XL.zl, Pl - q.P(i - 1, j0 - 1), Vl - q.V(i - 1, j0 - 1),
+                  s1, s2bl, iz);
+    var_strengths(md.U(i + 1, j0 - 1), XL.zr, Pr - q.P(i + 1, j0 - 1), Vr - q.V(i + 1, j0 - 1),
+                  s1, s2br, iz);
+  }
+  T cfl = T(0);
+  for (int j = j0; j < j1; ++j) {
+    // row j+1: its x-line and x-fluctuation, and the neighbours' p, v there
+    T u1, pl1, pr1;
+    const VarLine<T> XN = xline(j + 1, Pc[3], Cc[3], Zc[3], Wc[3], u1, pl1, pr1);
+    const T vl1 = q.V(i - 1, j + 1), vr1 = q.V(i + 1, j + 1);
+    const T Xpt = XN.c0 * XN.z0 * XN.xs;
+    // y-line of row j from the carried edges
+    const VarLine<T> Y = var_line_edges<T, LIM>(b1, b2, bz, Cc, Zc, Wc[1], Wc[2], Wc[3], dtdy);
+    // y-fluctuation p-parts of the cells left and right: their y-edge j+1/2
+    T s1tl, s2tl, izl, s1tr, s2tr, izr;
+    var_strengths(XL.zl, XN.zl, pl1 - Pl, vl1 - Vl, s1tl, s2tl, izl);
+    var_strengths(XL.zr, XN.zr, pr1 - Pr, vr1 - Vr, s1tr, s2tr, izr);
+    const T Ypl = XL.cl * XL.zl * (s2bl + s1tl), Ypr = XL.cr * XL.zr * (s2br + s1tr);
+    T pn, un, vn, cj;
+    var_combine(XL, Y, Xpb, Xpt, Ypl, Ypr, Pc[2], u0, Vc[2], dtdx, dtdy, pn, un, vn, cj);
+    cfl = fmax(cfl, cj);
+    store<T>(qo, pr.plane, pr.ld, i, j, pr.mx, pr.my, pr.bc, pn, un, vn);
+    if (j + 1 >= j1) break;
+    // slide up one row
+    Xpb = XL.c0 * XL.z0 * XL.xs;
+    XL = XN;
+    u0 = u1;
+    Pl = pl1, Vl = vl1, Pr = pr1, Vr = vr1, s2bl = s2tl, s2br = s2tr;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      Pc[d] = Pc[d + 1], Vc[d] = Vc[d + 1], Cc[d] = Cc[d + 1], Zc[d] = Zc[d + 1], Wc[d] = Wc[d + 1];
+    }
+    Pc[4] = q.P(i, j + 3), Vc[4] = q.V(i, j + 3);
+    Cc[4] = md.P(i, j + 3), Zc[4] = md.U(i, j + 3), Wc[4] = md.V(i, j + 3);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) b1[e] = b1[e + 1], b2[e] = b2[e + 1], bz[e] = bz[e + 1];
+    var_strengths(Zc[3], Zc[4], Pc[4] - Pc[3], Vc[4] - Vc[3], b1[3], b2[3], bz[3]);
+  }
+  return cfl;
 }
 
 // Whole-wavefront lane shifts (DPP): shr gives lane l the value of lane l-1,
@@ -1050,17 +1202,14 @@ __device__ __attribute__((always_inline)) inline double do_unit(const StepArgs &
     const Planes<T> q{qi, qi + pr.plane, qi + 2 * pr.plane, pr.ld};
     if constexpr (VAR) {
       // heterogeneous medium: the tile's Courant number is reduced from its cells
-      const T *mi = reinterpret_cast<const T *>(a.medium) + org;
-      const Planes<T> md{mi, mi + pr.plane, mi + 2 * pr.plane, pr.ld};
+      const int64_t first = 2 * (int64_t)pr.ld + 2;  // padded (-2, -2) from interior (0, 0)
+      const uint32_t plb = (uint32_t)(pr.plane * (int64_t)sizeof(T));
+      const Planes32<T> q32{reinterpret_cast<const char *>(qi - first), (uint32_t)pr.ld, plb};
+      const Planes32<T> md{reinterpret_cast<const char *>(reinterpret_cast<const T *>(a.medium) +
+                                                          org - first),
+                           (uint32_t)pr.ld, plb};
       T cfl = T(0);
-      if (i < pr.mx && j0 < j1) {
-        for (int j = j0; j < j1; ++j) {
-          T pn, un, vn, cj;
-          cell_update_var<T, LIM>(q, md, i, j, k, pn, un, vn, cj);
-          cfl = fmax(cfl, cj);
-          store<T>(qo, pr.plane, pr.ld, i, j, pr.mx, pr.my, pr.bc, pn, un, vn);
-        }
-      }
+      if (i < pr.mx && j0 < j1) cfl = march_col_var<T, LIM>(q32, md, i, j0, j1, k, qo, pr);
       return wave_max((double)cfl);
     }
     if (i < pr.mx && j0 < j1) {

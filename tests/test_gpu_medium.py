@@ -2,8 +2,9 @@
 the oracle's heterogeneous step, through the C ABI.
 
 FP64 within a relative L-infinity of 1e-12 per component (the Courant number
-bitwise), FP32 within 1e-5; tilings and batched vs per-patch launches
-bitwise equal; a uniform medium reproduces the homogeneous kernels.
+bitwise), FP32 within 1e-5; tilings (one to 64 rows marched per thread) and
+batched vs per-patch launches bitwise equal; a uniform medium reproduces the
+homogeneous kernels.
 """
 
 import math
@@ -128,7 +129,9 @@ def test_tilings_and_batching_bitwise(ws):
 
     dt = 0.5 / 64 / 10.0
     outs = []
-    for tiling in [None, (8, 32), (64, 4), (32, 64), (256, 1)]:
+    # one row per thread (8x32, 64x4, 256x1) up to 64 rows per thread (64x256,
+    # 16x1024): each thread marches up its column carrying values between rows
+    for tiling in [None, (8, 32), (64, 4), (32, 64), (256, 1), (64, 256), (16, 1024)]:
         lev = make(tiling)
         for _ in range(3):
             lev.step(dt)
