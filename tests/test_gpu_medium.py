@@ -169,3 +169,33 @@ def test_medium_restrictions(ws):
     with pytest.raises(ws.WaveStepError):
         tc.set_medium(0, rho, K)
     tc.close()
+
+
+def test_full_size_layered_medium_matches_oracle(ws):
+    """The benchmark's heterogeneous workload at full size (2048^2 FP64 pulse
+    in the layered, perturbed medium, extrapolating sides), tiled by the
+    autotuner as the benchmark is: three steps at Courant number 0.9 against
+    the oracle over every cell, and the Courant number bitwise."""
+    import workloads
+    from paper_1808_02638_amd.autotune import autotune
+
+    n = 2048
+    dx = 1.0 / n
+    rho, K = workloads.layered_medium(n, n)
+    q = workloads.padded_state(n, n, 0.0, 0.0, dx, dx)
+    O.fill_bc(q, "extrap")
+    lev = ws.Level([dict(mx=n, my=n, dx=dx, dy=dx, bc="extrap")], [(1.0, 4.0)])
+    lev.set_medium(0, rho, K)
+    lev.upload(0, q)
+    autotune(lev, launches=4, use_cache=False)
+    dt = 0.9 * dx / float(np.sqrt(K / rho).max())
+    ref = q
+    for _ in range(3):
+        ref, cfl_o = O.step_var(ref, dx, dx, dt, rho, K, "mc")
+        O.fill_bc(ref, "extrap")
+        cfl_g = lev.step(dt)
+        assert cfl_g == cfl_o
+    err = rel_linf(lev.download(0), ref)
+    print(f"full-size medium: rel Linf {err}, tiling {lev.get_tiling()[:3]}")
+    assert err.max() <= FP64_TOL, err
+    lev.close()

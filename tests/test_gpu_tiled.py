@@ -203,3 +203,35 @@ def test_tiled_layouts_and_uses_are_checked(ws):
         ws.TwoLevel(coarse, lev, 2, [(0, 4, 4), (0, 10, 4)])
     coarse.close()
     lev.close()
+
+
+def test_full_size_tiled_level_equals_single_patch(ws):
+    """The benchmark's tiled workload at full size: the 2048^2 FP64 pulse as
+    4 x 4 patches of 512^2 with extrapolating sides, autotuned, 20 steps at
+    Courant number 0.9 in one captured graph, equals the domain as one patch
+    bitwise, ghosts included."""
+    import workloads
+    from paper_1808_02638_amd.autotune import autotune
+
+    n, t = 2048, 4
+    w, dx = n // t, 1.0 / n
+    q = workloads.padded_state(n, n, 0.0, 0.0, dx, dx)
+    O.fill_bc(q, "extrap")
+    origins = [(w * a, w * b) for b in range(t) for a in range(t)]
+    tiled = ws.Level([dict(mx=w, my=w, dx=dx, dy=dx) for _ in origins], [(RHO, KB)])
+    tiled.link(origins, (n, n), (False, False))
+    for k, (x0, y0) in enumerate(origins):
+        tiled.upload(k, np.ascontiguousarray(q[:, y0:y0 + w + 4, x0:x0 + w + 4]))
+    one = ws.Level([dict(mx=n, my=n, dx=dx, dy=dx, bc="extrap")], [(RHO, KB)])
+    one.upload(0, q)
+    for L in (tiled, one):
+        autotune(L, launches=4, use_cache=False)
+        L.set_dt([0.9 * dx / C0])
+        L.capture(20, 0.9)
+        L.graph_launch()
+    R = one.download(0)
+    for k, (x0, y0) in enumerate(origins):
+        assert np.array_equal(tiled.download(k), R[:, y0:y0 + w + 4, x0:x0 + w + 4]), k
+    assert np.array_equal(tiled.read_dt_cfl()[0], one.read_dt_cfl()[0])
+    tiled.close()
+    one.close()
