@@ -203,7 +203,7 @@ def run_tiled(ws, torch, n=2048, tiles=4, steps=200, warmup=10, tune=True):
     return {"domain": f"{n}x{n}", "tiles": f"{tiles}x{tiles} of {w}x{w}", "steps": steps,
             "value": round(n * n * steps / (ms / 1e3) / 1e9, 3),
             "us_per_step": round(ms / steps * 1e3, 2),
-            "exchange_bytes_per_step": ghosts * (2 * 3 * 8 + 12),
+            "exchange_bytes_per_step": ghosts * (2 * 3 * 8 + 16),
             "tiling": {"variant": var[0], "tile_w": int(tw[0]), "tile_h": int(th[0]),
                        "wg_per_cu": wg},
             "cfl_max": float(cfl_max[0]), "finite": finite}

@@ -173,8 +173,9 @@ int ws_fill_ghosts(ws_ctx *ctx);
  * the domain as one patch.  ws_step_record_masks, ws_adjoint_step and use as
  * the fine level of a coupling refuse a tiled level.
  *
- * Bytes of the link buffer: 8 per patch (ring offsets) and 12 per ghost cell
- * (source patch and cell), each part rounded up to 256. */
+ * Bytes of the link buffer: 8 per patch (ring offsets) and 16 per ghost cell
+ * (the source cell's pool offset and its patch's plane stride), each part
+ * rounded up to 256. */
 int ws_link_layout(ws_ctx *ctx, int64_t *bytes);
 /* origins: 2 per patch, global cell (x0, y0) of its interior cell (0, 0).
  * The patches must cover [0, domain_mx) x [0, domain_my) exactly, without

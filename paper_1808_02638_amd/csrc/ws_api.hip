@@ -242,7 +242,7 @@ struct ws_ctx {
   void *medium = nullptr;          // per-cell (c, Z) planes, laid out like a q pool
   // tiled level: per-patch ghost-ring offsets and the ghost source table
   const int64_t *link_ring0 = nullptr;
-  const int32_t *link_src = nullptr;
+  const int64_t *link_src = nullptr;
   int link_max_ring = 0;
   // limiter code of the kernel launchers (the medium selects its own kernel)
   int lim_code() const { return limiter | (medium ? kMediumFlag : 0); }
@@ -526,7 +526,7 @@ int ws_link_layout(ws_ctx *c, int64_t *bytes) {
   if (!c || !bytes) return fail(WS_EINVAL, "NULL argument");
   int64_t ghosts = 0;
   for (const PatchRow &r : c->rows) ghosts += ring_size(r.mx, r.my);
-  *bytes = round_up(8 * (int64_t)std::max(c->n_patches, 1), 256) + round_up(12 * ghosts, 256);
+  *bytes = round_up(8 * (int64_t)std::max(c->n_patches, 1), 256) + round_up(16 * ghosts, 256);
   return WS_OK;
 }
 
@@ -569,10 +569,10 @@ int ws_link_level(ws_ctx *c, const int32_t *origins, int32_t domain_mx, int32_t 
   // each ghost: mapped into the domain by the physical condition of its
   // direction (wrap or clamp), then the interior cell of the holding patch
   std::vector<int64_t> ring0(c->n_patches);
-  std::vector<int32_t> src;
+  std::vector<int64_t> src;
   for (int k = 0; k < c->n_patches; ++k) {
     const int mx = c->rows[k].mx, my = c->rows[k].my, n = ring_size(mx, my);
-    ring0[k] = (int64_t)src.size() / 3;
+    ring0[k] = (int64_t)src.size() / 2;
     for (int g = 0; g < n; ++g) {
       int i, j;
       ring_cell(g, mx, my, i, j);
@@ -580,20 +580,21 @@ int ws_link_level(ws_ctx *c, const int32_t *origins, int32_t domain_mx, int32_t 
       gx = (periodic & 1) ? ((gx % DX) + DX) % DX : std::min<int64_t>(std::max<int64_t>(gx, 0), DX - 1);
       gy = (periodic & 2) ? ((gy % DY) + DY) % DY : std::min<int64_t>(std::max<int64_t>(gy, 0), DY - 1);
       const int32_t o = own[(size_t)(gy * DX + gx)];
-      src.push_back(o);
-      src.push_back((int32_t)(gx - origins[2 * o]));
-      src.push_back((int32_t)(gy - origins[2 * o + 1]));
+      const PatchRow &sr = c->rows[o];
+      const int64_t si = gx - origins[2 * o], sj = gy - origins[2 * o + 1];
+      src.push_back(sr.q_off + (sj + 2) * (int64_t)sr.ld + sr.col0 + si);
+      src.push_back(sr.plane);
     }
   }
   char *b = static_cast<char *>(buffer);
   const int64_t off_src = round_up(8 * (int64_t)std::max(c->n_patches, 1), 256);
   HIPCHK(hipStreamSynchronize(c->stream));
   HIPCHK(hipMemcpyAsync(b, ring0.data(), 8 * ring0.size(), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemcpyAsync(b + off_src, src.data(), 4 * src.size(), hipMemcpyHostToDevice,
+  HIPCHK(hipMemcpyAsync(b + off_src, src.data(), 8 * src.size(), hipMemcpyHostToDevice,
                         c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
   c->link_ring0 = reinterpret_cast<const int64_t *>(b);
-  c->link_src = reinterpret_cast<const int32_t *>(b + off_src);
+  c->link_src = reinterpret_cast<const int64_t *>(b + off_src);
   c->link_max_ring = 0;
   for (const PatchRow &r : c->rows) c->link_max_ring = std::max(c->link_max_ring, ring_size(r.mx, r.my));
   c->drop_graph();

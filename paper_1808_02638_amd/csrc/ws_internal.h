@@ -109,10 +109,10 @@ __host__ __device__ inline void ring_cell(int g, int mx, int my, int &i, int &j)
 }
 
 // Ghosts of a level whose patches tile a domain: ghost g of patch p takes
-// the value of interior cell (src[3 e + 1], src[3 e + 2]) of patch
-// src[3 e], e = ring0[p] + g.
+// components m = 0, 1, 2 from pool elements src[2 e] + m src[2 e + 1],
+// e = ring0[p] + g (the source cell's offset and its patch's plane stride).
 hipError_t launch_link_ghosts(int dtype, const PatchRow *patches, int n_patches, int max_ring,
-                              const int64_t *ring0, const int32_t *src, void *q, hipStream_t s);
+                              const int64_t *ring0, const int64_t *src, void *q, hipStream_t s);
 
 hipError_t launch_fill_ghosts(int dtype, const PatchRow *patches, int n_patches,
                               int max_padded_cells, void *q, hipStream_t s);

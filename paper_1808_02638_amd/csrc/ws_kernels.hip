@@ -1427,24 +1427,24 @@ __global__ __launch_bounds__(kThreads) void fill_ghosts_kernel(const PatchRow *p
 // Ghosts of the patches of a tiled level, each copied from the interior cell
 // of the patch (possibly itself) that its host-built table names (Sec. 2.2:
 // copied from the patch of the same level holding it, after the physical
-// condition has mapped a ghost outside the domain into it).  Writes ghosts,
-// reads interiors: no cell is both.
+// condition has mapped a ghost outside the domain into it).  The table holds,
+// per ghost, the pool element offset of the source cell's first component and
+// the source patch's plane stride, so each ghost is one table load and three
+// data loads.  Writes ghosts, reads interiors: no cell is both.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void link_ghosts_kernel(const PatchRow *patches,
                                                                const int64_t *ring0,
-                                                               const int32_t *src, T *q) {
+                                                               const int64_t *src, T *q) {
   const PatchRow pr = patches[blockIdx.y];
   const int ring = ring_size(pr.mx, pr.my);
-  const int32_t *tab = src + 3 * ring0[blockIdx.y];
+  const int64_t *tab = src + 2 * ring0[blockIdx.y];
   T *dst = q + pr.q_off + 2 * (int64_t)pr.ld + pr.col0;
   for (int g = blockIdx.x * kThreads + threadIdx.x; g < ring; g += gridDim.x * kThreads) {
     int i, j;
     ring_cell(g, pr.mx, pr.my, i, j);
-    const PatchRow sr = patches[tab[3 * g]];
-    const T *s = q + sr.q_off + 2 * (int64_t)sr.ld + sr.col0 + (int64_t)tab[3 * g + 2] * sr.ld +
-                 tab[3 * g + 1];
+    const int64_t so = tab[2 * g], sp = tab[2 * g + 1];
+    const T a = q[so], b = q[so + sp], c = q[so + 2 * sp];
     const int64_t d = (int64_t)j * pr.ld + i;
-    const T a = s[0], b = s[sr.plane], c = s[2 * sr.plane];
     dst[d] = a;
     dst[pr.plane + d] = b;
     dst[2 * pr.plane + d] = c;
@@ -1700,7 +1700,7 @@ hipError_t launch_fill_ghosts(int dtype, const PatchRow *patches, int n_patches,
 }
 
 hipError_t launch_link_ghosts(int dtype, const PatchRow *patches, int n_patches, int max_ring,
-                              const int64_t *ring0, const int32_t *src, void *q, hipStream_t s) {
+                              const int64_t *ring0, const int64_t *src, void *q, hipStream_t s) {
   if (n_patches <= 0) return hipSuccess;
   const dim3 grid((unsigned)max(1, min(64, (max_ring + kThreads - 1) / kThreads)),
                   (unsigned)n_patches);
