@@ -235,3 +235,32 @@ def test_full_size_tiled_level_equals_single_patch(ws):
     assert np.array_equal(tiled.read_dt_cfl()[0], one.read_dt_cfl()[0])
     tiled.close()
     one.close()
+
+
+@pytest.mark.parametrize("bc", ["periodic", "extrap"])
+def test_degenerate_tilings_equal_single_patch(ws, bc):
+    """One patch linked to itself (its ghosts come from its own interior, by
+    the domain's wrap or clamp) steps like the same patch with that physical
+    condition; a domain cut into one-cell-wide columns does too, bitwise."""
+    DX, DY = 13, 9
+    periodic = (bc == "periodic",) * 2
+    interior = domain_state(DX, DY, seed=21)
+    whole = np.zeros((3, DY + 4, DX + 4))
+    whole[:, 2:-2, 2:-2] = interior
+    O.fill_bc(whole, bc)
+    dt = 0.8 / DX / C0
+    ref = ws.Level([dict(mx=DX, my=DY, dx=1 / DX, dy=1 / DX, bc=bc)], [(RHO, KB)])
+    ref.upload(0, whole)
+    for _ in range(6):
+        ref.step(dt, read_cfl=False)
+    R = ref.download(0)
+    ref.close()
+    layouts = [([(DX, DY)], [(0, 0)]), ([(1, DY)] * DX, [(x, 0) for x in range(DX)])]
+    for shapes, origins in layouts:
+        qs = tiles_of(interior, shapes, origins, (DX, DY), periodic)
+        lev = tiled_level(ws, shapes, origins, (DX, DY), periodic, qs)
+        for _ in range(6):
+            lev.step(dt, read_cfl=False)
+        for k, ((mx, my), (x0, y0)) in enumerate(zip(shapes, origins)):
+            assert np.array_equal(lev.download(k), R[:, y0:y0 + my + 4, x0:x0 + mx + 4]), (len(shapes), k)
+        lev.close()
