@@ -179,7 +179,8 @@ int ws_fill_ghosts(ws_ctx *ctx);
 int ws_link_layout(ws_ctx *ctx, int64_t *bytes);
 /* origins: 2 per patch, global cell (x0, y0) of its interior cell (0, 0).
  * The patches must cover [0, domain_mx) x [0, domain_my) exactly, without
- * overlap, have bc WS_BC_NONE, one instance and one cell size.  periodic:
+ * overlap, have bc WS_BC_NONE, one instance and one cell size, and the level
+ * must not be the fine level of a live coupling.  periodic:
  * bit 0 for x, bit 1 for y.  buffer: caller-owned device memory of at least
  * ws_link_layout bytes, kept for the context's lifetime; the table is built on
  * the host and uploaded (synchronises the stream).  Drops a captured graph.

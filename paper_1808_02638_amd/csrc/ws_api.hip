@@ -244,6 +244,7 @@ struct ws_ctx {
   const int64_t *link_ring0 = nullptr;
   const int64_t *link_src = nullptr;
   int link_max_ring = 0;
+  int fine_in_couplings = 0;  // couplings whose fine level this is (its ghosts come from them)
   // limiter code of the kernel launchers (the medium selects its own kernel)
   int lim_code() const { return limiter | (medium ? kMediumFlag : 0); }
 
@@ -534,6 +535,9 @@ int ws_link_level(ws_ctx *c, const int32_t *origins, int32_t domain_mx, int32_t 
                   int32_t periodic, void *buffer, int64_t bytes) {
   if (!c || !origins || !buffer) return fail(WS_EINVAL, "NULL argument");
   if (domain_mx < 1 || domain_my < 1 || c->n_patches < 1) return fail(WS_EINVAL, "empty domain");
+  if (c->fine_in_couplings > 0)
+    return fail(WS_EINVAL, "the level is the fine level of a coupling (its ghosts come from the "
+                "coarse level)");
   if (periodic & ~3) return fail(WS_EINVAL, "periodic takes bits 0 (x) and 1 (y) only");
   int64_t need = 0;
   ws_link_layout(c, &need);
@@ -554,7 +558,8 @@ int ws_link_level(ws_ctx *c, const int32_t *origins, int32_t domain_mx, int32_t 
   const int64_t DX = domain_mx, DY = domain_my;
   std::vector<int32_t> own((size_t)(DX * DY), -1);
   for (int k = 0; k < c->n_patches; ++k) {
-    const int x0 = origins[2 * k], y0 = origins[2 * k + 1], mx = c->rows[k].mx, my = c->rows[k].my;
+    const int64_t x0 = origins[2 * k], y0 = origins[2 * k + 1];
+    const int mx = c->rows[k].mx, my = c->rows[k].my;
     if (x0 < 0 || y0 < 0 || x0 + mx > DX || y0 + my > DY)
       return fail(WS_EINVAL, "patch %d does not lie in the domain", k);
     for (int j = 0; j < my; ++j)
@@ -1166,6 +1171,7 @@ int ws_cf_init(ws_cf **out, ws_ctx *coarse, ws_ctx *fine, int32_t ratio,
     delete cf;
     return fail(WS_EHIP, "cannot upload the placement table");
   }
+  ++fine->fine_in_couplings;
   *out = cf;
   return WS_OK;
 }
@@ -1236,6 +1242,7 @@ int ws_cf_nest(ws_cf *outer, ws_cf *inner) {
 int ws_cf_destroy(ws_cf *cf) {
   if (!cf) return WS_OK;
   (void)hipStreamSynchronize(cf->coarse->stream);
+  --cf->fine->fine_in_couplings;
   delete cf;
   return WS_OK;
 }

@@ -201,6 +201,15 @@ def test_tiled_layouts_and_uses_are_checked(ws):
                       stream=lev.stream)
     with pytest.raises(ws.WaveStepError):  # a tiled level as the fine level of a coupling
         ws.TwoLevel(coarse, lev, 2, [(0, 4, 4), (0, 10, 4)])
+    # and the other order: a coupling's fine level cannot be linked while it lives
+    fine = ws.Level([dict(mx=8, my=8, dx=0.01, dy=0.01), dict(mx=8, my=8, dx=0.01, dy=0.01)],
+                    [(RHO, KB)], stream=coarse.stream)
+    tl = ws.TwoLevel(coarse, fine, 2, [(0, 4, 4), (0, 8, 4)])
+    with pytest.raises(ws.WaveStepError):
+        fine.link([(0, 0), (8, 0)], (16, 8))
+    tl.close()
+    fine.link([(0, 0), (8, 0)], (16, 8))  # allowed once the coupling is gone
+    fine.close()
     coarse.close()
     lev.close()
 
