@@ -123,7 +123,10 @@ def autotune(level, *, launches=40, use_cache=True, cache_path=None, verbose=Fal
     dt_saved = level.read_dt_cfl()[0]
     dt_safe = level.stable_dt(0.5)
     level.set_dt(dt_safe)
-    saved = [p.clone() for p in level.pools]
+    # saved and restored on the level's own stream, in order with its kernels
+    torch.cuda.synchronize(level.device)
+    with torch.cuda.stream(level.stream):
+        saved = [p.clone() for p in level.pools]
     torch.cuda.synchronize(level.device)
 
     def timed(choice, wg):
@@ -164,9 +167,11 @@ def autotune(level, *, launches=40, use_cache=True, cache_path=None, verbose=Fal
     best = timed(choice, wg)  # the kept choice, timed once more
     _apply(level, classes, choice, wg)
     torch.cuda.synchronize(level.device)
-    for p, s in zip(level.pools, saved):
-        p.copy_(s)
+    with torch.cuda.stream(level.stream):
+        for p, s in zip(level.pools, saved):
+            p.copy_(s)
     torch.cuda.synchronize(level.device)
+    del saved
     level.set_dt([d if np.isfinite(d) and d > 0 else s for d, s in zip(dt_saved, dt_safe)])
     if use_cache:
         cache[key] = {"classes": {json.dumps(list(c)): list(v) for c, v in choice.items()},
