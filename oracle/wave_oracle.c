@@ -242,7 +242,7 @@ void oracle_fill_bc(double *q, int mx, int my, int bc_kind) {
 /*
  * q_in, q_out : dense [3][my+4][mx+4]; q_out's interior receives Q^{n+1},
  *               its ghosts are copied from q_in (the boundary fill is a
- *               separate call made by the driver between steps).
+ *               separate call the caller makes between steps).
  * limiter     : OR_LIM_*.
  * options     : OR_OPT_* bits.  OR_OPT_DROP_ZERO_WAVE omits the speed-0
  *               wave.  OR_OPT_TRANSVERSE_CORR selects the variant whose
