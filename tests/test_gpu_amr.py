@@ -446,3 +446,52 @@ def test_three_levels_touching_match_oracle_and_conserve(ws, dtype):
     h.close()
     for lev in levs:
         lev.close()
+
+
+def test_full_size_layout_cut_into_touching_quadrants_equals_uncut(ws):
+    """The benchmark's two-level layout (1024^2 coarse, 364 ratio-4 patches
+    of 30^2 coarse cells), and the same with every patch cut into four
+    touching quadrants (1456 patches whose ghosts partly come from siblings,
+    the cuts carrying no fix): three composite steps give the same coarse
+    and fine states to rounding."""
+    import workloads
+
+    n, r = 1024, 4
+    rects = workloads.two_level_layout(n)
+    dx = 1.0 / n
+
+    def run(rect_list):
+        qc = workloads.padded_state(n, n, 0.0, 0.0, dx, dx)
+        O.fill_bc(qc, "extrap")
+        coarse = ws.Level([dict(mx=n, my=n, dx=dx, dy=dx, bc="extrap")], [(RHO, KB)])
+        fine = ws.Level([dict(mx=r * w, my=r * h, dx=dx / r, dy=dx / r) for (_, _, w, h) in rect_list],
+                        [(RHO, KB)], stream=coarse.stream)
+        coarse.upload(0, qc)
+        for k, (ci0, cj0, w, h) in enumerate(rect_list):
+            fine.upload(k, workloads.padded_state(r * w, r * h, ci0 * dx, cj0 * dx, dx / r, dx / r))
+        tl = ws.TwoLevel(coarse, fine, r, [(0, ci0, cj0) for (ci0, cj0, _, _) in rect_list])
+        for _ in range(3):
+            tl.step(0.9 * dx / C0)
+        out = coarse.download(0), [fine.download(k)[:, 2:-2, 2:-2] for k in range(len(rect_list))]
+        for lev in (tl, fine, coarse):
+            lev.close()
+        return out
+
+    quads = []
+    for (ci0, cj0, w, h) in rects:
+        a, b = w // 2, h // 2
+        quads += [(ci0, cj0, a, b), (ci0 + a, cj0, w - a, b), (ci0, cj0 + b, a, h - b),
+                  (ci0 + a, cj0 + b, w - a, h - b)]
+    qa, fa = run(rects)
+    qb, fb = run(quads)
+    scale = np.abs(qa).max()
+    print(f"uncut vs quadrants: coarse max diff {np.abs(qa - qb).max() / scale:.2e}")
+    assert np.abs(qa - qb).max() <= 1e-13 * scale
+    for k, (ci0, cj0, w, h) in enumerate(rects):
+        a, b = w // 2, h // 2
+        whole = fa[k]
+        parts = fb[4 * k:4 * k + 4]
+        assert np.abs(whole[:, :r * b, :r * a] - parts[0]).max() <= 1e-13 * scale
+        assert np.abs(whole[:, :r * b, r * a:] - parts[1]).max() <= 1e-13 * scale
+        assert np.abs(whole[:, r * b:, :r * a] - parts[2]).max() <= 1e-13 * scale
+        assert np.abs(whole[:, r * b:, r * a:] - parts[3]).max() <= 1e-13 * scale
