@@ -273,3 +273,37 @@ def test_degenerate_tilings_equal_single_patch(ws, bc):
         for k, ((mx, my), (x0, y0)) in enumerate(zip(shapes, origins)):
             assert np.array_equal(lev.download(k), R[:, y0:y0 + my + 4, x0:x0 + mx + 4]), (len(shapes), k)
         lev.close()
+
+
+def test_tiled_level_in_a_heterogeneous_medium_equals_single_patch(ws):
+    """A 2x2 tiling of a layered, perturbed medium (each tile's medium taken
+    from the domain's padded arrays, ghosts included), extrapolating sides:
+    six steps equal the domain as one patch bitwise."""
+    import workloads
+
+    DX, DY = 70, 52
+    rho, K = workloads.layered_medium(DX, DY)
+    interior = domain_state(DX, DY, seed=9)
+    whole = np.zeros((3, DY + 4, DX + 4))
+    whole[:, 2:-2, 2:-2] = interior
+    O.fill_bc(whole, "extrap")
+    one = ws.Level([dict(mx=DX, my=DY, dx=1 / DX, dy=1 / DX, bc="extrap")], [(RHO, KB)])
+    one.set_medium(0, rho, K)
+    one.upload(0, whole)
+    shapes, origins = [(30, 20), (40, 20), (30, 32), (40, 32)], [(0, 0), (30, 0), (0, 20), (30, 20)]
+    qs = tiles_of(interior, shapes, origins, (DX, DY), (False, False))
+    lev = ws.Level([dict(mx=mx, my=my, dx=1 / DX, dy=1 / DX) for (mx, my) in shapes], [(RHO, KB)])
+    lev.link(origins, (DX, DY), (False, False))
+    for k, ((mx, my), (x0, y0)) in enumerate(zip(shapes, origins)):
+        lev.set_medium(k, rho[y0:y0 + my + 4, x0:x0 + mx + 4], K[y0:y0 + my + 4, x0:x0 + mx + 4])
+        lev.upload(k, qs[k])
+    dt = 0.8 / DX / float(np.sqrt(K / rho).max())
+    for _ in range(6):
+        c1 = one.step(dt)
+        c2 = lev.step(dt)
+        assert c1 == c2
+    R = one.download(0)
+    for k, ((mx, my), (x0, y0)) in enumerate(zip(shapes, origins)):
+        assert np.array_equal(lev.download(k), R[:, y0:y0 + my + 4, x0:x0 + mx + 4]), k
+    lev.close()
+    one.close()
