@@ -254,15 +254,16 @@ def step_patches(states, dxs, dys, dts, rhos, Ks, limiter="mc"):
 
 
 def run(q0, nsteps, dx, dy, rho, K, *, limiter="mc", bc="extrap", dt=None,
-        cfl_desired=None, drop_zero_wave=False, transverse_corr=False, parallel=True):
+        cfl_desired=None, dt0=None, drop_zero_wave=False, transverse_corr=False,
+        parallel=True):
     """Advance ``nsteps`` unsplit steps.
 
     Ghosts are filled from the interior (``bc``) before the first step and
     after every step, so the returned state has valid ghosts.  With ``bc=None``
     ghosts stay as given.  The time step is either fixed (``dt``) or chosen from
-    the desired Courant number: dt0 = nu * min(dx, dy) / c and then
-    dt_{n+1} = dt_n * nu / cfl_n (Sec. 2.5 eq. (2.11)).
-    Returns dict(q, dts, cfls).
+    the desired Courant number: dt0 = nu * min(dx, dy) / c (or the given
+    ``dt0``, to continue an earlier run) and then dt_{n+1} = dt_n * nu / cfl_n
+    (Sec. 2.5 eq. (2.11)).  Returns dict(q, dts, cfls, next_dt).
     """
     q = np.array(q0, dtype=np.float64, order="C", copy=True)
     if bc is not None:
@@ -271,7 +272,7 @@ def run(q0, nsteps, dx, dy, rho, K, *, limiter="mc", bc="extrap", dt=None,
     if dt is None:
         if cfl_desired is None:
             raise ValueError("give dt or cfl_desired")
-        cur_dt = cfl_desired * min(dx, dy) / c
+        cur_dt = cfl_desired * min(dx, dy) / c if dt0 is None else float(dt0)
     else:
         cur_dt = float(dt)
     dts, cfls = [], []
@@ -285,7 +286,7 @@ def run(q0, nsteps, dx, dy, rho, K, *, limiter="mc", bc="extrap", dt=None,
         cfls.append(cfl)
         if dt is None:
             cur_dt = cur_dt * cfl_desired / cfl
-    return {"q": q, "dts": np.array(dts), "cfls": np.array(cfls)}
+    return {"q": q, "dts": np.array(dts), "cfls": np.array(cfls), "next_dt": cur_dt}
 
 
 def frozen_step(x, dx, dy, dt, rho, K, masks, bc="extrap"):

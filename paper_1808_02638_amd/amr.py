@@ -18,7 +18,7 @@ from typing import Sequence
 import torch
 
 from . import _lib as C
-from .level import Level
+from .level import Level, poisoned
 
 
 class TwoLevel:
@@ -35,7 +35,7 @@ class TwoLevel:
         self.coarse, self.fine, self.ratio = coarse, fine, int(ratio)
         nb = ctypes.c_int64(0)
         C.check(self._L.ws_cf_layout(fine._ctx, self.ratio, ctypes.byref(nb)))
-        self.workspace = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=coarse.device)
+        self.workspace = poisoned(nb.value, coarse.device)
         torch.cuda.synchronize(coarse.device)
         pl = (C.FinePlace * fine.n)()
         for k, (cp, ci0, cj0) in enumerate(places):

@@ -835,8 +835,9 @@ int ws_time_step_kernel(ws_ctx *c, int32_t n_launches, int32_t per_patch, double
     } else if (e == hipSuccess) {
       e = launch_step(c->dtype, c->lim_code(), c->vars, a, c->grid, c->stream);
     }
+    // the state moved to the other pool only if every launch of the step went in
+    if (e == hipSuccess) c->cur = 1 - c->cur;
     if (e == hipSuccess) e = hipEventRecord(ev[2 * s + 1], c->stream);
-    c->cur = 1 - c->cur;
   }
   if (e == hipSuccess) e = hipEventSynchronize(ev[2 * (size_t)n_launches - 1]);
   double total = 0.0;

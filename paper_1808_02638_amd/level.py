@@ -20,6 +20,14 @@ _BCS = {None: C.WS_BC_NONE, "none": C.WS_BC_NONE, "extrap": C.WS_BC_EXTRAP,
         "periodic": C.WS_BC_PERIODIC}
 
 
+def poisoned(nbytes: int, device) -> torch.Tensor:
+    """Raw device bytes, every byte 0xFF: as FP64 or FP32 values that is a NaN.
+    Pools and workspaces start out this way, so a kernel that read memory the
+    library had not written would turn the result non-finite every time,
+    instead of depending on what the allocator last held there."""
+    return torch.full((max(int(nbytes), 1),), 0xFF, dtype=torch.uint8, device=device)
+
+
 def _get(p, name, default=None):
     if isinstance(p, dict):
         return p.get(name, default)
@@ -77,9 +85,8 @@ class Level:
                                   ctypes.byref(ws_b)))
         self.device = torch.device(device)
         self.pool_bytes = pool_b.value
-        self.pools = [torch.empty(pool_b.value, dtype=torch.uint8, device=self.device)
-                      for _ in range(2)]
-        self.workspace = torch.empty(ws_b.value, dtype=torch.uint8, device=self.device)
+        self.pools = [poisoned(pool_b.value, self.device) for _ in range(2)]
+        self.workspace = poisoned(ws_b.value, self.device)
         # A stream of our own (default priority): graph capture cannot use the
         # legacy null stream.  Allocation above ran on torch's stream.
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
@@ -104,7 +111,7 @@ class Level:
         if rho.shape != (my + 4, mx + 4) or K.shape != rho.shape:
             raise ValueError(f"patch {k}: rho and K must have shape {(my + 4, mx + 4)}")
         if getattr(self, "medium", None) is None:
-            self.medium = torch.empty(self.pool_bytes, dtype=torch.uint8, device=self.device)
+            self.medium = poisoned(self.pool_bytes, self.device)
             torch.cuda.synchronize(self.device)
             C.check(self._L.ws_attach_medium(self._ctx, ctypes.c_void_p(self.medium.data_ptr()),
                                              self.pool_bytes))
@@ -124,7 +131,7 @@ class Level:
         org = np.ascontiguousarray(np.asarray(origins, dtype=np.int32).reshape(self.n, 2))
         nbytes = ctypes.c_int64(0)
         C.check(self._L.ws_link_layout(self._ctx, ctypes.byref(nbytes)))
-        self.links = torch.empty(max(nbytes.value, 1), dtype=torch.uint8, device=self.device)
+        self.links = poisoned(nbytes.value, self.device)
         torch.cuda.synchronize(self.device)
         bits = (1 if periodic[0] else 0) | (2 if periodic[1] else 0)
         C.check(self._L.ws_link_level(self._ctx, org.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
@@ -250,7 +257,7 @@ class Level:
 
     def new_masks(self) -> torch.Tensor:
         """A device buffer for the branches of one step."""
-        return torch.empty(self.mask_bytes(), dtype=torch.uint8, device=self.device)
+        return poisoned(self.mask_bytes(), self.device)
 
     def new_buffer(self) -> torch.Tensor:
         """A zeroed FP64 device buffer in the pools' layout (for cotangents)."""

@@ -326,6 +326,92 @@ def test_three_levels_conserve(ws):
         lev.close()
 
 
+def test_tuned_composite_steps_from_poisoned_memory_match_oracle(ws):
+    """Pools and workspaces start as NaN bytes (the binding allocates them
+    so), every level is autotuned (many timed steps, the state saved and
+    restored) and the composite steps run after that: two levels (r = 4) and
+    three levels (r = 2) match the oracle at 1e-12 and stay finite, so no
+    kernel of the composite step reads memory the library has not written."""
+    from paper_1808_02638_amd.autotune import autotune
+
+    probe = ws.Level([dict(mx=20, my=10, dx=0.05, dy=0.1)], [(RHO, KB)])
+    for b in (*probe.pools, probe.workspace):
+        assert bool((b == 0xFF).all()), "allocations are not poisoned"
+    probe.close()
+
+    n, steps, r = 48, 8, 4
+    dt = 0.8 / n / C0
+    qc, fines, coarse, fine, tl = build(ws, n, RECTS, r, "extrap")
+    for lev in (coarse, fine):
+        autotune(lev, launches=4, use_cache=False)
+    q, fs = qc, fines
+    for _ in range(steps):
+        q, fs = oamr.two_level_step(q, fs, 1 / n, 1 / n, dt, RHO, KB, r, bc="extrap")
+        tl.step(dt)
+    got = coarse.download(0)
+    assert np.isfinite(got).all()
+    err = rel_linf(got, q)
+    print(f"tuned two-level from poisoned memory: coarse rel Linf {err}")
+    assert err.max() <= FP64_TOL, err
+    for k, f in enumerate(fs):
+        gf = fine.download(k)
+        assert np.isfinite(gf).all(), k
+        assert rel_linf(gf[:, 2:-2, 2:-2], f.q[:, 2:-2, 2:-2]).max() <= FP64_TOL, k
+    tl.close()
+    fine.close()
+    coarse.close()
+
+    n, r = 32, 2
+    qc, levels, levs, h = build3(ws, n, r, "extrap")
+    for lev in levs:
+        autotune(lev, launches=4, use_cache=False)
+    dt = 0.8 / n / C0
+    q, lv = qc, levels
+    for _ in range(4):
+        q, lv = oamr.multi_level_step(q, lv, 1 / n, 1 / n, dt, RHO, KB, r, bc="extrap")
+        h.step(dt)
+    err = rel_linf(levs[0].download(0), q)
+    print(f"tuned three levels from poisoned memory: level-0 rel Linf {err}")
+    assert err.max() <= FP64_TOL, err
+    for l in (1, 2):
+        for k, P in enumerate(lv[l - 1]):
+            g = levs[l].download(k)
+            assert np.isfinite(g).all(), (l, k)
+            assert rel_linf(g[:, 2:-2, 2:-2], P.q[:, 2:-2, 2:-2]).max() <= FP64_TOL, (l, k)
+    h.close()
+    for lev in levs:
+        lev.close()
+
+
+def test_tuned_full_size_two_level_stays_finite(ws):
+    """The benchmark's two-level leg as the benchmark runs it (1024^2 coarse,
+    364 ratio-4 fine patches, both levels autotuned, then composite steps),
+    from poisoned memory: every cell of both levels stays finite, and the
+    coarse cells far from all patches equal those of the plain coarse step."""
+    from paper_1808_02638_amd.autotune import autotune
+
+    n, r, rects, qc, fq, coarse, fine, tl = _full_layout(ws, "extrap")
+    for lev in (coarse, fine):
+        autotune(lev, launches=6, use_cache=False)
+    dt = 0.9 / n / C0
+    plain = ws.Level([dict(mx=n, my=n, dx=1 / n, dy=1 / n, bc="extrap")], [(RHO, KB)])
+    plain.upload(0, qc)
+    for _ in range(3):
+        tl.step(dt)
+        plain.step(dt, read_cfl=False)
+    got = coarse.download(0)
+    assert np.isfinite(got).all()
+    for k in range(len(rects)):
+        assert np.isfinite(fine.download(k)).all(), k
+    far = np.ones((n, n), bool)
+    for (ci0, cj0, w, h) in rects:
+        far[max(cj0 - 9, 0):cj0 + h + 9, max(ci0 - 9, 0):ci0 + w + 9] = False
+    ref = plain.download(0)
+    assert np.array_equal(got[:, 2:-2, 2:-2][:, far], ref[:, 2:-2, 2:-2][:, far])
+    for lev in (tl, fine, coarse, plain):
+        lev.close()
+
+
 def test_nesting_is_checked(ws):
     n, r = 32, 2
     _, _, levs, h = build3(ws, n, r, "extrap")

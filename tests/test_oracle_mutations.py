@@ -73,6 +73,10 @@ MUTATIONS = {
     "tcorr_y_dropped": ("bp_[m] -= 2.0 * G[f][m];\n          bm_[m] += 2.0 * G[f][m];", "(void)0;"),
     "tcorr_ignored": ("const int tcorr = (options & OR_OPT_TRANSVERSE_CORR) != 0;",
                       "const int tcorr = 0;"),
+    # the batched wrapper that steps every patch of a level
+    "step_patches_dx_dy_swapped": ("mx[k], my[k], dx[k],\n                           dy[k], dt[k]",
+                                   "mx[k], my[k], dy[k],\n                           dx[k], dt[k]"),
+    "step_patches_first_medium": ("dt[k], rho[k], K[k], limiter", "dt[k], rho[0], K[0], limiter"),
     "tcorr_ghost_rows_skipped": ("if (interior || tcorr)\n      for (int e = 0; e <= mx; ++e) {",
                                  "if (interior)\n      for (int e = 0; e <= mx; ++e) {"),
 }
@@ -81,6 +85,7 @@ MUTATIONS = {
 PIN_CALLS = [
     ("ghosts", lambda o: pins.test_extrapolation_ghosts_take_nearest_interior(o)),
     ("cfl", lambda o: pins.test_cfl_closed_form(o)),
+    ("step_patches", lambda o: pins.test_step_patches_equals_each_patch_stepped_alone(o, "mc")),
     ("riemann_x", lambda o: pins.test_riemann_solver_eigen_structure(o, 0.7, 2.3, 0)),
     ("riemann_y", lambda o: pins.test_riemann_solver_eigen_structure(o, 0.7, 2.3, 1)),
     ("split_x", lambda o: pins.test_transverse_split_matches_matrix_split(o, 0)),

@@ -282,6 +282,37 @@ def test_cfl_closed_form(oracle_lib):
         assert abs(cfl - expect) <= 2 * np.spacing(expect)
 
 
+@pytest.mark.parametrize("limiter", ["mc", "vanleer"])
+def test_step_patches_equals_each_patch_stepped_alone(oracle_lib, limiter):
+    """The batched wrapper (the reference of a whole AMR level, one step of
+    eq. (2.3) per patch with that patch's own cell sizes, time step and
+    medium) equals the single-patch step of every patch, bitwise, and returns
+    each patch's Courant number, c dt / min(dx, dy) (eq. (2.10))."""
+    rng = np.random.default_rng(2361)
+    # differing shapes, dx != dy, time steps and media; one patch a single cell
+    specs = [(13, 7, 1 / 40, 1 / 25, 0.7, 2.3), (24, 31, 1 / 64, 1 / 48, 1.9, 8.1),
+             (5, 40, 1 / 16, 1 / 90, 1.0, 4.0), (32, 32, 1 / 32, 1 / 32, 0.55, 1.4),
+             (1, 1, 1 / 8, 1 / 11, 1.3, 3.3)]
+    states, dxs, dys, dts, rhos, Ks = [], [], [], [], [], []
+    for mx, my, dx, dy, rho, K in specs:
+        q = np.ascontiguousarray(rng.normal(size=(3, my + 4, mx + 4)))
+        q[0] += 2.0
+        states.append(q)
+        c = math.sqrt(K / rho)
+        dxs.append(dx), dys.append(dy), rhos.append(rho), Ks.append(K)
+        dts.append(rng.uniform(0.3, 0.95) * min(dx, dy) / c)
+    outs, cfls = oracle_lib.step_patches(states, dxs, dys, dts, rhos, Ks, limiter)
+    assert len(outs) == len(specs) and cfls.shape == (len(specs),)
+    for k, q in enumerate(states):
+        ref, cfl, _ = oracle_lib.step(q, dxs[k], dys[k], dts[k], rhos[k], Ks[k], limiter)
+        assert np.array_equal(outs[k][:, 2:-2, 2:-2], ref[:, 2:-2, 2:-2]), k
+        assert cfls[k] == cfl, (k, cfls[k], cfl)
+        expect = math.sqrt(Ks[k] / rhos[k]) * dts[k] / min(dxs[k], dys[k])
+        assert abs(cfls[k] - expect) <= 2 * np.spacing(expect), k
+        # the wrapper steps every patch once: not a patch stepped twice or left
+        assert not np.array_equal(outs[k][:, 2:-2, 2:-2], q[:, 2:-2, 2:-2]), k
+
+
 def test_zero_speed_wave_changes_nothing(oracle_lib):
     """Two-wave and three-wave solvers give equal updates (the speed-0 wave has
     no fluctuation, no correction weight and no speed)."""
