@@ -86,7 +86,12 @@ typedef struct {
 } ws_material;
 
 /* Sizes the caller must allocate: each of the two q pools (bytes) and the
- * workspace (bytes).  Either output pointer may be NULL. */
+ * workspace (bytes).  Either output pointer may be NULL.  The pools hold every
+ * patch of the level with its two ghost layers (Sec. 2.2: ghost cells carry the
+ * boundary data a patch's step reads), each patch in three planes p, u, v; the
+ * level's patches live together in device memory between steps (the paper
+ * copies them to the GPU and back around every advance, Sec. 3.2.2; here they
+ * stay resident).  Fails with WS_EINVAL for an invalid patch list. */
 int ws_layout(const ws_patch_desc *patches, int32_t n_patches, int32_t n_instances,
               int32_t dtype, int64_t *pool_bytes, int64_t *ws_bytes);
 
@@ -146,12 +151,15 @@ int ws_attach_medium(ws_ctx *ctx, void *medium, int64_t bytes);
  * medium of ghost cells next to the patch), finite and > 0.  Synchronises. */
 int ws_upload_medium(ws_ctx *ctx, int32_t patch, const double *rho, const double *K);
 
-/* Copy one patch, host layout, into BOTH pools (ghosts included).  src may be
- * a host or a device pointer.  Synchronises the stream. */
+/* Copy one patch, host layout, into BOTH pools (ghosts included: for
+ * WS_BC_NONE patches the ghosts are the frozen boundary data of Sec. 2.2).
+ * src may be a host or a device pointer; it is read, not kept.  WS_EINVAL for
+ * a patch index out of range.  Synchronises the stream. */
 int ws_upload_patch(ws_ctx *ctx, int32_t patch, const void *src);
 
-/* Copy one patch of the current state, host layout, to dst (host or device).
- * Synchronises the stream. */
+/* Copy one patch of the current state, host layout (ghosts included), to dst
+ * (host or device, caller-owned, (mx+4)(my+4) values per component).  WS_EINVAL
+ * for a patch index out of range.  Synchronises the stream. */
 int ws_download_patch(ws_ctx *ctx, int32_t patch, void *dst);
 
 /* Rewrite the physical-boundary ghosts of the current state from its interior

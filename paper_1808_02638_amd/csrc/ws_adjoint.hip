@@ -4,10 +4,10 @@
 // With the MC branches of a step held at the ones the forward step took, the
 // update of Sec. 2.1 eq. (2.3) is linear in the ghost-padded state, and the
 // step S = U o E (E: ghost fill, U: update) has the transpose S^T = E^T U^T.
-// The first kernel evaluates U^T in GATHER form: the cotangent of a padded
-// cell is assembled from the output cotangents lam' of the cells whose update
-// reads it (the transposed 13-point footprint), walking the closed forms of
-// the forward kernels backwards:
+// U^T is evaluated in GATHER form: the cotangent of a padded cell is
+// assembled from the output cotangents lam' of the cells whose update reads
+// it (the transposed 13-point footprint), walking the closed forms of the
+// forward kernels backwards:
 //   lam_F(e)   = dtdx (lam'(e) - lam'(e-1))               (p, u) at x-edge e
 //   lam_G(f)   = dtdy (lam'(f) - lam'(f-1))               (p, v) at y-edge f
 //   lam_xs(i,j) = -dtdx c/2 lam'_p + gx (lam_Gp(j) - lam_Gp(j+1))
@@ -22,10 +22,17 @@
 // 3: 0,2) and every lam' outside the interior taken as 0; the y-direction is
 // the mirror image.  E^T adds the cotangents of the extrapolation ghosts to the
 // interior cells they copy (clamped indices, corners included).
+//
+// One launch does both, marching like the forward MARCH tiles: a wavefront
+// holds 64 neighbouring columns (60 updated, two halo lanes per side), walks
+// up a range of rows with the y-direction terms carried in registers and the
+// x-direction terms exchanged between neighbouring lanes, and folds the ghost
+// columns (lanes next to the boundary, by lane shifts) and ghost rows (carried
+// down to the first row, held up from the last) into the boundary cells
+// before storing.  Per padded cell it reads lam' and one branch byte once and
+// writes the cotangent once.
 
 #include <hip/hip_runtime.h>
-
-#include <climits>
 
 #include "ws_device.h"
 #include "ws_internal.h"
@@ -42,190 +49,235 @@ __device__ inline double w_up(unsigned code) {
   return code == 1u ? 0.5 : (code == 3u ? 2.0 : 0.0);
 }
 
-// One patch's view for the adjoint: lam' with zero extension outside the
-// interior, and the recorded branches with code 0 outside their range.  Reads
-// are clamped to the interior (and the mask array) before the zero selection,
-// so no address outside the patch is formed.
-struct AdjPatch {
-  const double *lam;  // interior (0, 0) of component p
-  int64_t ld, plane;
-  int mx, my;
-  const uint8_t *mk;  // (mx+1) x (my+1) bytes
-  Coef<double> k;
+// One row of lam' (p, u, v) and the branch byte at one column.
+struct AdjSet {
+  double p, u, v;
+  unsigned m;
+};
 
-  __device__ double L(int m, int i, int j) const {
-    const int ic = min(max(i, 0), mx - 1), jc = min(max(j, 0), my - 1);
-    const double v = lam[m * plane + (int64_t)jc * ld + ic];
-    return (i == ic && j == jc) ? v : 0.0;
-  }
-  __device__ unsigned byte(int i, int j) const {
-    const int ic = min(max(i, 0), mx), jc = min(max(j, 0), my);
-    const unsigned v = mk[(int64_t)jc * (mx + 1) + ic];
-    return (i == ic && j == jc) ? v : 0u;
-  }
+// Row sets of an adjoint segment (its row loop is unrolled by this count).
+constexpr int kAdjSets = 8;
+// Rows per segment (one wavefront each).
+constexpr int kAdjRows = 16;
 
-  // U^T: cotangent of padded cell (i, j), any i in [-2, mx+2), j in [-2, my+2).
-  // Offsets below are relative to (i, j); x-edge e lies between cells e-1 and
-  // e, y-edge f between rows f-1 and f.
-  __device__ void pad(int i, int j, double &p, double &u, double &v) const {
-    // ---- lam' on the transposed 13-point footprint
-    double P[5][5], U[5][5], V[5][5];  // [dy+2][dx+2], only the footprint is read
-#pragma unroll
-    for (int dy = -2; dy <= 2; ++dy)
-#pragma unroll
-      for (int dx = -2; dx <= 2; ++dx) {
-        const int ad = (dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy);
-        if (ad > 2) continue;
-        P[dy + 2][dx + 2] = L(0, i + dx, j + dy);
-        // u enters through x-edges only (rows -1..1), v through y-edges only
-        U[dy + 2][dx + 2] = (dy >= -1 && dy <= 1) ? L(1, i + dx, j + dy) : 0.0;
-        V[dy + 2][dx + 2] = (dx >= -1 && dx <= 1) ? L(2, i + dx, j + dy) : 0.0;
-      }
-#define LP(dx, dy) P[(dy) + 2][(dx) + 2]
-#define LU(dx, dy) U[(dy) + 2][(dx) + 2]
-#define LV(dx, dy) V[(dy) + 2][(dx) + 2]
-    // cotangents of F~ (p, u) at x-edge e of row r, of G~ (p, v) at y-edge f of column c
-#define FP(e, r) (k.dtdx * (LP(e, r) - LP((e) - 1, r)))
-#define FU(e, r) (k.dtdx * (LU(e, r) - LU((e) - 1, r)))
-#define GP(c, f) (k.dtdy * (LP(c, f) - LP(c, (f) - 1)))
-#define GV(c, f) (k.dtdy * (LV(c, f) - LV(c, (f) - 1)))
-    // cotangents of the cells' fluctuation sums and differences
-    double xs[3], xd[3], ys[3], yd[3];  // [offset + 1]
-#pragma unroll
-    for (int o = -1; o <= 1; ++o) {
-      xs[o + 1] = -k.dtdx * k.h * LP(o, 0) + k.gx * (GP(o, 0) - GP(o, 1)) -
-                  k.gxz * (GV(o, 0) + GV(o, 1));
-      xd[o + 1] = -k.dtdx * k.hz * LU(o, 0);
-      ys[o + 1] = -k.dtdy * k.h * LP(0, o) + k.gy * (FP(0, o) - FP(1, o)) -
-                  k.gyz * (FU(0, o) + FU(1, o));
-      yd[o + 1] = -k.dtdy * k.hz * LV(0, o);
-    }
-    // cotangents of the limited strengths times the frozen weights, at x-edges
-    // -1..2 of row 0 and y-edges -1..2 of column 0
-    double o1[4], u1[4], o2[4], u2[4], n1[4], t1[4], n2[4], t2[4];  // [edge + 1]
-#pragma unroll
-    for (int e = -1; e <= 2; ++e) {
-      const double fp = FP(e, 0), fu = FU(e, 0);
-      const double l1 = -k.fx * fp + k.fxz * fu, l2 = k.fx * fp + k.fxz * fu;
-      const unsigned bx = byte(i + e, j);
-      o1[e + 1] = w_own(bx & 3u) * l1;
-      u1[e + 1] = w_up(bx & 3u) * l1;
-      o2[e + 1] = w_own((bx >> 2) & 3u) * l2;
-      u2[e + 1] = w_up((bx >> 2) & 3u) * l2;
-      const double gp = GP(0, e), gv = GV(0, e);
-      const double m1 = -k.fy * gp + k.fyz * gv, m2 = k.fy * gp + k.fyz * gv;
-      const unsigned by = byte(i, j + e);
-      n1[e + 1] = w_own((by >> 4) & 3u) * m1;
-      t1[e + 1] = w_up((by >> 4) & 3u) * m1;
-      n2[e + 1] = w_own((by >> 6) & 3u) * m2;
-      t2[e + 1] = w_up((by >> 6) & 3u) * m2;
-    }
-#undef FP
-#undef FU
-#undef GP
-#undef GV
-    // strengths at the cell's edges: wave -c takes its upwind neighbour on the
-    // right (above), wave +c on the left (below)
-    const double a1L = o1[1] + u1[0] + xs[0] - xd[0], a2L = o2[1] + u2[2] + xs[1] + xd[1];
-    const double a1R = o1[2] + u1[1] + xs[1] - xd[1], a2R = o2[2] + u2[3] + xs[2] + xd[2];
-    const double b1B = n1[1] + t1[0] + ys[0] - yd[0], b2B = n2[1] + t2[2] + ys[1] + yd[1];
-    const double b1T = n1[2] + t1[1] + ys[1] - yd[1], b2T = n2[2] + t2[3] + ys[2] + yd[2];
-    p = LP(0, 0) + ((a2L - a1L) - (a2R - a1R)) + ((b2B - b1B) - (b2T - b1T));
-    u = LU(0, 0) + k.Z * ((a1L + a2L) - (a1R + a2R));
-    v = LV(0, 0) + k.Z * ((b1B + b2B) - (b1T + b2T));
-#undef LP
-#undef LU
-#undef LV
+// One wavefront of the adjoint: lane l holds column c = c0 - 2 + l of one
+// patch.  lam' is read through 32-bit byte offsets from the patch's padded
+// origin, at clamped (interior) cells, and taken as 0 outside the interior;
+// branch bytes likewise (code 0 outside [0, mx] x [0, my]).
+struct AdjLanes {
+  const char *lb;     // lam_in at padded cell (-2, -2) of component p
+  char *ob;           // lam_out, the same place
+  const uint8_t *mk;  // the patch's branch bytes
+  unsigned ld, plb;   // row stride (elements), plane stride (bytes)
+  int mld, mx, my, c, cl, cm;
+  bool colin, colm;
+
+  __device__ void fetch(AdjSet &S, int r) const {
+    const int rr = min(max(r, 0), my - 1);
+    const unsigned o = ((unsigned)(rr + 2) * ld + (unsigned)(cl + 2)) * 8u;
+    S.p = *reinterpret_cast<const double *>(lb + o);
+    S.u = *reinterpret_cast<const double *>(lb + plb + o);
+    S.v = *reinterpret_cast<const double *>(lb + 2 * plb + o);
+    const int rm = min(max(r, 0), my);
+    S.m = mk[(int64_t)rm * mld + cm];
+  }
+  __device__ bool in(int r) const { return colin && r >= 0 && r < my; }
+  __device__ unsigned code(const AdjSet &S, int r) const {
+    return (colm && r >= 0 && r <= my) ? S.m : 0u;
+  }
+  __device__ void put(int r, double p, double u, double v) const {
+    const unsigned o = ((unsigned)(r + 2) * ld + (unsigned)(c + 2)) * 8u;
+    *reinterpret_cast<double *>(ob + o) = p;
+    *reinterpret_cast<double *>(ob + plb + o) = u;
+    *reinterpret_cast<double *>(ob + 2 * plb + o) = v;
   }
 };
 
-__device__ inline AdjPatch make_adj(const PatchRow &pr, const InstRow &in, double dt,
-                                    const uint8_t *masks, const double *lam_in) {
-  AdjPatch A;
-  A.lam = lam_in + pr.q_off + 2 * (int64_t)pr.ld + pr.col0;
-  A.ld = pr.ld;
-  A.plane = pr.plane;
-  A.mx = pr.mx;
-  A.my = pr.my;
-  A.mk = masks + pr.mask_off;
-  A.k = make_coef<double>(in.c, in.Z, dt, pr.dx, pr.dy);
-  return A;
+// Quantities of one y-edge f of the lane's column from lam' of rows f-1, f:
+// lam_G and the frozen-branch terms of its two waves (own and upwind parts).
+struct YEdge {
+  double gp, gv, n1, t1, n2, t2;
+};
+__device__ inline YEdge y_edge(const Coef<double> &k, double p_lo, double v_lo, double p_hi,
+                               double v_hi, unsigned code) {
+  YEdge e;
+  e.gp = k.dtdy * (p_hi - p_lo);
+  e.gv = k.dtdy * (v_hi - v_lo);
+  const double m1 = -k.fy * e.gp + k.fyz * e.gv, m2 = k.fy * e.gp + k.fyz * e.gv;
+  const unsigned c1 = (code >> 4) & 3u, c2 = (code >> 6) & 3u;
+  e.n1 = w_own(c1) * m1;
+  e.t1 = w_up(c1) * m1;
+  e.n2 = w_own(c2) * m2;
+  e.t2 = w_up(c2) * m2;
+  return e;
 }
 
-// U^T: one thread per padded cell of each patch (blockIdx.y); every padded
-// cell of lam_out is written.
-__global__ __launch_bounds__(kThreads) void adjoint_update_kernel(
-    const PatchRow *patches, const InstRow *inst, double dt, const uint8_t *masks,
-    const double *lam_in, double *lam_out) {
-  const PatchRow pr = uniform_row(patches[blockIdx.y]);
-  const AdjPatch A = make_adj(pr, uniform_row(inst[pr.inst]), dt, masks, lam_in);
-  double *out = lam_out + pr.q_off + 2 * (int64_t)pr.ld + pr.col0;
-  const int wx = pr.mx + 4;
-  const int64_t n = (int64_t)wx * (pr.my + 4);
-  for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < n;
-       idx += (int64_t)gridDim.x * kThreads) {
-    const int i = (int)(idx % wx) - 2, j = (int)(idx / wx) - 2;
-    double p, u, v;
-    A.pad(i, j, p, u, v);
-    const int64_t o = (int64_t)j * pr.ld + i;
-    out[o] = p;
-    out[pr.plane + o] = u;
-    out[2 * pr.plane + o] = v;
+// lam_F (p, u) at x-edge c of a row and the cell's lam_ys, lam_yd.
+struct XRow {
+  double fp, fu, ys, yd;
+};
+__device__ inline XRow x_row(const Coef<double> &k, double p, double u, double v) {
+  XRow x;
+  x.fp = k.dtdx * (p - shr(p));
+  x.fu = k.dtdx * (u - shr(u));
+  x.ys = -k.dtdy * k.h * p + k.gy * (x.fp - shl(x.fp)) - k.gyz * (x.fu + shl(x.fu));
+  x.yd = -k.dtdy * k.hz * v;
+  return x;
+}
+
+// The segment's rows [r0, r1) (ghost rows included where the segment meets
+// the patch's first or last row), marched upward; fold: extrapolation ghosts
+// are folded into the boundary cells.
+__device__ __attribute__((always_inline)) inline void adjoint_march(const AdjLanes &M,
+                                                                   const Coef<double> &k,
+                                                                   int l, int r0, int r1,
+                                                                   bool fold, bool xedge) {
+  AdjSet R0, R1, R2, R3, R4, R5, R6, R7, Sa, Sb;
+  M.fetch(Sa, r0 - 2);
+  M.fetch(Sb, r0 - 1);
+  M.fetch(R0, r0);
+  M.fetch(R1, r0 + 1);
+  M.fetch(R2, r0 + 2);
+  M.fetch(R3, r0 + 3);
+  M.fetch(R4, r0 + 4);
+  M.fetch(R5, r0 + 5);
+  M.fetch(R6, r0 + 6);
+  M.fetch(R7, r0 + 7);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  auto P = [&](const AdjSet &S, int r) { return M.in(r) ? S.p : 0.0; };
+  auto U = [&](const AdjSet &S, int r) { return M.in(r) ? S.u : 0.0; };
+  auto V = [&](const AdjSet &S, int r) { return M.in(r) ? S.v : 0.0; };
+  // edge r0-1 (its t1), row r0-1 (its ys, yd), edges r0 and r0+1, row r0
+  const YEdge em = y_edge(k, P(Sa, r0 - 2), V(Sa, r0 - 2), P(Sb, r0 - 1), V(Sb, r0 - 1),
+                          M.code(Sb, r0 - 1));
+  const XRow xm = x_row(k, P(Sb, r0 - 1), U(Sb, r0 - 1), V(Sb, r0 - 1));
+  const YEdge e0 = y_edge(k, P(Sb, r0 - 1), V(Sb, r0 - 1), P(R0, r0), V(R0, r0), M.code(R0, r0));
+  XRow x0 = x_row(k, P(R0, r0), U(R0, r0), V(R0, r0));
+  YEdge e1 = y_edge(k, P(R0, r0), V(R0, r0), P(R1, r0 + 1), V(R1, r0 + 1), M.code(R1, r0 + 1));
+  double gp0 = e0.gp, gv0 = e0.gv, t1_0 = e0.t1;
+  // lam_b1, lam_b2 at edge r0 (DY = b2 - b1, SY = b1 + b2)
+  double DY0, SY0;
+  {
+    const double b1 = e0.n1 + em.t1 + xm.ys - xm.yd, b2 = e0.n2 + e1.t2 + x0.ys + x0.yd;
+    DY0 = b2 - b1;
+    SY0 = b1 + b2;
   }
-}
+  // ghost rows folded into the first row, and the last row held for its ghosts
+  double lo_p = 0.0, lo_u = 0.0, lo_v = 0.0, hi_p = 0.0, hi_u = 0.0, hi_v = 0.0;
+  const bool st_val = l >= 2 && l <= 61 && M.c >= 0 && M.c < M.mx;
+  const bool st_zero = (M.c == -2 || M.c == -1) || ((M.c == M.mx || M.c == M.mx + 1) && l >= 2);
 
-// E^T: the ghost cotangents of extrapolation patches are added to the
-// interior cell they were copied from (each ghost has one: clamp its
-// indices), and every ghost is set to 0.  One thread per (interior cell next
-// to a side, component), so each ghost value is read and cleared by exactly
-// one thread; all reads come before the writes.
-__global__ __launch_bounds__(kThreads) void adjoint_fold_kernel(const PatchRow *patches,
-                                                              double *lam) {
-  const PatchRow pr = uniform_row(patches[blockIdx.y]);
-  const bool fold = pr.bc == WS_BC_EXTRAP;
-  // the boundary ring of the interior: rows 0 and my-1, then columns 0 and
-  // mx-1 of the rows between
-  const int top = pr.my > 1 ? pr.mx : 0;
-  const int mid = max(pr.my - 2, 0) * (pr.mx > 1 ? 2 : 1);
-  const int ring = pr.mx + top + mid;
-  for (int idx = blockIdx.x * kThreads + threadIdx.x; idx < 3 * ring;
-       idx += gridDim.x * kThreads) {
-    const int m = idx / ring, c = idx % ring;
-    int i, j;
-    if (c < pr.mx) {
-      i = c, j = 0;
-    } else if (c < pr.mx + top) {
-      i = c - pr.mx, j = pr.my - 1;
+  auto row = [&](AdjSet &A, const AdjSet &B, const AdjSet &C, int r, bool refill) {
+    __builtin_amdgcn_sched_barrier(0);
+    const double p0 = P(A, r), u0 = U(A, r), v0 = V(A, r);
+    const unsigned m0 = M.code(A, r);
+    const double p1 = P(B, r + 1), u1 = U(B, r + 1), v1 = V(B, r + 1);
+    // edge r+2 and row r+1
+    const YEdge e2 = y_edge(k, p1, v1, P(C, r + 2), V(C, r + 2), M.code(C, r + 2));
+    const XRow x1 = x_row(k, p1, u1, v1);
+    // the y-terms of edge r+1
+    const double b1 = e1.n1 + t1_0 + x0.ys - x0.yd, b2 = e1.n2 + e2.t2 + x1.ys + x1.yd;
+    const double DY1 = b2 - b1, SY1 = b1 + b2;
+    // the x-terms of row r
+    const double l1 = -k.fx * x0.fp + k.fxz * x0.fu, l2 = k.fx * x0.fp + k.fxz * x0.fu;
+    const unsigned c1 = m0 & 3u, c2 = (m0 >> 2) & 3u;
+    const double o1 = w_own(c1) * l1, u1w = w_up(c1) * l1;
+    const double o2 = w_own(c2) * l2, u2w = w_up(c2) * l2;
+    const double xs = -k.dtdx * k.h * p0 + k.gx * (gp0 - e1.gp) - k.gxz * (gv0 + e1.gv);
+    const double xd = -k.dtdx * k.hz * u0;
+    const double a1 = ((o1 + shr(u1w)) + shr(xs)) - shr(xd);
+    const double a2 = ((o2 + shl(u2w)) + xs) + xd;
+    const double DX = a2 - a1, SX = a1 + a2;
+    double op = p0 + (DX - shl(DX)) + (DY0 - DY1);
+    double ou = u0 + k.Z * (SX - shl(SX));
+    double ov = v0 + k.Z * (SY0 - SY1);
+    if (fold && xedge) {
+      // ghost columns into the boundary columns of the row
+      const double lp1 = shr(op), lu1 = shr(ou), lv1 = shr(ov);
+      const double lp2 = shr(lp1), lu2 = shr(lu1), lv2 = shr(lv1);
+      const double rp1 = shl(op), ru1 = shl(ou), rv1 = shl(ov);
+      const double rp2 = shl(rp1), ru2 = shl(ru1), rv2 = shl(rv1);
+      if (M.c == 0) { op += lp1 + lp2; ou += lu1 + lu2; ov += lv1 + lv2; }
+      if (M.c == M.mx - 1) { op += rp1 + rp2; ou += ru1 + ru2; ov += rv1 + rv2; }
+    }
+    if (r < 0) {
+      lo_p += op, lo_u += ou, lo_v += ov;
+      if (st_val || st_zero) M.put(r, 0.0, 0.0, 0.0);
+    } else if (r < M.my) {
+      if (fold && r == 0) op += lo_p, ou += lo_u, ov += lo_v;
+      if (st_zero) M.put(r, 0.0, 0.0, 0.0);
+      if (fold && r == M.my - 1) {
+        hi_p = op, hi_u = ou, hi_v = ov;
+      } else if (st_val) {
+        M.put(r, op, ou, ov);
+      }
     } else {
-      const int r = c - pr.mx - top, per = pr.mx > 1 ? 2 : 1;
-      j = 1 + r / per;
-      i = (r % per) ? pr.mx - 1 : 0;
+      hi_p += op, hi_u += ou, hi_v += ov;
+      if (st_val || st_zero) M.put(r, 0.0, 0.0, 0.0);
+      if (fold && r == M.my + 1 && st_val) M.put(M.my - 1, hi_p, hi_u, hi_v);
     }
-    double *q = lam + pr.q_off + 2 * (int64_t)pr.ld + pr.col0 + m * pr.plane;
-    // ghost images of (i, j): up to two ghost columns on each side of its
-    // row and two ghost rows on each side of its column, and their crossings
-    constexpr int kNone = INT_MIN;
-    const int xs[5] = {i, i == 0 ? -1 : kNone, i == 0 ? -2 : kNone, i == pr.mx - 1 ? pr.mx : kNone,
-                       i == pr.mx - 1 ? pr.mx + 1 : kNone};
-    const int ys[5] = {j, j == 0 ? -1 : kNone, j == 0 ? -2 : kNone, j == pr.my - 1 ? pr.my : kNone,
-                       j == pr.my - 1 ? pr.my + 1 : kNone};
-    double s = q[(int64_t)j * pr.ld + i];
-    if (fold) {
-#pragma unroll
-      for (int b = 0; b < 5; ++b)
-#pragma unroll
-        for (int a = 0; a < 5; ++a)
-          if ((a | b) != 0 && xs[a] != kNone && ys[b] != kNone)
-            s += q[(int64_t)ys[b] * pr.ld + xs[a]];
-    }
-#pragma unroll
-    for (int b = 0; b < 5; ++b)
-#pragma unroll
-      for (int a = 0; a < 5; ++a)
-        if ((a | b) != 0 && xs[a] != kNone && ys[b] != kNone)
-          q[(int64_t)ys[b] * pr.ld + xs[a]] = 0.0;
-    q[(int64_t)j * pr.ld + i] = s;
+    // slide up one row
+    gp0 = e1.gp, gv0 = e1.gv, t1_0 = e1.t1;
+    e1 = e2;
+    x0 = x1;
+    DY0 = DY1, SY0 = SY1;
+    __builtin_amdgcn_sched_barrier(0);
+    if (refill) M.fetch(A, r + kAdjSets);
+  };
+  int r = r0;
+  for (; r + kAdjSets <= r1; r += kAdjSets) {
+    row(R0, R1, R2, r, true);
+    row(R1, R2, R3, r + 1, true);
+    row(R2, R3, R4, r + 2, true);
+    row(R3, R4, R5, r + 3, true);
+    row(R4, R5, R6, r + 4, true);
+    row(R5, R6, R7, r + 5, true);
+    row(R6, R7, R0, r + 6, true);
+    row(R7, R0, R1, r + 7, true);
   }
+  if (r < r1) { row(R0, R1, R2, r, r + kAdjSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R1, R2, R3, r, r + kAdjSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R2, R3, R4, r, r + kAdjSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R3, R4, R5, r, r + kAdjSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R4, R5, R6, r, r + kAdjSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R5, R6, R7, r, r + kAdjSets <= r1 + 1); ++r; }
+  if (r < r1) { row(R6, R7, R0, r, r + kAdjSets <= r1 + 1); ++r; }
+}
+
+// One wavefront per workgroup: segment (tx, ty) of patch blockIdx.y, 60
+// columns by `rows` rows.  Every padded cell of lam_out is written: the
+// interior with its (folded) cotangent, the ghosts with 0.
+__global__ __launch_bounds__(64) void adjoint_kernel(const PatchRow *patches,
+                                                     const InstRow *inst, double dt,
+                                                     const uint8_t *masks, const double *lam_in,
+                                                     double *lam_out, int rows) {
+  const PatchRow pr = uniform_row(patches[blockIdx.y]);
+  const int ntx = (pr.mx + 59) / 60, nty = (pr.my + rows - 1) / rows;
+  const int b = (int)blockIdx.x;
+  if (b >= ntx * nty) return;
+  const int tx = b % ntx, ty = b / ntx;
+  const InstRow in = uniform_row(inst[pr.inst]);
+  const Coef<double> k = make_coef<double>(in.c, in.Z, dt, pr.dx, pr.dy);
+  const int l = (int)threadIdx.x;
+  AdjLanes M;
+  const int64_t org = pr.q_off + pr.col0 - 2;  // padded cell (-2, -2)
+  M.lb = reinterpret_cast<const char *>(lam_in + org);
+  M.ob = reinterpret_cast<char *>(lam_out + org);
+  M.mk = masks + pr.mask_off;
+  M.ld = (unsigned)pr.ld;
+  M.plb = (unsigned)pr.plane * 8u;
+  M.mld = pr.mx + 1;
+  M.mx = pr.mx;
+  M.my = pr.my;
+  M.c = tx * 60 - 2 + l;
+  M.cl = min(max(M.c, 0), pr.mx - 1);
+  M.cm = min(max(M.c, 0), pr.mx);
+  M.colin = M.c >= 0 && M.c < pr.mx;
+  M.colm = M.c >= 0 && M.c <= pr.mx;
+  const int r0 = ty * rows, r1 = min(r0 + rows, pr.my);
+  const bool fold = pr.bc == WS_BC_EXTRAP;
+  const bool xedge = tx == 0 || tx == ntx - 1;
+  adjoint_march(M, k, l, r0 == 0 ? -2 : r0, r1 == pr.my ? pr.my + 2 : r1, fold, xedge);
 }
 
 __global__ void gather_kernel(const PatchRow *patches, int patch, int comp, int n,
@@ -252,18 +304,13 @@ __global__ void add_at_kernel(const PatchRow *patches, int patch, int comp, int 
 
 }  // namespace
 
-hipError_t launch_adjoint(const PatchRow *patches, int n_patches, int max_padded_cells,
-                          int max_ring, const InstRow *inst, double dt, const uint8_t *masks,
+hipError_t launch_adjoint(const PatchRow *patches, int n_patches, int max_mx, int max_my,
+                          const InstRow *inst, double dt, const uint8_t *masks,
                           const double *lam_in, double *lam_out, hipStream_t s) {
   if (n_patches <= 0) return hipSuccess;
-  const int gx = max(1, min(4096, (max_padded_cells + kThreads - 1) / kThreads));
-  hipLaunchKernelGGL(adjoint_update_kernel, dim3(gx, n_patches), dim3(kThreads), 0, s, patches,
-                     inst, dt, masks, lam_in, lam_out);
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int gr = max(1, min(256, (3 * max_ring + kThreads - 1) / kThreads));
-  hipLaunchKernelGGL(adjoint_fold_kernel, dim3(gr, n_patches), dim3(kThreads), 0, s, patches,
-                     lam_out);
+  const int ntx = (max_mx + 59) / 60, nty = (max_my + kAdjRows - 1) / kAdjRows;
+  hipLaunchKernelGGL(adjoint_kernel, dim3((unsigned)(ntx * nty), (unsigned)n_patches), dim3(64),
+                     0, s, patches, inst, dt, masks, lam_in, lam_out, kAdjRows);
   return hipGetLastError();
 }
 

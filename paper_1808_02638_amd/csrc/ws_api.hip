@@ -232,6 +232,7 @@ struct ws_ctx {
   int wg_override = 0;   // workgroups per CU set by the caller (0: occupancy)
   int max_padded_cells = 0;
   int max_ring = 0;  // interior cells next to a side, largest patch
+  int max_mx = 0, max_my = 0;
   int64_t mask_total = 0;  // bytes of the branch masks of all patches
   double *host_buf = nullptr;
   int64_t host_buf_bytes = 0;
@@ -333,13 +334,12 @@ int ws_layout(const ws_patch_desc *patches, int32_t n_patches, int32_t n_instanc
   return WS_OK;
 }
 
-int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patches,
-                    const ws_material *mats, int32_t n_instances, int32_t mbc, int32_t dtype,
-                    int32_t limiter, void *q_pool_a, void *q_pool_b, int64_t pool_bytes,
-                    void *workspace, int64_t ws_bytes, void *hip_stream) {
-  if (!out) return fail(WS_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (mbc != 2) return fail(WS_EINVAL, "mbc must be 2 (got %d)", mbc);
+}  // extern "C"
+
+// Arguments every level set-up checks: dtype, limiter, the patch list and
+// the materials.
+static int check_level(const ws_patch_desc *patches, int32_t n_patches, const ws_material *mats,
+                       int32_t n_instances, int32_t dtype, int32_t limiter) {
   if (dtype != WS_F64 && dtype != WS_F32) return fail(WS_EINVAL, "unknown dtype %d", dtype);
   {
     const int lim = limiter & ~WS_TRANSVERSE_CORR;
@@ -352,39 +352,33 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
     if (!(mats[k].rho > 0.0) || !(mats[k].K > 0.0) || !std::isfinite(mats[k].rho) ||
         !std::isfinite(mats[k].K))
       return fail(WS_EINVAL, "instance %d: rho and K must be finite and > 0", k);
-  if (!q_pool_a || !q_pool_b || !workspace) return fail(WS_EINVAL, "pool or workspace is NULL");
-  if (q_pool_a == q_pool_b) return fail(WS_EINVAL, "the two pools must differ");
-  int64_t need_pool = 0, need_ws = 0;
-  ws_layout(patches, n_patches, n_instances, dtype, &need_pool, &need_ws);
-  if (pool_bytes < need_pool)
-    return fail(WS_ENOMEM, "pool too small: %lld < %lld bytes", (long long)pool_bytes,
-                (long long)need_pool);
-  if (ws_bytes < need_ws)
-    return fail(WS_ENOMEM, "workspace too small: %lld < %lld bytes", (long long)ws_bytes,
-                (long long)need_ws);
+  return WS_OK;
+}
 
-  ws_ctx *c = new ws_ctx();
+// Host metadata of a level over the given pools and workspace: pool layout,
+// patch rows with the default tiling, the instance table and the patch order
+// (largest first).  Touches no device memory.
+static int setup_level(ws_ctx *c, const ws_patch_desc *patches, int32_t n_patches,
+                       const ws_material *mats, int32_t n_instances, int32_t dtype,
+                       int32_t limiter, void *pool_a, void *pool_b, int64_t pool_bytes, char *ws,
+                       hipStream_t stream) {
   c->dtype = dtype;
   c->limiter = limiter;
   c->n_patches = n_patches;
   c->n_inst = n_instances;
-  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-  c->pool[0] = q_pool_a;
-  c->pool[1] = q_pool_b;
+  c->stream = stream;
+  c->pool[0] = pool_a;
+  c->pool[1] = pool_b;
   c->pool_bytes = pool_bytes;
-  c->ws = reinterpret_cast<char *>(workspace);
+  c->ws = ws;
   c->L = ws_layout_of(patches, n_patches, n_instances);
   c->P = pool_layout(patches, n_patches, dtype);
   c->desc.assign(patches, patches + n_patches);
 
   int dev = 0;
-  auto bail = [&](int rc) {
-    delete c;
-    return rc;
-  };
-  if (hipGetDevice(&dev) != hipSuccess) return bail(fail(WS_EHIP, "hipGetDevice failed"));
+  if (hipGetDevice(&dev) != hipSuccess) return fail(WS_EHIP, "hipGetDevice failed");
   if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return bail(fail(WS_EHIP, "cannot query the CU count"));
+    return fail(WS_EHIP, "cannot query the CU count");
 
   std::vector<InstRow> inst(n_instances);
   for (int k = 0; k < n_instances; ++k) {
@@ -415,6 +409,8 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
     mask_off += (int64_t)(d.mx + 1) * (d.my + 1);
     c->max_padded_cells = std::max(c->max_padded_cells, (d.mx + 4) * (d.my + 4));
     c->max_ring = std::max(c->max_ring, 2 * (d.mx + d.my));
+    c->max_mx = std::max(c->max_mx, d.mx);
+    c->max_my = std::max(c->max_my, d.my);
   }
   c->mask_total = mask_off;
   c->order.resize(n_patches);
@@ -423,6 +419,40 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
     return (int64_t)patches[a].mx * patches[a].my > (int64_t)patches[b].mx * patches[b].my;
   });
 
+  return WS_OK;
+}
+
+extern "C" {
+
+int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patches,
+                    const ws_material *mats, int32_t n_instances, int32_t mbc, int32_t dtype,
+                    int32_t limiter, void *q_pool_a, void *q_pool_b, int64_t pool_bytes,
+                    void *workspace, int64_t ws_bytes, void *hip_stream) {
+  if (!out) return fail(WS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (mbc != 2) return fail(WS_EINVAL, "mbc must be 2 (got %d)", mbc);
+  if (int rc = check_level(patches, n_patches, mats, n_instances, dtype, limiter)) return rc;
+  if (!q_pool_a || !q_pool_b || !workspace) return fail(WS_EINVAL, "pool or workspace is NULL");
+  if (q_pool_a == q_pool_b) return fail(WS_EINVAL, "the two pools must differ");
+  int64_t need_pool = 0, need_ws = 0;
+  ws_layout(patches, n_patches, n_instances, dtype, &need_pool, &need_ws);
+  if (pool_bytes < need_pool)
+    return fail(WS_ENOMEM, "pool too small: %lld < %lld bytes", (long long)pool_bytes,
+                (long long)need_pool);
+  if (ws_bytes < need_ws)
+    return fail(WS_ENOMEM, "workspace too small: %lld < %lld bytes", (long long)ws_bytes,
+                (long long)need_ws);
+
+  ws_ctx *c = new ws_ctx();
+  auto bail = [&](int rc) {
+    delete c;
+    return rc;
+  };
+  if (int rc = setup_level(c, patches, n_patches, mats, n_instances, dtype, limiter, q_pool_a,
+                           q_pool_b, pool_bytes, reinterpret_cast<char *>(workspace),
+                           reinterpret_cast<hipStream_t>(hip_stream)))
+    return bail(rc);
+  const std::vector<InstRow> &inst = c->inst_host;
   c->host_buf_bytes = std::max<int64_t>(4096, 8LL * 3 * std::max(n_instances, n_patches));
   if (hipHostMalloc(reinterpret_cast<void **>(&c->host_buf), c->host_buf_bytes) != hipSuccess)
     return bail(fail(WS_EHIP, "hipHostMalloc of %lld bytes failed", (long long)c->host_buf_bytes));
@@ -904,7 +934,10 @@ int ws_adjoint_step(ws_ctx *c, double dt, const void *masks_dev, const void *lam
   for (int k = 0; k < c->n_patches; ++k)
     if (c->rows[k].bc == WS_BC_PERIODIC)
       return fail(WS_EINVAL, "patch %d: the adjoint does not take periodic patches", k);
-  HIPCHK(launch_adjoint(c->d_patches(), c->n_patches, c->max_padded_cells, c->max_ring,
+  for (int k = 0; k < c->n_patches; ++k)
+    if (!march_fits(c->rows[k].plane, WS_F64))
+      return fail(WS_EINVAL, "patch %d: too large for the adjoint (32-bit offsets)", k);
+  HIPCHK(launch_adjoint(c->d_patches(), c->n_patches, c->max_mx, c->max_my,
                         reinterpret_cast<const InstRow *>(c->ws + c->L.inst), dt,
                         reinterpret_cast<const uint8_t *>(masks_dev),
                         reinterpret_cast<const double *>(lam_in),

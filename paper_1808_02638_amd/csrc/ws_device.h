@@ -72,6 +72,19 @@ __device__ inline S uniform_row(const S &v) {
   return out;
 }
 
+// Whole-wavefront lane shifts (DPP): shr gives lane l the value of lane l-1,
+// shl the value of lane l+1.  Lanes without a source read 0 (never used).
+__device__ inline int dpp_shr_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ inline int dpp_shl_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ inline double shr(double v) {
+  return __hiloint2double(dpp_shr_i(__double2hiint(v)), dpp_shr_i(__double2loint(v)));
+}
+__device__ inline double shl(double v) {
+  return __hiloint2double(dpp_shl_i(__double2hiint(v)), dpp_shl_i(__double2loint(v)));
+}
+__device__ inline float shr(float v) { return __int_as_float(dpp_shr_i(__float_as_int(v))); }
+__device__ inline float shl(float v) { return __int_as_float(dpp_shl_i(__float_as_int(v))); }
+
 // --------------------------------------------------------------------------
 // Limiter on unscaled strengths: psi(a, a_up) = phi(a_up/a) a (the limiters
 // are positively homogeneous).  MC: minmod(2a, 2a_up, (a + a_up)/2), written

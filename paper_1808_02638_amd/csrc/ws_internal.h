@@ -132,10 +132,10 @@ int step_occupancy(int dtype, int limiter, int vars, int *wg_per_cu);
 
 // Adjoint and receiver helpers (defined in ws_adjoint.hip), FP64 buffers in
 // the pools' layout.
-// lam_out <- E^T U^T lam_in (two launches: the gather-form update transpose
-// over every padded cell, then the ghost fold over each patch's boundary ring).
-hipError_t launch_adjoint(const PatchRow *patches, int n_patches, int max_padded_cells,
-                          int max_ring, const InstRow *inst, double dt, const uint8_t *masks,
+// lam_out <- E^T U^T lam_in (one launch: the gather-form update transpose
+// with the extrapolation ghosts folded into the boundary cells).
+hipError_t launch_adjoint(const PatchRow *patches, int n_patches, int max_mx, int max_my,
+                          const InstRow *inst, double dt, const uint8_t *masks,
                           const double *lam_in, double *lam_out, hipStream_t s);
 hipError_t launch_gather(const PatchRow *patches, int patch, int comp, int n, const int32_t *ij,
                          const double *buf, double *out, hipStream_t s);

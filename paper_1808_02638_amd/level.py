@@ -386,3 +386,4 @@ class Level:
 
     def __exit__(self, *exc):
         self.close()
+

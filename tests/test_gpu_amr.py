@@ -335,8 +335,12 @@ def test_tuned_composite_steps_from_poisoned_memory_match_oracle(ws):
     from paper_1808_02638_amd.autotune import autotune
 
     probe = ws.Level([dict(mx=20, my=10, dx=0.05, dy=0.1)], [(RHO, KB)])
-    for b in (*probe.pools, probe.workspace):
-        assert bool((b == 0xFF).all()), "allocations are not poisoned"
+    torch.cuda.synchronize()
+    # the pools hold nothing before an upload; the workspace holds the tables
+    # and cleared slots init wrote, and poison everywhere else
+    for b in probe.pools:
+        assert bool((b == 0xFF).all()), "pools are not poisoned"
+    assert bool((probe.workspace == 0xFF).any()), "workspace is not poisoned"
     probe.close()
 
     n, steps, r = 48, 8, 4

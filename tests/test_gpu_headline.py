@@ -5,9 +5,13 @@ configuration the benchmark times (autotuned tiling, steps in one hipGraph):
   against the FP64 oracle on every cell (1e-12), and the FP32 variant against
   the same oracle (1e-5, the error printed per component);
 * the 512^2, 200-step frozen-limiter adjoint (Courant 0.8, 16 receivers,
-  checkpoints every 20 steps): the GPU gradient against the oracle's adjoint
-  sweep (1e-12), and against central differences (h = 1e-6) along 16 single
-  cells of the pulse annulus and 4 smooth directions supported on it;
+  checkpoints every 20 steps): the traces against the oracle (1e-12), the
+  branches on which the two sides differ shown to be ties, the library's
+  adjoint steps with the oracle's branches against the oracle's adjoint sweep
+  (1e-12), and the gradient with the library's own branches against central
+  differences (h = 1e-6) along 48 single cells of the pulse annulus and 4
+  smooth directions supported on it (1e-6 where no branch flips, at least
+  four such probes; 1e-3 for every probe);
 * a seeded sample of the 64-instance ensemble (with its largest and smallest
   instances) against the oracle over its 200 graph steps.
 
@@ -135,16 +139,73 @@ def _gpu_forward(ws, n, p0, steps, dt, receivers):
     return out
 
 
+def _branch_value(code, a, a_up):
+    """The limited strength a frozen MC branch gives (0: 0, 1: mean, 2: 2a,
+    3: 2 a_up)."""
+    return np.select([code == 1, code == 2, code == 3], [0.5 * (a + a_up), 2 * a, 2 * a_up], 0.0)
+
+
+def _near_tie_excess(q, m_gpu, m_or, n):
+    """For every branch field where the two recorded masks of one step
+    differ, the two branches' limited strengths are evaluated from the
+    oracle's state q (padded, before the step); returns the largest
+    |difference| divided by the largest strength of the step (0 when the
+    masks agree).  A disagreement is a valid alternative when this is at
+    roundoff level: the two branches give the same limited strength."""
+    Z = math.sqrt(KB * RHO)
+    P, U, V = q[0], q[1], q[2]
+    # x-edge e (cells e-1 | e) of interior row j, for e = -1 .. n+1: index e+1
+    dpx, dux = P[2:-2, 1:] - P[2:-2, :-1], U[2:-2, 1:] - U[2:-2, :-1]
+    ax1, ax2 = (-dpx + Z * dux) / (2 * Z), (dpx + Z * dux) / (2 * Z)
+    dpy, dvy = P[1:, 2:-2] - P[:-1, 2:-2], V[1:, 2:-2] - V[:-1, 2:-2]
+    ay1, ay2 = (-dpy + Z * dvy) / (2 * Z), (dpy + Z * dvy) / (2 * Z)
+    scale = max(np.abs(ax1).max(), np.abs(ax2).max(), np.abs(ay1).max(), np.abs(ay2).max())
+    diff = m_gpu != m_or
+    if not diff.any():
+        return 0.0, 0
+    jj, ii = np.nonzero(diff)
+    worst, fields = 0.0, 0
+    for f in range(4):
+        cg = (m_gpu[jj, ii] >> (2 * f)) & 3
+        co = (m_or[jj, ii] >> (2 * f)) & 3
+        sel = cg != co
+        if not sel.any():
+            continue
+        j, i, cg, co = jj[sel], ii[sel], cg[sel], co[sel]
+        fields += int(sel.sum())
+        if f < 2:  # x-edge i - 1/2 of row j (rows j < n only carry x bits)
+            assert (j < n).all()
+            own = (ax1 if f == 0 else ax2)[j, i + 1]
+            up = ax1[j, i + 2] if f == 0 else ax2[j, i]
+        else:  # y-edge j - 1/2 of column i
+            assert (i < n).all()
+            own = (ay1 if f == 2 else ay2)[j + 1, i]
+            up = ay1[j + 2, i] if f == 2 else ay2[j, i]
+        d = np.abs(_branch_value(cg, own, up) - _branch_value(co, own, up)).max()
+        worst = max(worst, d / scale)
+    return worst, fields
+
+
 def test_cfg5_full_size_gradient_against_oracle_adjoint_and_differences(ws, oracle_lib):
+    """The branches are decided by floating point, and the library's closed
+    forms round differently from the oracle's eigen-decomposition: where a
+    wave meets the flat background (strengths at rounding level) or a
+    limiter ratio sits at a tie, the two sides may record different but
+    equally valid branches, and a frozen-branch gradient depends on them.
+    So: the traces match at 1e-12; every branch on which the two sides
+    differ is a tie (both branches give the same limited strength to
+    rounding); the library's adjoint steps driven by the oracle's branches
+    reproduce the oracle gradient at 1e-12; the gradient with the library's
+    own branches is checked by central differences where no branch flips."""
     setup = workloads.adjoint_setup()
     n, steps, dt, rec = setup.n, setup.steps, setup.dt, setup.receivers
     p0 = setup.p0()
     t0 = time.perf_counter()
     target = oracle_lib.forward_traces(setup.target_p0(), steps, 1 / n, 1 / n, dt, RHO, KB,
                                        rec)[1]
-    J_o, g_o, tr_o, _m = oracle_lib.adjoint_run(p0, steps, 1 / n, 1 / n, dt, RHO, KB, rec,
-                                                target)
-    del _m
+    J_o, g_o, tr_o, masks_o = oracle_lib.adjoint_run(p0, steps, 1 / n, 1 / n, dt, RHO, KB, rec,
+                                                     target)
+    states_o = oracle_lib.forward_traces(p0, steps, 1 / n, 1 / n, dt, RHO, KB, rec)[2]
     progress(f"oracle adjoint 512^2 x 200: {time.perf_counter() - t0:.0f} s")
     run = ws.AcousticsAdjoint(n, n, 1 / n, 1 / n, RHO, KB, rec, steps, dt,
                               checkpoint_every=setup.checkpoint_every)
@@ -156,15 +217,51 @@ def test_cfg5_full_size_gradient_against_oracle_adjoint_and_differences(ws, orac
     g = p.grad.cpu().numpy()
     run.close()
     e_tr = np.abs(tr.detach().cpu().numpy() - tr_o).max() / np.abs(tr_o).max()
-    e_g = np.abs(g - g_o).max() / np.abs(g_o).max()
-    print(f"512^2 x 200 adjoint: traces rel Linf {e_tr:.2e}, gradient rel Linf vs the oracle "
-          f"adjoint {e_g:.2e}, J {float(J):.12e} vs {J_o:.12e}")
-    assert e_tr <= FP64_TOL and e_g <= FP64_TOL
-    assert abs(float(J) - J_o) <= 1e-10 * J_o
+    e_own = np.abs(g - g_o).max() / np.abs(g_o).max()
+    print(f"512^2 x 200 adjoint: traces rel Linf {e_tr:.2e}, J {float(J.detach()):.12e} vs "
+          f"{J_o:.12e}; gradient with the library's own branches vs the oracle's {e_own:.2e}")
+    assert e_tr <= FP64_TOL
+    assert abs(float(J.detach()) - J_o) <= 1e-10 * J_o
 
-    # central differences of the GPU misfit, graded where no branch changes
-    tr_t = target
+    # the branches of both sides, step by step
     _, m0 = _gpu_forward(ws, n, p0, steps, dt, rec)
+    m_gpu = m0.cpu().numpy().reshape(steps, n + 1, n + 1)
+    worst, n_fields, n_steps = 0.0, 0, 0
+    for s in range(steps):
+        w, f = _near_tie_excess(states_o[s], m_gpu[s], masks_o[s], n)
+        worst, n_fields, n_steps = max(worst, w), n_fields + f, n_steps + (f > 0)
+    del states_o
+    print(f"branch fields that differ: {n_fields} in {n_steps} of {steps} steps; largest "
+          f"difference of the two branches' limited strengths {worst:.2e} of the step's largest")
+    assert worst <= 1e-12, worst
+
+    # the library's adjoint steps with the oracle's branches: the same linear
+    # maps, so the same gradient
+    lev = ws.Level([dict(mx=n, my=n, dx=1 / n, dy=1 / n, bc="extrap")], [(RHO, KB)])
+    mk = torch.from_numpy(np.stack(masks_o).reshape(steps, -1)).cuda()
+    resid = torch.from_numpy(np.ascontiguousarray(tr_o - target)).cuda()
+    ij = torch.from_numpy(np.ascontiguousarray(rec, np.int32)).cuda()
+    lam, lam2 = lev.new_buffer(), lev.new_buffer()
+    for s in range(steps - 1, -1, -1):
+        lev.add_at(0, 0, ij, resid[s].contiguous(), buf=lam)
+        lev.adjoint_step(dt, mk[s], lam, lam2)
+        lam, lam2 = lam2, lam
+    g_om = lev.patch_view(lam, 0)[0, 2:-2, 2:-2].cpu().numpy()
+    lev.close()
+    e_om = np.abs(g_om - g_o).max() / np.abs(g_o).max()
+    print(f"gradient of the library's adjoint steps with the oracle's branches vs the oracle "
+          f"adjoint: rel Linf {e_om:.2e}")
+    assert e_om <= FP64_TOL, e_om
+
+    # central differences of the GPU misfit.  The background is exactly flat
+    # (strengths exactly 0), so a perturbation of 1e-6 reaching it, or any
+    # near-tie, changes branches: J is not differentiable there and the
+    # difference quotient averages two one-sided slopes.  Probes whose
+    # branches do not change anywhere in the 200 steps are graded at 1e-6 (at
+    # least four of them); every probe must still agree to 1e-3 (a smooth
+    # direction straddles a few thousand kinks, which move the quotient by up
+    # to about 1e-4).  Flip counts are reported.
+    tr_t = target
     rng = np.random.default_rng(18085)
     xs = (np.arange(n) + 0.5) / n
     X, Y = np.meshgrid(xs, xs, indexing="xy")
@@ -172,7 +269,7 @@ def test_cfg5_full_size_gradient_against_oracle_adjoint_and_differences(ws, orac
     annulus = np.abs(r - 0.25) < 0.09
     cells = np.argwhere(annulus)
     probes = []
-    for j, i in cells[rng.choice(len(cells), size=16, replace=False)]:
+    for j, i in cells[rng.choice(len(cells), size=48, replace=False)]:
         v = np.zeros((n, n))
         v[j, i] = 1.0
         probes.append((f"cell ({i},{j})", v))
@@ -193,13 +290,16 @@ def test_cfg5_full_size_gradient_against_oracle_adjoint_and_differences(ws, orac
         terms = 0.5 * (tp - tm) * ((tp - tr_t) + (tm - tr_t))
         fd = math.fsum(terms.ravel().tolist()) / (2 * h)
         rows.append((name, fd, float(np.vdot(g, v)), flips))
-    print("512^2 x 200 central differences (probe, fd, adjoint, branch flips):")
-    for row in rows:
-        print(f"   {row[0]:>20s} {row[1]: .10e} {row[2]: .10e} {row[3]}")
+    print("512^2 x 200 central differences (probe, fd, adjoint, relative difference, "
+          "branch flips):")
+    for nm, fd, ad, fl in rows:
+        print(f"   {nm:>20s} {fd: .10e} {ad: .10e} {abs(fd - ad) / abs(ad):.1e} {fl}")
     graded = [(nm, fd, ad) for nm, fd, ad, fl in rows if fl == 0]
-    print(f"graded {len(graded)} of {len(rows)}")
+    print(f"graded (no branch flips) {len(graded)} of {len(rows)}")
     for nm, fd, ad in graded:
-        assert abs(fd - ad) <= 1e-6 * max(abs(ad), 1e-8), (nm, fd, ad)
+        assert abs(fd - ad) <= 1e-6 * abs(ad), (nm, fd, ad)
+    for nm, fd, ad, _fl in rows:
+        assert abs(fd - ad) <= 1e-3 * abs(ad), (nm, fd, ad)
     assert len(graded) >= 4, rows
 
 
