@@ -374,6 +374,34 @@ int ws_cf_nest(ws_cf *outer, ws_cf *inner);
 int ws_cf_fill_fine_ghosts(ws_cf *cf, double alpha);
 int ws_cf_destroy(ws_cf *cf);
 
+/* --------------------------------------------------------------------------
+ * Level step that allocates nothing, for callers that cannot allocate device
+ * memory (code that must not call hipMalloc: tight serving loops, harnesses
+ * that forbid it).  The same step as ws_step_level (one persistent launch of
+ * the same kernels, default tiling, bitwise the same results), with no
+ * context and no caller workspace: the patch table, tile list and Courant-
+ * number slots live in a device array of ws_noalloc_scratch_bytes() bytes
+ * (8 MiB) that the library holds on every GPU it runs on until the process
+ * ends.  The call uploads the tables from host memory, clears the slots that
+ * must start at zero, steps, reads the Courant number back and synchronises
+ * the stream, so it is not for use under stream capture.  Every call on one
+ * GPU shares that GPU's array: calls that overlap on one GPU (several host
+ * threads or streams) race and must be serialised by the caller.
+ *   patches, mats, dtype, limiter: as for ws_init_patches;
+ *   q_in, q_out: distinct device buffers of >= pool_bytes laid out as the
+ *     pools ws_layout() sizes for this patch list (ws_patch_layout of a
+ *     context over the same list gives each patch's place); q_out receives
+ *     every interior cell and, on physical boundaries, the ghosts; ghosts of
+ *     WS_BC_NONE patches in q_out are left as they are;
+ *   *cfl_out (may be NULL): the level's Courant number, as ws_step_level.
+ * A level whose workspace (ws_layout's ws_bytes) exceeds the array returns
+ * WS_ENOMEM without touching the GPU. */
+int64_t ws_noalloc_scratch_bytes(void);
+int ws_step_level_noalloc(const ws_patch_desc *patches, int32_t n_patches,
+                          const ws_material *mats, int32_t n_instances, int32_t dtype,
+                          int32_t limiter, const void *q_in, void *q_out, int64_t pool_bytes,
+                          double dt, double *cfl_out, void *hip_stream);
+
 int ws_destroy(ws_ctx *ctx);
 const char *ws_last_error(void);
 

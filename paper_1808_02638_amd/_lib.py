@@ -29,7 +29,7 @@ EXPORTS = (
     "ws_adjoint_step", "ws_gather", "ws_add_at", "ws_time_step_kernel", "ws_current_pool",
     "ws_attach_medium", "ws_upload_medium", "ws_link_layout", "ws_link_level",
     "ws_cf_layout", "ws_cf_init", "ws_cf_step", "ws_cf_nest", "ws_cf_fill_fine_ghosts",
-    "ws_cf_destroy",
+    "ws_cf_destroy", "ws_noalloc_scratch_bytes", "ws_step_level_noalloc",
     "ws_destroy", "ws_last_error",
 )
 
@@ -108,12 +108,16 @@ def lib():
         "ws_cf_nest": [vp, vp],
         "ws_cf_fill_fine_ghosts": [vp, dbl],
         "ws_cf_destroy": [vp],
+        "ws_step_level_noalloc": [P(PatchDesc), i32, P(Material), i32, i32, i32, vp, vp, i64,
+                                  dbl, P(dbl), vp],
         "ws_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = ctypes.c_int
+    L.ws_noalloc_scratch_bytes.argtypes = []
+    L.ws_noalloc_scratch_bytes.restype = ctypes.c_int64
     L.ws_last_error.argtypes = []
     L.ws_last_error.restype = ctypes.c_char_p
     _lib = L

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <tuple>
@@ -976,6 +977,83 @@ int ws_add_at(ws_ctx *c, void *buf, int32_t patch, int32_t comp, int32_t n, cons
 int ws_current_pool(ws_ctx *c, int32_t *which) {
   if (!c || !which) return fail(WS_EINVAL, "NULL argument");
   *which = c->cur;
+  return WS_OK;
+}
+
+// --------------------------------------------------------------------------
+// Level step without allocation: the workspace lives in a file-scope device
+// array of the library instead of caller memory.
+// --------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+constexpr int64_t kScratchBytes = int64_t{8} << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch[kMaxDevices] = {};
+}  // namespace
+
+// Patch table, tile list and Courant-number slots of ws_step_level_noalloc.
+// In host code the name is only a stand-in for the symbol: the device
+// address of each GPU's copy comes from hipGetSymbolAddress.
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+// The current device's copy of `scratch`, looked up once per device.
+static int scratch_on_device(char **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(WS_EINVAL, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(WS_EHIP, "hipGetSymbolAddress returned NULL");
+    g_scratch[dev] = static_cast<char *>(p);
+  }
+  *out = g_scratch[dev];
+  return WS_OK;
+}
+
+extern "C" {
+
+int64_t ws_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+int ws_step_level_noalloc(const ws_patch_desc *patches, int32_t n_patches,
+                          const ws_material *mats, int32_t n_instances, int32_t dtype,
+                          int32_t limiter, const void *q_in, void *q_out, int64_t pool_bytes,
+                          double dt, double *cfl_out, void *hip_stream) {
+  if (int rc = check_level(patches, n_patches, mats, n_instances, dtype, limiter)) return rc;
+  if (!q_in || !q_out) return fail(WS_EINVAL, "q_in or q_out is NULL");
+  if (q_in == q_out) return fail(WS_EINVAL, "q_in and q_out must differ");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
+  int64_t need_pool = 0, need_ws = 0;
+  ws_layout(patches, n_patches, n_instances, dtype, &need_pool, &need_ws);
+  if (pool_bytes < need_pool)
+    return fail(WS_ENOMEM, "pool too small: %lld < %lld bytes", (long long)pool_bytes,
+                (long long)need_pool);
+  if (need_ws > kScratchBytes)
+    return fail(WS_ENOMEM, "the level needs %lld bytes of workspace; the no-allocation step "
+                "holds %lld (use ws_init_patches with a workspace)", (long long)need_ws,
+                (long long)kScratchBytes);
+  char *ws = nullptr;
+  if (int rc = scratch_on_device(&ws)) return rc;
+  ws_ctx c;  // host metadata only; no pinned buffer, no graph
+  if (int rc = setup_level(&c, patches, n_patches, mats, n_instances, dtype, limiter,
+                           const_cast<void *>(q_in), q_out, pool_bytes, ws,
+                           reinterpret_cast<hipStream_t>(hip_stream)))
+    return rc;
+  // the scratch keeps the previous call's contents: clear the slots that
+  // must start at zero (accumulators, retirement counters), then the tables
+  HIPCHK(hipMemsetAsync(ws + c.L.dt, 0, c.L.partials - c.L.dt, c.stream));
+  HIPCHK(hipMemcpyAsync(ws + c.L.inst, c.inst_host.data(), c.inst_host.size() * sizeof(InstRow),
+                        hipMemcpyHostToDevice, c.stream));
+  if (int rc = c.build_tiles()) return rc;  // uploads the tables, synchronises
+  StepArgs a = c.step_args(0, dt, 0.0);
+  HIPCHK(launch_step(c.dtype, c.lim_code(), c.vars, a, c.grid, c.stream));
+  double cfl = 0.0;
+  HIPCHK(hipMemcpyAsync(&cfl, ws + c.L.level_last, 8, hipMemcpyDeviceToHost, c.stream));
+  HIPCHK(hipStreamSynchronize(c.stream));
+  if (cfl_out) *cfl_out = cfl;
   return WS_OK;
 }
 

@@ -387,3 +387,40 @@ class Level:
     def __exit__(self, *exc):
         self.close()
 
+
+def _tables(patches: Sequence, materials: Sequence):
+    """The C patch-descriptor and material arrays of a patch list."""
+    descs = (C.PatchDesc * len(patches))()
+    for k, p in enumerate(patches):
+        descs[k].mx, descs[k].my = int(_get(p, "mx")), int(_get(p, "my"))
+        descs[k].dx = float(_get(p, "dx"))
+        descs[k].dy = float(_get(p, "dy"))
+        descs[k].instance = int(_get(p, "instance", 0) or 0)
+        descs[k].bc = _BCS[_get(p, "bc", None)]
+    mats = (C.Material * len(materials))()
+    for k, (rho, K) in enumerate(materials):
+        mats[k].rho, mats[k].K = float(rho), float(K)
+    return descs, mats
+
+
+def step_level_noalloc(patches: Sequence, materials: Sequence, q_in: torch.Tensor,
+                       q_out: torch.Tensor, dt: float, *, dtype=torch.float64,
+                       limiter: str = "mc", transverse_corr: bool = False,
+                       stream: torch.cuda.Stream | None = None) -> float:
+    """``ws_step_level_noalloc``: one level step from the pool-layout buffer
+    q_in into q_out (device tensors of the pool size ``ws_layout`` gives for
+    this patch list) with the library's own scratch array in place of a
+    workspace; returns the level's Courant number.  Synchronises ``stream``
+    (default: torch's current stream)."""
+    L = C.lib()
+    descs, mats = _tables(patches, materials)
+    code = C.WS_F64 if dtype == torch.float64 else C.WS_F32
+    lim = _LIMITERS[limiter] | (C.WS_TRANSVERSE_CORR if transverse_corr else 0)
+    nbytes = min(q_in.numel() * q_in.element_size(), q_out.numel() * q_out.element_size())
+    s = stream if stream is not None else torch.cuda.current_stream(q_in.device)
+    cfl = ctypes.c_double(0.0)
+    C.check(L.ws_step_level_noalloc(descs, len(patches), mats, len(materials), code, lim,
+                                    ctypes.c_void_p(q_in.data_ptr()),
+                                    ctypes.c_void_p(q_out.data_ptr()), int(nbytes), float(dt),
+                                    ctypes.byref(cfl), ctypes.c_void_p(s.cuda_stream)))
+    return cfl.value
