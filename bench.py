@@ -240,7 +240,7 @@ def run_amr(ws, torch, dtype, level_steps, tune=True):
 
     levels = workloads.amr_level_batch()
     out = {"levels": [], "n_patches": sum(len(l) for l in levels)}
-    tot_cells = 0
+    tot_cells = tot_bytes = 0
     tb = tp = 0.0
     for specs in levels:
         lev = ws.Level([dict(mx=p.mx, my=p.my, dx=p.dx, dy=p.dy) for p in specs], [(RHO, K_BULK)],
@@ -253,17 +253,41 @@ def run_amr(ws, torch, dtype, level_steps, tune=True):
             autotune(lev)
         lev.time_step_kernel(2)
         lev.time_step_kernel(2, per_patch=True)
-        ms_b = lev.time_step_kernel(level_steps)
+        ms_br = lev.time_step_kernel(level_steps)
         ms_p = lev.time_step_kernel(level_steps, per_patch=True)
+        # the batched level steps as one captured graph (level_steps launches,
+        # the Courant number filed inside each), so no per-launch event pair
+        # or host call enters the time; the per-patch baseline is one launch
+        # per patch from the host, as such a code runs
+        steps_g = level_steps + level_steps % 2
+        lev.capture(steps_g, 0.9)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        lev.graph_launch()
+        times = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            e0.record(lev.stream)
+            lev.graph_launch()
+            e1.record(lev.stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / steps_g)
+        ms_b = sorted(times)[len(times) // 2]
         cells = sum(p.mx * p.my for p in specs)
+        nbytes = algorithmic_bytes([(p.mx, p.my) for p in specs], dtype.itemsize, False)
         tot_cells += cells
+        tot_bytes += nbytes
         tb += ms_b
         tp += ms_p
         out["levels"].append(dict(patches=len(specs), cells=cells,
-                                  batched_gcells=cells / ms_b / 1e6,
-                                  per_patch_gcells=cells / ms_p / 1e6))
+                                  batched_gcells=round(cells / ms_b / 1e6, 3),
+                                  batched_us=round(ms_b * 1e3, 2),
+                                  batched_bracketed_us=round(ms_br * 1e3, 2),
+                                  frac=round(nbytes / (ms_b / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  per_patch_gcells=round(cells / ms_p / 1e6, 3)))
         lev.close()
     out["batched_gcells"] = tot_cells / tb / 1e6
+    out["batched_frac"] = round(tot_bytes / (tb / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     out["per_patch_gcells"] = tot_cells / tp / 1e6
     out["speedup"] = tp / tb
     out["cells_per_level_step"] = tot_cells
@@ -523,27 +547,39 @@ def run_three_level(ws, torch, steps=10, warmup=2, r=4, n=512, tune=True):
             "frac": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "finite": finite}
 
 
-def measured_traffic(tiling, profile=PROFILE):
-    """HBM bytes per launch of the FP64 step kernel from the committed counter
-    summary, or None when the library has been rebuilt since the counters were
-    taken or the tiling differs from the one they were taken with."""
+STEP_KERNEL_SOURCES = ("ws_kernels.hip", "ws_device.h", "ws_internal.h")
+
+
+def step_kernel_sha1():
+    """SHA-1 of the step kernel's sources (the kernel file and the two headers
+    it includes from the library), in that order."""
     import hashlib
 
-    from paper_1808_02638_amd import _lib
+    h = hashlib.sha1()
+    for name in STEP_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1808_02638_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
+
+def measured_traffic(tiling, profile=PROFILE, n=2048):
+    """HBM bytes per launch of the FP64 step kernel on the n x n grid (2048 or
+    4096) from the committed counter summary, or None when the step kernel's
+    sources have changed since the counters were taken or the tiling differs
+    from the one they were taken with."""
     try:
         text = open(profile).read()
     except OSError:
         return None
+    sfx = "" if n == 2048 else f"_{n}"
+    keys = ("kernel_source_sha1", f"traffic{sfx}_bytes_per_launch", f"tiling{sfx}")
     fields = dict(line.split(": ", 1) for line in text.splitlines()
-                  if line.startswith(("library_sha1: ", "traffic_bytes_per_launch: ", "tiling: ")))
-    with open(_lib.LIB_PATH, "rb") as f:
-        sha = hashlib.sha1(f.read()).hexdigest()
-    if fields.get("library_sha1", "").strip() != sha:
+                  if line.split(": ", 1)[0] in keys)
+    if fields.get("kernel_source_sha1", "").strip() != step_kernel_sha1():
         return None
-    if fields.get("tiling", "").strip() != f"{tiling['variant']}/{tiling['tile_w']}/{tiling['tile_h']}":
+    if fields.get(keys[2], "").strip() != f"{tiling['variant']}/{tiling['tile_w']}/{tiling['tile_h']}":
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    return int(fields[keys[1]]) if keys[1] in fields else None
 
 
 def cpu_model():
@@ -829,6 +865,7 @@ def main():
             "value": round(big * big * 100 / (rb["ms"] / 1e3) / 1e9, 3), "steps": 100,
             "kernel_ms": rb["ms"] / 100,
             "frac": round(bb / (rb["ms"] / 100 / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "bytes_per_launch": bb, "traffic": measured_traffic(rb["tiling"], n=big),
             "tiling": rb["tiling"]}
         line["copy_reference"] = {"pool_size": copy_bandwidth(torch, bytes64 // 2),
                                   "cache_free": copy_bandwidth(torch, 4 * bytes64)}

@@ -57,8 +57,11 @@ struct AdjSet {
 
 // Row sets of an adjoint segment (its row loop is unrolled by this count).
 constexpr int kAdjSets = 8;
-// Rows per segment (one wavefront each).
-constexpr int kAdjRows = 16;
+
+// Wavefronts per CU the launch aims for when it picks the segment height.
+#ifndef WS_ADJ_WAVES_PER_CU
+#define WS_ADJ_WAVES_PER_CU 8
+#endif
 
 // One wavefront of the adjoint: lane l holds column c = c0 - 2 + l of one
 // patch.  lam' is read through 32-bit byte offsets from the patch's padded
@@ -305,12 +308,20 @@ __global__ void add_at_kernel(const PatchRow *patches, int patch, int comp, int 
 }  // namespace
 
 hipError_t launch_adjoint(const PatchRow *patches, int n_patches, int max_mx, int max_my,
-                          const InstRow *inst, double dt, const uint8_t *masks,
+                          int n_cu, const InstRow *inst, double dt, const uint8_t *masks,
                           const double *lam_in, double *lam_out, hipStream_t s) {
   if (n_patches <= 0) return hipSuccess;
-  const int ntx = (max_mx + 59) / 60, nty = (max_my + kAdjRows - 1) / kAdjRows;
+  // rows per segment: the tallest of 32, 16, 8, 4, 2 that still gives
+  // WS_ADJ_WAVES_PER_CU wavefronts per CU (a small level is worked by many
+  // short segments)
+  const int ntx = (max_mx + 59) / 60;
+  int rows = 32;
+  while (rows > 2 && (int64_t)ntx * ((max_my + rows - 1) / rows) * n_patches <
+                         WS_ADJ_WAVES_PER_CU * (int64_t)max(n_cu, 1))
+    rows /= 2;
+  const int nty = (max_my + rows - 1) / rows;
   hipLaunchKernelGGL(adjoint_kernel, dim3((unsigned)(ntx * nty), (unsigned)n_patches), dim3(64),
-                     0, s, patches, inst, dt, masks, lam_in, lam_out, kAdjRows);
+                     0, s, patches, inst, dt, masks, lam_in, lam_out, rows);
   return hipGetLastError();
 }
 

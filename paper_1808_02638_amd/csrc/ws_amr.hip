@@ -153,12 +153,16 @@ struct GhostSrc {
     const T vn = m == 0 ? qn.P(ci, cj) : m == 1 ? qn.U(ci, cj) : qn.V(ci, cj);
     return bl * vo + al * vn;
   }
-  // All three components of fine cell (i, j): the cell's coarse position is
-  // worked out once and the 30 coarse loads are issued together.
-  __device__ void value3(int i, int j, T out[3]) const {
+  // The coarse cell holding fine cell (i, j) and the fine cell's offsets from
+  // its centre.
+  __device__ void locate(int i, int j, int &ci, int &cj, T &xi, T &eta) const {
     const double X = ci0 + (i + 0.5) / r, Y = cj0 + (j + 0.5) / r;
-    const int ci = (int)floor(X), cj = (int)floor(Y);
-    const T xi = (T)(X - (ci + 0.5)), eta = (T)(Y - (cj + 0.5));
+    ci = (int)floor(X), cj = (int)floor(Y);
+    xi = (T)(X - (ci + 0.5)), eta = (T)(Y - (cj + 0.5));
+  }
+  // The coarse cell's value at the fine time and its limited slopes, all
+  // three components (the 30 coarse loads issued together).
+  __device__ void slopes(int ci, int cj, T q0[3], T sx[3], T sy[3]) const {
     T c[3][5];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
@@ -170,11 +174,19 @@ struct GhostSrc {
     }
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      const T q0 = c[m][0];
-      const T sx = mc_slope(q0 - c[m][1], c[m][2] - q0);
-      const T sy = mc_slope(q0 - c[m][3], c[m][4] - q0);
-      out[m] = q0 + xi * sx + eta * sy;
+      q0[m] = c[m][0];
+      sx[m] = mc_slope(q0[m] - c[m][1], c[m][2] - q0[m]);
+      sy[m] = mc_slope(q0[m] - c[m][3], c[m][4] - q0[m]);
     }
+  }
+  // All three components of fine cell (i, j).
+  __device__ void value3(int i, int j, T out[3]) const {
+    int ci, cj;
+    T xi, eta, q0[3], sx[3], sy[3];
+    locate(i, j, ci, cj, xi, eta);
+    slopes(ci, cj, q0, sx, sy);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) out[m] = q0[m] + xi * sx[m] + eta * sy[m];
   }
 };
 
@@ -195,19 +207,67 @@ struct FineGhost {
   int n;
   const PatchRow *fpatch;
   const void *f_cur;
-  __device__ void value3(int i, int j, T out[3]) const {
+  // The ghost's value from a sibling holding it; false if none does.
+  __device__ bool sibling3(int i, int j, T out[3]) const {
     for (int c = 0; c < n; ++c) {
       const CfCopy k = cp[c];
       if (i >= k.i0 && i < k.i1 && j >= k.j0 && j < k.j1) {
         const View<T> s = view<T>(f_cur, fpatch[k.src]);
         out[0] = s.P(i + k.di, j + k.dj), out[1] = s.U(i + k.di, j + k.dj),
         out[2] = s.V(i + k.di, j + k.dj);
-        return;
+        return true;
       }
     }
-    G.value3(i, j, out);
+    return false;
+  }
+  __device__ void value3(int i, int j, T out[3]) const {
+    if (!sibling3(i, j, out)) G.value3(i, j, out);
   }
 };
+
+// Floor division by a positive divisor.
+__device__ inline int fdiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Every ghost cell (outside the mx x my interior) of the fine rectangle
+// [ia, ib) x [ja, jb), evaluated as FineGhost::value3 does but with one
+// thread per coarse cell: the thread loads its coarse cell's neighbourhood
+// once and evaluates the fine ghosts inside it (2r of them along a side for
+// r >= 2), each handed to sink(i, j, v).  The threads of the block stride
+// over the rectangle's coarse cells.
+template <typename T, class Sink>
+__device__ inline void ghost_region(const FineGhost<T> &F, int mx, int my, int ia, int ib,
+                                    int ja, int jb, Sink &&sink) {
+  const GhostSrc<T> &G = F.G;
+  const int r = G.r;
+  // coarse cell of fine cell i: ci0 + floor((i + 1/2)/r), exactly, as an integer
+  const int CIa = fdiv(2 * ia + 1, 2 * r), CIb = fdiv(2 * (ib - 1) + 1, 2 * r);
+  const int CJa = fdiv(2 * ja + 1, 2 * r), CJb = fdiv(2 * (jb - 1) + 1, 2 * r);
+  const int nI = CIb - CIa + 1, nJ = CJb - CJa + 1;
+  for (int k = (int)threadIdx.x; k < nI * nJ; k += (int)blockDim.x) {
+    const int I = CIa + k % nI, J = CJa + k / nI;  // relative to (ci0, cj0)
+    const int i0 = max(ia, I * r), i1 = min(ib, I * r + r);
+    const int j0 = max(ja, J * r), j1 = min(jb, J * r + r);
+    T q0[3], sx[3], sy[3];
+    bool have = false;
+    for (int j = j0; j < j1; ++j)
+      for (int i = i0; i < i1; ++i) {
+        if (i >= 0 && i < mx && j >= 0 && j < my) continue;
+        T v[3];
+        if (!F.sibling3(i, j, v)) {
+          int ci, cj;
+          T xi, eta;
+          G.locate(i, j, ci, cj, xi, eta);
+          if (!have) {
+            G.slopes(ci, cj, q0, sx, sy);
+            have = true;
+          }
+#pragma unroll
+          for (int m = 0; m < 3; ++m) v[m] = q0[m] + xi * sx[m] + eta * sy[m];
+        }
+        sink(i, j, v);
+      }
+  }
+}
 
 template <typename T>
 __device__ inline FineGhost<T> fine_ghost(const CfArgs &a, const CfPlace &pl, const PatchRow &cp,
@@ -341,34 +401,26 @@ __global__ __launch_bounds__(kThreads) void cf_fine_step_kernel(CfArgs a, int st
   const Coef<T> k = make_coef<T>(in.c, in.Z, dt_fine, fp.dx, fp.dy);
   const View<T> q = view<T>(a.f_cur, fp);
   const FineGhost<T> G = fine_ghost<T>(a, pl, cp, (double)step / r);
-  // all three components of fine cell (i, j): a ghost from a sibling or the
-  // coarse level, an interior cell from the fine state
-  auto fine3 = [&](int i, int j, T v[3]) {
-    if (i < 0 || i >= mx || j < 0 || j >= my) {
-      G.value3(i, j, v);
-    } else {
-      v[0] = q.P(i, j), v[1] = q.U(i, j), v[2] = q.V(i, j);
-    }
-  };
   if (b < 2 * nxb) {
-    // left (e = 0) or right (e = mx) side, rows j0 .. j1-1
+    // left (e = 0) or right (e = mx) side, rows j0 .. j1-1: the strip holds
+    // columns e-2 .. e+1 of rows j0-1 .. j1; the block owns the side's two
+    // ghost columns of its rows
     const bool left = b < nxb;
     const int j0 = (left ? b : b - nxb) * kStrip, j1 = min(j0 + kStrip, my);
     const int e = left ? 0 : mx;
-    // the ghosts this block owns: the side's two ghost columns of its rows
-    for (int x = t; x < 2 * (j1 - j0); x += kThreads) {
-      const int j = j0 + x / 2, i = left ? x % 2 - 2 : mx + x % 2;
-      T v[3];
-      G.value3(i, j, v);
-      for (int m = 0; m < 3; ++m) *cell_ptr<T>(a.f_cur, fp, m, i, j) = v[m];
-    }
-    const int rows = j1 - j0 + 2;  // j0-1 .. j1
+    const int rows = j1 - j0 + 2;
     for (int x = t; x < rows * 4; x += kThreads) {
       const int j = j0 - 1 + x / 4, i = e - 2 + x % 4;
-      T v[3];
-      fine3(i, j, v);
-      for (int m = 0; m < 3; ++m) strip[(m * (kStrip + 2) + (j - j0 + 1)) * 4 + (i - e + 2)] = v[m];
+      if (i >= 0 && i < mx && j >= 0 && j < my)
+        for (int m = 0; m < 3; ++m)
+          strip[(m * (kStrip + 2) + (j - j0 + 1)) * 4 + (i - e + 2)] =
+              m == 0 ? q.P(i, j) : m == 1 ? q.U(i, j) : q.V(i, j);
     }
+    ghost_region<T>(G, mx, my, e - 2, e + 2, j0 - 1, j1 + 1, [&](int i, int j, const T v[3]) {
+      for (int m = 0; m < 3; ++m) strip[(m * (kStrip + 2) + (j - j0 + 1)) * 4 + (i - e + 2)] = v[m];
+      if ((left ? i < 0 : i >= mx) && j >= j0 && j < j1)
+        for (int m = 0; m < 3; ++m) *cell_ptr<T>(a.f_cur, fp, m, i, j) = v[m];
+    });
     __syncthreads();
     const int j = j0 + t;
     if (j < j1) {
@@ -378,28 +430,32 @@ __global__ __launch_bounds__(kThreads) void cf_fine_step_kernel(CfArgs a, int st
                         a.acc + 3 * ((int64_t)pl.fedge0 + (left ? j : my + j)));
     }
   } else {
-    // bottom (f = 0) or top (f = my) side, columns i0 .. i1-1
+    // bottom (f = 0) or top (f = my) side, columns i0 .. i1-1: the strip holds
+    // rows f-2 .. f+1 of columns i0-1 .. i1; the block owns the side's two
+    // ghost rows over its columns, and the corner columns for the first and
+    // last block of the side
     b -= 2 * nxb;
     const bool bottom = b < nyb;
     const int c = bottom ? b : b - nyb;
     const int i0 = c * kStrip, i1 = min(i0 + kStrip, mx);
     const int f = bottom ? 0 : my;
-    // the ghosts this block owns: the side's two ghost rows over its columns,
-    // and the corner columns for the first and last block of the side
     const int lo = c == 0 ? -2 : i0, hi = i1 == mx ? mx + 2 : i1;
-    for (int x = t; x < 2 * (hi - lo); x += kThreads) {
-      const int i = lo + x % (hi - lo), j = bottom ? x / (hi - lo) - 2 : my + x / (hi - lo);
-      T v[3];
-      G.value3(i, j, v);
-      for (int m = 0; m < 3; ++m) *cell_ptr<T>(a.f_cur, fp, m, i, j) = v[m];
-    }
-    const int cols = i1 - i0 + 2;  // i0-1 .. i1
+    const int cols = i1 - i0 + 2;
     for (int x = t; x < cols * 4; x += kThreads) {
       const int j = f - 2 + x / cols, i = i0 - 1 + x % cols;  // consecutive columns
-      T v[3];
-      fine3(i, j, v);
-      for (int m = 0; m < 3; ++m) strip[(m * (kStrip + 2) + (i - i0 + 1)) * 4 + (j - f + 2)] = v[m];
+      if (i >= 0 && i < mx && j >= 0 && j < my)
+        for (int m = 0; m < 3; ++m)
+          strip[(m * (kStrip + 2) + (i - i0 + 1)) * 4 + (j - f + 2)] =
+              m == 0 ? q.P(i, j) : m == 1 ? q.U(i, j) : q.V(i, j);
     }
+    ghost_region<T>(G, mx, my, min(lo, i0 - 1), max(hi, i1 + 1), f - 2, f + 2,
+                    [&](int i, int j, const T v[3]) {
+      if (i >= i0 - 1 && i <= i1)
+        for (int m = 0; m < 3; ++m)
+          strip[(m * (kStrip + 2) + (i - i0 + 1)) * 4 + (j - f + 2)] = v[m];
+      if ((bottom ? j < 0 : j >= my) && i >= lo && i < hi)
+        for (int m = 0; m < 3; ++m) *cell_ptr<T>(a.f_cur, fp, m, i, j) = v[m];
+    });
     __syncthreads();
     const int i = i0 + t;
     if (i < i1) {

@@ -938,7 +938,7 @@ int ws_adjoint_step(ws_ctx *c, double dt, const void *masks_dev, const void *lam
   for (int k = 0; k < c->n_patches; ++k)
     if (!march_fits(c->rows[k].plane, WS_F64))
       return fail(WS_EINVAL, "patch %d: too large for the adjoint (32-bit offsets)", k);
-  HIPCHK(launch_adjoint(c->d_patches(), c->n_patches, c->max_mx, c->max_my,
+  HIPCHK(launch_adjoint(c->d_patches(), c->n_patches, c->max_mx, c->max_my, c->n_cu,
                         reinterpret_cast<const InstRow *>(c->ws + c->L.inst), dt,
                         reinterpret_cast<const uint8_t *>(masks_dev),
                         reinterpret_cast<const double *>(lam_in),

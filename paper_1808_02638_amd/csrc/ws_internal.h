@@ -135,7 +135,7 @@ int step_occupancy(int dtype, int limiter, int vars, int *wg_per_cu);
 // lam_out <- E^T U^T lam_in (one launch: the gather-form update transpose
 // with the extrapolation ghosts folded into the boundary cells).
 hipError_t launch_adjoint(const PatchRow *patches, int n_patches, int max_mx, int max_my,
-                          const InstRow *inst, double dt, const uint8_t *masks,
+                          int n_cu, const InstRow *inst, double dt, const uint8_t *masks,
                           const double *lam_in, double *lam_out, hipStream_t s);
 hipError_t launch_gather(const PatchRow *patches, int patch, int comp, int n, const int32_t *ij,
                          const double *buf, double *out, hipStream_t s);
