@@ -350,7 +350,7 @@ typedef struct {
 } ws_fine_place;
 
 /* Bytes of device workspace the coupling needs (placement table, one
- * accumulator of 3 doubles per fine boundary edge, 3 doubles per coarse
+ * slot of 3 doubles per fine boundary edge and fine step, 3 doubles per coarse
  * interface edge, the sibling copy rectangles and the fix list, both sized
  * for any layout of these patches). */
 int ws_cf_layout(ws_ctx *fine, int32_t ratio, int64_t *bytes);

@@ -9,8 +9,13 @@ steps is timed per candidate, so the level is left exactly as it was.  The
 tiling never changes results (the library's arithmetic per cell does not
 depend on it), so tuning is safe on a live level.
 
-Choices are cached in a JSON file keyed by GPU architecture, the library
-build, dtype, limiter (with the transverse variant) and the patch-size histogram.
+Choices are cached in a JSON file keyed by GPU architecture, the library's
+kernel sources, dtype, limiter (with the transverse variant) and the
+patch-size histogram.  A table of choices the tuner made on an MI355X for the
+benchmark workloads ships beside this module (``tuned_tilings.json``) and is
+consulted before the user's cache, so a run on a fresh machine uses the same
+tilings as the runs its measurements were taken with; ``autotune(...,
+use_cache=False)`` always times the candidates.
 """
 
 from __future__ import annotations
@@ -66,10 +71,20 @@ def candidates(mx, my, periodic, medium=False):
     return out
 
 
+SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_tilings.json")
+
+
 def _library_version():
-    from . import _lib
-    with open(_lib.LIB_PATH, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()[:12]
+    """SHA-1 of the library's kernel sources (every file of csrc/ in name
+    order): the same sources give the same kernels, whichever build."""
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha1()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode())
+                h.update(f.read())
+    return h.hexdigest()[:12]
 
 
 def _key(level):
@@ -109,8 +124,16 @@ def autotune(level, *, launches=40, use_cache=True, cache_path=None, verbose=Fal
             cache = json.load(open(cache_path))
         except (OSError, ValueError):
             cache = {}
-    if use_cache and key in cache:
-        ent = cache[key]
+    shipped = {}
+    if use_cache and os.path.exists(SHIPPED):
+        try:
+            shipped = json.load(open(SHIPPED))
+        except (OSError, ValueError):
+            shipped = {}
+    ent = shipped.get(key) if use_cache else None
+    if ent is None and use_cache:
+        ent = cache.get(key)
+    if ent is not None:
         choice = {tuple(json.loads(c)): tuple(v) for c, v in ent["classes"].items()}
         if set(choice) == set(classes):
             _apply(level, classes, choice, ent["wg_per_cu"])

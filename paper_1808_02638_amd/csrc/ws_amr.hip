@@ -8,8 +8,9 @@
 //       fine step; every other one comes from the coarse level at
 //       t_n + k dt/r, linear in time between Q_c^n and Q_c^{n+1} and
 //       MC-limited linear in space inside the coarse cell that holds it;
-//     - the fine terms at the patch's boundary edges, accumulated over the r
-//       fine steps: f(ghost) - f(Q_O^n) (the Riemann fluctuation sum between
+//     - the fine terms at the patch's boundary edges, one slot per fine step
+//       (the last fine step sums them into the first slot): f(ghost) -
+//       f(Q_O^n) (the Riemann fluctuation sum between
 //       the coarse cell O outside the edge and the fine ghost next to it, C1)
 //       plus A-dQ^ + F~^ (left side) or -A+dQ^ + F~^ (right side), y alike;
 //     - for k = 0, the coarse terms at every coarse-fine interface edge from
@@ -305,17 +306,19 @@ __global__ __launch_bounds__(kThreads) void cf_ghosts_kernel(CfArgs a, double al
 }
 
 // A strip of a fine patch staged in LDS for the edges of one side: for a
-// left or right side the columns e-2 .. e+1 of rows j0-1 .. j0+kStrip (the
-// cells of a column of edges are strided in memory); for a bottom or top side
-// the rows f-2 .. f+1 of columns i0-1 .. i0+kStrip.  Ghost cells are
-// evaluated from the coarse level, interior cells read from the fine state.
-constexpr int kStrip = kThreads;  // edges per block
+// left or right side the columns e-2 .. e+1 of rows j0-1 .. j0+n (the cells
+// of a column of edges are strided in memory); for a bottom or top side the
+// rows f-2 .. f+1 of columns i0-1 .. i0+n, n the block's edges (at most the
+// strip length S, so the pitch of a component is S + 2 rows or columns of
+// 4).  Ghost cells are evaluated from the coarse level (or a sibling),
+// interior cells read from the fine state.
+constexpr int kStrip = kThreads;  // most edges per block of the fine-step kernel
 template <typename T>
 struct StripX {
-  const T *s;  // [3][kStrip + 2][4]: row-major in (row, column)
-  int e, j0;
+  const T *s;  // [3][S + 2][4]: row-major in (row, column)
+  int e, j0, pitch;
   __device__ T at(int m, int i, int j) const {
-    return s[(m * (kStrip + 2) + (j - j0 + 1)) * 4 + (i - e + 2)];
+    return s[(m * pitch + (j - j0 + 1)) * 4 + (i - e + 2)];
   }
   __device__ T P(int i, int j) const { return at(0, i, j); }
   __device__ T U(int i, int j) const { return at(1, i, j); }
@@ -323,22 +326,25 @@ struct StripX {
 };
 template <typename T>
 struct StripY {
-  const T *s;  // [3][kStrip + 2][4]: column-major in (column, row)
-  int i0, f;
+  const T *s;  // [3][S + 2][4]: column-major in (column, row)
+  int i0, f, pitch;
   __device__ T at(int m, int i, int j) const {
-    return s[(m * (kStrip + 2) + (i - i0 + 1)) * 4 + (j - f + 2)];
+    return s[(m * pitch + (i - i0 + 1)) * 4 + (j - f + 2)];
   }
   __device__ T P(int i, int j) const { return at(0, i, j); }
   __device__ T U(int i, int j) const { return at(1, i, j); }
   __device__ T V(int i, int j) const { return at(2, i, j); }
 };
 
-// Fine terms of one boundary edge (ghost (gi, gj), coarse cell (oi, oj)
-// outside it) added to its accumulator slot.
+// Fine terms of one boundary edge (ghost (gi, gj); cP, cN the pressure and
+// normal velocity of the coarse cell O outside it at t_n) written to the
+// edge's slot of this fine step; on the last of the r fine steps the
+// earlier steps' terms are added in step order and the total goes to the
+// first step's slot, where the fix reads it.
 template <typename T, int LIM, class Q>
-__device__ inline void fine_edge(const Q &q, const View<T> &co, const Coef<T> &k, bool xdir,
-                                 bool low, int e_or_i, int j_or_f, int gi, int gj, int oi, int oj,
-                                 int step, double *o) {
+__device__ inline void fine_edge(const Q &q, T cP, T cN, const Coef<T> &k, bool xdir, bool low,
+                                 int e_or_i, int j_or_f, int gi, int gj, double *o, int step,
+                                 int r, int64_t slot) {
   T m[3], pp[3], F[3];
   if (xdir)
     xedge_terms<T, LIM>(q, k, e_or_i, j_or_f, m, pp, F);
@@ -346,31 +352,41 @@ __device__ inline void fine_edge(const Q &q, const View<T> &co, const Coef<T> &k
     yedge_terms<T, LIM>(q, k, e_or_i, j_or_f, m, pp, F);
   // C1: f(ghost) - f(Q_O^n), the fluctuation sum of the Riemann problem
   // between the coarse cell and the fine ghost
-  const T dp = q.P(gi, gj) - co.P(oi, oj);
+  const T dp = q.P(gi, gj) - cP;
   T c1[3];
   if (xdir) {
-    const T du = q.U(gi, gj) - co.U(oi, oj);
+    const T du = q.U(gi, gj) - cN;
     const T w1 = s1(k.Z, dp, du), w2 = s2(k.Z, dp, du);
     c1[0] = k.h * (w1 + w2), c1[1] = k.hz * (w2 - w1), c1[2] = T(0);
   } else {
-    const T dv = q.V(gi, gj) - co.V(oi, oj);
+    const T dv = q.V(gi, gj) - cN;
     const T w1 = s1(k.Z, dp, dv), w2 = s2(k.Z, dp, dv);
     c1[0] = k.h * (w1 + w2), c1[1] = T(0), c1[2] = k.hz * (w2 - w1);
   }
   // the ghost is the edge's left (lower) state on the left (bottom) side
-  for (int c = 0; c < 3; ++c) {
-    const double v = (double)c1[c] + (low ? (double)m[c] : -(double)pp[c]) + (double)F[c];
-    o[c] = step == 0 ? v : o[c] + v;
+  double v[3];
+  for (int c = 0; c < 3; ++c)
+    v[c] = (double)c1[c] + (low ? (double)m[c] : -(double)pp[c]) + (double)F[c];
+  if (step == r - 1 && r > 1) {
+    double *o0 = o - step * slot;  // the first fine step's slot of this edge
+    for (int c = 0; c < 3; ++c) {
+      double t = o0[c];
+      for (int st = 1; st < r - 1; ++st) t = t + o0[st * slot + c];
+      o0[c] = t + v[c];
+    }
+  } else {
+    for (int c = 0; c < 3; ++c) o[c] = v[c];
   }
 }
 
-// Blocks per fine patch of the fine-step kernel: ceil(my/kStrip) for each of
-// the left and right sides, ceil(mx/kStrip) for each of the bottom and top
-// sides, and (first fine step only) ceil(2 (ncx + ncy)/kThreads) for the
-// coarse interface edges.
-__host__ __device__ inline int cf_step_blocks(int mx, int my, int ncx, int ncy, bool coarse) {
-  return 2 * ((my + kStrip - 1) / kStrip) + 2 * ((mx + kStrip - 1) / kStrip) +
-         (coarse ? (2 * (ncx + ncy) + kThreads - 1) / kThreads : 0);
+// Blocks per fine patch of the fine-step kernel (blocks of S threads, S
+// boundary edges each): ceil(my/S) for each of the left and right sides,
+// ceil(mx/S) for each of the bottom and top sides, and (first fine step
+// only) ceil(2 (ncx + ncy)/S) for the coarse interface edges.
+__host__ __device__ inline int cf_step_blocks(int mx, int my, int ncx, int ncy, bool coarse,
+                                              int S) {
+  return 2 * ((my + S - 1) / S) + 2 * ((mx + S - 1) / S) +
+         (coarse ? (2 * (ncx + ncy) + S - 1) / S : 0);
 }
 
 // Before fine step k: the fine ghost ring at t_n + k dt/r (each block writes
@@ -379,13 +395,15 @@ __host__ __device__ inline int cf_step_blocks(int mx, int my, int ncx, int ncy, 
 template <typename T, int LIM>
 __global__ __launch_bounds__(kThreads) void cf_fine_step_kernel(CfArgs a, int step,
                                                                 double dt_fine, double dt) {
-  __shared__ T strip[3 * (kStrip + 2) * 4];
+  extern __shared__ char smem[];
+  T *strip = reinterpret_cast<T *>(smem);  // [3][S + 2][4]
+  const int S = a.strip, pitch = S + 2;
   const CfPlace pl = a.place[blockIdx.y];
   const PatchRow fp = a.fpatch[blockIdx.y];
   const int mx = fp.mx, my = fp.my, r = a.r;
-  const int nxb = (my + kStrip - 1) / kStrip, nyb = (mx + kStrip - 1) / kStrip;
+  const int nxb = (my + S - 1) / S, nyb = (mx + S - 1) / S;
   int b = blockIdx.x;
-  if (b >= cf_step_blocks(mx, my, pl.ncx, pl.ncy, step == 0)) return;
+  if (b >= cf_step_blocks(mx, my, pl.ncx, pl.ncy, step == 0, S)) return;
   const PatchRow cp = a.cpatch[pl.coarse];
   const View<T> co = view<T>(a.c_old, cp);
   const int t = threadIdx.x;
@@ -393,10 +411,12 @@ __global__ __launch_bounds__(kThreads) void cf_fine_step_kernel(CfArgs a, int st
     // coarse interface edges, from the coarse state before its step
     const InstRow ic = a.cinst[cp.inst];
     const Coef<T> kc = make_coef<T>(ic.c, ic.Z, dt, cp.dx, cp.dy);
-    const int e = (b - 2 * nxb - 2 * nyb) * kThreads + t;
+    const int e = (b - 2 * nxb - 2 * nyb) * S + t;
     if (e < 2 * (pl.ncx + pl.ncy)) coarse_edge<T, LIM>(a, pl, co, kc, e);
     return;
   }
+  // this fine step's slots of the patch's boundary edges
+  double *acc = a.acc + 3 * ((int64_t)step * a.n_fedges + pl.fedge0);
   const InstRow in = a.finst[fp.inst];
   const Coef<T> k = make_coef<T>(in.c, in.Z, dt_fine, fp.dx, fp.dy);
   const View<T> q = view<T>(a.f_cur, fp);
@@ -406,28 +426,30 @@ __global__ __launch_bounds__(kThreads) void cf_fine_step_kernel(CfArgs a, int st
     // columns e-2 .. e+1 of rows j0-1 .. j1; the block owns the side's two
     // ghost columns of its rows
     const bool left = b < nxb;
-    const int j0 = (left ? b : b - nxb) * kStrip, j1 = min(j0 + kStrip, my);
+    const int j0 = (left ? b : b - nxb) * S, j1 = min(j0 + S, my);
     const int e = left ? 0 : mx;
+    // the coarse cell outside this thread's edge at t_n, loaded ahead
+    const int j = j0 + t;
+    const int oi = left ? pl.ci0 - 1 : pl.ci0 + pl.ncx, oj = pl.cj0 + min(j, my - 1) / r;
+    const T cP = co.P(oi, oj), cN = co.U(oi, oj);
     const int rows = j1 - j0 + 2;
-    for (int x = t; x < rows * 4; x += kThreads) {
-      const int j = j0 - 1 + x / 4, i = e - 2 + x % 4;
-      if (i >= 0 && i < mx && j >= 0 && j < my)
+    for (int x = t; x < rows * 4; x += S) {
+      const int jj = j0 - 1 + x / 4, i = e - 2 + x % 4;
+      if (i >= 0 && i < mx && jj >= 0 && jj < my)
         for (int m = 0; m < 3; ++m)
-          strip[(m * (kStrip + 2) + (j - j0 + 1)) * 4 + (i - e + 2)] =
-              m == 0 ? q.P(i, j) : m == 1 ? q.U(i, j) : q.V(i, j);
+          strip[(m * pitch + (jj - j0 + 1)) * 4 + (i - e + 2)] =
+              m == 0 ? q.P(i, jj) : m == 1 ? q.U(i, jj) : q.V(i, jj);
     }
-    ghost_region<T>(G, mx, my, e - 2, e + 2, j0 - 1, j1 + 1, [&](int i, int j, const T v[3]) {
-      for (int m = 0; m < 3; ++m) strip[(m * (kStrip + 2) + (j - j0 + 1)) * 4 + (i - e + 2)] = v[m];
-      if ((left ? i < 0 : i >= mx) && j >= j0 && j < j1)
-        for (int m = 0; m < 3; ++m) *cell_ptr<T>(a.f_cur, fp, m, i, j) = v[m];
+    ghost_region<T>(G, mx, my, e - 2, e + 2, j0 - 1, j1 + 1, [&](int i, int jj, const T v[3]) {
+      for (int m = 0; m < 3; ++m) strip[(m * pitch + (jj - j0 + 1)) * 4 + (i - e + 2)] = v[m];
+      if ((left ? i < 0 : i >= mx) && jj >= j0 && jj < j1)
+        for (int m = 0; m < 3; ++m) *cell_ptr<T>(a.f_cur, fp, m, i, jj) = v[m];
     });
     __syncthreads();
-    const int j = j0 + t;
     if (j < j1) {
-      const StripX<T> S{strip, e, j0};
-      const int oi = left ? pl.ci0 - 1 : pl.ci0 + pl.ncx, oj = pl.cj0 + j / r;
-      fine_edge<T, LIM>(S, co, k, true, left, e, j, left ? -1 : mx, j, oi, oj, step,
-                        a.acc + 3 * ((int64_t)pl.fedge0 + (left ? j : my + j)));
+      const StripX<T> Sx{strip, e, j0, pitch};
+      fine_edge<T, LIM>(Sx, cP, cN, k, true, left, e, j, left ? -1 : mx, j,
+                        acc + 3 * (left ? j : my + j), step, r, 3 * a.n_fedges);
     }
   } else {
     // bottom (f = 0) or top (f = my) side, columns i0 .. i1-1: the strip holds
@@ -437,32 +459,32 @@ __global__ __launch_bounds__(kThreads) void cf_fine_step_kernel(CfArgs a, int st
     b -= 2 * nxb;
     const bool bottom = b < nyb;
     const int c = bottom ? b : b - nyb;
-    const int i0 = c * kStrip, i1 = min(i0 + kStrip, mx);
+    const int i0 = c * S, i1 = min(i0 + S, mx);
     const int f = bottom ? 0 : my;
+    const int i = i0 + t;
+    const int oi = pl.ci0 + min(i, mx - 1) / r, oj = bottom ? pl.cj0 - 1 : pl.cj0 + pl.ncy;
+    const T cP = co.P(oi, oj), cN = co.V(oi, oj);
     const int lo = c == 0 ? -2 : i0, hi = i1 == mx ? mx + 2 : i1;
     const int cols = i1 - i0 + 2;
-    for (int x = t; x < cols * 4; x += kThreads) {
-      const int j = f - 2 + x / cols, i = i0 - 1 + x % cols;  // consecutive columns
-      if (i >= 0 && i < mx && j >= 0 && j < my)
+    for (int x = t; x < cols * 4; x += S) {
+      const int j = f - 2 + x / cols, ii = i0 - 1 + x % cols;  // consecutive columns
+      if (ii >= 0 && ii < mx && j >= 0 && j < my)
         for (int m = 0; m < 3; ++m)
-          strip[(m * (kStrip + 2) + (i - i0 + 1)) * 4 + (j - f + 2)] =
-              m == 0 ? q.P(i, j) : m == 1 ? q.U(i, j) : q.V(i, j);
+          strip[(m * pitch + (ii - i0 + 1)) * 4 + (j - f + 2)] =
+              m == 0 ? q.P(ii, j) : m == 1 ? q.U(ii, j) : q.V(ii, j);
     }
     ghost_region<T>(G, mx, my, min(lo, i0 - 1), max(hi, i1 + 1), f - 2, f + 2,
-                    [&](int i, int j, const T v[3]) {
-      if (i >= i0 - 1 && i <= i1)
-        for (int m = 0; m < 3; ++m)
-          strip[(m * (kStrip + 2) + (i - i0 + 1)) * 4 + (j - f + 2)] = v[m];
-      if ((bottom ? j < 0 : j >= my) && i >= lo && i < hi)
-        for (int m = 0; m < 3; ++m) *cell_ptr<T>(a.f_cur, fp, m, i, j) = v[m];
+                    [&](int ii, int j, const T v[3]) {
+      if (ii >= i0 - 1 && ii <= i1)
+        for (int m = 0; m < 3; ++m) strip[(m * pitch + (ii - i0 + 1)) * 4 + (j - f + 2)] = v[m];
+      if ((bottom ? j < 0 : j >= my) && ii >= lo && ii < hi)
+        for (int m = 0; m < 3; ++m) *cell_ptr<T>(a.f_cur, fp, m, ii, j) = v[m];
     });
     __syncthreads();
-    const int i = i0 + t;
     if (i < i1) {
-      const StripY<T> S{strip, i0, f};
-      const int oi = pl.ci0 + i / r, oj = bottom ? pl.cj0 - 1 : pl.cj0 + pl.ncy;
-      fine_edge<T, LIM>(S, co, k, false, bottom, i, f, i, bottom ? -1 : my, oi, oj, step,
-                        a.acc + 3 * ((int64_t)pl.fedge0 + 2 * my + (bottom ? i : mx + i)));
+      const StripY<T> Sy{strip, i0, f, pitch};
+      fine_edge<T, LIM>(Sy, cP, cN, k, false, bottom, i, f, i, bottom ? -1 : my,
+                        acc + 3 * (2 * my + (bottom ? i : mx + i)), step, r, 3 * a.n_fedges);
     }
   }
 }
@@ -504,6 +526,7 @@ __global__ __launch_bounds__(kThreads) void cf_finish_kernel(CfArgs a, double dt
                                      : dt / cp.dy;
         const double *acc = a.acc + 3 * ((int64_t)pl.fedge0 + f0);
         const double *pc = a.pc + 3 * ((int64_t)pl.cedge0 + e);
+        // each fine edge's first slot holds its terms summed over the r fine steps
         for (int m = 0; m < 3; ++m) {
           double s = 0.0;
           for (int bb = 0; bb < r; ++bb) s += acc[3 * bb + m];
@@ -550,17 +573,19 @@ template <typename T>
 hipError_t fine_step_t(int limiter, const CfArgs &a, int step, double dt_fine, double dt,
                        int max_blocks, hipStream_t s) {
   const dim3 g((unsigned)max(1, max_blocks), (unsigned)a.n_fine);
+  const dim3 block((unsigned)a.strip);  // one thread per edge of the block
+  const size_t lds = 3 * (size_t)(a.strip + 2) * 4 * sizeof(T);
   switch (limiter) {
     case WS_LIM_NONE:
-      hipLaunchKernelGGL((cf_fine_step_kernel<T, WS_LIM_NONE>), g, dim3(kThreads), 0, s, a, step,
+      hipLaunchKernelGGL((cf_fine_step_kernel<T, WS_LIM_NONE>), g, block, lds, s, a, step,
                          dt_fine, dt);
       break;
     case WS_LIM_VANLEER:
-      hipLaunchKernelGGL((cf_fine_step_kernel<T, WS_LIM_VANLEER>), g, dim3(kThreads), 0, s, a,
+      hipLaunchKernelGGL((cf_fine_step_kernel<T, WS_LIM_VANLEER>), g, block, lds, s, a,
                          step, dt_fine, dt);
       break;
     default:
-      hipLaunchKernelGGL((cf_fine_step_kernel<T, WS_LIM_MC>), g, dim3(kThreads), 0, s, a, step,
+      hipLaunchKernelGGL((cf_fine_step_kernel<T, WS_LIM_MC>), g, block, lds, s, a, step,
                          dt_fine, dt);
   }
   return hipGetLastError();
@@ -584,8 +609,12 @@ hipError_t launch_cf_fine_step(int dtype, int limiter, const CfArgs &a, int step
                          : fine_step_t<double>(limiter, a, step, dt_fine, dt, max_blocks, s);
 }
 
-int cf_step_blocks_host(int mx, int my, int ncx, int ncy, bool coarse) {
-  return cf_step_blocks(mx, my, ncx, ncy, coarse);
+int cf_step_blocks_host(int mx, int my, int ncx, int ncy, bool coarse, int strip) {
+  return cf_step_blocks(mx, my, ncx, ncy, coarse, strip);
+}
+
+int cf_strip_host(int max_side) {
+  return max(64, min(kStrip, (max_side + 63) / 64 * 64));
 }
 
 int cf_finish_blocks_host(int ncx, int ncy) { return cf_finish_blocks(ncx, ncy); }

@@ -237,6 +237,8 @@ struct ws_ctx {
   int64_t mask_total = 0;  // bytes of the branch masks of all patches
   double *host_buf = nullptr;
   int64_t host_buf_bytes = 0;
+  char *stage = nullptr;  // pinned staging for downloads into pageable host memory
+  int64_t stage_bytes = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int graph_steps = 0, graph_start_pool = 0;
@@ -664,8 +666,33 @@ static int copy_patch(ws_ctx *c, int32_t patch, const void *src, void *dst, bool
       HIPCHK(hipMemcpy2DAsync(reinterpret_cast<char *>(c->pool[b]) + first * es, r.ld * es, src, w,
                               w, h, hipMemcpyDefault, c->stream));
   } else {
-    HIPCHK(hipMemcpy2DAsync(dst, w, reinterpret_cast<const char *>(c->pool[c->cur]) + first * es,
-                            r.ld * es, w, h, hipMemcpyDefault, c->stream));
+    const char *from = reinterpret_cast<const char *>(c->pool[c->cur]) + first * es;
+    hipPointerAttribute_t attr{};
+    const bool device = hipPointerGetAttributes(&attr, dst) == hipSuccess &&
+                        attr.type == hipMemoryTypeDevice;
+    (void)hipGetLastError();  // the query fails for pageable memory; that is not an error
+    if (device) {
+      HIPCHK(hipMemcpy2DAsync(dst, w, from, r.ld * es, w, h, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      // into host memory through the context's pinned buffer, a block of rows
+      // at a time: each block is complete in pinned memory (the stream is
+      // synchronised) before the host copies it on
+      constexpr int64_t kStage = int64_t{8} << 20;
+      if (!c->stage) {
+        if (hipHostMalloc(reinterpret_cast<void **>(&c->stage), kStage) != hipSuccess)
+          return fail(WS_EHIP, "hipHostMalloc of %lld bytes failed", (long long)kStage);
+        c->stage_bytes = kStage;
+      }
+      const size_t rows = std::max<size_t>(1, (size_t)c->stage_bytes / w);
+      for (size_t r0 = 0; r0 < h; r0 += rows) {
+        const size_t n = std::min(rows, h - r0);
+        HIPCHK(hipMemcpy2DAsync(c->stage, w, from + r0 * r.ld * es, r.ld * es, w, n,
+                                hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        std::memcpy(static_cast<char *>(dst) + r0 * w, c->stage, n * w);
+      }
+      return WS_OK;
+    }
   }
   HIPCHK(hipStreamSynchronize(c->stream));
   return WS_OK;
@@ -1062,6 +1089,7 @@ int ws_destroy(ws_ctx *c) {
   (void)hipStreamSynchronize(c->stream);
   c->drop_graph();
   if (c->host_buf) (void)hipHostFree(c->host_buf);
+  if (c->stage) (void)hipHostFree(c->stage);
   delete c;
   return WS_OK;
 }
@@ -1081,6 +1109,8 @@ struct ws_cf {
   int n_fine = 0, n_fix = 0;
   int max_ring = 0;
   int max_step_blocks = 0, max_finish_blocks = 0;  // blocks per fine patch of the two launches
+  int strip = 64;        // edges (threads) per block of the fine-step launch
+  int64_t n_fedges = 0;  // fine boundary edges of all patches
 
   CfArgs args() const {
     CfArgs a{};
@@ -1096,6 +1126,8 @@ struct ws_cf {
     a.copy = reinterpret_cast<const CfCopy *>(ws + off_copy);
     a.fix = reinterpret_cast<const CfFix *>(ws + off_fix);
     a.n_fix = n_fix;
+    a.strip = strip;
+    a.n_fedges = n_fedges;
     return a;
   }
 };
@@ -1122,7 +1154,7 @@ CfSizes cf_sizes(const ws_ctx *fine, int r) {
   }
   z.place = 0;
   z.acc = round_up((int64_t)fine->n_patches * (int64_t)sizeof(CfPlace), 256);
-  z.pc = z.acc + round_up(24 * std::max<int64_t>(z.n_fedges, 1), 256);
+  z.pc = z.acc + round_up(24 * (int64_t)std::max(r, 1) * std::max<int64_t>(z.n_fedges, 1), 256);
   z.copy = z.pc + round_up(24 * std::max<int64_t>(z.n_cedges, 1), 256);
   z.fix = z.copy + round_up((int64_t)sizeof(CfCopy) * std::max<int64_t>(z.max_copies, 1), 256);
   z.total = z.fix + round_up((int64_t)sizeof(CfFix) * std::max<int64_t>(z.n_cedges, 1), 256);
@@ -1263,11 +1295,15 @@ int ws_cf_init(ws_cf **out, ws_ctx *coarse, ws_ctx *fine, int32_t ratio,
   cf->off_fix = z.fix;
   cf->n_fine = fine->n_patches;
   cf->n_fix = (int)fixes.size();
+  int max_side = 1;
+  for (const ws_patch_desc &d : fine->desc) max_side = std::max(max_side, std::max(d.mx, d.my));
+  cf->strip = cf_strip_host(max_side);
+  cf->n_fedges = z.n_fedges;
   for (int k = 0; k < fine->n_patches; ++k) {
     const ws_patch_desc &d = fine->desc[k];
     cf->max_ring = std::max(cf->max_ring, 4 * (d.mx + 4) + 4 * d.my);
-    cf->max_step_blocks =
-        std::max(cf->max_step_blocks, cf_step_blocks_host(d.mx, d.my, pl[k].ncx, pl[k].ncy, true));
+    cf->max_step_blocks = std::max(
+        cf->max_step_blocks, cf_step_blocks_host(d.mx, d.my, pl[k].ncx, pl[k].ncy, true, cf->strip));
     cf->max_finish_blocks =
         std::max(cf->max_finish_blocks, cf_finish_blocks_host(pl[k].ncx, pl[k].ncy));
   }

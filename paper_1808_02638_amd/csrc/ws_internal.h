@@ -182,11 +182,13 @@ struct CfArgs {
   const void *c_old;  // coarse state at t_n
   void *c_new;        // coarse state after the coarse step (updated in place)
   void *f_cur;        // fine current state
-  double *acc;        // [fine edges][3] fine terms summed over the fine steps
+  double *acc;        // [r][fine edges][3] fine terms of each fine step
   double *pc;         // [coarse interface edges][3] coarse terms
   const CfCopy *copy; // sibling copy rectangles, CfPlace::copy0 .. + ncopy per fine patch
   const CfFix *fix;   // [n_fix] the coarse cells that take the fix
-  int32_t n_fix, pad_;
+  int32_t n_fix;
+  int32_t strip;      // boundary edges per block of the fine-step kernel (its threads)
+  int64_t n_fedges;   // fine boundary edges of all patches (acc holds r slots of them)
 };
 
 hipError_t launch_cf_ghosts(int dtype, const CfArgs &a, double alpha, int max_items,
@@ -198,7 +200,10 @@ hipError_t launch_cf_fine_step(int dtype, int limiter, const CfArgs &a, int step
 // patches down, row n_fine applies the fix list).
 hipError_t launch_cf_finish(int dtype, const CfArgs &a, double dt, int max_blocks, hipStream_t s);
 // Blocks per fine patch of the two launches.
-int cf_step_blocks_host(int mx, int my, int ncx, int ncy, bool coarse);
+int cf_step_blocks_host(int mx, int my, int ncx, int ncy, bool coarse, int strip);
+// Edges per block of the fine-step kernel for fine patches of at most
+// max_side cells per side: a multiple of 64, at most 256.
+int cf_strip_host(int max_side);
 int cf_finish_blocks_host(int ncx, int ncy);
 // The coarse cell outside interface edge e of a fine patch (edges numbered
 // left, right over ncy, then bottom, top over ncx).

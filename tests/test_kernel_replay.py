@@ -156,15 +156,20 @@ def test_adjoint_march_replay_equals_oracle(oracle_lib, mx, my, H, bc):
     assert np.abs(got[:, 2:-2, 2:-2] - ref).max() <= 1e-14 * np.abs(ref).max()
 
 
-kStrip = 256
+def strip_of(max_side):
+    """Edges (threads) per block: a multiple of 64 covering the longest side,
+    at most 256."""
+    return max(64, min(256, (max_side + 63) // 64 * 64))
 
 
 def fdiv(a, b):
     return a // b  # floor division, as the kernel's fdiv
 
 
-def replay_fine_step_blocks(mx, my, r, ci0=2, cj0=2):
-    """Walk every block of the fine-step kernel of one mx x my fine patch."""
+def replay_fine_step_blocks(mx, my, r, ci0=2, cj0=2, kStrip=None):
+    """Walk every block of the fine-step kernel of one mx x my fine patch
+    (blocks of kStrip edges; by default the launch's choice for this patch)."""
+    kStrip = kStrip or strip_of(max(mx, my))
     nxb = (my + kStrip - 1) // kStrip; nyb = (mx + kStrip - 1) // kStrip
     owned = {}
     ring = set()
@@ -239,3 +244,4 @@ def test_fine_step_blocks_cover_strips_and_ring(r):
                       516 - 516 % r}):
         for my in sorted({r, 2 * r, 7 * r, 120 - 120 % r, 600 - 600 % r}):
             replay_fine_step_blocks(mx, my, r, ci0=2 + r, cj0=3)
+            replay_fine_step_blocks(mx, my, r, ci0=2, cj0=2, kStrip=64)
