@@ -349,7 +349,10 @@ def run_ensemble(ws, torch, steps, tune=True):
     _dt, cfl_last, _ = lev.read_dt_cfl()
     var, _tw, _th, wg, grid = lev.get_tiling()
     lev.close()
+    nbytes = algorithmic_bytes([(e.mx, e.my) for e in insts], 8, True)
     return {"instances": len(insts), "cells": cells, "steps": steps,
+            "bytes_per_step": nbytes,
+            "frac": round(nbytes / (graph_ms / steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "graph_gcells": round(cells * steps / graph_ms / 1e6, 3),
             "eager_gcells": round(cells * steps / eager_ms / 1e6, 3),
             "graph_us_per_step": round(graph_ms * 1e3 / steps, 2),
