@@ -256,13 +256,17 @@ def run_amr(ws, torch, dtype, level_steps, tune=True):
         for k, p in enumerate(specs):
             lev.upload(k, workloads.padded_state(p.mx, p.my, p.xlo, p.ylo, p.dx, p.dy))
         lev.set_dt([0.9 * specs[0].dx / C_SOUND])
+        # the per-patch baseline: one launch per patch of the library's
+        # default tiles (a PACKED tile holds several patches, so per-patch
+        # launches take the default tiling)
+        lev.time_step_kernel(2, per_patch=True)
+        ms_p = lev.time_step_kernel(level_steps, per_patch=True)
         if tune:
             from paper_1808_02638_amd.autotune import autotune
             autotune(lev)
         lev.time_step_kernel(2)
-        lev.time_step_kernel(2, per_patch=True)
         ms_br = lev.time_step_kernel(level_steps)
-        ms_p = lev.time_step_kernel(level_steps, per_patch=True)
+        tuned_vars = sorted(set(lev.get_tiling()[0]))
         # the batched level steps as one captured graph (level_steps launches,
         # the Courant number filed inside each), so no per-launch event pair
         # or host call enters the time; the per-patch baseline is one launch
@@ -292,6 +296,7 @@ def run_amr(ws, torch, dtype, level_steps, tune=True):
                                   batched_us=round(ms_b * 1e3, 2),
                                   batched_bracketed_us=round(ms_br * 1e3, 2),
                                   frac=round(nbytes / (ms_b / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                  tile_variants=tuned_vars,
                                   per_patch_gcells=round(cells / ms_p / 1e6, 3)))
         lev.close()
     out["batched_gcells"] = tot_cells / tb / 1e6
@@ -556,12 +561,12 @@ def run_three_level(ws, torch, steps=10, warmup=2, r=4, n=512, tune=True):
             "frac": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "finite": finite}
 
 
-STEP_KERNEL_SOURCES = ("ws_kernels.hip", "ws_device.h", "ws_internal.h")
+STEP_KERNEL_SOURCES = ("ws_kernels.hip", "ws_device.h", "ws_internal.h", "ws_tables.h")
 
 
 def step_kernel_sha1():
-    """SHA-1 of the step kernel's sources (the kernel file and the two headers
-    it includes from the library), in that order."""
+    """SHA-1 of the step kernel's sources (the kernel file and the three
+    headers it includes from the library), in that order."""
     import hashlib
 
     h = hashlib.sha1()

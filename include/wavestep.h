@@ -109,7 +109,8 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
                     void *hip_stream);
 
 /* Tiling per patch (arrays of n_patches; all NULL keeps the defaults) and
- * workgroups per CU of the persistent launch (0 keeps the default).  Every
+ * workgroups per CU of the persistent launch (0: the default, as many as fit
+ * on a CU at the kernel's occupancy).  Every
  * tile is worked by one workgroup of 256 threads.
  *   variant WS_TILE_DIRECT: tile_w x tile_h cells, tile_w in {8,16,...,256},
  *     one thread per column computing each cell from its 13-point footprint;
@@ -117,13 +118,22 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
  *     lanes stacked vertically; each segment updates 60 columns and tile_h/4
  *     rows, carrying y-terms up the column in registers and exchanging
  *     x-terms between neighbouring lanes.  Patches of more than 2^31 bytes
- *     (three planes) take DIRECT tiles only.
+ *     (three planes) take DIRECT tiles only;
+ *   variant WS_TILE_PACKED: tile_w = 64; the MARCH sweep with one
+ *     wavefront's 64 lanes shared by column blocks of several narrow patches
+ *     (each block of at most 60 columns takes its width plus four halo
+ *     lanes).  The patch is cut into row segments of tile_h/4 rows (4 to
+ *     64); blocks over the same rows of patches with the same instance, dx
+ *     and dy share wavefronts, four wavefronts to a tile.  For patches with
+ *     frozen ghosts (WS_BC_NONE) in pools under 2^31 bytes; a level with
+ *     PACKED tiles refuses ws_step_level_per_patch, per-patch timing and
+ *     ws_step_record_masks.
  * tile_h must be a multiple of 256/tile_w with at most 64 rows per thread
- * (DIRECT) or per segment (MARCH).
+ * (DIRECT) or per segment (MARCH, PACKED).
  * Periodic patches take DIRECT tiles only.
  * variant may be NULL (all DIRECT).  Results do not depend on the tiling
  * (bitwise).  Invalidates a captured graph. */
-enum { WS_TILE_DIRECT = 0, WS_TILE_MARCH = 1 };
+enum { WS_TILE_DIRECT = 0, WS_TILE_MARCH = 1, WS_TILE_PACKED = 2 };
 
 /* The tiling in use: per patch variant, tile_w, tile_h (arrays of n_patches,
  * each may be NULL) and the persistent launch's workgroups per CU and grid

@@ -18,7 +18,7 @@ WS_F64, WS_F32 = 0, 1
 WS_LIM_MC, WS_LIM_NONE, WS_LIM_VANLEER = 0, 1, 2
 WS_TRANSVERSE_CORR = 0x100
 WS_BC_NONE, WS_BC_EXTRAP, WS_BC_PERIODIC = 0, 1, 2
-WS_TILE_DIRECT, WS_TILE_MARCH = 0, 1
+WS_TILE_DIRECT, WS_TILE_MARCH, WS_TILE_PACKED = 0, 1, 2
 
 #: every symbol the header declares
 EXPORTS = (

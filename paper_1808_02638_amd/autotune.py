@@ -28,9 +28,11 @@ from collections import defaultdict
 import numpy as np
 import torch
 
-DIRECT, MARCH = "direct", "march"
+from ._lib import WaveStepError
+
+DIRECT, MARCH, PACKED = "direct", "march", "packed"
 _BUCKETS = (0, 12, 24, 40, 72, 136, 264, 1 << 30)
-_WG_CHOICES = (0, 1, 2, 3, 4, 6, 8)
+_WG_CHOICES = (0, 1, 2, 3, 4, 6, 8, 12, 16, 32)
 
 
 def _bucket(n):
@@ -41,18 +43,18 @@ def _bucket(n):
 
 
 def size_classes(level):
-    """Patch indices grouped by (x bucket, y bucket, periodic)."""
+    """Patch indices grouped by (x bucket, y bucket, periodic, frozen ghosts)."""
     cls = defaultdict(list)
     for k, (mx, my) in enumerate(level.shapes):
-        cls[(_bucket(mx), _bucket(my), level.bcs[k] == "periodic")].append(k)
+        cls[(_bucket(mx), _bucket(my), level.bcs[k] == "periodic", level.bcs[k] is None)].append(k)
     return dict(cls)
 
 
-def candidates(mx, my, periodic, medium=False):
+def candidates(mx, my, periodic, medium=False, frozen=False):
     """Tilings worth timing for patches of about mx x my cells (DIRECT only when
-    ``periodic``: periodic patches and heterogeneous media).  A heterogeneous
-    medium's DIRECT threads march up their column, so taller runs of rows per
-    thread are tried too."""
+    ``periodic``: periodic patches and heterogeneous media; PACKED for patches
+    with frozen ghosts).  A heterogeneous medium's DIRECT threads march up
+    their column, so taller runs of rows per thread are tried too."""
     out = []
     rows = (1, 2, 4, 8, 16, 32, 64) if medium else (1, 2, 4, 8)
     for tw in (8, 16, 32, 64, 128):
@@ -68,6 +70,11 @@ def candidates(mx, my, periodic, medium=False):
             if 4 * r > 2 * my and r > 4:
                 continue
             out.append((MARCH, 64, 4 * r))
+        if frozen:
+            for r in (4, 8, 12, 16, 24, 32, 48, 64):  # rows per wavefront
+                if 4 * r > 2 * my and r > 4:
+                    continue
+                out.append((PACKED, 64, 4 * r))
     return out
 
 
@@ -164,19 +171,47 @@ def autotune(level, *, launches=40, use_cache=True, cache_path=None, verbose=Fal
     choice = {c: (var0[idx[0]], int(tw0[idx[0]]), int(th0[idx[0]])) for c, idx in classes.items()}
     wg = 0
     best = timed(choice, wg)
+    medium = getattr(level, "medium", None) is not None
+    # Level-wide starts: every non-periodic class MARCH, or every class of
+    # frozen-ghost patches PACKED (they share wavefronts only when packed
+    # together, and a level of one tile kind runs a kernel of that kind
+    # alone), over a few segment heights and workgroups per CU; then refine
+    # class by class.
+    nonper = [c for c in classes if not c[2]] if not medium else []
+    frozen = [c for c in nonper if c[3]]
+    starts = []
+    for r in (4, 8, 16, 32, 64):
+        if nonper:
+            starts.append({c: (MARCH, 64, 4 * r) for c in nonper})
+        if frozen:
+            starts.append({c: (PACKED, 64, 4 * r) for c in frozen})
+    for st in starts:
+        trial = dict(choice)
+        trial.update(st)
+        for w in (0, 8, 16):
+            try:
+                t = timed(trial, w)
+            except WaveStepError:  # a tiling some patch cannot take
+                break
+            if verbose:
+                print(f"level-wide {sorted(set(st.values()))} wg {w}: {t:.4f} ms", flush=True)
+            if t < best:
+                best, choice, wg = t, trial, w
     order = sorted(classes, key=lambda c: -sum(level.shapes[k][0] * level.shapes[k][1]
                                                 for k in classes[c]))
     for c in order:
         idx = classes[c]
         mx = int(np.median([level.shapes[k][0] for k in idx]))
         my = int(np.median([level.shapes[k][1] for k in idx]))
-        medium = getattr(level, "medium", None) is not None
-        for cand in candidates(mx, my, c[2] or medium, medium):
+        for cand in candidates(mx, my, c[2] or medium, medium, c[3] and not medium):
             if cand == choice[c]:
                 continue
             trial = dict(choice)
             trial[c] = cand
-            t = timed(trial, wg)
+            try:
+                t = timed(trial, wg)
+            except WaveStepError:
+                continue
             if verbose:
                 print(f"class {c} {cand}: {t:.4f} ms", flush=True)
             if t < best:

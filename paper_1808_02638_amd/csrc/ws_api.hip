@@ -26,6 +26,7 @@
 
 #include "../../include/wavestep.h"
 #include "ws_internal.h"
+#include "ws_pack.h"
 
 using namespace ws;
 
@@ -113,6 +114,9 @@ int64_t max_tiles_of(const ws_patch_desc *p, int n) {
   return t;
 }
 
+// Workspace of a level.  Tiles: a patch takes at most max_tiles_of's count,
+// or with frozen ghosts packed_tile_bound's; PACKED wavefronts stay within
+// packed_wave_bound per patch.
 WsLayout ws_layout_of(const ws_patch_desc *p, int n, int n_inst) {
   WsLayout L{};
   int64_t cur = 0;
@@ -122,9 +126,20 @@ WsLayout ws_layout_of(const ws_patch_desc *p, int n, int n_inst) {
     return o;
   };
   L.max_tiles = max_tiles_of(p, n);
+  L.max_pack_waves = 0;
+  L.n_sum_tiles = 0;
+  for (int k = 0; k < n; ++k) {
+    if (p[k].bc == WS_BC_NONE) {
+      L.max_tiles += packed_tile_bound(p[k].mx, p[k].my);
+      L.max_pack_waves += packed_wave_bound(p[k].mx, p[k].my);
+    }
+    L.n_sum_tiles += sum_tiles_of(p[k].mx, p[k].my);
+  }
   L.patches = take((int64_t)n * sizeof(PatchRow));
   L.inst = take((int64_t)n_inst * sizeof(InstRow));
   L.tiles = take(L.max_tiles * (int64_t)sizeof(TileEntry));
+  L.packs = take(L.max_pack_waves * (int64_t)sizeof(PackWave));
+  L.stiles = take(L.n_sum_tiles * (int64_t)sizeof(TileEntry));
   L.dt = take(8LL * n_inst);
   L.cfl_tile = take(8 * L.max_tiles);
   L.inst_acc = take(8LL * kGroups * n_inst);
@@ -133,7 +148,7 @@ WsLayout ws_layout_of(const ws_patch_desc *p, int n, int n_inst) {
   L.cfl_patch_last = take(8LL * n);
   L.level_last = take(8);
   L.retire = take(4LL * kLine * (kGroups + 1));
-  L.partials = take(24 * L.max_tiles);
+  L.partials = take(24 * L.n_sum_tiles);
   L.patch_sums = take(24LL * n);
   L.sums = take(24LL * n_inst);
   L.total = cur;
@@ -141,6 +156,9 @@ WsLayout ws_layout_of(const ws_patch_desc *p, int n, int n_inst) {
 }
 
 bool valid_tile(int variant, int tw, int th) {
+  if (variant == kPacked)  // four wavefronts of th / 4 rows
+    return tw == kMarchWidth && th % 4 == 0 && th / 4 >= kMinPackedRows &&
+           th / 4 <= kMaxMarchRows;
   if (variant != kDirect && variant != kMarch) return false;
   bool ok_w = false;
   for (int w : kTileWidths) ok_w |= (w == tw);
@@ -227,9 +245,11 @@ struct ws_ctx {
   std::vector<ws_patch_desc> desc;
   std::vector<PatchRow> rows;
   std::vector<TileEntry> tiles;
+  std::vector<PackWave> packs;  // wavefronts of the PACKED tiles
+  std::vector<TileEntry> stiles;  // conservation-sum tiles (fixed by the patch sizes)
   std::vector<int> order;  // patches largest first
   int n_cu = 0, wg_per_cu = 0, grid = 0, occupancy = 0;
-  int vars = 1;          // tile variants present (bit 0 DIRECT, bit 1 MARCH)
+  int vars = 1;          // tile variants present (bit 0 DIRECT, bit 1 MARCH, bit 2 PACKED)
   int wg_override = 0;   // workgroups per CU set by the caller (0: occupancy)
   int max_padded_cells = 0;
   int max_ring = 0;  // interior cells next to a side, largest patch
@@ -273,8 +293,10 @@ struct ws_ctx {
     a.n_tiles = (int32_t)tiles.size();
     a.tile_base = 0;
     a.persistent = 1;
+    a.packs = reinterpret_cast<const PackWave *>(ws + L.packs);
     a.qin = pool[src];
     a.qout = pool[1 - src];
+    a.pool_bytes = (int32_t)std::min<int64_t>(pool_bytes, INT32_MAX);
     a.inst = reinterpret_cast<const InstRow *>(ws + L.inst);
     a.slots = slots();
     a.dt = a.slots.dt;
@@ -294,11 +316,20 @@ struct ws_ctx {
     graph_steps = 0;
   }
 
-  // Tile list: patches largest first, each patch's tiles row by row.
+  int pack_tiles() {
+    pack_level(rows, order, dtype == WS_F32 ? 4 : 8, tiles, packs);
+    if ((int64_t)packs.size() > L.max_pack_waves)
+      return fail(WS_EINVAL, "PACKED wavefront list overflow");
+    return WS_OK;
+  }
+
+  // Tile list: patches largest first, each patch's tiles row by row; then the
+  // PACKED tiles.
   int build_tiles() {
     tiles.clear();
     for (int k : order) {
       PatchRow &r = rows[k];
+      if (r.variant == kPacked) continue;
       const int cols = tile_cols(r.variant, r.tw);
       r.ntx = (r.mx + cols - 1) / cols;
       r.nty = (r.my + r.th - 1) / r.th;
@@ -307,14 +338,20 @@ struct ws_ctx {
         for (int tx = 0; tx < r.ntx; ++tx) tiles.push_back(TileEntry{k, (uint16_t)tx, (uint16_t)ty});
       r.n_tiles = (int32_t)tiles.size() - r.tile_begin;
     }
+    if (int rc = pack_tiles()) return rc;
     if ((int64_t)tiles.size() > L.max_tiles) return fail(WS_EINVAL, "tile list overflow");
     vars = 0;
-    for (const PatchRow &r : rows) vars |= (r.variant == kMarch) ? 2 : 1;
+    for (const PatchRow &r : rows) vars |= r.variant == kPacked ? 4 : r.variant == kMarch ? 2 : 1;
     if (step_occupancy(dtype, lim_code(), vars, &occupancy) != 0 || occupancy < 1) occupancy = 1;
     wg_per_cu = wg_override > 0 ? wg_override : occupancy;
     HIPCHK(hipMemcpyAsync(ws + L.patches, rows.data(), rows.size() * sizeof(PatchRow),
                           hipMemcpyHostToDevice, stream));
     HIPCHK(hipMemcpyAsync(ws + L.tiles, tiles.data(), tiles.size() * sizeof(TileEntry),
+                          hipMemcpyHostToDevice, stream));
+    if (!packs.empty())
+      HIPCHK(hipMemcpyAsync(ws + L.packs, packs.data(), packs.size() * sizeof(PackWave),
+                            hipMemcpyHostToDevice, stream));
+    HIPCHK(hipMemcpyAsync(ws + L.stiles, stiles.data(), stiles.size() * sizeof(TileEntry),
                           hipMemcpyHostToDevice, stream));
     HIPCHK(hipStreamSynchronize(stream));
     grid = (int)std::min<int64_t>((int64_t)n_cu * wg_per_cu, (int64_t)tiles.size());
@@ -416,6 +453,7 @@ static int setup_level(ws_ctx *c, const ws_patch_desc *patches, int32_t n_patche
     c->max_my = std::max(c->max_my, d.my);
   }
   c->mask_total = mask_off;
+  sum_tiles(c->rows, c->stiles);
   c->order.resize(n_patches);
   std::iota(c->order.begin(), c->order.end(), 0);
   std::stable_sort(c->order.begin(), c->order.end(), [&](int a, int b) {
@@ -488,6 +526,12 @@ int ws_set_tiling(ws_ctx *c, const int32_t *variant, const int32_t *tile_w,
         return fail(WS_EINVAL, "patch %d: a heterogeneous medium takes DIRECT tiles only", k);
       if (v == kMarch && !march_fits(c->rows[k].plane, c->dtype))
         return fail(WS_EINVAL, "patch %d: too large for MARCH tiles (32-bit offsets)", k);
+      if (v == kPacked && c->rows[k].bc != WS_BC_NONE)
+        return fail(WS_EINVAL, "patch %d: PACKED tiles take patches with frozen ghosts only", k);
+      if (v == kPacked && c->medium)
+        return fail(WS_EINVAL, "patch %d: a heterogeneous medium takes DIRECT tiles only", k);
+      if (v == kPacked && c->P.elems * (c->dtype == WS_F32 ? 4 : 8) >= (int64_t{1} << 31))
+        return fail(WS_EINVAL, "PACKED tiles need pools under 2 GiB (32-bit offsets)");
     }
   HIPCHK(hipStreamSynchronize(c->stream));
   if (tile_w)
@@ -496,7 +540,7 @@ int ws_set_tiling(ws_ctx *c, const int32_t *variant, const int32_t *tile_w,
       c->rows[k].tw = tile_w[k];
       c->rows[k].th = tile_h[k];
     }
-  if (wg_per_cu > 0) c->wg_override = wg_per_cu;
+  c->wg_override = wg_per_cu;  // 0: the kernel's occupancy
   c->drop_graph();
   return c->build_tiles();
 }
@@ -748,6 +792,7 @@ int ws_step_level(ws_ctx *c, double dt, double *cfl_out) {
 
 int ws_step_level_per_patch(ws_ctx *c, double dt, double *cfl_out) {
   if (!c) return fail(WS_EINVAL, "ctx is NULL");
+  if (c->vars & 4) return fail(WS_EINVAL, "per-patch launches need a tiling without PACKED tiles");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
   HIPCHK(launch_set_dt(c->slots(), dt, c->stream));
   StepArgs a = c->step_args(c->cur, 0.0, 0.0);
@@ -858,8 +903,10 @@ int ws_conservation_sums(ws_ctx *c, double *sums) {
   double *partials = reinterpret_cast<double *>(c->ws + c->L.partials);
   double *dsums = reinterpret_cast<double *>(c->ws + c->L.sums);
   double *psums = reinterpret_cast<double *>(c->ws + c->L.patch_sums);
-  HIPCHK(launch_sums(c->dtype, c->d_patches(), c->n_patches, c->d_tiles(), (int)c->tiles.size(),
-                     c->pool[c->cur], partials, psums, c->n_inst, dsums, c->stream));
+  HIPCHK(launch_sums(c->dtype, c->d_patches(), c->n_patches,
+                     reinterpret_cast<const TileEntry *>(c->ws + c->L.stiles),
+                     (int)c->stiles.size(), c->pool[c->cur], partials, psums, c->n_inst, dsums,
+                     c->stream));
   const size_t n = 24 * (size_t)c->n_inst;
   HIPCHK(hipMemcpyAsync(c->host_buf, dsums, n, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -871,6 +918,8 @@ int ws_time_step_kernel(ws_ctx *c, int32_t n_launches, int32_t per_patch, double
   if (!c) return fail(WS_EINVAL, "ctx is NULL");
   if (n_launches < 1 || n_launches > 100000 || !ms_per_step)
     return fail(WS_EINVAL, "need 1 <= n_launches <= 100000 and an output");
+  if (per_patch && (c->vars & 4))
+    return fail(WS_EINVAL, "per-patch launches need a tiling without PACKED tiles");
   // one event pair per level step: the mean bracketed duration, without the
   // gaps between back-to-back launches
   std::vector<hipEvent_t> ev(2 * (size_t)n_launches, nullptr);
@@ -935,6 +984,7 @@ int ws_step_record_masks(ws_ctx *c, double dt, void *masks_dev, double *cfl_out)
                 "branches exist for the MC limiter of the default variant in a homogeneous medium");
   if (c->link_src)
     return fail(WS_EINVAL, "branch recording (for the adjoint) does not take a tiled level");
+  if (c->vars & 4) return fail(WS_EINVAL, "branch recording needs a tiling without PACKED tiles");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(WS_EINVAL, "dt must be finite and > 0");
   StepArgs a = c->step_args(c->cur, dt, 0.0);
   a.masks = reinterpret_cast<uint8_t *>(masks_dev);

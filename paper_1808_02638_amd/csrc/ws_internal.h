@@ -5,54 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ws_tables.h"
+
 namespace ws {
-
-constexpr int kThreads = 256;  // threads per workgroup of every tile kernel
-constexpr int kGroups = 8;     // tile groups of the persistent launch, one per XCD
-constexpr int kLine = 32;      // retirement counters sit 128 bytes (32 uints) apart
-constexpr int kMaxRowsPerThread = 64;  // DIRECT tiles
-constexpr int kMaxMarchRows = 64;      // MARCH segments
-
-// Tile kernels.  DIRECT: one thread per column, every cell computed from its
-// 13-point footprint.  MARCH: lane segments sweep up their columns carrying
-// the y-direction terms in registers and exchanging x-direction terms with
-// neighbouring lanes; a segment of w lanes updates w-4 columns.
-enum TileVariant { kDirect = 0, kMarch = 1 };
-constexpr int kMarchWidth = 64;  // MARCH segments are one wavefront wide
-
-// One row of the device patch table.
-struct PatchRow {
-  int64_t q_off;   // element offset of the patch's storage (row j = -2 of plane p)
-  int32_t mx, my;  // interior cells
-  int32_t ld;      // row stride (elements)
-  int32_t col0;    // storage column of interior i = 0 (ghost i=-2 sits at col0-2)
-  int64_t plane;   // plane stride (elements): ld * (my + 4)
-  int32_t inst;    // instance (material, dt)
-  int32_t bc;      // WS_BC_*
-  int32_t variant;  // TileVariant
-  int32_t tw, th;  // DIRECT: tile of tw x th cells; MARCH: segments of tw lanes, th rows
-  int32_t ntx, nty;  // tiles in x and y
-  double dx, dy;
-  int64_t mask_off;  // byte offset of the patch's (mx+1)*(my+1) mask bytes
-  int32_t tile_begin, n_tiles;  // the patch's tiles in the tile list
-  int32_t pad_;
-};
-
-struct TileEntry {
-  int32_t patch;
-  uint16_t tx, ty;
-};
-
-struct InstRow {
-  double c, Z;
-};
-
-// Workspace carve-up (byte offsets inside the caller's workspace buffer).
-struct WsLayout {
-  int64_t patches, inst, tiles, dt, cfl_tile, inst_acc, cfl_last, cfl_max, cfl_patch_last,
-      level_last, retire, partials, patch_sums, sums, total;
-  int64_t max_tiles;
-};
 
 // Per-step Courant-number bookkeeping inside the workspace.
 struct CflSlots {
@@ -68,11 +23,13 @@ struct CflSlots {
 struct StepArgs {
   const PatchRow *patches;
   const TileEntry *tiles;
+  const PackWave *packs;  // wavefronts of PACKED tiles
   int32_t n_tiles;
   int32_t tile_base;   // direct mode: first tile of this launch
   int32_t persistent;  // 1: persistent launch over all tiles; 0: tile = base + blockIdx
   const void *qin;
   void *qout;
+  int32_t pool_bytes;  // bytes of each pool (PACKED tiles: below 2^31)
   const InstRow *inst;
   double *dt;          // per instance
   double dt_override;  // > 0: every instance steps with this dt (stored into dt)
@@ -88,7 +45,8 @@ struct StepArgs {
 constexpr int kMediumFlag = 0x10000;
 
 // Kernel launchers (defined in ws_kernels.hip).
-// vars: bit 0 -> DIRECT tiles present, bit 1 -> MARCH tiles present.
+// vars: bit 0 -> DIRECT tiles present, bit 1 -> MARCH tiles present, bit 2 ->
+// PACKED tiles present.
 hipError_t launch_step(int dtype, int limiter, int vars, const StepArgs &a, int grid,
                        hipStream_t s);
 // The ghost ring of an mx x my patch in one numbering, shared by the kernels
@@ -125,8 +83,10 @@ hipError_t launch_finish_step(const CflSlots &c, double cfl_desired, hipStream_t
 // cfl_patch[k] = max of cfl_tile over patch k's tiles.
 hipError_t launch_patch_cfl(const PatchRow *patches, int n_patches, const double *cfl_tile,
                             double *cfl_patch, hipStream_t s);
-hipError_t launch_sums(int dtype, const PatchRow *patches, int n_patches, const TileEntry *tiles,
-                       int n_tiles, const void *q, double *partials, double *patch_sums,
+// Conservation sums over the fixed sum tiles (kSumTile x kSumTile cells of a
+// patch each, independent of the step's tiling).
+hipError_t launch_sums(int dtype, const PatchRow *patches, int n_patches, const TileEntry *stiles,
+                       int n_stiles, const void *q, double *partials, double *patch_sums,
                        int n_inst, double *sums, hipStream_t s);
 int step_occupancy(int dtype, int limiter, int vars, int *wg_per_cu);
 

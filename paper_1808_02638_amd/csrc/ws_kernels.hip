@@ -734,6 +734,45 @@ struct MarchLanes {
   }
 };
 
+// Lanes of one PACKED wavefront: the MARCH lanes' interface, with the patch
+// chosen per lane.  Lane l belongs to the column block (piece) whose lanes it
+// falls in and holds column i of that piece's patch; loads and stores use
+// unsigned 32-bit byte offsets from the pool's base (the pools of a level
+// with PACKED tiles span less than 2^31 bytes).  Every piece's patch has
+// frozen ghosts (no ghost images are written) and holds every row the
+// wavefront marches over.  A piece's two lanes on either side play the part
+// of a MARCH segment's halo lanes: whatever a neighbouring piece leaves in
+// them reaches no updated column.
+template <typename T>
+struct PackedLanes {
+  static constexpr int w = kMarchWidth;
+  const char *base;           // the input pool
+  __amdgpu_buffer_rsrc_t ob;  // the output pool as a raw buffer
+  unsigned colb;   // byte offset of the lane's read column in row -2 of plane p
+  unsigned ocolb;  // the same for the lane's own column (stores)
+  unsigned ldb, plb;  // row and plane strides of the lane's patch (bytes)
+  int rlo, rhi;       // rows a fetch is clamped to: the march's rows and two either side
+  bool out;           // lane updates a column of its piece
+  // the MARCH lanes' branch-recording fields (never recorded here)
+  static constexpr int l = 0, i = 0, mx = 0, my = 0;
+
+  __device__ unsigned at(int r) const { return colb + (unsigned)(r + 2) * ldb; }
+  __device__ unsigned oat(int r) const { return ocolb + (unsigned)(r + 2) * ldb; }
+  __device__ T get(unsigned boff) const { return *reinterpret_cast<const T *>(base + boff); }
+  __device__ void fetch(Row3<T> &S, int r) const {
+    const unsigned o = at(min(max(r, rlo), rhi));
+    S.p = get(o);
+    S.u = get(o + plb);
+    S.v = get(o + 2 * plb);
+  }
+  __device__ void emit(T pn, T un, T vn, int r) const {
+    const unsigned so = out ? oat(r) : kDropOffset;
+    bstore(ob, pn, so);
+    bstore(ob, un, so + plb);
+    bstore(ob, vn, so + 2 * plb);
+  }
+};
+
 // Row sets of a MARCH segment: set k holds one row from its load until its
 // last use (as row r+2, r+1, then r of the row being updated; mirrored for a
 // downward march), and is then refilled in place with the row kSets further
@@ -798,8 +837,8 @@ __device__ __attribute__((always_inline)) inline void sweep_down(RowFn &row, Row
 // Upward MARCH over rows [r0, r1).  x-neighbour terms come through lane
 // shifts; y-direction terms slide up the column in registers.  Each quantity
 // uses the same expression as in cell_update, so the result is bitwise equal.
-template <typename T, int LIM, bool MASKS>
-__device__ __attribute__((always_inline)) inline void march_up(const MarchLanes<T> &M, const Coef<T> &k, int r0, int r1,
+template <typename T, int LIM, bool MASKS, class L>
+__device__ __attribute__((always_inline)) inline void march_up(const L &M, const Coef<T> &k, int r0, int r1,
                                 uint8_t *masks) {
   constexpr int w = kMarchWidth;
   const T Z = k.Z;
@@ -895,8 +934,8 @@ __device__ __attribute__((always_inline)) inline void march_up(const MarchLanes<
 // neighbouring segments march in opposite directions, so the rows two of them
 // share are read by both at about the same time (both at their start, or
 // both at their end) and the second read finds them in L2.
-template <typename T, int LIM>
-__device__ __attribute__((always_inline)) inline void march_down(const MarchLanes<T> &M, const Coef<T> &k, int r0, int r1) {
+template <typename T, int LIM, class L>
+__device__ __attribute__((always_inline)) inline void march_down(const L &M, const Coef<T> &k, int r0, int r1) {
   const T Z = k.Z;
   Row3<T> R0, R1, R2, R3, R4, R5, R6, R7;
   // ---- prologue: rows r1+1, r1 and the sets (rows r1-1 down to r1-8)
@@ -970,8 +1009,8 @@ __device__ __attribute__((always_inline)) inline void march_down(const MarchLane
 // row ahead and carried (l1, l2) into the next row's F~; the y-edges' limited
 // strengths of a cell's top edge serve its split vector and G~, and slide down
 // as the bottom edge's (eB).
-template <typename T, int LIM>
-__device__ __attribute__((always_inline)) inline void march_up_tc(const MarchLanes<T> &M, const Coef<T> &k, int r0, int r1) {
+template <typename T, int LIM, class L>
+__device__ __attribute__((always_inline)) inline void march_up_tc(const L &M, const Coef<T> &k, int r0, int r1) {
   const T Z = k.Z;
   Row3<T> R0, R1, R2, R3, R4, R5, R6, R7;
   const unsigned om2 = M.at(r0 - 2), om1 = M.at(r0 - 1);
@@ -1051,8 +1090,8 @@ __device__ __attribute__((always_inline)) inline void march_up_tc(const MarchLan
 // Downward MARCH of the transverse-correction variant: the mirror of
 // march_up_tc (limited strengths of row r-1 formed one row ahead, the top
 // edge's eT carried).
-template <typename T, int LIM>
-__device__ __attribute__((always_inline)) inline void march_down_tc(const MarchLanes<T> &M, const Coef<T> &k, int r0, int r1) {
+template <typename T, int LIM, class L>
+__device__ __attribute__((always_inline)) inline void march_down_tc(const L &M, const Coef<T> &k, int r0, int r1) {
   const T Z = k.Z;
   Row3<T> R0, R1, R2, R3, R4, R5, R6, R7;
   const unsigned oa2 = M.at(r1 + 1), oa1 = M.at(r1);
@@ -1142,13 +1181,64 @@ __device__ inline double wave_max(double v) {
 // One work unit, quarter q of tile t (MARCH: segment q; DIRECT: threads
 // q*64 .. q*64+63 of the tile), worked by one wavefront; returns the tile's
 // Courant number.  No barrier: wavefronts take units independently.
-// VARS: bit 0 -> DIRECT tiles may occur, bit 1 -> MARCH tiles may occur.
+// VARS: bit 0 -> DIRECT tiles may occur, bit 1 -> MARCH tiles, bit 2 -> PACKED
+// tiles (the step without branch recording or a medium only).
 // TC: the transverse-correction variant (never with MASKS).
 template <typename T, int LIM, bool MASKS, int VARS, bool TC, bool VAR = false>
-__device__ __attribute__((always_inline)) inline double do_unit(const StepArgs &a, int t, int q) {
+__device__ __attribute__((always_inline)) inline double do_unit(const StepArgs &a, int t, int q,
+                                                                int &inst) {
   const TileEntry te = uniform_row(a.tiles[t]);
+  if constexpr ((VARS & 4) != 0 && !MASKS && !VAR) {
+    if (te.patch < 0) {
+      // PACKED tile -1 - te.patch: wavefront q works its column blocks
+      const PackWave pw = uniform_row(a.packs[4 * (-1 - te.patch) + q]);
+      // every piece shares the first one's instance and cell sizes
+      const PatchRow p0 = uniform_row(a.patches[pw.patch[0]]);
+      const InstRow in = uniform_row(a.inst[p0.inst]);
+      inst = p0.inst;
+      const double dt = a.dt_override > 0.0 ? a.dt_override : a.dt[p0.inst];
+      const Coef<T> k = make_coef<T>(in.c, in.Z, dt, p0.dx, p0.dy);
+      if (pw.n > 0) {
+        const int lx = (int)threadIdx.x & 63;
+        // the lane's piece: the last whose first lane is at or before it
+        unsigned org = pw.org[0], ldb = pw.ldb[0], plb = pw.plb[0];
+        int pw_w = pw.w[0], lane0 = pw.lane0[0], lim = pw.lim[0];
+#pragma unroll
+        for (int n = 1; n < kMaxPieces; ++n)
+          if (n < pw.n && lx >= pw.lane0[n]) {
+            org = pw.org[n], ldb = pw.ldb[n], plb = pw.plb[n];
+            pw_w = pw.w[n], lane0 = pw.lane0[n], lim = pw.lim[n];
+          }
+        const int off = lx - lane0;  // the lane holds column c0 - 2 + off of its piece
+        PackedLanes<T> M;
+        M.base = reinterpret_cast<const char *>(a.qin);
+        M.ob = __builtin_amdgcn_make_buffer_rsrc(a.qout, 0, a.pool_bytes, kRawBufferWord3);
+        M.colb = org + (unsigned)min(off, lim) * (unsigned)sizeof(T);
+        M.ocolb = org + (unsigned)off * (unsigned)sizeof(T);
+        M.ldb = ldb;
+        M.plb = plb;
+        M.rlo = pw.r0 - 2;
+        M.rhi = pw.r1 + 1;
+        M.out = off >= 2 && off < pw_w + 2;
+        const bool up = ((t * (kThreads / kMarchWidth) + q) & 1) == 0;
+        if constexpr (TC) {
+          if (up)
+            march_up_tc<T, LIM>(M, k, pw.r0, pw.r1);
+          else
+            march_down_tc<T, LIM>(M, k, pw.r0, pw.r1);
+        } else {
+          if (up)
+            march_up<T, LIM, false>(M, k, pw.r0, pw.r1, nullptr);
+          else
+            march_down<T, LIM>(M, k, pw.r0, pw.r1);
+        }
+      }
+      return fmax(in.c * (dt / p0.dx), in.c * (dt / p0.dy));
+    }
+  }
   const PatchRow pr = uniform_row(a.patches[te.patch]);
   const InstRow in = uniform_row(a.inst[pr.inst]);
+  inst = pr.inst;
   const double dt = a.dt_override > 0.0 ? a.dt_override : a.dt[pr.inst];
   const Coef<T> k = make_coef<T>(in.c, in.Z, dt, pr.dx, pr.dy);
   const int64_t org = pr.q_off + 2 * (int64_t)pr.ld + pr.col0;
@@ -1286,9 +1376,9 @@ __device__ inline void flush_cfl(const StepArgs &a, int group, CflRun &run) {
 
 // Thread 0 after a tile: record the tile's value (for the per-patch array)
 // where every XCD can read it, and fold it into the running maximum.
-__device__ inline void file_tile(const StepArgs &a, int group, CflRun &run, int t, double m) {
+__device__ inline void file_tile(const StepArgs &a, int group, CflRun &run, int t, double m,
+                                 int inst) {
   __hip_atomic_store(&a.slots.cfl_tile[t], m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int inst = a.patches[a.tiles[t].patch].inst;
   if (inst != run.inst) {
     flush_cfl(a, group, run);
     run.inst = inst;
@@ -1322,10 +1412,11 @@ __device__ __attribute__((always_inline)) inline void step_body(const StepArgs &
   if (!a.persistent) {
     const int t = a.tile_base + (int)blockIdx.x;
     if (t < a.n_tiles) {
-      double m = do_unit<T, LIM, MASKS, VARS, TC, VAR>(a, t, wave);
+      int inst = 0;
+      double m = do_unit<T, LIM, MASKS, VARS, TC, VAR>(a, t, wave, inst);
       if constexpr (VAR) m = tile_max(m, lane, wave);
-      if (lane == 0) {
-        file_tile(a, 0, run, t, m);
+      if (lane == 0 && wave == 0) {
+        file_tile(a, 0, run, t, m, inst);
         flush_cfl(a, 0, run);
       }
     }
@@ -1338,9 +1429,10 @@ __device__ __attribute__((always_inline)) inline void step_body(const StepArgs &
   const int beg = (int)((int64_t)a.n_tiles * x / groups);
   const int end = (int)((int64_t)a.n_tiles * (x + 1) / groups);
   for (int t = beg + y; t < end; t += in_group) {
-    double m = do_unit<T, LIM, MASKS, VARS, TC, VAR>(a, t, wave);
+    int inst = 0;
+    double m = do_unit<T, LIM, MASKS, VARS, TC, VAR>(a, t, wave, inst);
     if constexpr (VAR) m = tile_max(m, lane, wave);
-    if (lane == 0 && wave == 0) file_tile(a, x, run, t, m);
+    if (lane == 0 && wave == 0) file_tile(a, x, run, t, m, inst);
   }
   // Retire: the workgroup's values are filed (and waited for) before its
   // count; the last workgroup of each run counts the run, and the last run's
@@ -1475,18 +1567,20 @@ __global__ __launch_bounds__(kThreads) void patch_cfl_kernel(const PatchRow *pat
 // Conservation sums: FP64 per-tile partials, per-patch sums of those, per-
 // instance sums of those; every stage in a fixed order.
 // --------------------------------------------------------------------------
+// One workgroup per sum tile (kSumTile x kSumTile cells of a patch, in a
+// list of their own), so the order of every addition is fixed by the patch
+// sizes alone, whatever the step's tiling.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void tile_sums_kernel(const PatchRow *patches,
-                                                           const TileEntry *tiles, const T *q,
+                                                           const TileEntry *stiles, const T *q,
                                                            double *partials) {
   __shared__ double s[3][kThreads];
-  const TileEntry te = tiles[blockIdx.x];
+  const TileEntry te = stiles[blockIdx.x];
   const PatchRow pr = patches[te.patch];
-  const int tw = pr.tw;
-  const int rpt = pr.th / (kThreads / tw);
-  const int lx = threadIdx.x % tw, ly = threadIdx.x / tw;
-  const int i = te.tx * tw + lx;
-  const int j0 = te.ty * pr.th + ly * rpt;
+  constexpr int rpt = kSumTile / (kThreads / kSumTile);
+  const int lx = threadIdx.x % kSumTile, ly = threadIdx.x / kSumTile;
+  const int i = te.tx * kSumTile + lx;
+  const int j0 = te.ty * kSumTile + ly * rpt;
   const int j1 = min(j0 + rpt, pr.my);
   const int64_t org = pr.q_off + 2 * (int64_t)pr.ld + pr.col0;
   double acc[3] = {0.0, 0.0, 0.0};
@@ -1517,13 +1611,13 @@ __device__ inline void block_sum3(double acc[3], double *out) {
   if (threadIdx.x < 3) out[threadIdx.x] = s[threadIdx.x][0];
 }
 
-// One workgroup per patch: the sums of its tiles' partials.
+// One workgroup per patch: the sums of its sum tiles' partials.
 __global__ __launch_bounds__(kThreads) void patch_sums_kernel(const PatchRow *patches,
                                                             const double *partials,
                                                             double *patch_sums) {
   const PatchRow pr = patches[blockIdx.x];
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int t = pr.tile_begin + (int)threadIdx.x; t < pr.tile_begin + pr.n_tiles; t += kThreads)
+  for (int t = pr.sum_begin + (int)threadIdx.x; t < pr.sum_begin + pr.sum_n; t += kThreads)
     for (int m = 0; m < 3; ++m) acc[m] += partials[3 * (int64_t)t + m];
   block_sum3(acc, patch_sums + 3 * (int64_t)blockIdx.x);
 }
@@ -1552,12 +1646,22 @@ hipError_t launch_step_t(const StepArgs &a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+// PACKED tiles: a kernel for levels with PACKED tiles only, one for PACKED
+// with MARCH, and one with every variant.
 template <typename T, int LIM, bool MASKS, bool TC>
 hipError_t launch_step_v(int vars, const StepArgs &a, int grid, hipStream_t s) {
   switch (vars) {
     case 1: return launch_step_t<T, LIM, MASKS, 1, TC>(a, grid, s);
     case 2: return launch_step_t<T, LIM, MASKS, 2, TC>(a, grid, s);
-    default: return launch_step_t<T, LIM, MASKS, 3, TC>(a, grid, s);
+    case 3: return launch_step_t<T, LIM, MASKS, 3, TC>(a, grid, s);
+    default:
+      if constexpr (MASKS) {
+        return hipErrorInvalidValue;
+      } else {
+        if (vars == 4) return launch_step_t<T, LIM, false, 4, TC>(a, grid, s);
+        if (vars == 6) return launch_step_t<T, LIM, false, 6, TC>(a, grid, s);
+        return launch_step_t<T, LIM, false, 7, TC>(a, grid, s);
+      }
   }
 }
 
@@ -1619,8 +1723,20 @@ int occupancy_of(int vars, int *n) {
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel_march<T, LIM, false, TC>,
                                                        kThreads, 0);
       break;
-    default:
+    case 3:
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel<T, LIM, false, 3, TC>,
+                                                       kThreads, 0);
+      break;
+    case 4:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel<T, LIM, false, 4, TC>,
+                                                       kThreads, 0);
+      break;
+    case 6:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel<T, LIM, false, 6, TC>,
+                                                       kThreads, 0);
+      break;
+    default:
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel<T, LIM, false, 7, TC>,
                                                        kThreads, 0);
       break;
   }
@@ -1719,16 +1835,16 @@ hipError_t launch_patch_cfl(const PatchRow *patches, int n_patches, const double
   return hipGetLastError();
 }
 
-hipError_t launch_sums(int dtype, const PatchRow *patches, int n_patches, const TileEntry *tiles,
-                       int n_tiles, const void *q, double *partials, double *patch_sums,
+hipError_t launch_sums(int dtype, const PatchRow *patches, int n_patches, const TileEntry *stiles,
+                       int n_stiles, const void *q, double *partials, double *patch_sums,
                        int n_inst, double *sums, hipStream_t s) {
-  if (n_tiles > 0) {
+  if (n_stiles > 0) {
     if (dtype == WS_F32)
-      hipLaunchKernelGGL(tile_sums_kernel<float>, dim3(n_tiles), dim3(kThreads), 0, s, patches,
-                         tiles, reinterpret_cast<const float *>(q), partials);
+      hipLaunchKernelGGL(tile_sums_kernel<float>, dim3(n_stiles), dim3(kThreads), 0, s, patches,
+                         stiles, reinterpret_cast<const float *>(q), partials);
     else
-      hipLaunchKernelGGL(tile_sums_kernel<double>, dim3(n_tiles), dim3(kThreads), 0, s, patches,
-                         tiles, reinterpret_cast<const double *>(q), partials);
+      hipLaunchKernelGGL(tile_sums_kernel<double>, dim3(n_stiles), dim3(kThreads), 0, s, patches,
+                         stiles, reinterpret_cast<const double *>(q), partials);
   }
   hipLaunchKernelGGL(patch_sums_kernel, dim3(n_patches), dim3(kThreads), 0, s, patches, partials,
                      patch_sums);

@@ -220,12 +220,15 @@ class Level:
         return np.array(out).reshape(self.n_inst, 3)
 
     def set_tiling(self, tile_w=None, tile_h=None, wg_per_cu: int = 0, variant="direct") -> None:
-        """Tiling per patch (scalars broadcast): variant "direct" or "march"
-        (or 0/1 codes), tile width and height; and persistent workgroups per CU."""
+        """Tiling per patch (scalars broadcast): variant "direct", "march" or
+        "packed" (or 0/1/2 codes), tile width and height; and persistent
+        workgroups per CU (0: as many as the kernel's occupancy allows).
+        Without tile sizes the tiling in use is kept."""
         if tile_w is None:
             C.check(self._L.ws_set_tiling(self._ctx, None, None, None, int(wg_per_cu)))
             return
-        codes = {"direct": C.WS_TILE_DIRECT, "march": C.WS_TILE_MARCH}
+        codes = {"direct": C.WS_TILE_DIRECT, "march": C.WS_TILE_MARCH,
+                 "packed": C.WS_TILE_PACKED}
         var = np.asarray([codes.get(v, v) if isinstance(v, str) else v
                           for v in np.broadcast_to(np.asarray(variant, dtype=object), (self.n,))],
                          np.int32)
@@ -346,7 +349,7 @@ class Level:
 
     def get_tiling(self):
         """(variants, tile_w, tile_h, wg_per_cu, grid) in use; variants as
-        "direct"/"march" strings."""
+        "direct"/"march"/"packed" strings."""
         P = ctypes.POINTER(ctypes.c_int32)
         var = np.zeros(self.n, np.int32)
         tw = np.zeros(self.n, np.int32)
@@ -354,7 +357,8 @@ class Level:
         wg, grid = ctypes.c_int32(0), ctypes.c_int32(0)
         C.check(self._L.ws_get_tiling(self._ctx, var.ctypes.data_as(P), tw.ctypes.data_as(P),
                                       th.ctypes.data_as(P), ctypes.byref(wg), ctypes.byref(grid)))
-        names = {C.WS_TILE_DIRECT: "direct", C.WS_TILE_MARCH: "march"}
+        names = {C.WS_TILE_DIRECT: "direct", C.WS_TILE_MARCH: "march",
+                 C.WS_TILE_PACKED: "packed"}
         return [names[int(v)] for v in var], tw, th, wg.value, grid.value
 
     def time_step_kernel(self, n_launches: int, per_patch: bool = False) -> float:

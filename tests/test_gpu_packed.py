@@ -1,0 +1,215 @@
+"""GPU parity of PACKED tiles (column blocks of several narrow patches sharing
+one wavefront) through the C ABI: the oracle's step of every patch (FP64 to
+1e-12, FP32 to 1e-5), the same state bitwise as every other tiling, the same
+Courant numbers and conservation sums, graphs equal to eager steps, and the
+calls that a PACKED tiling refuses."""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from helpers import FP32_TOL, FP64_TOL, rel_linf
+
+pytestmark = pytest.mark.gpu
+
+RHO, KB, C0 = 1.0, 4.0, 2.0
+
+
+@pytest.fixture(scope="module")
+def ws():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1808_02638_amd as ws
+    return ws
+
+
+def _level(ws, patches, states, mats, dtype, limiter="mc", tc=False):
+    lev = ws.Level(patches, mats, dtype=dtype, limiter=limiter, transverse_corr=tc)
+    for k, q in enumerate(states):
+        lev.upload(k, q)
+    return lev
+
+
+def _amr(level_index):
+    specs = workloads.amr_level_batch()[level_index]
+    patches = [dict(mx=p.mx, my=p.my, dx=p.dx, dy=p.dy) for p in specs]
+    states = [workloads.padded_state(p.mx, p.my, p.xlo, p.ylo, p.dx, p.dy) for p in specs]
+    return specs, patches, states
+
+
+def _level_err(lev, ref):
+    """Relative L-infinity per component over all the level's patches."""
+    diff, refmax = np.zeros(3), np.zeros(3)
+    for k, r in enumerate(ref):
+        a = lev.download(k)
+        diff = np.maximum(diff, np.abs(a - r).reshape(3, -1).max(axis=1))
+        refmax = np.maximum(refmax, np.abs(r).reshape(3, -1).max(axis=1))
+    return diff / refmax
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("th", [16, 64, 256])
+def test_amr_level_packed_matches_oracle_and_default_tiling(ws, oracle_lib, dtype, th):
+    """The finest level of the synthetic hierarchy (~2800 patches of 16..64
+    cells, frozen ghosts), every patch PACKED: each step's Courant number is
+    the oracle's, the state matches the oracle and equals the default
+    tiling's bitwise, and so do the per-patch Courant numbers and the
+    conservation sums."""
+    specs, patches, states = _amr(2)
+    lev_p = _level(ws, patches, states, [(RHO, KB)], dtype)
+    lev_p.set_tiling(64, th, variant="packed")
+    var = lev_p.get_tiling()[0]
+    assert set(var) == {"packed"}
+    lev_d = _level(ws, patches, states, [(RHO, KB)], dtype)
+    assert "packed" not in set(lev_d.get_tiling()[0])
+    dx = specs[0].dx
+    dt = 0.9 * dx / C0
+    cur = states
+    for _ in range(3):
+        cp = lev_p.step(dt)
+        cd = lev_d.step(dt)
+        cur, cfl_o = oracle_lib.step_patches(cur, dx, dx, dt, RHO, KB, "mc")
+        assert cp == cd == cfl_o.max()
+    for k in range(len(specs)):
+        assert np.array_equal(lev_p.download(k), lev_d.download(k)), k
+    err = _level_err(lev_p, cur)
+    tol = FP64_TOL if dtype == torch.float64 else FP32_TOL
+    print(f"packed th={th} {len(specs)} patches {dtype}: level rel Linf {err}")
+    assert err.max() <= tol
+    assert np.array_equal(lev_p.patch_cfl(), lev_d.patch_cfl())
+    assert np.array_equal(lev_p.conservation_sums(), lev_d.conservation_sums())
+    lev_p.close()
+    lev_d.close()
+
+
+def _mixed(seed, n=160):
+    """Patches of three materials and two cell sizes (dx != dy on some),
+    1..150 cells per side, with random states."""
+    rng = np.random.default_rng(seed)
+    mats = [(1.0, 4.0), (0.5, 9.0), (2.0, 1.0)]
+    patches, states = [], []
+    for _ in range(n):
+        mx, my = int(rng.integers(1, 150)), int(rng.integers(1, 110))
+        inst = int(rng.integers(0, 3))
+        dx = float(rng.choice([1 / 64, 1 / 128]))
+        dy = float(rng.choice([dx, 1 / 96]))
+        patches.append(dict(mx=mx, my=my, dx=dx, dy=dy, instance=inst))
+        states.append(rng.normal(size=(3, my + 4, mx + 4)))
+    return patches, states, mats, rng
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_mixed_variants_groups_and_sizes(ws, oracle_lib, dtype):
+    """PACKED tiles of several segment heights beside MARCH and DIRECT tiles,
+    over patches of three materials and two cell sizes (so several groups of
+    patches share tiles, and ragged blocks split across wavefronts): the
+    oracle's step of every patch, and bitwise the all-DIRECT state."""
+    patches, states, mats, rng = _mixed(11)
+    n = len(patches)
+    variant = [str(rng.choice(["packed", "packed", "march", "direct"])) for _ in range(n)]
+    th = [int(rng.choice([16, 20, 28, 64, 100, 256])) if v != "direct" else 64 for v in variant]
+    tw = [64 if v != "direct" else 32 for v in variant]
+    th = [t if v != "direct" else 8 for t, v in zip(th, variant)]
+    lev_m = _level(ws, patches, states, mats, dtype)
+    lev_m.set_tiling(tw, th, variant=variant)
+    lev_d = _level(ws, patches, states, mats, dtype)
+    lev_d.set_tiling(32, 8, variant="direct")
+    dt = 0.3 / 128 / 3.0  # stable for every material and cell size
+    cur = states
+    rhos = [mats[p["instance"]][0] for p in patches]
+    Ks = [mats[p["instance"]][1] for p in patches]
+    for _ in range(3):
+        cm = lev_m.step(dt)
+        cd = lev_d.step(dt)
+        assert cm == cd
+        cur, _ = oracle_lib.step_patches(cur, [p["dx"] for p in patches],
+                                         [p["dy"] for p in patches], dt, rhos, Ks, "mc")
+    tol = FP64_TOL if dtype == torch.float64 else FP32_TOL
+    worst = 0.0
+    for k in range(n):
+        a = lev_m.download(k)
+        assert np.array_equal(a, lev_d.download(k)), (k, patches[k], variant[k])
+        worst = max(worst, rel_linf(a, cur[k]).max())
+    print(f"mixed variants {dtype}: worst patch rel Linf {worst:.3e}")
+    assert worst <= tol
+    assert np.array_equal(lev_m.patch_cfl(), lev_d.patch_cfl())
+    assert np.array_equal(lev_m.read_dt_cfl()[1], lev_d.read_dt_cfl()[1])
+    assert np.array_equal(lev_m.conservation_sums(), lev_d.conservation_sums())
+    lev_m.close()
+    lev_d.close()
+
+
+@pytest.mark.parametrize("limiter,tc", [("vanleer", False), ("none", False), ("mc", True)])
+def test_packed_limiters_and_transverse_variant(ws, oracle_lib, limiter, tc):
+    """Other limiters and the transverse-correction variant: PACKED equals
+    MARCH bitwise and matches the oracle."""
+    patches, states, mats, _ = _mixed(23, n=60)
+    for p in patches:
+        p["instance"] = 0
+        p["dx"] = p["dy"] = 1 / 64
+    lev_p = _level(ws, patches, states, mats[:1], torch.float64, limiter, tc)
+    lev_p.set_tiling(64, 48, variant="packed")
+    lev_m = _level(ws, patches, states, mats[:1], torch.float64, limiter, tc)
+    lev_m.set_tiling(64, 48, variant="march")
+    dt = 0.4 / 64 / C0
+    for _ in range(3):
+        assert lev_p.step(dt) == lev_m.step(dt)
+    worst = 0.0
+    for k, q in enumerate(states):
+        a = lev_p.download(k)
+        assert np.array_equal(a, lev_m.download(k)), k
+        ref = oracle_lib.run(q, 3, 1 / 64, 1 / 64, RHO, KB, limiter=limiter, bc=None, dt=dt,
+                             transverse_corr=tc)
+        worst = max(worst, rel_linf(a, ref["q"]).max())
+    assert worst <= FP64_TOL, worst
+    lev_p.close()
+    lev_m.close()
+
+
+def test_packed_graph_equals_eager(ws):
+    """Captured steps with the device-resident dt update equal eager steps
+    bitwise on a PACKED level."""
+    _, patches, states = _amr(1)
+    levs = []
+    for _ in range(2):
+        lev = _level(ws, patches, states, [(RHO, KB)], torch.float64)
+        lev.set_tiling(64, 64, variant="packed")
+        lev.set_dt(lev.stable_dt(0.5))
+        levs.append(lev)
+    g, e = levs
+    g.capture(4, 0.9)
+    g.graph_launch()
+    g.graph_launch()
+    for _ in range(8):
+        e.step_auto(0.9)
+    torch.cuda.synchronize()
+    for k in range(len(patches)):
+        assert np.array_equal(g.download(k), e.download(k)), k
+    assert np.array_equal(g.read_dt_cfl()[0], e.read_dt_cfl()[0])
+    g.close()
+    e.close()
+
+
+def test_packed_refusals(ws):
+    """A PACKED tiling refuses per-patch launches and branch recording, and
+    PACKED tiles refuse patches whose ghosts the step writes."""
+    patches = [dict(mx=20, my=20, dx=0.05, dy=0.05), dict(mx=30, my=10, dx=0.05, dy=0.05)]
+    states = [np.ones((3, 24, 24)), np.ones((3, 14, 34))]
+    lev = _level(ws, patches, states, [(RHO, KB)], torch.float64)
+    lev.set_tiling(64, 16, variant="packed")
+    with pytest.raises(ws.WaveStepError, match="PACKED"):
+        lev.step_per_patch(0.001)
+    with pytest.raises(ws.WaveStepError, match="PACKED"):
+        lev.time_step_kernel(1, per_patch=True)
+    with pytest.raises(ws.WaveStepError, match="PACKED"):
+        lev.step_record_masks(0.001, lev.new_masks())
+    with pytest.raises(ws.WaveStepError):
+        lev.set_tiling(64, 12, variant="packed")  # three rows per wavefront
+    lev.set_tiling(64, 16, variant="march")
+    lev.step_per_patch(0.001)
+    lev.close()
+    ext = _level(ws, [dict(mx=20, my=20, dx=0.05, dy=0.05, bc="extrap")], states[:1],
+                 [(RHO, KB)], torch.float64)
+    with pytest.raises(ws.WaveStepError, match="frozen ghosts"):
+        ext.set_tiling(64, 16, variant="packed")
+    ext.close()

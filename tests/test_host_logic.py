@@ -7,7 +7,7 @@ import numpy as np
 import workloads
 from oracle import amr as oamr
 from oracle import tiled as otiled
-from paper_1808_02638_amd.autotune import DIRECT, MARCH, candidates
+from paper_1808_02638_amd.autotune import DIRECT, MARCH, PACKED, candidates
 
 
 def test_candidates_cover_the_tile_kinds_each_level_may_take():
@@ -20,8 +20,13 @@ def test_candidates_cover_the_tile_kinds_each_level_may_take():
     medium = candidates(2048, 2048, periodic=True, medium=True)
     assert all(v == DIRECT for v, _, _ in medium)
     assert max(th // (256 // tw) for _, tw, th in medium) == 64
+    # PACKED tiles for patches with frozen ghosts only, 4..64 rows per wavefront
+    assert not any(v == PACKED for v, _, _ in plain)
+    frozen = candidates(40, 40, periodic=False, frozen=True)
+    packed = [th for v, _, th in frozen if v == PACKED]
+    assert packed and min(packed) >= 16 and max(packed) <= 256
     # every candidate is a whole number of rows per thread / per segment
-    for v, tw, th in plain + medium:
+    for v, tw, th in plain + medium + frozen:
         assert th % (256 // tw) == 0
 
 
