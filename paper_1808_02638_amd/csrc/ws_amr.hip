@@ -229,23 +229,45 @@ struct FineGhost {
 // Floor division by a positive divisor.
 __device__ inline int fdiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
+// Coarse cells a block of the fine-step kernel stages for its ghosts: the
+// coarse cells under a range of at most 4 fine indices one way and S + 4 the
+// other, with one coarse cell of stencil on every side.
+__host__ __device__ inline int cf_box_cells(int S, int r) {
+  return ((3 + r - 1) / r + 3) * ((S + 3 + r - 1) / r + 3);
+}
+
 // Every ghost cell (outside the mx x my interior) of the fine rectangle
-// [ia, ib) x [ja, jb), evaluated as FineGhost::value3 does but with one
-// thread per coarse cell: the thread loads its coarse cell's neighbourhood
-// once and evaluates the fine ghosts inside it (2r of them along a side for
-// r >= 2), each handed to sink(i, j, v).  The threads of the block stride
-// over the rectangle's coarse cells.
+// [ia, ib) x [ja, jb), each handed to sink(i, j, v): a sibling's value where
+// one holds it, else the coarse level's.  The block's coarse neighbourhood
+// is staged in LDS first: every coarse cell of the box around the region's
+// coarse cells is read once, at the fine time (GhostSrc::q's expression), by
+// the whole block.  Then one thread per coarse cell evaluates the fine ghosts
+// inside it (2r of them along a side for r >= 2), taking the limited slopes
+// from LDS with GhostSrc::slopes' expressions, so every ghost has the same
+// bits as FineGhost::value3 gives it.  box: at least 3 cf_box_cells(S, r)
+// elements for the block's S threads.  Every thread of the block must call
+// it.
 template <typename T, class Sink>
-__device__ inline void ghost_region(const FineGhost<T> &F, int mx, int my, int ia, int ib,
-                                    int ja, int jb, Sink &&sink) {
+__device__ inline void ghost_region_staged(const FineGhost<T> &F, int mx, int my, int ia, int ib,
+                                           int ja, int jb, T *box, Sink &&sink) {
   const GhostSrc<T> &G = F.G;
   const int r = G.r;
-  // coarse cell of fine cell i: ci0 + floor((i + 1/2)/r), exactly, as an integer
   const int CIa = fdiv(2 * ia + 1, 2 * r), CIb = fdiv(2 * (ib - 1) + 1, 2 * r);
   const int CJa = fdiv(2 * ja + 1, 2 * r), CJb = fdiv(2 * (jb - 1) + 1, 2 * r);
   const int nI = CIb - CIa + 1, nJ = CJb - CJa + 1;
+  // the box: coarse cells (CIa - 1 .. CIb + 1) x (CJa - 1 .. CJb + 1), relative
+  const int bw = nI + 2, bh = nJ + 2;
+  for (int k = (int)threadIdx.x; k < bw * bh; k += (int)blockDim.x) {
+    const int ci = G.ci0 + CIa - 1 + k % bw, cj = G.cj0 + CJa - 1 + k / bw;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) box[m * bw * bh + k] = G.q(m, ci, cj);
+  }
+  __syncthreads();
+  auto at = [&](int m, int ci, int cj) {  // absolute coarse indices
+    return box[m * bw * bh + (cj - G.cj0 - CJa + 1) * bw + (ci - G.ci0 - CIa + 1)];
+  };
   for (int k = (int)threadIdx.x; k < nI * nJ; k += (int)blockDim.x) {
-    const int I = CIa + k % nI, J = CJa + k / nI;  // relative to (ci0, cj0)
+    const int I = CIa + k % nI, J = CJa + k / nI;
     const int i0 = max(ia, I * r), i1 = min(ib, I * r + r);
     const int j0 = max(ja, J * r), j1 = min(jb, J * r + r);
     T q0[3], sx[3], sy[3];
@@ -259,7 +281,12 @@ __device__ inline void ghost_region(const FineGhost<T> &F, int mx, int my, int i
           T xi, eta;
           G.locate(i, j, ci, cj, xi, eta);
           if (!have) {
-            G.slopes(ci, cj, q0, sx, sy);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+              q0[m] = at(m, ci, cj);
+              sx[m] = mc_slope(q0[m] - at(m, ci - 1, cj), at(m, ci + 1, cj) - q0[m]);
+              sy[m] = mc_slope(q0[m] - at(m, ci, cj - 1), at(m, ci, cj + 1) - q0[m]);
+            }
             have = true;
           }
 #pragma unroll
@@ -398,6 +425,7 @@ __global__ __launch_bounds__(kThreads) void cf_fine_step_kernel(CfArgs a, int st
   extern __shared__ char smem[];
   T *strip = reinterpret_cast<T *>(smem);  // [3][S + 2][4]
   const int S = a.strip, pitch = S + 2;
+  T *box = strip + 3 * pitch * 4;  // [3][cf_box_cells(S, r)]: the staged coarse cells
   const CfPlace pl = a.place[blockIdx.y];
   const PatchRow fp = a.fpatch[blockIdx.y];
   const int mx = fp.mx, my = fp.my, r = a.r;
@@ -440,7 +468,8 @@ __global__ __launch_bounds__(kThreads) void cf_fine_step_kernel(CfArgs a, int st
           strip[(m * pitch + (jj - j0 + 1)) * 4 + (i - e + 2)] =
               m == 0 ? q.P(i, jj) : m == 1 ? q.U(i, jj) : q.V(i, jj);
     }
-    ghost_region<T>(G, mx, my, e - 2, e + 2, j0 - 1, j1 + 1, [&](int i, int jj, const T v[3]) {
+    ghost_region_staged<T>(G, mx, my, e - 2, e + 2, j0 - 1, j1 + 1, box,
+                           [&](int i, int jj, const T v[3]) {
       for (int m = 0; m < 3; ++m) strip[(m * pitch + (jj - j0 + 1)) * 4 + (i - e + 2)] = v[m];
       if ((left ? i < 0 : i >= mx) && jj >= j0 && jj < j1)
         for (int m = 0; m < 3; ++m) *cell_ptr<T>(a.f_cur, fp, m, i, jj) = v[m];
@@ -473,8 +502,8 @@ __global__ __launch_bounds__(kThreads) void cf_fine_step_kernel(CfArgs a, int st
           strip[(m * pitch + (ii - i0 + 1)) * 4 + (j - f + 2)] =
               m == 0 ? q.P(ii, j) : m == 1 ? q.U(ii, j) : q.V(ii, j);
     }
-    ghost_region<T>(G, mx, my, min(lo, i0 - 1), max(hi, i1 + 1), f - 2, f + 2,
-                    [&](int ii, int j, const T v[3]) {
+    ghost_region_staged<T>(G, mx, my, min(lo, i0 - 1), max(hi, i1 + 1), f - 2, f + 2, box,
+                           [&](int ii, int j, const T v[3]) {
       if (ii >= i0 - 1 && ii <= i1)
         for (int m = 0; m < 3; ++m) strip[(m * pitch + (ii - i0 + 1)) * 4 + (j - f + 2)] = v[m];
       if ((bottom ? j < 0 : j >= my) && ii >= lo && ii < hi)
@@ -574,7 +603,7 @@ hipError_t fine_step_t(int limiter, const CfArgs &a, int step, double dt_fine, d
                        int max_blocks, hipStream_t s) {
   const dim3 g((unsigned)max(1, max_blocks), (unsigned)a.n_fine);
   const dim3 block((unsigned)a.strip);  // one thread per edge of the block
-  const size_t lds = 3 * (size_t)(a.strip + 2) * 4 * sizeof(T);
+  const size_t lds = 3 * ((size_t)(a.strip + 2) * 4 + cf_box_cells(a.strip, a.r)) * sizeof(T);
   switch (limiter) {
     case WS_LIM_NONE:
       hipLaunchKernelGGL((cf_fine_step_kernel<T, WS_LIM_NONE>), g, block, lds, s, a, step,

@@ -11,8 +11,10 @@ oracle and against the sets they must cover (no GPU):
 * the coarse-fine fine-step kernel's blocks: every strip cell a block reads
   is filled (interior cells loaded, ghost cells evaluated once per coarse
   cell), every ghost of the ring is written by exactly one block, the coarse
-  cell found by integer floor division equals the floating-point one, and
-  every strip index lies in the block's LDS array.
+  cell found by integer floor division equals the floating-point one, every
+  strip index lies in the block's LDS array, and the coarse box a block
+  stages holds every coarse cell its ghosts' stencils read and fits the LDS
+  the launch gives it.
 """
 
 import math
@@ -177,10 +179,20 @@ def replay_fine_step_blocks(mx, my, r, ci0=2, cj0=2, kStrip=None):
         for i in range(-2, mx + 2):
             if not (0 <= i < mx and 0 <= j < my): ring.add((i, j))
     LDS = 3 * (kStrip + 2) * 4
+    box_cells = ((3 + r - 1) // r + 3) * ((kStrip + 3 + r - 1) // r + 3)  # cf_box_cells
+    LDS_BYTES = 8 * (LDS + 3 * box_cells)
+    assert LDS_BYTES <= 64 * 1024
     def region(ia, ib, ja, jb, sink):
         CIa, CIb = fdiv(2*ia+1, 2*r), fdiv(2*(ib-1)+1, 2*r)
         CJa, CJb = fdiv(2*ja+1, 2*r), fdiv(2*(jb-1)+1, 2*r)
         nI, nJ = CIb - CIa + 1, CJb - CJa + 1
+        # the staged coarse box and the stencil cells read from it
+        bw, bh = nI + 2, nJ + 2
+        assert bw * bh <= box_cells, (ia, ib, ja, jb, r, kStrip)
+        def box_index(ci, cj):  # absolute coarse indices, as the kernel's at()
+            x, y = ci - ci0 - CIa + 1, cj - cj0 - CJa + 1
+            assert 0 <= x < bw and 0 <= y < bh
+            return y * bw + x
         seen = set()
         for k in range(nI * nJ):
             I, J = CIa + k % nI, CJa + k // nI
@@ -189,6 +201,9 @@ def replay_fine_step_blocks(mx, my, r, ci0=2, cj0=2, kStrip=None):
                     if 0 <= i < mx and 0 <= j < my: continue
                     X = ci0 + (i + 0.5) / r; Y = cj0 + (j + 0.5) / r
                     assert math.floor(X) == ci0 + I and math.floor(Y) == cj0 + J
+                    ci, cj = math.floor(X), math.floor(Y)
+                    for (di, dj) in ((0, 0), (-1, 0), (1, 0), (0, -1), (0, 1)):
+                        box_index(ci + di, cj + dj)
                     assert (i, j) not in seen; seen.add((i, j))
                     sink(i, j)
         want = {(i, j) for i in range(ia, ib) for j in range(ja, jb) if not (0 <= i < mx and 0 <= j < my)}
