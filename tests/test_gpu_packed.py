@@ -1,8 +1,9 @@
 """GPU parity of PACKED tiles (column blocks of several narrow patches sharing
 one wavefront) through the C ABI: the oracle's step of every patch (FP64 to
 1e-12, FP32 to 1e-5), the same state bitwise as every other tiling, the same
-Courant numbers and conservation sums, graphs equal to eager steps, and the
-calls that a PACKED tiling refuses."""
+Courant numbers and conservation sums, graphs equal to eager steps, composite
+coarse-fine steps and a tiled level with PACKED tiles equal to their other
+tilings bitwise, and the calls that a PACKED tiling refuses."""
 
 import numpy as np
 import pytest
@@ -213,3 +214,77 @@ def test_packed_refusals(ws):
     with pytest.raises(ws.WaveStepError, match="frozen ghosts"):
         ext.set_tiling(64, 16, variant="packed")
     ext.close()
+
+
+def _two_level(ws, rects, n, r, fine_tiling, dtype=torch.float64):
+    """The benchmark-shaped two-level composite (radial pulse) with the fine
+    level's tiling given; returns the states after three composite steps."""
+    import workloads
+    dx = 1.0 / n
+    coarse = ws.Level([dict(mx=n, my=n, dx=dx, dy=dx, bc="extrap")], [(RHO, KB)], dtype=dtype)
+    fine = ws.Level([dict(mx=r * w, my=r * h, dx=dx / r, dy=dx / r) for (_, _, w, h) in rects],
+                    [(RHO, KB)], dtype=dtype, stream=coarse.stream)
+    coarse.upload(0, workloads.padded_state(n, n, 0.0, 0.0, dx, dx))
+    coarse.fill_ghosts()
+    for k, (ci0, cj0, w, h) in enumerate(rects):
+        fine.upload(k, workloads.padded_state(r * w, r * h, ci0 * dx, cj0 * dx, dx / r, dx / r))
+    if fine_tiling is not None:
+        var, tw, th, wg = fine_tiling
+        fine.set_tiling(tw, th, wg_per_cu=wg, variant=var)
+    tl = ws.TwoLevel(coarse, fine, r, [(0, ci0, cj0) for (ci0, cj0, _, _) in rects])
+    for _ in range(3):
+        tl.step(0.9 * dx / C0)
+    out = coarse.download(0), [fine.download(k) for k in range(len(rects))]
+    for lev in (tl, fine, coarse):
+        lev.close()
+    return out
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_composite_step_with_a_packed_fine_level(ws, dtype):
+    """Coarse-fine composite steps (fine ghosts from the coarse level, the
+    fine terms, updating and the conservation fix) give the same bits with
+    the fine level in PACKED tiles as in its default tiles: the coupling reads
+    and writes the pools only, whatever tiles stepped them.  Fine patches of
+    several widths, some taller than a tile, two of them touching."""
+    n, r = 256, 4
+    rects = [(20, 20, 9, 7), (40, 30, 4, 12), (44, 30, 6, 12), (70, 60, 20, 5),
+             (100, 100, 3, 3), (130, 40, 17, 22)]
+    qa, fa = _two_level(ws, rects, n, r, None, dtype)
+    for tiling in (("packed", 64, 16, 0), ("packed", 64, 64, 16), ("packed", 64, 256, 0)):
+        qb, fb = _two_level(ws, rects, n, r, tiling, dtype)
+        assert np.array_equal(qa, qb), tiling
+        for k in range(len(rects)):
+            assert np.array_equal(fa[k], fb[k]), (tiling, k)
+
+
+def test_tiled_level_in_packed_tiles_equals_one_patch(ws):
+    """A domain cut into tiles of several widths and stepped in PACKED tiles
+    (the ghost exchange after every step) equals the domain stepped as one
+    patch, bitwise."""
+    DX, DY = 96, 40
+    shapes = [(20, 40), (36, 17), (36, 23), (40, 40)]
+    origins = [(0, 0), (20, 0), (20, 17), (56, 0)]
+    rng = np.random.default_rng(4)
+    interior = 1.0 + 0.1 * rng.normal(size=(3, DY, DX))
+    whole = np.zeros((3, DY + 4, DX + 4))
+    whole[:, 2:-2, 2:-2] = interior
+    for m in range(3):  # periodic ghosts
+        whole[m] = np.pad(interior[m], 2, mode="wrap")
+    one = ws.Level([dict(mx=DX, my=DY, dx=1 / DX, dy=1 / DX, bc="periodic")], [(RHO, KB)])
+    one.upload(0, whole)
+    lev = ws.Level([dict(mx=mx, my=my, dx=1 / DX, dy=1 / DX) for (mx, my) in shapes], [(RHO, KB)])
+    lev.link(origins, (DX, DY), (True, True))
+    for k, ((mx, my), (x0, y0)) in enumerate(zip(shapes, origins)):
+        lev.upload(k, whole[:, y0:y0 + my + 4, x0:x0 + mx + 4])
+    lev.set_tiling(64, 32, variant="packed")
+    assert set(lev.get_tiling()[0]) == {"packed"}
+    dt = 0.8 / DX / C0
+    for _ in range(5):
+        lev.step(dt, read_cfl=False)
+        one.step(dt, read_cfl=False)
+    R = one.download(0)
+    for k, ((mx, my), (x0, y0)) in enumerate(zip(shapes, origins)):
+        assert np.array_equal(lev.download(k), R[:, y0:y0 + my + 4, x0:x0 + mx + 4]), k
+    lev.close()
+    one.close()
