@@ -10,8 +10,8 @@ tiling never changes results (the library's arithmetic per cell does not
 depend on it), so tuning is safe on a live level.
 
 Choices are cached in a JSON file keyed by GPU architecture, the library's
-kernel sources, dtype, limiter (with the transverse variant) and the
-patch-size histogram.  A table of choices the tuner made on an MI355X for the
+step-kernel and tiling sources, dtype, limiter (with the transverse variant)
+and the patch-size histogram.  A table of choices the tuner made on an MI355X for the
 benchmark workloads ships beside this module (``tuned_tilings.json``) and is
 consulted before the user's cache, so a run on a fresh machine uses the same
 tilings as the runs its measurements were taken with; ``autotune(...,
@@ -81,16 +81,22 @@ def candidates(mx, my, periodic, medium=False, frozen=False):
 SHIPPED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_tilings.json")
 
 
+# The sources that decide how fast a tiling steps: the step kernels, the
+# tables they read and the host code that builds the tile lists.
+TILING_SOURCES = ("ws_api.hip", "ws_device.h", "ws_internal.h", "ws_kernels.hip", "ws_pack.h",
+                  "ws_tables.h")
+
+
 def _library_version():
-    """SHA-1 of the library's kernel sources (every file of csrc/ in name
-    order): the same sources give the same kernels, whichever build."""
+    """SHA-1 of the library's step-kernel and tiling sources (TILING_SOURCES
+    in name order): the same sources give the same kernels and tile lists,
+    whichever build."""
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     h = hashlib.sha1()
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in sorted(TILING_SOURCES):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:12]
 
 

@@ -575,8 +575,29 @@ __global__ __launch_bounds__(kThreads) void cf_finish_kernel(CfArgs a, double dt
   const int cidx = b * kThreads + threadIdx.x;
   if (cidx >= pl.ncx * pl.ncy) return;
   const int I = cidx % pl.ncx, J = cidx / pl.ncx;
-  // row by row, the row's loads issued together (up to 4 cells at a time)
+  // row by row, cell by cell, component by component
   double s[3] = {0.0, 0.0, 0.0};
+  if (r <= 4) {
+    // every load of the r x r block issued before the first addition
+    T v[4][3][4];
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+      for (int aa = 0; aa < 4; ++aa) {
+        const int i = I * r + min(aa, r - 1), j = J * r + min(bb, r - 1);
+        v[bb][0][aa] = f.P(i, j), v[bb][1][aa] = f.U(i, j), v[bb][2][aa] = f.V(i, j);
+      }
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+      for (int aa = 0; aa < 4; ++aa)
+        if (bb < r && aa < r)
+#pragma unroll
+          for (int m = 0; m < 3; ++m) s[m] += (double)v[bb][m][aa];
+    for (int m = 0; m < 3; ++m)
+      *cell_ptr<T>(a.c_new, cp, m, pl.ci0 + I, pl.cj0 + J) = (T)(s[m] / (double)(r * r));
+    return;
+  }
   for (int bb = 0; bb < r; ++bb) {
     const int j = J * r + bb;
     for (int a0 = 0; a0 < r; a0 += 4) {
