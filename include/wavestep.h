@@ -122,12 +122,14 @@ int ws_init_patches(ws_ctx **out, const ws_patch_desc *patches, int32_t n_patche
  *   variant WS_TILE_PACKED: tile_w = 64; the MARCH sweep with one
  *     wavefront's 64 lanes shared by column blocks of several narrow patches
  *     (each block of at most 60 columns takes its width plus four halo
- *     lanes).  The patch is cut into row segments of tile_h/4 rows (4 to
- *     64); blocks over the same rows of patches with the same instance, dx
- *     and dy share wavefronts, four wavefronts to a tile.  For patches with
- *     frozen ghosts (WS_BC_NONE) in pools under 2^31 bytes; a level with
- *     PACKED tiles refuses ws_step_level_per_patch, per-patch timing and
- *     ws_step_record_masks.
+ *     lanes).  Patches with the same instance, dx, dy, my and tile_h are
+ *     laid side by side into 64-lane columns (a patch may continue into the
+ *     next one), and each lane column is tiled like a MARCH patch: tiles of
+ *     tile_h rows (16 to 256), four stacked wavefronts of at most tile_h/4
+ *     rows each, the rows spread evenly over the four when the patch is
+ *     shorter.  For patches with frozen ghosts (WS_BC_NONE) in pools under
+ *     2^31 bytes; a level with PACKED tiles refuses ws_step_level_per_patch,
+ *     per-patch timing and ws_step_record_masks.
  * tile_h must be a multiple of 256/tile_w with at most 64 rows per thread
  * (DIRECT) or per segment (MARCH, PACKED).
  * Periodic patches take DIRECT tiles only.
