@@ -149,7 +149,8 @@ int ws_set_tiling(ws_ctx *ctx, const int32_t *variant, const int32_t *tile_w,
  * rho and K per cell instead of per instance.  medium: caller-owned device
  * buffer of at least pool_bytes (it holds c, Z and 1/(Z^2 + 1) per cell,
  * laid out like the q pools), kept until ws_destroy.  Attaching switches every patch to
- * DIRECT tiles (MARCH tiles are refused afterwards); the step then uses the
+ * DIRECT tiles; ws_set_tiling may then choose DIRECT or MARCH tiles (not
+ * PACKED), with the same results bitwise; the step then uses the
  * normal solver for two media (waves along (-Z_l, 1, 0) with speed -c_l and
  * (Z_r, 1, 0) with +c_r), limits on wave vectors, splits transversely with
  * the impedances of the neighbouring cells, and reduces the Courant number

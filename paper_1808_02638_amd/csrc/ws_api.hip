@@ -522,14 +522,12 @@ int ws_set_tiling(ws_ctx *c, const int32_t *variant, const int32_t *tile_w,
                     tile_h[k]);
       if (v == kMarch && c->rows[k].bc == WS_BC_PERIODIC)
         return fail(WS_EINVAL, "patch %d: periodic patches take DIRECT tiles only", k);
-      if (v == kMarch && c->medium)
-        return fail(WS_EINVAL, "patch %d: a heterogeneous medium takes DIRECT tiles only", k);
       if (v == kMarch && !march_fits(c->rows[k].plane, c->dtype))
         return fail(WS_EINVAL, "patch %d: too large for MARCH tiles (32-bit offsets)", k);
       if (v == kPacked && c->rows[k].bc != WS_BC_NONE)
         return fail(WS_EINVAL, "patch %d: PACKED tiles take patches with frozen ghosts only", k);
       if (v == kPacked && c->medium)
-        return fail(WS_EINVAL, "patch %d: a heterogeneous medium takes DIRECT tiles only", k);
+        return fail(WS_EINVAL, "patch %d: a heterogeneous medium takes DIRECT or MARCH tiles", k);
       if (v == kPacked && c->P.elems * (c->dtype == WS_F32 ? 4 : 8) >= (int64_t{1} << 31))
         return fail(WS_EINVAL, "PACKED tiles need pools under 2 GiB (32-bit offsets)");
     }

@@ -1181,6 +1181,106 @@ __device__ inline double wave_max(double v) {
 // One work unit, quarter q of tile t (MARCH: segment q; DIRECT: threads
 // q*64 .. q*64+63 of the tile), worked by one wavefront; returns the tile's
 // Courant number.  No barrier: wavefronts take units independently.
+// MARCH segment in a heterogeneous medium, marching up over rows [r0, r1):
+// the quantities of cell_update_var, each formed by the same expression from
+// the same inputs, so every cell's result is bitwise that of
+// cell_update_var.  Each lane solves only its column's left x-edge and, once
+// per row, the y-edge above its window; what a cell needs of its neighbours'
+// edges and fluctuations comes through lane shifts (an x-edge's limited
+// correction is the left edge of one lane and the right edge of the lane to
+// its left), and along the column the five-row window of (p, u, v) and
+// (c, Z, 1/(Z^2 + 1)), the four y-edges and the x-fluctuation of the row
+// below are carried.  One row is loaded ahead of the window (two ahead kept
+// 170 registers, two waves per SIMD, and ran slower).  D addresses
+// the medium's planes as M does the state's.  Returns the largest Courant
+// number of the lane's cells (0 on lanes that update none).
+template <typename T>
+struct VarXEdge {
+  T a1, a2, iz;  // strengths of the lane's left edge and 1/(Z_left + Z)
+  T Fp, Fn;      // its limited normal correction
+};
+
+template <typename T, int LIM>
+__device__ __attribute__((always_inline)) inline VarXEdge<T> var_xedge(const Row3<T> &Q,
+                                                                        const Row3<T> &E,
+                                                                        T dtdx) {
+  VarXEdge<T> X;
+  const T pl = shr(Q.p), ul = shr(Q.u), cl = shr(E.p), Zl = shr(E.u), wl = shr(E.v);
+  var_strengths(Zl, E.u, Q.p - pl, Q.u - ul, X.a1, X.a2, X.iz);
+  T l1, l2;
+  var_limited<T, LIM>(X.a1, X.a2, shl(X.a1), shr(X.a2), Zl, E.u, wl, E.v, l1, l2);
+  var_corr(cl, Zl, E.p, E.u, l1, l2, dtdx, X.Fp, X.Fn);
+  return X;
+}
+
+template <typename T, int LIM>
+__device__ __attribute__((always_inline)) inline T march_up_var(const MarchLanes<T> &M,
+                                                                const MarchLanes<T> &D,
+                                                                const Coef<T> &k, int r0, int r1) {
+  const T dtdx = k.dtdx, dtdy = k.dtdy;
+  Row3<T> Q[5], E[5], Qa, Ea;  // window rows r-2 .. r+2; row r+3
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    M.fetch(Q[d], r0 + d - 2);
+    D.fetch(E[d], r0 + d - 2);
+  }
+  M.fetch(Qa, r0 + 3);
+  D.fetch(Ea, r0 + 3);
+  // y-edge e between window rows e and e+1
+  T b1[4], b2[4], bz[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    var_strengths(E[e].u, E[e + 1].u, Q[e + 1].p - Q[e].p, Q[e + 1].v - Q[e].v, b1[e], b2[e],
+                  bz[e]);
+  // x-edges of rows r0-1 and r0; the x-fluctuation p-part of row r0-1
+  T Xpb;
+  {
+    const VarXEdge<T> B = var_xedge<T, LIM>(Q[1], E[1], dtdx);
+    Xpb = E[1].p * E[1].u * (B.a2 + shl(B.a1));
+  }
+  VarXEdge<T> XR = var_xedge<T, LIM>(Q[2], E[2], dtdx);
+  T cfl = T(0);
+  for (int r = r0; r < r1; ++r) {
+    // x-edges of row r+1 and its cells' x-fluctuation p-part
+    const VarXEdge<T> XN = var_xedge<T, LIM>(Q[3], E[3], dtdx);
+    const T Xpt = E[3].p * E[3].u * (XN.a2 + shl(XN.a1));
+    // the cell's x-line: its left edge here, its right edge the next lane's left
+    VarLine<T> X;
+    X.Fl_p = XR.Fp, X.Fl_n = XR.Fn, X.Fr_p = shl(XR.Fp), X.Fr_n = shl(XR.Fn);
+    const T a1r = shl(XR.a1);
+    X.xs = XR.a2 + a1r;
+    X.xd = XR.a2 - a1r;
+    X.izl = XR.iz, X.izr = shl(XR.iz);
+    X.cl = shr(E[2].p), X.zl = shr(E[2].u), X.c0 = E[2].p, X.z0 = E[2].u;
+    X.cr = shl(E[2].p), X.zr = shl(E[2].u);
+    // the y-line from the carried edges
+    const T Cc[5] = {E[0].p, E[1].p, E[2].p, E[3].p, E[4].p};
+    const T Zc[5] = {E[0].u, E[1].u, E[2].u, E[3].u, E[4].u};
+    const VarLine<T> Y = var_line_edges<T, LIM>(b1, b2, bz, Cc, Zc, E[1].v, E[2].v, E[3].v, dtdy);
+    // y-fluctuation p-parts of the cells left and right
+    const T Yp = E[2].p * E[2].u * Y.xs;
+    T pn, un, vn, cj;
+    var_combine(X, Y, Xpb, Xpt, shr(Yp), shl(Yp), Q[2].p, Q[2].u, Q[2].v, dtdx, dtdy, pn, un, vn,
+                cj);
+    if (M.out) cfl = fmax(cfl, cj);
+    M.emit(pn, un, vn, r);
+    // slide up one row
+    Xpb = X.c0 * X.z0 * X.xs;
+    XR = XN;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) Q[d] = Q[d + 1], E[d] = E[d + 1];
+    Q[4] = Qa, E[4] = Ea;
+    if (r + 4 <= r1 + 1) {
+      M.fetch(Qa, r + 4);
+      D.fetch(Ea, r + 4);
+    }
+#pragma unroll
+    for (int e = 0; e < 3; ++e) b1[e] = b1[e + 1], b2[e] = b2[e + 1], bz[e] = bz[e + 1];
+    var_strengths(E[3].u, E[4].u, Q[4].p - Q[3].p, Q[4].v - Q[3].v, b1[3], b2[3], bz[3]);
+  }
+  return cfl;
+}
+
 // VARS: bit 0 -> DIRECT tiles may occur, bit 1 -> MARCH tiles, bit 2 -> PACKED
 // tiles (the step without branch recording or a medium only).
 // TC: the transverse-correction variant (never with MASKS).
@@ -1253,6 +1353,17 @@ __device__ __attribute__((always_inline)) inline double do_unit(const StepArgs &
     const int i = te.tx * (kMarchWidth - 4) - 2 + lx;
     const int r0 = te.ty * pr.th + q * rows;
     const int r1 = min(r0 + rows, pr.my);
+    if constexpr (VAR) {
+      // heterogeneous medium: the tile's Courant number is reduced from its cells
+      T cfl = T(0);
+      if (r0 < r1) {
+        const MarchLanes<T> M(qi, qo, pr, lx, i);
+        const T *mi = reinterpret_cast<const T *>(a.medium) + org;
+        const MarchLanes<T> D(mi, const_cast<T *>(mi), pr, lx, i);
+        cfl = march_up_var<T, LIM>(M, D, k, r0, r1);
+      }
+      return wave_max((double)cfl);
+    }
     if (r0 < r1) {
       const MarchLanes<T> M(qi, qo, pr, lx, i);
       // segments alternate direction up the patch (the recording step marches up)
@@ -1465,10 +1576,10 @@ __global__ __launch_bounds__(kThreads) void step_kernel(StepArgs a) {
   step_body<T, LIM, MASKS, VARS, TC>(a);
 }
 
-// Heterogeneous media: DIRECT tiles only.
-template <typename T, int LIM>
+// Heterogeneous media: DIRECT tiles, MARCH tiles (VARS 2), or both (3).
+template <typename T, int LIM, int VARS>
 __global__ __launch_bounds__(kThreads) void step_kernel_var(StepArgs a) {
-  step_body<T, LIM, false, 1, false, true>(a);
+  step_body<T, LIM, false, VARS, false, true>(a);
 }
 
 // MARCH-only levels: a kernel of their own, free of the DIRECT path's registers.
@@ -1680,28 +1791,34 @@ hipError_t launch_step_m(bool tc, int vars, const StepArgs &a, int grid, hipStre
   return launch_step_v<T, LIM, false, false>(vars, a, grid, s);
 }
 
-template <typename T>
-hipError_t launch_step_var(int lim, const StepArgs &a, int grid, hipStream_t s) {
-  if (a.masks) return hipErrorInvalidValue;
-  switch (lim) {
-    case WS_LIM_NONE:
-      hipLaunchKernelGGL((step_kernel_var<T, WS_LIM_NONE>), dim3(grid), dim3(kThreads), 0, s, a);
-      break;
-    case WS_LIM_VANLEER:
-      hipLaunchKernelGGL((step_kernel_var<T, WS_LIM_VANLEER>), dim3(grid), dim3(kThreads), 0, s, a);
-      break;
-    default:
-      hipLaunchKernelGGL((step_kernel_var<T, WS_LIM_MC>), dim3(grid), dim3(kThreads), 0, s, a);
+template <typename T, int LIM>
+hipError_t launch_step_var_l(int vars, const StepArgs &a, int grid, hipStream_t s) {
+  switch (vars) {
+    case 1: hipLaunchKernelGGL((step_kernel_var<T, LIM, 1>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((step_kernel_var<T, LIM, 2>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((step_kernel_var<T, LIM, 3>), dim3(grid), dim3(kThreads), 0, s, a); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_step_var(int lim, int vars, const StepArgs &a, int grid, hipStream_t s) {
+  if (a.masks) return hipErrorInvalidValue;
+  switch (lim) {
+    case WS_LIM_NONE: return launch_step_var_l<T, WS_LIM_NONE>(vars, a, grid, s);
+    case WS_LIM_VANLEER: return launch_step_var_l<T, WS_LIM_VANLEER>(vars, a, grid, s);
+    default: return launch_step_var_l<T, WS_LIM_MC>(vars, a, grid, s);
+  }
 }
 
 // limiter: WS_LIM_*, optionally with WS_TRANSVERSE_CORR or kMediumFlag.
 template <typename T>
 hipError_t launch_step_l(int limiter, int vars, const StepArgs &a, int grid, hipStream_t s) {
   if (limiter & kMediumFlag) {
-    if (vars != 1 || !a.medium || (limiter & WS_TRANSVERSE_CORR)) return hipErrorInvalidValue;
-    return launch_step_var<T>(limiter & 0xff, a, grid, s);
+    if (vars < 1 || vars > 3 || !a.medium || (limiter & WS_TRANSVERSE_CORR))
+      return hipErrorInvalidValue;
+    return launch_step_var<T>(limiter & 0xff, vars, a, grid, s);
   }
   const bool tc = (limiter & WS_TRANSVERSE_CORR) != 0;
   switch (limiter & ~WS_TRANSVERSE_CORR) {
@@ -1757,24 +1874,26 @@ hipError_t launch_step(int dtype, int limiter, int vars, const StepArgs &a, int 
                          : launch_step_l<double>(limiter, vars, a, grid, s);
 }
 
+template <typename T, int LIM>
+int occupancy_var(int vars, int *n) {
+  hipError_t e;
+  if (vars == 2)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel_var<T, LIM, 2>, kThreads, 0);
+  else if (vars == 3)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel_var<T, LIM, 3>, kThreads, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(n, step_kernel_var<T, LIM, 1>, kThreads, 0);
+  return e == hipSuccess ? 0 : -1;
+}
+
 template <typename T>
 int occupancy_l(int limiter, int vars, int *wg_per_cu) {
   if (limiter & kMediumFlag) {
-    hipError_t e;
     switch (limiter & 0xff) {
-      case WS_LIM_NONE:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, step_kernel_var<T, WS_LIM_NONE>,
-                                                         kThreads, 0);
-        break;
-      case WS_LIM_VANLEER:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            wg_per_cu, step_kernel_var<T, WS_LIM_VANLEER>, kThreads, 0);
-        break;
-      default:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(wg_per_cu, step_kernel_var<T, WS_LIM_MC>,
-                                                         kThreads, 0);
+      case WS_LIM_NONE: return occupancy_var<T, WS_LIM_NONE>(vars, wg_per_cu);
+      case WS_LIM_VANLEER: return occupancy_var<T, WS_LIM_VANLEER>(vars, wg_per_cu);
+      default: return occupancy_var<T, WS_LIM_MC>(vars, wg_per_cu);
     }
-    return e == hipSuccess ? 0 : -1;
   }
   const bool tc = (limiter & WS_TRANSVERSE_CORR) != 0;
   switch (limiter & ~WS_TRANSVERSE_CORR) {

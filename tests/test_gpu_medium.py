@@ -2,9 +2,10 @@
 the oracle's heterogeneous step, through the C ABI.
 
 FP64 within a relative L-infinity of 1e-12 per component (the Courant number
-bitwise), FP32 within 1e-5; tilings (one to 64 rows marched per thread) and
-batched vs per-patch launches bitwise equal; a uniform medium reproduces the
-homogeneous kernels.
+bitwise), FP32 within 1e-5, with DIRECT tiles and with MARCH tiles (lane
+segments sharing edges); tilings (one to 64 rows marched per thread, MARCH
+segments of 1 to 64 rows) and batched vs per-patch launches bitwise equal; a
+uniform medium reproduces the homogeneous kernels.
 """
 
 import math
@@ -75,20 +76,26 @@ def test_matches_oracle(ws, dtype, limiter, kind):
     dt = 0.8 / max(mx, my) / cmax
     steps = 12 if limiter != "none" or kind != "rough" else 3
     lev = level(ws, mx, my, rho, K, q, dtype, limiter)
+    levm = level(ws, mx, my, rho, K, q, dtype, limiter)
+    levm.set_tiling(64, 24, variant="march")
     ref = q.copy()
     for _ in range(steps):
         ref, cfl_o = O.step_var(ref, 1 / mx, 1 / my, dt, rho, K, limiter)
         O.fill_bc(ref, "extrap")
         cfl_g = lev.step(dt)
+        assert levm.step(dt) == cfl_g
         if dtype == torch.float64:
             assert cfl_g == cfl_o
         else:
             assert abs(cfl_g - cfl_o) <= 1e-6 * cfl_o
-    err = rel_linf(lev.download(0), ref)
+    out = lev.download(0)
+    assert np.array_equal(levm.download(0), out)
+    err = rel_linf(out, ref)
     tol = FP64_TOL if dtype == torch.float64 else FP32_TOL
     print(f"medium {kind} {limiter} {dtype}: rel Linf {err}")
     assert err.max() <= tol, err
     lev.close()
+    levm.close()
 
 
 def test_uniform_medium_reproduces_the_homogeneous_kernel(ws):
@@ -124,14 +131,20 @@ def test_tilings_and_batching_bitwise(ws):
         for k, q in enumerate(states):
             lev.upload(k, q)
         if tiling:
-            lev.set_tiling(*tiling, variant="direct")
+            lev.set_tiling(*tiling[1:], variant=tiling[0])
         return lev
 
     dt = 0.5 / 64 / 10.0
     outs = []
     # one row per thread (8x32, 64x4, 256x1) up to 64 rows per thread (64x256,
-    # 16x1024): each thread marches up its column carrying values between rows
-    for tiling in [None, (8, 32), (64, 4), (32, 64), (256, 1), (64, 256), (16, 1024)]:
+    # 16x1024): each thread marches up its column carrying values between rows;
+    # MARCH segments of 1, 9 and 64 rows; a mix of the two kinds
+    mixed = (["march", "direct", "march", "direct"], [64, 32, 64, 16], [20, 32, 256, 64])
+    for tiling in [None, ("direct", 8, 32), ("direct", 64, 4), ("direct", 32, 64),
+                   ("direct", 256, 1), ("direct", 64, 256), ("direct", 16, 1024),
+                   ("march", 64, 4), ("march", 64, 36), ("march", 64, 256), mixed]:
+        if tiling is mixed:
+            tiling = (mixed[0], mixed[1], mixed[2])
         lev = make(tiling)
         for _ in range(3):
             lev.step(dt)
@@ -156,7 +169,7 @@ def test_medium_restrictions(ws):
     variants, _, _, _, _ = lev.get_tiling()
     assert variants == ["direct"]
     with pytest.raises(ws.WaveStepError):
-        lev.set_tiling(64, 8, variant="march")
+        lev.set_tiling(64, 16, variant="packed")
     with pytest.raises(ws.WaveStepError):
         lev.step_record_masks(0.001, lev.new_masks())
     bad = rho.copy()
