@@ -53,10 +53,11 @@ def size_classes(level):
 
 
 def candidates(mx, my, periodic, medium=False, frozen=False):
-    """Tilings worth timing for patches of about mx x my cells (DIRECT only for
-    periodic patches; PACKED for patches with frozen ghosts in a homogeneous
-    medium).  A heterogeneous medium's DIRECT threads march up their column,
-    so taller runs of rows per thread are tried too."""
+    """Tilings worth timing for patches of about mx x my cells: DIRECT and
+    MARCH tiles (DIRECT only for periodic patches), and PACKED tiles for
+    patches with frozen ghosts in a homogeneous medium.  In a heterogeneous
+    medium DIRECT threads march up their column, so taller runs of rows per
+    thread are tried too."""
     out = []
     rows = (1, 2, 4, 8, 16, 32, 64) if medium else (1, 2, 4, 8)
     for tw in (8, 16, 32, 64, 128):

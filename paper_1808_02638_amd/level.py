@@ -103,7 +103,8 @@ class Level:
     def set_medium(self, k: int, rho, K) -> None:
         """Heterogeneous medium of patch k: rho, K as (my+4, mx+4) arrays (ghost
         cells included).  The first call attaches a medium buffer to the level
-        (every patch then takes DIRECT tiles); patches never given a medium
+        and resets every patch to its default DIRECT tiles (set_tiling or the
+        autotuner may then choose MARCH tiles); patches never given a medium
         keep whatever the buffer holds, so give every patch one."""
         mx, my = self.shapes[k]
         rho = np.ascontiguousarray(rho, dtype=np.float64)
