@@ -372,7 +372,8 @@ def run_adjoint(ws, torch):
     """The adjoint workload: 512^2 FP64, 200 fixed-dt steps at Courant 0.8, 16
     receivers, checkpoints every 20 steps: forward traces and the backward
     sweep (re-run forward segments recording the branches, then the adjoint
-    steps), and the adjoint step kernel alone."""
+    steps), and the adjoint step kernel alone; then the same with every
+    step's branches recorded in the forward pass (no re-run)."""
     import numpy as np
 
     import workloads
@@ -396,6 +397,7 @@ def run_adjoint(ws, torch):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     grad_ok = bool(torch.isfinite(p0.grad).all())
+    grad_ckpt = p0.grad.detach().clone()
     # the adjoint step alone: lam' -> S^T lam' on the recorded branches
     lev = run.level
     masks = lev.new_masks()
@@ -423,11 +425,33 @@ def run_adjoint(ws, torch):
     adj_ms = e0.elapsed_time(e1) / reps
     byts = n * n * (48 + 1)  # lam in, lam out (3 FP64 each), one mask byte per cell
     run.close()
+    # every step's branches recorded in the forward pass instead of the
+    # checkpoints: the backward pass runs only the adjoint steps
+    runb = ws.AcousticsAdjoint(n, n, setup.dx, setup.dx, RHO, K_BULK, setup.receivers, steps,
+                               setup.dt, checkpoint_every=setup.checkpoint_every,
+                               store_branches=True)
+    for _ in range(2):  # warm
+        p0.grad = None
+        runb.misfit(p0, target).backward()
+    torch.cuda.synchronize()
+    p0.grad = None
+    t3 = time.perf_counter()
+    loss = runb.misfit(p0, target)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    same = bool(torch.equal(p0.grad, grad_ckpt))
+    runb.close()
     return {"grid": f"{n}x{n}", "steps": steps, "checkpoint_every": setup.checkpoint_every,
             "forward_ms": round((t1 - t0) * 1e3, 3), "backward_ms": round((t2 - t1) * 1e3, 3),
             "adjoint_step_us": round(adj_ms * 1e3, 2),
             "adjoint_step_gcells": round(n * n / adj_ms / 1e6, 2),
-            "adjoint_step_GBs": round(byts / (adj_ms / 1e3) / 1e9, 1), "grad_finite": grad_ok}
+            "adjoint_step_GBs": round(byts / (adj_ms / 1e3) / 1e9, 1), "grad_finite": grad_ok,
+            "stored_branches": {"forward_ms": round((t4 - t3) * 1e3, 3),
+                                "backward_ms": round((t5 - t4) * 1e3, 3),
+                                "branch_bytes": steps * n * n, "grad_equal": same}}
 
 
 PROFILE = os.path.join(ROOT, "profiles", "step_kernel_march_f64_2048sq.md")

@@ -13,6 +13,12 @@ frozen-branch adjoint steps run in reverse, each first adding the trace
 cotangent of its step at the receivers.  The result is the cotangent of the
 interior pressure p0.  All work runs in the library's kernels on the level's
 stream; torch provides the buffers.
+
+With ``store_branches=True`` the forward pass itself records every step's
+branches (one byte per cell and step: 52 MB for 200 steps of 512^2, small
+beside the GPU's memory) and keeps no checkpoints; the backward pass then
+runs only the adjoint steps.  The recording step gives the same state as the
+plain one, so the traces and the gradient are the same bits either way.
 """
 
 from __future__ import annotations
@@ -51,9 +57,10 @@ class AcousticsAdjoint:
     with respect to p0 (shape (my, mx), FP64, on the GPU)."""
 
     def __init__(self, mx, my, dx, dy, rho, K, receivers, nsteps, dt, checkpoint_every=20,
-                 velocity0=None, device="cuda"):
+                 velocity0=None, device="cuda", store_branches=False):
         if nsteps < 1 or checkpoint_every < 1:
             raise ValueError("nsteps and checkpoint_every must be >= 1")
+        self.store_branches = bool(store_branches)
         if not (dt > 0.0 and math.isfinite(dt)):
             raise ValueError("dt must be finite and > 0")
         self.mx, self.my = int(mx), int(my)
@@ -110,11 +117,23 @@ class AcousticsAdjoint:
             ckpts = []
             ij, nr, dt = ctypes.c_void_p(self.ij.data_ptr()), self.nr, self.dt
             base = traces.data_ptr()
-            for n in range(self.nsteps):
-                if n % self.k == 0:
-                    ckpts.append(lev.state_view(0).clone())
-                C.check(L.ws_step_level(ctx, dt, None))
-                C.check(L.ws_gather(ctx, None, 0, 0, nr, ij, ctypes.c_void_p(base + 8 * nr * n)))
+            if self.store_branches:
+                # every step records its branches; no checkpoints
+                nb = (lev.mask_bytes() + 255) // 256 * 256
+                masks = torch.empty(self.nsteps * nb, dtype=torch.uint8, device=lev.device)
+                mb = masks.data_ptr()
+                for n in range(self.nsteps):
+                    C.check(L.ws_step_record_masks(ctx, dt, ctypes.c_void_p(mb + nb * n), None))
+                    C.check(L.ws_gather(ctx, None, 0, 0, nr, ij,
+                                        ctypes.c_void_p(base + 8 * nr * n)))
+                ckpts = masks
+            else:
+                for n in range(self.nsteps):
+                    if n % self.k == 0:
+                        ckpts.append(lev.state_view(0).clone())
+                    C.check(L.ws_step_level(ctx, dt, None))
+                    C.check(L.ws_gather(ctx, None, 0, 0, nr, ij,
+                                        ctypes.c_void_p(base + 8 * nr * n)))
         lev.stream.synchronize()
         return traces, ckpts
 
@@ -126,6 +145,21 @@ class AcousticsAdjoint:
             if g.shape != (self.nsteps, self.nr):
                 raise ValueError("trace cotangent has the wrong shape")
             lam, lam_next = lev.new_buffer(), lev.new_buffer()
+            if self.store_branches:
+                # the forward pass recorded every step's branches (ckpts)
+                bufs = [ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(lam_next.data_ptr())]
+                ij, nr, dt, gb = ctypes.c_void_p(self.ij.data_ptr()), self.nr, self.dt, g.data_ptr()
+                nb, mb = (lev.mask_bytes() + 255) // 256 * 256, ckpts.data_ptr()
+                cur = 0
+                for n in range(self.nsteps - 1, -1, -1):
+                    C.check(L.ws_add_at(ctx, bufs[cur], 0, 0, nr, ij,
+                                        ctypes.c_void_p(gb + 8 * nr * n)))
+                    C.check(L.ws_adjoint_step(ctx, dt, ctypes.c_void_p(mb + nb * n), bufs[cur],
+                                              bufs[1 - cur]))
+                    cur = 1 - cur
+                grad = lev.patch_view(lam if cur == 0 else lam_next, 0)[0, 2:-2, 2:-2].clone()
+                lev.stream.synchronize()
+                return grad
             masks = [lev.new_masks() for _ in range(min(self.k, self.nsteps))]
             mp = [ctypes.c_void_p(m.data_ptr()) for m in masks]
             bufs = [ctypes.c_void_p(lam.data_ptr()), ctypes.c_void_p(lam_next.data_ptr())]

@@ -232,20 +232,26 @@ def test_gradient_matches_oracle_adjoint(ws, oracle_lib):
 
 
 def test_gradient_independent_of_checkpoint_interval(ws):
+    """Checkpoints every 1, 7, 25 or 40 steps, or every step's branches
+    recorded in the forward pass (no re-run in the backward pass): the same
+    traces and gradient, bit for bit."""
     n, steps = 40, 25
     setup = workloads.adjoint_setup(n=n, steps=steps)
     p0, vel, _ = _smooth_problem(n, seed=4)
     target = torch.zeros((steps, len(setup.receivers)), dtype=torch.float64, device="cuda")
-    grads = []
-    for k in (1, 7, 25, 40):
+    grads, traces = [], []
+    for k, store in ((1, False), (7, False), (25, False), (40, False), (7, True)):
         run = ws.AcousticsAdjoint(n, n, 1 / n, 1 / n, RHO, KB, setup.receivers, steps, setup.dt,
-                                  checkpoint_every=k, velocity0=vel)
+                                  checkpoint_every=k, velocity0=vel, store_branches=store)
         p = torch.tensor(p0, device="cuda", requires_grad=True)
-        run.misfit(p, target).backward()
+        tr = run.traces(p)
+        (0.5 * ((tr - target) ** 2).sum()).backward()
         grads.append(p.grad.cpu().numpy())
+        traces.append(tr.detach().cpu().numpy())
         run.close()
-    for g in grads[1:]:
+    for g, t in zip(grads[1:], traces[1:]):
         assert np.array_equal(g, grads[0])
+        assert np.array_equal(t, traces[0])
 
 
 def _gpu_forward(ws, n, p0, vel, steps, dt, receivers):
