@@ -71,7 +71,7 @@ def dump(tmp_path_factory):
     return run
 
 
-ES = 8  # the driver's pool layout is of FP64 elements
+ES = 8  # the dump program lays out FP64 pools
 
 
 def lane_map(pw, shapes, P):
