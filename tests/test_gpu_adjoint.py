@@ -339,6 +339,13 @@ def test_full_size_gradient_central_differences(ws):
     g = p.grad.cpu().numpy()
     run.close()
     assert np.isfinite(g).all() and np.abs(g).max() > 0
+    # the same gradient bits with every step's branches stored in the forward pass
+    runb = ws.AcousticsAdjoint(n, n, 1 / n, 1 / n, RHO, KB, setup.receivers, steps, setup.dt,
+                               store_branches=True)
+    pb = torch.tensor(p0, device="cuda", requires_grad=True)
+    runb.misfit(pb, torch.from_numpy(tr_t).cuda()).backward()
+    assert np.array_equal(pb.grad.cpu().numpy(), g)
+    runb.close()
     _, m0 = _gpu_forward(ws, n, p0, vel, steps, setup.dt, setup.receivers)
     rng = np.random.default_rng(20)
     xs = (np.arange(n) + 0.5) / n
